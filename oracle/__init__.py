@@ -1,0 +1,27 @@
+"""Plain FP64 CPU oracle for the one-level AS / RAS / ORAS-preconditioned GMRES solve
+of the lowest-order Nedelec discretisation of curl curl E - (k^2 + i xi) E = F.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the C-ABI library and its Python
+binding) imports, links or runs anything here; only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark do.  The oracle shares no code with the GPU path.
+
+Every function is written from the paper (Bonazzoli, Dolean, Graham, Spence, Tournier,
+"Domain decomposition preconditioning for the high-frequency time-harmonic Maxwell equations
+with absorption", Math. Comp. 2019 / arXiv:1711.03789):
+
+* mesh.py      structured box mesh, Kuhn 6-tetrahedra split, edge numbering (Sec. 2.2)
+* fem.py       Whitney element matrices, Galerkin matrix A_xi and load f (Sec. 2.2,
+               eq:Helmholtzvf_intro, impedance condition eq:imp)
+* dd.py        non-overlapping boxes, overlap by tetrahedron layers (Sec. 6.1), local DOF
+               sets and restriction (eq:restriction1), minors (eq:minor), Boolean partition
+               of unity (eq:algebPartUnity), local impedance problems (ImpRAS, Sec. 6.3),
+               AS / RAS / ORAS application (eq:defAS without the coarse term, RAS_1, ImpRAS_1)
+* rcm.py       reverse Cuthill-McKee ordering of a local matrix graph (not in the paper: the
+               paper's local solves are sparse direct; the ordering is only compared
+               integer-for-integer with the library's own)
+* gmres.py     restarted right-preconditioned (F)GMRES with classical Gram-Schmidt twice and
+               complex Givens rotations (Sec. 5.2 minimal-residual definition, Sec. 6.1
+               stopping rule)
+
+Precision: float64 / complex128 throughout.
+"""

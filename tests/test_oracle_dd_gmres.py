@@ -1,0 +1,227 @@
+"""Pins of the oracle's partition, Schwarz preconditioners, RCM and GMRES (no GPU)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import dd, fem, gmres, rcm
+from oracle.mesh import Mesh
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_partition_of_unity_and_cover():
+    m = Mesh(6, 5, 4)
+    part = dd.Partition(m, 3, 2, 2, 2)
+    E = m.n_edge
+    for kind in (dd.RAS, dd.ORAS):
+        S = sp.csr_matrix((E, E))
+        cover = np.zeros(E, dtype=bool)
+        for l in range(part.N):
+            R = part.restriction(l, kind)
+            S = S + R.T @ sp.diags(part.pou(l, kind)) @ R
+            cover[part.local_set(kind)[l]] = True
+        assert abs(S - sp.identity(E)).max() == 0.0  # eq:algebPartUnity exactly
+        assert cover.all()  # the local sets cover all DOFs
+    for l in range(part.N):
+        assert set(part.as_sets[l]) <= set(part.oras_sets[l])
+        assert len(part.neighbours(l)) <= 26  # finite overlap for boxes
+
+
+def test_overlap_monotone_and_touching():
+    m = Mesh(6, 6, 6)
+    prev = None
+    for L in range(4):
+        part = dd.Partition(m, 2, 2, 2, L)
+        if prev is not None:
+            for l in range(part.N):
+                assert np.all(part.tet_masks[l] >= prev.tet_masks[l])
+        prev = part
+    # one sweep adds exactly the tetrahedra sharing a vertex with the previous set
+    part0 = dd.Partition(m, 2, 2, 2, 0)
+    part1 = dd.Partition(m, 2, 2, 2, 1)
+    v0 = set(m.tet_vert[part0.tet_masks[0]].ravel())
+    brute = np.array([bool(set(t) & v0) for t in m.tet_vert])
+    assert np.array_equal(brute, part1.tet_masks[0])
+    # L = 0: AS sets are interior edges of the boxes, ORAS sets all their edges
+    assert sum(len(s) for s in part0.oras_sets) > m.n_edge > sum(len(s) for s in part0.as_sets)
+
+
+def test_config1_local_sizes_symmetry():
+    """8^3 cubes, 2x2x2 boxes, 2 layers.  The Kuhn split is invariant under permutations of the
+    axes and under the point reflection x -> (1,1,1) - x, so the six boxes off the main diagonal
+    have equal local sizes and the two on it (0 and 7) are equal to each other."""
+    m = Mesh(8, 8, 8)
+    part = dd.Partition(m, 2, 2, 2, 2)
+    for sets in (part.oras_sets, part.as_sets):
+        n = [len(s) for s in sets]
+        assert n[0] == n[7] and len(set(n[1:7])) == 1 and n[0] > n[1]
+    assert len(part.oras_sets[0]) == 1854 and len(part.as_sets[0]) == 1512
+
+
+@pytest.mark.parametrize("kind", [dd.AS, dd.RAS, dd.ORAS])
+def test_dense_brute_force(kind):
+    m = Mesh(3, 3, 2)
+    k, xi = 3.0, 9.0
+    A = fem.assemble(m, k, xi)
+    part = dd.Partition(m, 2, 2, 1, 1)
+    B = dd.Schwarz(part, A, kind, k, xi)
+    Bd = dd.dense_schwarz(part, A, kind, k, xi)
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(m.n_edge) + 1j * rng.standard_normal(m.n_edge)
+    assert np.allclose(B(v), Bd @ v, rtol=1e-10, atol=1e-12 * np.abs(Bd @ v).max())
+    if kind == dd.AS:
+        assert np.abs(Bd - Bd.T).max() < 1e-10 * np.abs(Bd).max()  # AS is complex symmetric
+
+
+def test_as_local_projection():
+    """T^l = R^T (A^l)^-1 R A is a projection and R A (I - T^l) = 0 (Lemma thm:repQ)."""
+    m = Mesh(3, 3, 3)
+    k, xi = 3.0, 9.0
+    A = fem.assemble(m, k, xi).toarray()
+    part = dd.Partition(m, 2, 1, 1, 1)
+    idx = part.as_sets[0]
+    R = np.zeros((len(idx), m.n_edge))
+    R[np.arange(len(idx)), idx] = 1
+    Al = R @ A @ R.T
+    T = R.T @ np.linalg.solve(Al, R @ A)
+    assert np.abs(T @ T - T).max() < 1e-9
+    assert np.abs(R @ A @ (np.eye(m.n_edge) - T)).max() < 1e-9 * np.abs(A).max()
+    # the oracle's AS minors are exactly these
+    loc = dd.local_matrices(part, fem.assemble(m, k, xi), dd.AS, k, xi)
+    assert np.abs(loc[0].toarray() - Al).max() == 0.0
+
+
+@pytest.mark.parametrize("kind", [dd.AS, dd.RAS, dd.ORAS])
+def test_single_subdomain_is_exact(kind):
+    """N = 1: B^-1 = A^-1 (eq:defAS with one subdomain), GMRES converges in one iteration."""
+    m = Mesh(4, 3, 3)
+    k, xi = 4.0, 4.0
+    A = fem.assemble(m, k, xi)
+    part = dd.Partition(m, 1, 1, 1, 2)
+    B = dd.Schwarz(part, A, kind, k, xi)
+    f = np.random.default_rng(3).standard_normal(m.n_edge) + 0j
+    res = gmres.gmres(A, f, B, restart=10, rtol=1e-10)
+    assert res.iters == 1 and res.converged
+    assert np.linalg.norm(A @ res.x - f) < 1e-10 * np.linalg.norm(f)
+
+
+def test_full_overlap_limits():
+    """Every Omega_l = Omega: RAS and ORAS equal A^-1, AS equals N A^-1."""
+    m = Mesh(4, 4, 2)
+    k, xi = 3.0, 3.0
+    A = fem.assemble(m, k, xi)
+    part = dd.Partition(m, 2, 2, 1, 6)
+    assert all(mk.all() for mk in part.tet_masks)
+    v = np.random.default_rng(4).standard_normal(m.n_edge) + 1j
+    x = spla.spsolve(A.tocsc(), v)
+    for kind, scale in ((dd.RAS, 1), (dd.ORAS, 1), (dd.AS, part.N)):
+        z = dd.Schwarz(part, A, kind, k, xi)(v)
+        assert np.linalg.norm(z - scale * x) < 1e-9 * np.linalg.norm(x)
+
+
+def test_givens():
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        a, b = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        c, s, rho = gmres.givens(a, b)
+        x, y = gmres.apply_givens(c, s, a, b)
+        assert abs(x - rho) < 1e-14 and abs(y) < 1e-14
+        G = np.array([[c, s], [-np.conj(s), c]])
+        assert np.abs(G.conj().T @ G - np.eye(2)).max() < 1e-14
+    c, s, rho = gmres.givens(0.0, 2.0 - 1j)
+    assert c == 0 and rho == 2.0 - 1j
+
+
+@pytest.mark.parametrize("flexible", [False, True])
+def test_gmres_minimal_residual_brute_force(flexible):
+    """x_m minimises ||b - A x|| over x0 + M^-1 K_m(A M^-1, r0) (Sec. 5.2), checked against an
+    explicit Krylov basis and a dense least-squares solve for every m."""
+    rng = np.random.default_rng(6)
+    n = 24
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 6 * np.eye(n)
+    Minv = np.linalg.inv(A + 0.5 * rng.standard_normal((n, n)))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    C = A @ Minv
+    for msteps in range(1, 9):
+        res = gmres.gmres(A, b, lambda v: Minv @ v, restart=30, fixed_iters=msteps,
+                          flexible=flexible)
+        Kb = np.stack([np.linalg.matrix_power(C, j) @ b for j in range(msteps)], axis=1)
+        Q, _ = np.linalg.qr(Kb)
+        c, *_ = np.linalg.lstsq(C @ Q, b, rcond=None)
+        x_ref = Minv @ (Q @ c)
+        assert np.linalg.norm(res.x - x_ref) < 1e-9 * np.linalg.norm(x_ref)
+        assert res.iters == msteps
+
+
+def test_gmres_terminates_within_n():
+    rng = np.random.default_rng(7)
+    n = 12
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    b = rng.standard_normal(n) + 0j
+    res = gmres.gmres(A, b, restart=n, rtol=1e-12, max_iters=n)
+    assert res.converged and res.iters <= n
+
+
+def test_rcm_path_and_grid():
+    # path 0-1-2-3-4: least-key start 0 is already peripheral; CM order 0..4, reversed
+    n = 5
+    P = sp.diags([np.ones(n - 1), np.ones(n), np.ones(n - 1)], [-1, 0, 1]).tocsr()
+    perm = rcm.rcm(*rcm.pattern_graph(P))
+    assert list(perm) == [4, 3, 2, 1, 0]
+    # a 2-D 7x4 grid: starting at a corner the levels are anti-diagonals of width <= 4, and a
+    # Cuthill-McKee order keeps neighbours in adjacent levels, so the bandwidth is <= 2*4 - 1
+    nx, ny = 7, 4
+    idx = np.arange(nx * ny).reshape(ny, nx)
+    rows, cols = [], []
+    for (a, b) in [(idx[:, :-1], idx[:, 1:]), (idx[:-1, :], idx[1:, :])]:
+        rows += list(a.ravel()) + list(b.ravel())
+        cols += list(b.ravel()) + list(a.ravel())
+    G = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(nx * ny, nx * ny))
+    perm = rcm.rcm(*rcm.pattern_graph(G))
+    assert sorted(perm) == list(range(nx * ny))
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    Gp = G[perm][:, perm].tocoo()
+    assert np.abs(Gp.row - Gp.col).max() <= 2 * ny - 1
+    assert perm[-1] in (0, nx - 1, nx * (ny - 1), nx * ny - 1)  # a corner is the root
+    # envelope: first column of each permuted row, brute force
+    first = rcm.envelope(*rcm.pattern_graph(G), perm)
+    D = Gp.toarray() + np.eye(nx * ny)
+    assert np.array_equal(first, np.array([np.nonzero(D[i])[0].min() for i in range(nx * ny)]))
+
+
+def test_rcm_disconnected_components():
+    # two components {0,2} and {1,3,4}; isolated node 5
+    rows = [0, 2, 1, 3, 3, 4]
+    cols = [2, 0, 3, 1, 4, 3]
+    G = sp.csr_matrix((np.ones(6), (rows, cols)), shape=(6, 6))
+    perm = rcm.rcm(*rcm.pattern_graph(G))
+    assert sorted(perm) == list(range(6))
+    # isolated vertex has least key (0, 5): visited first, so it is last after reversal
+    assert perm[-1] == 5
+
+
+def test_paper_ordering_ras_beats_as():
+    """Sec. 6.3: RAS (and ORAS) need fewer iterations than AS at equal overlap (Table tab:rasHras
+    against tab:1 / tab:minOverlap).  The paper's counts are context (other meshes), only the
+    ordering is checked."""
+    with open(os.path.join(GOLDEN, "paper_one_level_counts.json")) as fh:
+        paper = json.load(fh)
+    t6 = paper["tab:rasHras"]["one_level_RAS_minimal_overlap"]
+    t2 = paper["tab:minOverlap"]["alpha_0.8"]
+    assert all(r < a for r, a in zip(t6, t2))
+    m = Mesh(8, 8, 8)
+    k, xi = 4.0, 16.0
+    A = fem.assemble(m, k, xi)
+    f = fem.load_vector(m, fem.gaussian_source((0.5, 0.5, 0.5), (1, 0, 0), 0.1))
+    part = dd.Partition(m, 2, 2, 2, 2)
+    its = {}
+    for kind in (dd.AS, dd.RAS, dd.ORAS):
+        res = gmres.gmres(A, f, dd.Schwarz(part, A, kind, k, xi), restart=50, rtol=1e-6)
+        assert res.converged and res.relres_true <= 1e-6
+        its[kind] = res.iters
+    assert its[dd.RAS] < its[dd.AS] and its[dd.ORAS] <= its[dd.RAS]
