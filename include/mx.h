@@ -1,0 +1,202 @@
+/*
+ * mx.h -- C ABI of the MI355X (gfx950) one-level Schwarz-preconditioned GMRES solver for the
+ * lowest-order Nedelec discretisation of  curl curl E - (k^2 + i xi) E = F  (Bonazzoli, Dolean,
+ * Graham, Spence, Tournier, "Domain decomposition preconditioning for the high-frequency
+ * time-harmonic Maxwell equations with absorption", arXiv:1711.03789).
+ *
+ * Conventions for every entry point:
+ *   - return value: MX_OK (0) or a negative MX_E* code; mx_last_error() gives a message for the
+ *     calling thread.  No C++ exception crosses this boundary.
+ *   - handles (mx_mesh, mx_matrix, mx_partition, mx_precond, mx_ctx) are created and destroyed
+ *     by the library; destroy functions accept NULL.
+ *   - "host" pointers are caller-owned CPU memory, borrowed for the duration of the call;
+ *     "dev" pointers are caller-owned device memory on the context's GPU (for instance the
+ *     data_ptr of a torch tensor), also borrowed.  Device results are written asynchronously on
+ *     the given stream (a hipStream_t passed as void*, NULL = the null stream) unless stated.
+ *   - complex vectors are interleaved (re, im) pairs: complex128 = 2 doubles, complex64 =
+ *     2 floats per entry (the C99 _Complex layout).
+ *   - a context is used by one host thread at a time.
+ */
+#ifndef MX_H
+#define MX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------------- */
+#define MX_OK 0
+#define MX_EINVAL (-1)    /* bad argument (sizes, kinds, NULL where not allowed)              */
+#define MX_ENOMEM (-2)    /* host or device allocation failed                                  */
+#define MX_EDEVICE (-3)   /* HIP runtime error or no usable gfx950 device                      */
+#define MX_EPIVOT (-4)    /* zero or non-finite pivot in a local LDL^T factorisation           */
+#define MX_ENAN (-5)      /* non-finite residual norm in GMRES                                 */
+#define MX_ESTALL (-6)    /* a bounded device-side wait expired (dependency never satisfied)   */
+
+/* ---- enums -------------------------------------------------------------------------------- */
+#define MX_BC_PEC 0        /* E x n = 0 on the boundary (eq:PECcond)                          */
+#define MX_BC_IMPEDANCE 1  /* first-order impedance condition (eq:imp)                        */
+
+#define MX_AS 0    /* additive Schwarz, PEC local minors, no partition of unity (eq:defAS)     */
+#define MX_RAS 1   /* restricted AS: PEC local minors, Boolean partition of unity (Sec. 6.3)   */
+#define MX_ORAS 2  /* ImpRAS: impedance local problems, Boolean partition of unity (Sec. 6.3)  */
+
+#define MX_C128 0  /* complex double factors                                                   */
+#define MX_C64 1   /* complex float factors (FP32 matrix-core updates, FP32 accumulation)      */
+
+typedef struct mx_ctx mx_ctx;
+typedef struct mx_mesh mx_mesh;
+typedef struct mx_matrix mx_matrix;
+typedef struct mx_partition mx_partition;
+typedef struct mx_precond mx_precond;
+
+const char *mx_last_error(void);
+int mx_version(void);
+
+/* ---- context ------------------------------------------------------------------------------ */
+/* Binds HIP device `device` (must be gfx950).  Errors: MX_EDEVICE. */
+int mx_ctx_create(int device, mx_ctx **out);
+void mx_ctx_destroy(mx_ctx *ctx);
+
+/* ---- mesh and edge numbering (host only; Sec. 2.2, Sec. 6.1) ------------------------------ */
+/* Box [0,lx]x[0,ly]x[0,lz] of nx*ny*nz cubes, each split into the 6 Kuhn tetrahedra (path
+ * o -> o+e_s0 -> o+e_s0+e_s1 -> o+(1,1,1) for the axis permutations s in lexicographic order).
+ * vertex (i,j,k) = i + (nx+1)(j + (ny+1)k); tet = 6*cube + permutation rank, cube x-fastest;
+ * edges = all vertex pairs of tetrahedra oriented lo -> hi, sorted by (lo, hi); the DOF of an
+ * edge is the tangential line integral along that orientation (lowest-order duality).
+ * Errors: MX_EINVAL (n < 1, length <= 0, more than 2^31-1 edges), MX_ENOMEM. */
+int mx_mesh_box(int nx, int ny, int nz, double lx, double ly, double lz, mx_mesh **out);
+int mx_mesh_sizes(const mx_mesh *m, int64_t *n_vert, int64_t *n_tet, int64_t *n_edge,
+                  int64_t *n_bface);
+/* Copies into caller buffers of sizes tet_vert[4T], edge_vert[2E], tet_edge[6T],
+ * tet_edge_sign[6T] (+1 when the tetrahedron's local edge a->b runs lo -> hi), bface_vert[3F]
+ * (boundary triangles, vertices ascending).  Any pointer may be NULL to skip that array. */
+int mx_mesh_export(const mx_mesh *m, int32_t *tet_vert, int32_t *edge_vert, int32_t *tet_edge,
+                   int8_t *tet_edge_sign, int32_t *bface_vert);
+void mx_mesh_destroy(mx_mesh *m);
+
+/* ---- Galerkin matrix and load (Sec. 2.2, eq:Helmholtzvf_intro, eq:imp) -------------------- */
+/* A = K - (k^2 + i xi) M - i sign(xi) k M_b (impedance; sign(0) = +1) or, for PEC, K - (k^2 +
+ * i xi) M with identity rows/columns on boundary edges.  Whitney element matrices in closed
+ * form.  The CSR (int64 row pointers, int32 columns sorted ascending, complex128 values, plus a
+ * complex64 copy of the values) is built on the host and kept on the context's device.
+ * Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE. */
+int mx_matrix_assemble(mx_ctx *ctx, const mx_mesh *m, double k, double xi, int bc,
+                       mx_matrix **out);
+int mx_matrix_sizes(const mx_matrix *A, int64_t *n, int64_t *nnz);
+/* Host copies: rowptr[n+1], col[nnz], val[2*nnz] (complex128).  Any may be NULL. */
+int mx_matrix_export(const mx_matrix *A, int64_t *rowptr, int32_t *col, double *val);
+void mx_matrix_destroy(mx_matrix *A);
+/* y = A x on the device; x_dev, y_dev complex128[n], must not overlap. */
+int mx_spmv(mx_ctx *ctx, const mx_matrix *A, const void *x_dev, void *y_dev, void *stream);
+/* Load f_e = int F . w_e for F = pol * exp(-|x - c|^2 / (2 sigma^2)) with the 4-point degree-2
+ * tetrahedron rule; zero on PEC boundary edges.  f_host: complex128[E] (host). */
+int mx_rhs_gaussian(const mx_mesh *m, int bc, const double center[3], const double pol[3],
+                    double sigma, double *f_host);
+
+/* ---- partition with overlap (Sec. 3.1, Sec. 6.1, eq:restriction1, eq:algebPartUnity) ----- */
+/* px*py*pz boxes of cubes cut at cx[0..px] (cx[0] = 0, cx[px] = nx, strictly increasing; NULL =
+ * even cuts floor(i*nx/px)), likewise cy, cz; subdomain l = bx + px(by + py bz).  `layers`
+ * sweeps each add every tetrahedron sharing a vertex with the current set.  AS/RAS local DOFs:
+ * edges all of whose tetrahedra lie in the subdomain; ORAS: all edges of its tetrahedra; both
+ * sorted by global edge id.  owner(e) = least non-overlapping part holding a tetrahedron of e.
+ * Errors: MX_EINVAL, MX_ENOMEM. */
+int mx_partition_box(const mx_mesh *m, int px, int py, int pz, const int32_t *cx,
+                     const int32_t *cy, const int32_t *cz, int layers, mx_partition **out);
+/* n_sub = px*py*pz; total = sum of local sizes for `kind` (MX_AS and MX_RAS share sets). */
+int mx_partition_sizes(const mx_partition *p, int kind, int32_t *n_sub, int64_t *total);
+/* offsets[n_sub+1] (int64), loc2glob[total] (local DOFs of subdomain l at offsets[l]..),
+ * owner[E], n_tet_local[n_sub] (tetrahedra per subdomain).  Any may be NULL. */
+int mx_partition_export(const mx_partition *p, int kind, int64_t *offsets, int32_t *loc2glob,
+                        int32_t *owner, int64_t *n_tet_local);
+void mx_partition_destroy(mx_partition *p);
+
+/* ---- one-level Schwarz preconditioner (eq:defAS, eq:minor, RAS_1, ImpRAS_1 of Sec. 6.3) --- */
+typedef struct {
+  int kind;        /* MX_AS | MX_RAS | MX_ORAS                                                */
+  double xi_prec;  /* absorption of the local problems (ORAS local assembly; AS/RAS use A's)  */
+  int precision;   /* MX_C128 | MX_C64 (local factors and local solves)                       */
+} mx_precond_opts;
+
+/* Host-only view of one local problem, as mx_precond_setup builds it (for inspection and
+ * tests): A^l in local numbering (local DOFs sorted by global id) as CSR rowptr[n+1],
+ * col[nnz], val[2*nnz], and its reverse Cuthill-McKee order perm[n] (new -> old; key (degree,
+ * index), George-Liu pseudo-peripheral start per component, neighbours by increasing key) with
+ * the envelope start first[n] of each permuted row.  Call once with rowptr == NULL to get *n and
+ * *nnz, then with buffers of those sizes (any array may be NULL).  Errors: MX_EINVAL. */
+int mx_local_problem(const mx_mesh *m, const mx_matrix *A, const mx_partition *p,
+                     const mx_precond_opts *opts, int l, int64_t *n, int64_t *nnz, int64_t *rowptr,
+                     int32_t *col, double *val, int32_t *perm, int32_t *first);
+
+typedef struct {
+  int32_t n_sub, tile;          /* subdomains, tile edge of the block-skyline storage         */
+  int64_t n_local_total;        /* sum of local sizes                                          */
+  int64_t max_local, max_blocks;
+  int64_t tiles;                /* stored tiles (tile x tile complex each)                     */
+  int64_t factor_bytes;         /* device bytes of the factor tiles                            */
+  int64_t env_entries;          /* sum over subdomains of the exact lower envelope (diag incl.)*/
+  double env_flops;             /* 8 * sum_i w_i^2 / 2 real flops (envelope LDL^T)             */
+  double tile_flops;            /* real flops of the blocked factorisation as executed         */
+  int64_t apply_bytes;          /* algorithmic bytes of one application (see mx_precond_apply)*/
+  double t_host_setup, t_upload, t_factor; /* seconds of the last mx_precond_setup phases      */
+} mx_precond_info;
+
+/* Builds the local matrices (AS/RAS: minors of A, so the matrix's k, xi and bc are used; ORAS:
+ * impedance local problems assembled with xi_prec, impedance coefficient k on the subdomain
+ * boundary), orders each by reverse Cuthill-McKee, stores it in block-skyline tiles and
+ * factors all subdomains together on the device (pivot-free complex-symmetric LDL^T, which
+ * exists for xi != 0 by the coercivity lemma).  Synchronous.
+ * Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EPIVOT. */
+int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
+                     const mx_precond_opts *opts, mx_precond **out);
+/* z = sum_l R_l^T D_l (A^l)^-1 R_l v (D_l = I for AS); v_dev, z_dev complex128[E], distinct.
+ * Enqueued on `stream`; device-side failures surface at the next synchronising call.
+ * apply_bytes = factors read twice (forward and backward sweep) + local vectors + gathers. */
+int mx_precond_apply(mx_ctx *ctx, mx_precond *P, const void *v_dev, void *z_dev, void *stream);
+int mx_precond_get_info(const mx_precond *P, mx_precond_info *info);
+/* For subdomain l: perm[n_l] (new -> old local index, RCM) and first[n_l] (envelope start of
+ * each permuted row).  Either may be NULL. */
+int mx_precond_export_perm(const mx_precond *P, int l, int32_t *perm, int32_t *first);
+/* Host copy of the factored diagonal D of subdomain l (complex128[n_l], permuted order). */
+int mx_precond_export_diag(const mx_precond *P, int l, double *d);
+/* Checks the device error word of P (set by a failed pivot or an expired wait). */
+int mx_precond_check(mx_precond *P);
+void mx_precond_destroy(mx_precond *P);
+
+/* ---- right-preconditioned restarted (F)GMRES (Sec. 5.2 definition, Sec. 6.1 stopping) ---- */
+typedef struct {
+  int restart;      /* m, Krylov vectors per cycle                                            */
+  int max_iters;    /* cap on total iterations (one iteration = one B^-1 and one A product)   */
+  int flexible;     /* 1: keep z_j = B^-1 v_j and update x += Z y (FGMRES)                    */
+  int fixed_iters;  /* > 0: run exactly this many iterations, ignoring rtol                   */
+  int spmv_c64;     /* 1: Arnoldi products with the complex64 copy of A (FP64 accumulate)     */
+  double rtol;      /* stop when ||b - A x|| <= rtol ||b - A x0||                             */
+} mx_gmres_opts;
+
+typedef struct {
+  int iters, cycles, converged;
+  double relres_true, relres_est;
+  double t_solve;  /* seconds */
+} mx_gmres_stats;
+
+/* Orthogonalisation: classical Gram-Schmidt twice; least squares: complex Givens rotations
+ * (c = |a|/r, s = (a/|a|) conj(b)/r), all in FP64 on the device.  x_dev holds x0 on entry and
+ * the solution on exit.  res_hist (host, may be NULL) receives |g_{j+1}|/||r0|| per iteration
+ * (max_iters + 1 entries, entry 0 = 1).  Non-convergence is not an error (converged = 0).
+ * Synchronous.  Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_ENAN, MX_ESTALL. */
+int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
+             const mx_gmres_opts *opts, mx_gmres_stats *stats, double *res_hist, void *stream);
+
+/* ---- device self-check -------------------------------------------------------------------- */
+/* Runs the matrix-core tile product used by the factorisation on random 64x64 complex tiles in
+ * both precisions and compares with a plain device loop; *err64, *err32 receive the max
+ * relative errors.  Synchronous. */
+int mx_selftest(mx_ctx *ctx, double *err64, double *err32);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MX_H */

@@ -1,0 +1,336 @@
+// extern "C" entry points of libmx: argument checks, error capture, handle lifetimes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "objects.hpp"
+
+namespace mx {
+static thread_local std::string g_last_error;
+void set_error(int code, const std::string &msg) {
+  (void)code;
+  g_last_error = msg;
+}
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+}  // namespace mx
+
+using mx::Error;
+
+#define MX_GUARD(...)                                               \
+  try {                                                             \
+    __VA_ARGS__;                                                    \
+    return MX_OK;                                                   \
+  } catch (const Error &e) {                                        \
+    mx::set_error(e.code, e.msg);                                   \
+    return e.code;                                                  \
+  } catch (const std::bad_alloc &) {                                \
+    mx::set_error(MX_ENOMEM, "host allocation failed");             \
+    return MX_ENOMEM;                                               \
+  } catch (const std::exception &e) {                               \
+    mx::set_error(MX_EINVAL, e.what());                             \
+    return MX_EINVAL;                                               \
+  }
+
+#define MX_REQUIRE(cond, msg) \
+  if (!(cond)) mx::fail(MX_EINVAL, msg)
+
+static void bind_device(int dev) { MX_HIP(hipSetDevice(dev)); }
+
+extern "C" {
+
+const char *mx_last_error(void) { return mx::g_last_error.c_str(); }
+int mx_version(void) { return 100; }
+
+int mx_ctx_create(int device, mx_ctx **out) {
+  MX_GUARD({
+    MX_REQUIRE(out, "out is NULL");
+    int n = 0;
+    MX_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) mx::fail(MX_EDEVICE, "no such HIP device");
+    hipDeviceProp_t prop;
+    MX_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      mx::fail(MX_EDEVICE, std::string("libmx is built for gfx950, device is ") + prop.gcnArchName);
+    bind_device(device);
+    auto c = std::make_unique<mx_ctx>();
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    MX_HIP(hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault));
+    *out = c.release();
+  });
+}
+
+void mx_ctx_destroy(mx_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+int mx_mesh_box(int nx, int ny, int nz, double lx, double ly, double lz, mx_mesh **out) {
+  MX_GUARD({
+    MX_REQUIRE(out, "out is NULL");
+    MX_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1, "mesh: need at least one cube per axis");
+    MX_REQUIRE(lx > 0 && ly > 0 && lz > 0, "mesh: lengths must be positive");
+    MX_REQUIRE((double)(nx + 1) * (ny + 1) * (nz + 1) < 2.0e9, "mesh: too many vertices");
+    auto m = std::make_unique<mx_mesh>();
+    mx::build_mesh(m->m, nx, ny, nz, lx, ly, lz);
+    *out = m.release();
+  });
+}
+
+int mx_mesh_sizes(const mx_mesh *m, int64_t *nv, int64_t *nt, int64_t *ne, int64_t *nbf) {
+  MX_GUARD({
+    MX_REQUIRE(m, "mesh is NULL");
+    if (nv) *nv = m->m.nv;
+    if (nt) *nt = m->m.nt;
+    if (ne) *ne = m->m.ne;
+    if (nbf) *nbf = (int64_t)m->m.bface_vert.size() / 3;
+  });
+}
+
+int mx_mesh_export(const mx_mesh *m, int32_t *tet_vert, int32_t *edge_vert, int32_t *tet_edge,
+                   int8_t *tet_edge_sign, int32_t *bface_vert) {
+  MX_GUARD({
+    MX_REQUIRE(m, "mesh is NULL");
+    const auto &M = m->m;
+    if (tet_vert) std::memcpy(tet_vert, M.tet_vert.data(), M.tet_vert.size() * 4);
+    if (edge_vert) std::memcpy(edge_vert, M.edge_vert.data(), M.edge_vert.size() * 4);
+    if (tet_edge) std::memcpy(tet_edge, M.tet_edge.data(), M.tet_edge.size() * 4);
+    if (tet_edge_sign) std::memcpy(tet_edge_sign, M.tet_sign.data(), M.tet_sign.size());
+    if (bface_vert) std::memcpy(bface_vert, M.bface_vert.data(), M.bface_vert.size() * 4);
+  });
+}
+
+void mx_mesh_destroy(mx_mesh *m) { delete m; }
+
+int mx_matrix_assemble(mx_ctx *ctx, const mx_mesh *m, double k, double xi, int bc, mx_matrix **out) {
+  MX_GUARD({
+    MX_REQUIRE(m && out, "NULL argument");
+    MX_REQUIRE(bc == MX_BC_PEC || bc == MX_BC_IMPEDANCE, "unknown boundary condition");
+    MX_REQUIRE(std::isfinite(k) && std::isfinite(xi) && k > 0, "need finite k > 0 and finite xi");
+    auto A = std::make_unique<mx_matrix>();
+    A->k = k, A->xi = xi, A->bc = bc;
+    mx::assemble_global(m->m, k, xi, bc, A->h);
+    if (ctx) {
+      bind_device(ctx->device);
+      A->device = ctx->device;
+      mx::matrix_upload(A.get());
+    }
+    *out = A.release();
+  });
+}
+
+int mx_matrix_sizes(const mx_matrix *A, int64_t *n, int64_t *nnz) {
+  MX_GUARD({
+    MX_REQUIRE(A, "matrix is NULL");
+    if (n) *n = A->h.n;
+    if (nnz) *nnz = A->h.nnz();
+  });
+}
+
+int mx_matrix_export(const mx_matrix *A, int64_t *rowptr, int32_t *col, double *val) {
+  MX_GUARD({
+    MX_REQUIRE(A, "matrix is NULL");
+    if (rowptr) std::memcpy(rowptr, A->h.rowptr.data(), A->h.rowptr.size() * 8);
+    if (col) std::memcpy(col, A->h.col.data(), A->h.col.size() * 4);
+    if (val) std::memcpy(val, A->h.val.data(), A->h.val.size() * 8);
+  });
+}
+
+void mx_matrix_destroy(mx_matrix *A) { delete A; }
+
+int mx_spmv(mx_ctx *ctx, const mx_matrix *A, const void *x_dev, void *y_dev, void *stream) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && A && x_dev && y_dev, "NULL argument");
+    MX_REQUIRE(A->rowptr.p, "matrix has no device copy (assembled without a context)");
+    MX_REQUIRE(x_dev != y_dev, "x and y must not overlap");
+    bind_device(ctx->device);
+    mx::spmv_run(A, x_dev, y_dev, false, (hipStream_t)stream);
+  });
+}
+
+int mx_rhs_gaussian(const mx_mesh *m, int bc, const double center[3], const double pol[3],
+                    double sigma, double *f_host) {
+  MX_GUARD({
+    MX_REQUIRE(m && center && pol && f_host, "NULL argument");
+    MX_REQUIRE(sigma > 0, "sigma must be positive");
+    mx::rhs_gaussian(m->m, bc, center, pol, sigma, f_host);
+  });
+}
+
+int mx_partition_box(const mx_mesh *m, int px, int py, int pz, const int32_t *cx,
+                     const int32_t *cy, const int32_t *cz, int layers, mx_partition **out) {
+  MX_GUARD({
+    MX_REQUIRE(m && out, "NULL argument");
+    auto p = std::make_unique<mx_partition>();
+    mx::build_partition(m->m, px, py, pz, cx, cy, cz, layers, p->p);
+    *out = p.release();
+  });
+}
+
+int mx_partition_sizes(const mx_partition *p, int kind, int32_t *n_sub, int64_t *total) {
+  MX_GUARD({
+    MX_REQUIRE(p, "partition is NULL");
+    MX_REQUIRE(kind >= MX_AS && kind <= MX_ORAS, "unknown kind");
+    if (n_sub) *n_sub = p->p.nsub;
+    if (total) {
+      int64_t t = 0;
+      for (const auto &s : p->p.set(kind)) t += (int64_t)s.size();
+      *total = t;
+    }
+  });
+}
+
+int mx_partition_export(const mx_partition *p, int kind, int64_t *offsets, int32_t *loc2glob,
+                        int32_t *owner, int64_t *n_tet_local) {
+  MX_GUARD({
+    MX_REQUIRE(p, "partition is NULL");
+    MX_REQUIRE(kind >= MX_AS && kind <= MX_ORAS, "unknown kind");
+    const auto &sets = p->p.set(kind);
+    int64_t o = 0;
+    for (int l = 0; l < p->p.nsub; ++l) {
+      if (offsets) offsets[l] = o;
+      if (loc2glob) std::memcpy(loc2glob + o, sets[l].data(), sets[l].size() * 4);
+      if (n_tet_local) n_tet_local[l] = (int64_t)p->p.tets[l].size();
+      o += (int64_t)sets[l].size();
+    }
+    if (offsets) offsets[p->p.nsub] = o;
+    if (owner) std::memcpy(owner, p->p.owner.data(), p->p.owner.size() * 4);
+  });
+}
+
+void mx_partition_destroy(mx_partition *p) { delete p; }
+
+int mx_local_problem(const mx_mesh *m, const mx_matrix *A, const mx_partition *p,
+                     const mx_precond_opts *opts, int l, int64_t *n, int64_t *nnz, int64_t *rowptr,
+                     int32_t *col, double *val, int32_t *perm, int32_t *first) {
+  MX_GUARD({
+    MX_REQUIRE(m && A && p && opts && n && nnz, "NULL argument");
+    MX_REQUIRE(l >= 0 && l < p->p.nsub, "subdomain out of range");
+    MX_REQUIRE(opts->kind >= MX_AS && opts->kind <= MX_ORAS, "unknown kind");
+    MX_REQUIRE(A->h.n == m->m.ne, "matrix and mesh disagree");
+    const auto &M = m->m;
+    const auto &sets = p->p.set(opts->kind);
+    mx::LocalCSR a;
+    std::vector<int32_t> g2l(M.ne, -1);
+    if (opts->kind == MX_ORAS) {
+      mx::KuhnElements ke;
+      mx::kuhn_elements(M.lx / M.nx, M.ly / M.ny, M.lz / M.nz, ke);
+      std::vector<int32_t> tstamp(M.nt, -1);
+      mx::local_impedance(M, ke, A->k, opts->xi_prec, A->bc, p->p.tets[l], sets[l], a, g2l,
+                          tstamp, l);
+    } else {
+      mx::local_minor(M, A->h, A->bc, sets[l], a, g2l);
+    }
+    *n = a.n;
+    *nnz = (int64_t)a.col.size();
+    if (rowptr) std::memcpy(rowptr, a.rowptr.data(), a.rowptr.size() * 8);
+    if (col) std::memcpy(col, a.col.data(), a.col.size() * 4);
+    if (val) std::memcpy(val, a.val.data(), a.val.size() * 8);
+    if (perm || first) {
+      mx::Skyline s;
+      mx::build_skyline(a, s);
+      if (perm) std::memcpy(perm, s.perm.data(), s.perm.size() * 4);
+      if (first) std::memcpy(first, s.first.data(), s.first.size() * 4);
+    }
+  });
+}
+
+int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
+                     const mx_precond_opts *opts, mx_precond **out) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && A && m && p && opts && out, "NULL argument");
+    bind_device(ctx->device);
+    auto P = std::make_unique<mx_precond>();
+    mx::precond_setup(ctx, A, m, p, opts, P.get());
+    *out = P.release();
+  });
+}
+
+int mx_precond_apply(mx_ctx *ctx, mx_precond *P, const void *v_dev, void *z_dev, void *stream) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && P && v_dev && z_dev, "NULL argument");
+    MX_REQUIRE(v_dev != z_dev, "v and z must be distinct");
+    bind_device(ctx->device);
+    mx::precond_apply(P, v_dev, z_dev, (hipStream_t)stream);
+  });
+}
+
+int mx_precond_get_info(const mx_precond *P, mx_precond_info *info) {
+  MX_GUARD({
+    MX_REQUIRE(P && info, "NULL argument");
+    *info = P->info;
+  });
+}
+
+int mx_precond_export_perm(const mx_precond *P, int l, int32_t *perm, int32_t *first) {
+  MX_GUARD({
+    MX_REQUIRE(P, "NULL argument");
+    MX_REQUIRE(l >= 0 && l < P->nsub, "subdomain out of range");
+    const auto &s = P->sky[l];
+    if (perm) std::memcpy(perm, s.perm.data(), s.perm.size() * 4);
+    if (first) std::memcpy(first, s.first.data(), s.first.size() * 4);
+  });
+}
+
+int mx_precond_export_diag(const mx_precond *P, int l, double *d) {
+  MX_GUARD({
+    MX_REQUIRE(P && d, "NULL argument");
+    MX_REQUIRE(l >= 0 && l < P->nsub, "subdomain out of range");
+    bind_device(P->device);
+    const auto &s = P->sky[l];
+    const size_t esz = P->prec == MX_C128 ? 16 : 8;
+    std::vector<char> tile((mx::TILE * mx::TILE) * esz);
+    for (int64_t I = 0; I < s.nb; ++I) {
+      int64_t t = P->sub_tile_base[l] + s.brow_off[I] + (I - s.bfirst[I]);
+      MX_HIP(hipMemcpy(tile.data(), P->pool.as<char>() + t * (mx::TILE * mx::TILE) * esz, tile.size(),
+                       hipMemcpyDeviceToHost));
+      for (int i = 0; i < mx::TILE && I * mx::TILE + i < s.n; ++i) {
+        int64_t q = (int64_t)i * mx::TILE + i, o = I * mx::TILE + i;
+        if (P->prec == MX_C128) {
+          std::memcpy(d + 2 * o, tile.data() + q * 16, 16);
+        } else {
+          float f[2];
+          std::memcpy(f, tile.data() + q * 8, 8);
+          d[2 * o] = f[0], d[2 * o + 1] = f[1];
+        }
+      }
+    }
+  });
+}
+
+int mx_precond_check(mx_precond *P) {
+  MX_GUARD({
+    MX_REQUIRE(P, "NULL argument");
+    bind_device(P->device);
+    MX_HIP(hipDeviceSynchronize());
+    mx::precond_check(P);
+  });
+}
+
+void mx_precond_destroy(mx_precond *P) { delete P; }
+
+int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
+             const mx_gmres_opts *opts, mx_gmres_stats *stats, double *res_hist, void *stream) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && A && b_dev && x_dev && opts && stats, "NULL argument");
+    MX_REQUIRE(b_dev != x_dev, "b and x must be distinct");
+    MX_REQUIRE(A->rowptr.p, "matrix has no device copy");
+    MX_REQUIRE(!P || P->E == A->h.n, "preconditioner and matrix sizes differ");
+    bind_device(ctx->device);
+    mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream);
+  });
+}
+
+int mx_selftest(mx_ctx *ctx, double *err64, double *err32) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && err64 && err32, "NULL argument");
+    bind_device(ctx->device);
+    mx::selftest_run(err64, err32);
+  });
+}
+
+}  // extern "C"

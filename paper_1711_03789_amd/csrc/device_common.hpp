@@ -1,0 +1,162 @@
+// Device-side helpers shared by the gfx950 kernels: complex arithmetic, matrix-core tile
+// products, wavefront reductions and bounded flag waits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mx {
+
+constexpr int kTile = 64;          // block-skyline tile edge
+constexpr int kTileElems = kTile * kTile;
+constexpr long kSpinLimit = 1L << 21;  // bounded waits: ~1-2 s before reporting MX_ESTALL
+
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a += b * c
+template <typename T>
+__device__ __forceinline__ void cfma(cx<T> &a, cx<T> b, cx<T> c) {
+  a.re += b.re * c.re - b.im * c.im;
+  a.im += b.re * c.im + b.im * c.re;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
+  T d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cinv(cx<T> b) {
+  T d = b.re * b.re + b.im * b.im;
+  return {b.re / d, -b.im / d};
+}
+template <typename To, typename Ti>
+__device__ __forceinline__ cx<To> ccast(cx<Ti> a) { return {(To)a.re, (To)a.im}; }
+
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_xor_c(cx<T> v, int m) {
+  return {__shfl_xor(v.re, m), __shfl_xor(v.im, m)};
+}
+
+// ---- matrix cores --------------------------------------------------------------------------------
+// 16x16x4 products: lane l supplies A[l%16][l/16] and B[l/16][l%16]; the 4 accumulator values of
+// lane l are D[4*(l/16) + r][l%16], r = 0..3 (checked at run time by mx_selftest).
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Complex tile product on one wavefront: a 32x32 quadrant (rows r0.., cols c0..) of
+//     P[i][j] = sum_k A[i][k] * s[k] * B[j][k]        (A, B row-major 64x64 tiles)
+// with complex products split into four real matrix-core products.  Each lane loads four
+// consecutive k of a row at once; the k order inside a 16-wide slab is permuted identically for
+// A and B, which leaves the sum unchanged.
+//   SCALE:   multiply B's column k by s[k] (the LDL^T diagonal D)
+//   UNITDIAG: B is a unit-lower tile stored with something else on its diagonal: read 1 there
+//             and 0 above it.
+template <typename T, bool SCALE, bool UNITDIAG>
+__device__ __forceinline__ void tile_nt_quadrant(const cx<T> *__restrict__ A,
+                                                 const cx<T> *__restrict__ B,
+                                                 const cx<T> *__restrict__ s, int r0, int c0,
+                                                 typename Mfma<T>::acc_t acc[2][2][2]) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[a][b][c] = acc_t{0, 0, 0, 0};
+  for (int kk = 0; kk < kTile; kk += 16) {
+    const int kb = kk + 4 * lk;  // this lane's 4 consecutive k
+    cx<T> av[2][4], bv[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const cx<T> *p = A + (r0 + rb * 16 + li) * kTile + kb;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) av[rb][e] = p[e];
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int j = c0 + cb * 16 + li;
+      const cx<T> *p = B + j * kTile + kb;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        cx<T> v = p[e];
+        if (UNITDIAG) {
+          int k = kb + e;
+          if (k == j) v = {(T)1, (T)0};
+          else if (k > j) v = {(T)0, (T)0};
+        }
+        if (SCALE) v = cmul(v, s[kb + e]);
+        bv[cb][e] = v;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          acc[rb][cb][0] = Mfma<T>::op(av[rb][e].re, bv[cb][e].re, acc[rb][cb][0]);
+          acc[rb][cb][0] = Mfma<T>::op(-av[rb][e].im, bv[cb][e].im, acc[rb][cb][0]);
+          acc[rb][cb][1] = Mfma<T>::op(av[rb][e].re, bv[cb][e].im, acc[rb][cb][1]);
+          acc[rb][cb][1] = Mfma<T>::op(av[rb][e].im, bv[cb][e].re, acc[rb][cb][1]);
+        }
+  }
+}
+
+// Row/column of accumulator element (rb, cb, r) of this lane inside the 64x64 tile.
+__device__ __forceinline__ int acc_row(int r0, int rb, int r) {
+  return r0 + rb * 16 + 4 * ((threadIdx.x & 63) >> 4) + r;
+}
+__device__ __forceinline__ int acc_col(int c0, int cb) { return c0 + cb * 16 + (threadIdx.x & 15); }
+
+// ---- bounded waits on agent-scope flags ----------------------------------------------------------
+__device__ __forceinline__ int load_flag(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_flag(int *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Spins until *flag == want; returns false (and raises *abort) after kSpinLimit polls or when
+// another workgroup has raised *abort.
+__device__ inline bool wait_flag(const int *flag, int want, int *abort) {
+  if (load_flag(flag) == want) return true;
+  for (long it = 0; it < kSpinLimit; ++it) {
+    __builtin_amdgcn_s_sleep(1);
+    if (load_flag(flag) == want) return true;
+    if ((it & 63) == 0 && load_flag(abort)) return false;
+  }
+  store_flag(abort, 1);
+  return false;
+}
+
+}  // namespace mx

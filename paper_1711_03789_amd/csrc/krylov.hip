@@ -1,0 +1,443 @@
+// Complex CSR SpMV and right-preconditioned restarted (F)GMRES on gfx950, FP64 throughout.
+//
+// GMRES is the minimal-residual Krylov iteration of Sec. 5.2 with the Euclidean inner product,
+// right preconditioned and stopped on the relative residual as in Sec. 6.1.  Orthogonalisation:
+// classical Gram-Schmidt applied twice with deterministic blocked reductions (fixed row blocks,
+// fixed reduction order); least squares: complex Givens rotations updated on the device; the host
+// reads one small status record per iteration to decide whether to stop.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <random>
+
+#include "device_common.hpp"
+#include "objects.hpp"
+
+namespace mx {
+
+// ---- SpMV: 16 lanes per row ------------------------------------------------------------------------
+template <typename TV>
+__global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ col,
+                                              const cx<TV> *__restrict__ val,
+                                              const cx<double> *__restrict__ x,
+                                              cx<double> *__restrict__ y) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int sub = threadIdx.x & 15;
+  cx<double> s = {0, 0};
+  if (row < n) {
+    const int64_t q1 = rowptr[row + 1];
+    for (int64_t q = rowptr[row] + sub; q < q1; q += 16) cfma(s, ccast<double>(val[q]), x[col[q]]);
+  }
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) s = cadd(s, shfl_xor_c(s, o));
+  if (row < n && sub == 0) y[row] = s;
+}
+
+// ---- vector kernels ----------------------------------------------------------------------------------
+__global__ void k_sub(int64_t n, const cx<double> *b, const cx<double> *y, cx<double> *r) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = csub(b[i], y[i]);
+}
+__global__ void k_add(int64_t n, cx<double> *x, const cx<double> *z) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = cadd(x[i], z[i]);
+}
+// dst = src / *nrm  (zeros when *nrm == 0)
+__global__ void k_scale(int64_t n, const cx<double> *src, const double *nrm, cx<double> *dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = *nrm;
+  double s = d > 0 ? 1.0 / d : 0.0;
+  dst[i] = {src[i].re * s, src[i].im * s};
+}
+// w -= sum_q V_q h_q
+__global__ void k_update(int64_t n, const cx<double> *__restrict__ V, int64_t ldv, int nv,
+                         const cx<double> *__restrict__ h, cx<double> *__restrict__ w) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cx<double> acc = w[i];
+  for (int q = 0; q < nv; ++q) {
+    cx<double> v = V[q * ldv + i], hq = h[q];
+    acc.re -= v.re * hq.re - v.im * hq.im;
+    acc.im -= v.re * hq.im + v.im * hq.re;
+  }
+  w[i] = acc;
+}
+// out = sum_q V_q y_q
+__global__ void k_combine(int64_t n, const cx<double> *__restrict__ V, int64_t ldv, int nv,
+                          const cx<double> *__restrict__ y, cx<double> *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cx<double> acc = {0, 0};
+  for (int q = 0; q < nv; ++q) cfma(acc, V[q * ldv + i], y[q]);
+  out[i] = acc;
+}
+
+// Block sum of 4 complex values over 256 threads; result valid in thread 0.
+__device__ inline void block_sum4(cx<double> v[4], cx<double> (*red)[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v[c] = cadd(v[c], shfl_xor_c(v[c], o));
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[w][c] = v[c];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = cadd(cadd(red[0][c], red[1][c]), cadd(red[2][c], red[3][c]));
+}
+
+// partial[q * G + b] = sum_{i in block b} conj(V_q[i]) w[i], q < nv (mode 0), or
+// partial[b] = sum |w_i|^2 (mode 1, nv ignored).  Block b covers a fixed row range.
+__global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const cx<double> *__restrict__ V,
+                                                     int64_t ldv, int nv,
+                                                     const cx<double> *__restrict__ w,
+                                                     cx<double> *__restrict__ partial, int mode) {
+  __shared__ cx<double> red[4][4];
+  const int G = gridDim.x, b = blockIdx.x;
+  const int64_t chunk = (n + G - 1) / G;
+  const int64_t i0 = b * chunk, i1 = std::min(n, i0 + chunk);
+  if (mode == 1) {
+    cx<double> v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) v[0].re += w[i].re * w[i].re + w[i].im * w[i].im;
+    block_sum4(v, red);
+    if (threadIdx.x == 0) partial[b] = v[0];
+    return;
+  }
+  for (int q0 = 0; q0 < nv; q0 += 4) {
+    cx<double> v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+      const cx<double> wi = w[i];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (q0 + c < nv) {
+          const cx<double> a = V[(q0 + c) * ldv + i];
+          v[c].re += a.re * wi.re + a.im * wi.im;
+          v[c].im += a.re * wi.im - a.im * wi.re;
+        }
+    }
+    block_sum4(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (q0 + c < nv) partial[(q0 + c) * G + b] = v[c];
+  }
+}
+
+// One block per q: fixed-order tree over the G partials.  mode 0: cur = sum = total;
+// mode 1: cur = total, sum += total; mode 2: cur[q] = sqrt(total.re) (norm).
+__global__ __launch_bounds__(256) void k_reduce(int G, const cx<double> *__restrict__ partial,
+                                                cx<double> *cur, cx<double> *sum, double *nrm,
+                                                int mode) {
+  __shared__ cx<double> s[256];
+  const int q = blockIdx.x;
+  cx<double> acc = {0, 0};
+  for (int b = threadIdx.x; b < G; b += 256) acc = cadd(acc, partial[(int64_t)q * G + b]);
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] = cadd(s[threadIdx.x], s[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cx<double> t = s[0];
+    if (mode == 0) cur[q] = t, sum[q] = t;
+    else if (mode == 1) cur[q] = t, sum[q] = cadd(sum[q], t);
+    else *nrm = sqrt(t.re);
+  }
+}
+
+struct GmresStatus {
+  double est;     // |g_{j+1}|
+  double hn;      // h_{j+1,j}
+  double beta;    // last norm computed by k_reduce mode 2 (copied)
+  int abort, pivot;
+};
+
+__device__ inline void givens(cx<double> a, cx<double> b, double &c, cx<double> &s, cx<double> &rho) {
+  const double aa = hypot(a.re, a.im);
+  if (aa == 0.0) {
+    c = 0.0, s = {1.0, 0.0}, rho = b;
+    return;
+  }
+  const double r = sqrt(aa * aa + b.re * b.re + b.im * b.im);
+  const cx<double> ph = {a.re / aa, a.im / aa};
+  c = aa / r;
+  s = cmul(ph, cx<double>{b.re / r, -b.im / r});
+  rho = {ph.re * r, ph.im * r};
+}
+// (x, y) -> (c x + s y, -conj(s) x + c y)
+__device__ inline void rot(double c, cx<double> s, cx<double> &x, cx<double> &y) {
+  const cx<double> nx = cadd(cx<double>{c * x.re, c * x.im}, cmul(s, y));
+  const cx<double> ny = csub(cx<double>{c * y.re, c * y.im}, cmul(cx<double>{s.re, -s.im}, x));
+  x = nx, y = ny;
+}
+
+// Column j of the Hessenberg matrix: h (j+1 entries) and hn = ||w||; previous rotations, new
+// rotation, right-hand side g; status for the host.
+__global__ void k_givens(int j, int ldh, const cx<double> *h, const double *hn_ptr, cx<double> *H,
+                         double *cs, cx<double> *sn, cx<double> *g, GmresStatus *st,
+                         const int *pctrl) {
+  if (threadIdx.x != 0) return;
+  cx<double> *col = H + (int64_t)j * ldh;
+  for (int i = 0; i <= j; ++i) col[i] = h[i];
+  const double hn = *hn_ptr;
+  col[j + 1] = {hn, 0.0};
+  for (int i = 0; i < j; ++i) rot(cs[i], sn[i], col[i], col[i + 1]);
+  double c;
+  cx<double> s, rho;
+  givens(col[j], col[j + 1], c, s, rho);
+  cs[j] = c, sn[j] = s;
+  col[j] = rho;
+  col[j + 1] = {0.0, 0.0};
+  rot(c, s, g[j], g[j + 1]);
+  st->est = hypot(g[j + 1].re, g[j + 1].im);
+  st->hn = hn;
+  st->abort = pctrl ? pctrl[2] : 0;
+  st->pivot = pctrl ? pctrl[3] : 0;
+}
+
+__global__ void k_init_g(int m, const double *beta, cx<double> *g, GmresStatus *st) {
+  for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = {0.0, 0.0};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    g[0] = {*beta, 0.0};
+    st->beta = *beta;
+  }
+}
+
+__global__ void k_copy_beta(const double *beta, GmresStatus *st) {
+  if (threadIdx.x == 0) st->beta = *beta;
+}
+
+// Back substitution H(0:k,0:k) y = g(0:k).
+__global__ void k_trisolve(int k, int ldh, const cx<double> *H, const cx<double> *g, cx<double> *y) {
+  if (threadIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    cx<double> acc = g[i];
+    for (int q = i + 1; q < k; ++q) acc = csub(acc, cmul(H[(int64_t)q * ldh + i], y[q]));
+    y[i] = cdiv(acc, H[(int64_t)i * ldh + i]);
+  }
+}
+
+// ---- host driver ---------------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+void spmv_run(const mx_matrix *A, const void *x, void *y, bool c64, hipStream_t st) {
+  const int64_t n = A->h.n;
+  if (n == 0) return;
+  if (c64)
+    k_spmv<float><<<nblk(n * 16), 256, 0, st>>>(n, A->rowptr.as<int64_t>(), A->col.as<int32_t>(),
+                                                 A->val32.as<cx<float>>(), (const cx<double> *)x,
+                                                 (cx<double> *)y);
+  else
+    k_spmv<double><<<nblk(n * 16), 256, 0, st>>>(n, A->rowptr.as<int64_t>(), A->col.as<int32_t>(),
+                                                  A->val.as<cx<double>>(), (const cx<double> *)x,
+                                                  (cx<double> *)y);
+  MX_HIP(hipGetLastError());
+}
+
+void matrix_upload(mx_matrix *A) {
+  A->rowptr.upload(A->h.rowptr);
+  A->col.upload(A->h.col);
+  A->val.upload(A->h.val);
+  std::vector<float> v32(A->h.val.begin(), A->h.val.end());
+  A->val32.upload(v32);
+}
+
+void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
+               const mx_gmres_opts *o, mx_gmres_stats *stats, double *hist, hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = A->h.n;
+  const int m = o->restart;
+  if (m < 1 || o->max_iters < 0 || o->fixed_iters < 0 || !(o->rtol >= 0)) fail(MX_EINVAL, "bad GMRES options");
+  const bool flex = o->flexible != 0, c64 = o->spmv_c64 != 0;
+  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 1023) / 1024));
+  // workspace layout (bytes, 256-aligned)
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t vb = al((size_t)n * 16);
+  size_t off = 0;
+  const size_t oV = off; off += vb * (m + 1);
+  const size_t oZ = off; off += flex ? vb * m : 0;
+  const size_t oW = off; off += vb;
+  const size_t oR = off; off += vb;
+  const size_t oT = off; off += vb;
+  const size_t oU = off; off += vb;
+  const size_t oP = off; off += al((size_t)G * (m + 1) * 16);
+  const size_t oH = off; off += al((size_t)(m + 1) * m * 16);
+  const size_t oG = off; off += al((size_t)(m + 1) * 16);
+  const size_t oC = off; off += al((size_t)m * 8);
+  const size_t oS = off; off += al((size_t)m * 16);
+  const size_t oh1 = off; off += al((size_t)(m + 1) * 16);
+  const size_t oh2 = off; off += al((size_t)(m + 1) * 16);
+  const size_t oY = off; off += al((size_t)(m + 1) * 16);
+  const size_t oN = off; off += 256;
+  const size_t oST = off; off += 256;
+  char *ws = (char *)ctx->krylov.get(off);
+  cx<double> *V = (cx<double> *)(ws + oV), *Z = flex ? (cx<double> *)(ws + oZ) : nullptr;
+  cx<double> *w = (cx<double> *)(ws + oW), *r = (cx<double> *)(ws + oR);
+  cx<double> *tmp = (cx<double> *)(ws + oT), *u = (cx<double> *)(ws + oU);
+  cx<double> *part = (cx<double> *)(ws + oP), *H = (cx<double> *)(ws + oH);
+  cx<double> *g = (cx<double> *)(ws + oG), *sn = (cx<double> *)(ws + oS);
+  double *cs = (double *)(ws + oC);
+  cx<double> *h1 = (cx<double> *)(ws + oh1), *h2 = (cx<double> *)(ws + oh2), *y = (cx<double> *)(ws + oY);
+  double *nrm = (double *)(ws + oN);
+  GmresStatus *dst = (GmresStatus *)(ws + oST);
+  GmresStatus *hst = (GmresStatus *)ctx->pinned;
+  const int64_t ldv = (int64_t)(vb / 16);
+  const int *pctrl = P ? P->d_ctrl.as<int>() : nullptr;
+  const cx<double> *b = (const cx<double> *)b_dev;
+  cx<double> *x = (cx<double> *)x_dev;
+
+  auto norm_of = [&](const cx<double> *vec) {
+    k_dot_partial<<<G, 256, 0, st>>>(n, nullptr, 0, 0, vec, part, 1);
+    k_reduce<<<1, 256, 0, st>>>(G, part, nullptr, nullptr, nrm, 2);
+  };
+  auto sync_status = [&]() {
+    MX_HIP(hipMemcpyAsync(hst, dst, sizeof(GmresStatus), hipMemcpyDeviceToHost, st));
+    MX_HIP(hipStreamSynchronize(st));
+    if (hst->pivot) fail(MX_EPIVOT, "zero or non-finite pivot in a local factorisation");
+    if (hst->abort) fail(MX_ESTALL, "a device-side wait in the block sweeps expired");
+  };
+  auto residual = [&]() {  // r = b - A x, beta -> status
+    spmv_run(A, x, tmp, false, st);
+    k_sub<<<nblk(n), 256, 0, st>>>(n, b, tmp, r);
+    norm_of(r);
+    k_copy_beta<<<1, 64, 0, st>>>(nrm, dst);
+    hst->pivot = hst->abort = 0;
+    MX_HIP(hipMemcpyAsync(hst, dst, sizeof(GmresStatus), hipMemcpyDeviceToHost, st));
+    MX_HIP(hipStreamSynchronize(st));
+    return hst->beta;
+  };
+  auto apply_prec = [&](const cx<double> *in, cx<double> *out) {
+    if (P) precond_apply(P, in, out, st);
+    else MX_HIP(hipMemcpyAsync(out, in, n * 16, hipMemcpyDeviceToDevice, st));
+  };
+  MX_HIP(hipMemsetAsync(dst, 0, sizeof(GmresStatus), st));
+  const double beta0 = residual();
+  int total = 0, cycles = 0;
+  const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
+  if (hist) hist[0] = 1.0;
+  double est = 1.0, beta = beta0;
+  bool converged = false;
+  if (!std::isfinite(beta0)) fail(MX_ENAN, "non-finite initial residual");
+  if (beta0 == 0.0) {
+    converged = true;
+  } else {
+    while (true) {
+      if (o->fixed_iters == 0 && beta <= o->rtol * beta0) {
+        converged = true;
+        break;
+      }
+      if (total >= limit) {
+        converged = o->fixed_iters > 0;
+        break;
+      }
+      ++cycles;
+      k_scale<<<nblk(n), 256, 0, st>>>(n, r, nrm, V);
+      k_init_g<<<1, 64, 0, st>>>(m, nrm, g, dst);
+      int jend = 0;
+      for (int j = 0; j < m; ++j) {
+        cx<double> *z = flex ? Z + (int64_t)j * ldv : tmp;
+        apply_prec(V + (int64_t)j * ldv, z);
+        spmv_run(A, z, w, c64, st);
+        const int nv = j + 1;
+        k_dot_partial<<<G, 256, 0, st>>>(n, V, ldv, nv, w, part, 0);
+        k_reduce<<<nv, 256, 0, st>>>(G, part, h2, h1, nullptr, 0);
+        k_update<<<nblk(n), 256, 0, st>>>(n, V, ldv, nv, h2, w);
+        k_dot_partial<<<G, 256, 0, st>>>(n, V, ldv, nv, w, part, 0);
+        k_reduce<<<nv, 256, 0, st>>>(G, part, h2, h1, nullptr, 1);
+        k_update<<<nblk(n), 256, 0, st>>>(n, V, ldv, nv, h2, w);
+        norm_of(w);
+        k_givens<<<1, 64, 0, st>>>(j, m + 1, h1, nrm, H, cs, sn, g, dst, pctrl);
+        k_scale<<<nblk(n), 256, 0, st>>>(n, w, nrm, V + (int64_t)(j + 1) * ldv);
+        MX_HIP(hipGetLastError());
+        sync_status();
+        ++total;
+        jend = j + 1;
+        est = hst->est / beta0;
+        if (hist) hist[total] = est;
+        if (!std::isfinite(hst->est) || !std::isfinite(hst->hn)) fail(MX_ENAN, "non-finite Arnoldi value");
+        if (o->fixed_iters == 0 && hst->est <= o->rtol * beta0) break;
+        if (total >= limit || hst->hn == 0.0) break;
+      }
+      k_trisolve<<<1, 64, 0, st>>>(jend, m + 1, H, g, y);
+      if (flex) {
+        k_combine<<<nblk(n), 256, 0, st>>>(n, Z, ldv, jend, y, u);
+        k_add<<<nblk(n), 256, 0, st>>>(n, x, u);
+      } else {
+        k_combine<<<nblk(n), 256, 0, st>>>(n, V, ldv, jend, y, u);
+        apply_prec(u, tmp);
+        k_add<<<nblk(n), 256, 0, st>>>(n, x, tmp);
+      }
+      beta = residual();
+      if (!std::isfinite(beta)) fail(MX_ENAN, "non-finite residual");
+      if (P) precond_check(P);
+    }
+  }
+  stats->iters = total;
+  stats->cycles = cycles;
+  stats->converged = converged ? 1 : 0;
+  stats->relres_true = beta0 > 0 ? beta / beta0 : 0.0;
+  stats->relres_est = est;
+  stats->t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---- self-test of the matrix-core tile product ----------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_selftest_mfma(const cx<T> *A, const cx<T> *B, const cx<T> *s,
+                                                       cx<T> *out) {
+  const int w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  typename Mfma<T>::acc_t acc[2][2][2];
+  tile_nt_quadrant<T, true, false>(A, B, s, r0, c0, acc);
+  for (int rb = 0; rb < 2; ++rb)
+    for (int cb = 0; cb < 2; ++cb)
+      for (int q = 0; q < 4; ++q)
+        out[acc_row(r0, rb, q) * kTile + acc_col(c0, cb)] = {acc[rb][cb][0][q], acc[rb][cb][1][q]};
+}
+template <typename T>
+__global__ void k_selftest_ref(const cx<T> *A, const cx<T> *B, const cx<T> *s, cx<T> *out) {
+  const int i = blockIdx.x, j = threadIdx.x;
+  cx<double> acc = {0, 0};
+  for (int k = 0; k < kTile; ++k)
+    cfma(acc, ccast<double>(A[i * kTile + k]), cmul(ccast<double>(s[k]), ccast<double>(B[j * kTile + k])));
+  out[i * kTile + j] = ccast<T>(acc);
+}
+
+template <typename T>
+static double selftest_t() {
+  std::mt19937_64 rng(12345);
+  std::normal_distribution<double> nd;
+  std::vector<T> h(2 * (2 * kTileElems + kTile));
+  for (auto &x : h) x = (T)nd(rng);
+  DevBuf d_in, d_a, d_b;
+  d_in.upload(h);
+  d_a.alloc(kTileElems * 2 * sizeof(T));
+  d_b.alloc(kTileElems * 2 * sizeof(T));
+  const cx<T> *A = d_in.as<cx<T>>(), *B = A + kTileElems, *s = B + kTileElems;
+  k_selftest_mfma<T><<<1, 256>>>(A, B, s, d_a.as<cx<T>>());
+  k_selftest_ref<T><<<kTile, kTile>>>(A, B, s, d_b.as<cx<T>>());
+  MX_HIP(hipGetLastError());
+  MX_HIP(hipDeviceSynchronize());
+  std::vector<T> ra(2 * kTileElems), rb(2 * kTileElems);
+  MX_HIP(hipMemcpy(ra.data(), d_a.p, ra.size() * sizeof(T), hipMemcpyDeviceToHost));
+  MX_HIP(hipMemcpy(rb.data(), d_b.p, rb.size() * sizeof(T), hipMemcpyDeviceToHost));
+  double err = 0, mag = 0;
+  for (size_t i = 0; i < ra.size(); ++i) {
+    err = std::max(err, (double)std::fabs((double)ra[i] - (double)rb[i]));
+    mag = std::max(mag, (double)std::fabs((double)rb[i]));
+  }
+  return err / mag;
+}
+
+void selftest_run(double *e64, double *e32) {
+  *e64 = selftest_t<double>();
+  *e32 = selftest_t<float>();
+}
+
+}  // namespace mx

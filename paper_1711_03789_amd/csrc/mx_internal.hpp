@@ -1,0 +1,149 @@
+// Internal types shared by the host topology code and the device code of libmx.
+#pragma once
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+#include <thread>
+#include <algorithm>
+
+#include "../../include/mx.h"
+
+namespace mx {
+
+// ---- errors ------------------------------------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+void set_error(int code, const std::string &msg);
+[[noreturn]] void fail(int code, const std::string &msg);
+
+// Runs f(begin, end) over [0, n) split across up to 16 host threads.
+template <class F>
+void parallel_for(int64_t n, F &&f, int64_t grain = 4096) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < grain || nt == 1) {
+    f((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    int64_t a = (int64_t)t * chunk, b = std::min(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([&f, a, b] { f(a, b); });
+  }
+  for (auto &x : th) x.join();
+}
+
+// ---- structured Kuhn mesh ------------------------------------------------------------------------
+struct Mesh {
+  int nx = 0, ny = 0, nz = 0;
+  double lx = 1, ly = 1, lz = 1;
+  int64_t nv = 0, nt = 0, ne = 0;
+  std::vector<int32_t> tet_vert;     // [nt][4]
+  std::vector<int32_t> tet_edge;     // [nt][6]
+  std::vector<int8_t> tet_sign;      // [nt][6]
+  std::vector<int32_t> edge_vert;    // [ne][2]
+  std::vector<int64_t> et_ptr;       // edge -> incident tetrahedra (CSR, tet ids ascending)
+  std::vector<int32_t> et_tet;
+  std::vector<int8_t> et_loc;        // local edge index of the edge in that tet
+  std::vector<int32_t> bface_vert;   // [nbf][3] boundary triangles, vertices ascending
+  std::vector<int32_t> bface_edge;   // [nbf][3] edges (0,1) (0,2) (1,2) of the triangle
+  std::vector<int64_t> eb_ptr;       // edge -> incident boundary triangles (CSR)
+  std::vector<int32_t> eb_face;
+  std::vector<uint8_t> edge_on_boundary;
+  std::vector<int64_t> edge_first_;  // first edge id with lo = v (closed-form numbering)
+
+  int32_t vid(int i, int j, int k) const { return i + (nx + 1) * (j + (ny + 1) * k); }
+  void vijk(int64_t v, int &i, int &j, int &k) const {
+    i = (int)(v % (nx + 1));
+    int64_t r = v / (nx + 1);
+    j = (int)(r % (ny + 1));
+    k = (int)(r / (ny + 1));
+  }
+  void xyz(int64_t v, double out[3]) const {
+    int i, j, k;
+    vijk(v, i, j, k);
+    out[0] = i * (lx / nx);
+    out[1] = j * (ly / ny);
+    out[2] = k * (lz / nz);
+  }
+  int32_t edge_id(int32_t lo, int32_t hi) const;  // -1 if not an edge
+};
+void build_mesh(Mesh &m, int nx, int ny, int nz, double lx, double ly, double lz);
+
+// Whitney element matrices of the 6 Kuhn tetrahedra of a cube with spacing (hx, hy, hz):
+// K[p][a][b], M[p][a][b] in local edge orientation; they are translation invariant.
+struct KuhnElements {
+  double K[6][6][6];
+  double M[6][6][6];
+};
+void kuhn_elements(double hx, double hy, double hz, KuhnElements &out);
+// Tangential Whitney mass of a triangle with vertices x0, x1, x2 (local edges (0,1) (0,2) (1,2)).
+void triangle_mass(const double x0[3], const double x1[3], const double x2[3], double Mb[3][3]);
+void tet_element(const double X[4][3], double K[6][6], double M[6][6], double *vol);
+
+// ---- complex CSR ---------------------------------------------------------------------------------
+struct HostCSR {
+  int64_t n = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;  // interleaved complex, 2 * nnz
+  int64_t nnz() const { return (int64_t)col.size(); }
+};
+void assemble_global(const Mesh &m, double k, double xi, int bc, HostCSR &A);
+void rhs_gaussian(const Mesh &m, int bc, const double c[3], const double pol[3], double sigma,
+                  double *f);
+
+// ---- partition -----------------------------------------------------------------------------------
+struct Partition {
+  int px = 1, py = 1, pz = 1, layers = 0, nsub = 1;
+  std::vector<int32_t> cuts[3];
+  std::vector<int32_t> part0;                       // per tet
+  std::vector<std::vector<int32_t>> tets;           // tets of each subdomain, ascending
+  std::vector<std::vector<int32_t>> as_set, oras_set;  // local DOFs, ascending global ids
+  std::vector<int32_t> owner;                       // per edge
+  const std::vector<std::vector<int32_t>> &set(int kind) const {
+    return kind == MX_ORAS ? oras_set : as_set;
+  }
+};
+void build_partition(const Mesh &m, int px, int py, int pz, const int32_t *cx, const int32_t *cy,
+                     const int32_t *cz, int layers, Partition &p);
+
+// ---- local problems, ordering, block skyline -------------------------------------------------------
+struct LocalCSR {  // a local matrix in local (sorted global id) numbering
+  int64_t n = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;  // interleaved complex
+};
+// AS/RAS minor of the global matrix (PEC-constrained rows/cols reduced to their diagonal).
+void local_minor(const Mesh &m, const HostCSR &A, int bc, const std::vector<int32_t> &set,
+                 LocalCSR &out, std::vector<int32_t> &g2l_scratch);
+// ORAS local impedance problem on the tetrahedra `tets` (local DOFs `set`).
+void local_impedance(const Mesh &m, const KuhnElements &ke, double k, double xi, int bc,
+                     const std::vector<int32_t> &tets, const std::vector<int32_t> &set,
+                     LocalCSR &out, std::vector<int32_t> &g2l_scratch,
+                     std::vector<int32_t> &tet_stamp, int32_t stamp);
+// Reverse Cuthill-McKee of the pattern of `a` (perm[new] = old).
+void rcm_order(const LocalCSR &a, std::vector<int32_t> &perm);
+
+constexpr int TILE = 64;
+
+struct Skyline {
+  int64_t n = 0, nb = 0;              // rows, block rows
+  std::vector<int32_t> perm, iperm;   // new -> old, old -> new
+  std::vector<int32_t> first;         // envelope start per permuted row
+  std::vector<int32_t> bfirst;        // first stored tile column per block row (monotone)
+  std::vector<int32_t> blast;         // last block row storing a tile in block column K
+  std::vector<int64_t> brow_off;      // tile offset (in tiles) of block row I, relative
+  int64_t tiles = 0;
+  int64_t env = 0;                    // exact lower envelope entries (diagonal included)
+  double env_flops = 0, tile_flops = 0;
+};
+void build_skyline(const LocalCSR &a, Skyline &s);
+
+}  // namespace mx

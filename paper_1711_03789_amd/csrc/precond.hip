@@ -1,0 +1,734 @@
+// One-level Schwarz preconditioner on gfx950: batched block-skyline LDL^T factorisation of all
+// local problems (matrix-core trailing updates) and the application
+//     z = sum_l R_l^T D_l (A^l)^-1 R_l v            (eq:defAS without the coarse term; RAS_1 and
+//                                                     ImpRAS_1 of Sec. 6.3 with Boolean D_l)
+// as restrict-gather -> persistent forward/backward block sweeps -> owner gather (or sum).
+//
+// Storage: each local matrix is reordered by reverse Cuthill-McKee and stored as 64x64 tiles of
+// its lower triangle, block row I holding tiles J = bfirst(I)..I (bfirst monotone, so the fill of
+// a pivot-free factorisation stays inside).  After factorisation a tile (I,J), J < I, holds L_IJ;
+// the diagonal tile holds inv(L_II) strictly below its diagonal and D_I on it.
+//
+// The local matrices are complex symmetric (A = A^T, Sec. 2.2), so A^l = L D L^T with no
+// conjugation; no pivoting is needed for xi != 0 because every principal submatrix of
+// Theta A^l has positive definite imaginary part (coercivity lemma of Sec. 2.3).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "device_common.hpp"
+#include "objects.hpp"
+
+namespace mx {
+
+// ---- tile addressing ---------------------------------------------------------------------------
+struct SubView {
+  const int32_t *nb, *brow_base;
+  const int64_t *tile_base, *vec_base;
+  const int64_t *brow_off;
+  const int32_t *bfirst, *blast;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> *tile_ptr(cx<T> *pool, const SubView &v, int l, int I, int J) {
+  const int bb = v.brow_base[l];
+  const int64_t t = v.tile_base[l] + v.brow_off[bb + I] + (J - v.bfirst[bb + I]);
+  return pool + t * (int64_t)kTileElems;
+}
+
+__device__ __forceinline__ int find_sub(const int32_t *pref, int nsub, int g) {
+  int lo = 0, hi = nsub;  // pref[lo] <= g < pref[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (pref[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ---- setup kernels ------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_scatter(int64_t n, const int64_t *__restrict__ off,
+                          const cx<double> *__restrict__ val, cx<T> *__restrict__ pool) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pool[off[i]] = ccast<T>(val[i]);
+}
+
+__global__ void k_zero(int64_t n16, uint4 *__restrict__ p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+// ---- factorisation: diagonal tile ----------------------------------------------------------------
+// One workgroup per subdomain: S = A_KK (lower triangle) is factored in LDS as L D L^T, then the
+// unit lower L is inverted in place; written back as inv(L) below the diagonal, D on it, 0 above.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fac_diag(int K, SubView v, cx<T> *pool, int *ctrl) {
+  const int l = blockIdx.x;
+  if (K >= v.nb[l]) return;
+  __shared__ cx<T> S[kTile][kTile];
+  __shared__ cx<T> tmp[kTile];
+  cx<T> *tile = tile_ptr(pool, v, l, K, K);
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kTileElems; q += 256) {
+    int i = q / kTile, j = q % kTile;
+    S[i][j] = j <= i ? tile[q] : cx<T>{0, 0};
+  }
+  bool bad = false;
+  for (int j = 0; j < kTile; ++j) {
+    __syncthreads();
+    cx<T> d = S[j][j];
+    T mag = d.re * d.re + d.im * d.im;
+    if (!(mag > (T)0) || !isfinite(mag)) {
+      bad = true;
+      d = {(T)1, (T)0};
+    }
+    cx<T> dinv = cinv(d);
+    // trailing update S[i][m] -= S[i][j] S[m][j] / d,  j < m <= i
+    const int i = tid & 63;
+    if (i > j) {
+      cx<T> lij = cmul(S[i][j], dinv);
+      for (int m = j + 1 + (tid >> 6); m <= i; m += 4) {
+        cx<T> t = cmul(lij, S[m][j]);
+        S[i][m] = csub(S[i][m], t);
+      }
+    }
+    __syncthreads();
+    if (tid < kTile && tid > j) S[tid][j] = cmul(S[tid][j], dinv);
+  }
+  if (bad && tid == 0) atomicOr(&ctrl[3], 1);
+  // in-place inverse of the unit lower triangle, columns right to left:
+  // X[i][j] = -(L[i][j] + sum_{j<m<i} X[i][m] L[m][j])
+  for (int j = kTile - 2; j >= 0; --j) {
+    __syncthreads();
+    if (tid < kTile && tid > j) {
+      const int i = tid;
+      cx<T> acc = S[i][j];
+      for (int m = j + 1; m < i; ++m) cfma(acc, S[i][m], S[m][j]);
+      tmp[i] = {-acc.re, -acc.im};
+    }
+    __syncthreads();
+    if (tid < kTile && tid > j) S[tid][j] = tmp[tid];
+  }
+  __syncthreads();
+  for (int q = tid; q < kTileElems; q += 256) {
+    int i = q / kTile, j = q % kTile;
+    tile[q] = j <= i ? S[i][j] : cx<T>{0, 0};
+  }
+}
+
+// ---- factorisation: panel L_IK = A_IK inv(L_KK)^T D_K^-1 -------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_fac_panel(int K, SubView v, const int32_t *pref, int nsub,
+                                                   cx<T> *pool) {
+  const int g = blockIdx.x;
+  const int l = find_sub(pref, nsub, g);
+  const int I = K + 1 + (g - pref[l]);
+  cx<T> *A = tile_ptr(pool, v, l, I, K);
+  const cx<T> *X = tile_ptr(pool, v, l, K, K);
+  const int w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  typename Mfma<T>::acc_t acc[2][2][2];
+  tile_nt_quadrant<T, false, true>(A, X, nullptr, r0, c0, acc);
+  __syncthreads();  // every wave has read all of A before any writes
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int col = acc_col(c0, cb);
+    const cx<T> dinv = cinv(X[col * kTile + col]);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = acc_row(r0, rb, r);
+        A[row * kTile + col] = cmul(cx<T>{acc[rb][cb][0][r], acc[rb][cb][1][r]}, dinv);
+      }
+  }
+}
+
+// ---- factorisation: trailing update A_IJ -= L_IK D_K L_JK^T ---------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_fac_update(int K, SubView v, const int32_t *pref, int nsub,
+                                                    cx<T> *pool) {
+  const int g = blockIdx.x;
+  const int l = find_sub(pref, nsub, g);
+  int t = g - pref[l];
+  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  const int c = t - r * (r + 1) / 2;
+  const int I = K + 1 + r, J = K + 1 + c;
+  __shared__ cx<T> dk[kTile];
+  const cx<T> *Xk = tile_ptr(pool, v, l, K, K);
+  if (threadIdx.x < kTile) dk[threadIdx.x] = Xk[threadIdx.x * kTile + threadIdx.x];
+  __syncthreads();
+  cx<T> *C = tile_ptr(pool, v, l, I, J);
+  const cx<T> *A = tile_ptr(pool, v, l, I, K);
+  const cx<T> *B = tile_ptr(pool, v, l, J, K);
+  const int w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  typename Mfma<T>::acc_t acc[2][2][2];
+  tile_nt_quadrant<T, true, false>(A, B, dk, r0, c0, acc);
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = acc_row(r0, rb, q), col = acc_col(c0, cb);
+        cx<T> cur = C[row * kTile + col];
+        C[row * kTile + col] = {cur.re - acc[rb][cb][0][q], cur.im - acc[rb][cb][1][q]};
+      }
+}
+
+// ---- application: restrict, persistent sweeps, prolong ---------------------------------------------
+template <typename T>
+__global__ void k_restrict(int64_t n, const int32_t *__restrict__ glob,
+                           const cx<double> *__restrict__ vin, cx<T> *__restrict__ r, int *ctrl) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) {
+    ctrl[0] += 1;  // epoch of this application
+    ctrl[1] = 0;   // ticket counter
+  }
+  if (p < n) {
+    int32_t g = glob[p];
+    r[p] = g >= 0 ? ccast<T>(vin[g]) : cx<T>{0, 0};
+  }
+}
+
+template <typename T>
+__global__ void k_prolong_owner(int64_t E, const int64_t *__restrict__ src,
+                                const cx<T> *__restrict__ z, cx<double> *__restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) out[e] = ccast<double>(z[src[e]]);
+}
+
+template <typename T>
+__global__ void k_prolong_sum(int64_t E, const int64_t *__restrict__ ptr,
+                              const int64_t *__restrict__ idx, const cx<T> *__restrict__ z,
+                              cx<double> *__restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  cx<double> s = {0, 0};
+  for (int64_t q = ptr[e]; q < ptr[e + 1]; ++q) s = cadd(s, ccast<double>(z[idx[q]]));
+  out[e] = s;
+}
+
+// Reduce 16 per-lane complex partial sums (one per row r of this wave's 16 rows) across the 64
+// lanes; afterwards lanes with (lane & 3) == 0 hold the total of row (lane >> 2).
+template <typename T>
+__device__ __forceinline__ cx<T> butterfly16(cx<T> acc[16]) {
+  const int lane = threadIdx.x & 63;
+  int cnt = 16;
+#pragma unroll
+  for (int o = 32; o >= 4; o >>= 1) {
+    const int half = cnt >> 1;
+    const bool upper = (lane & o) != 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < half) {
+        cx<T> send = upper ? acc[q] : acc[q + half];
+        cx<T> keep = upper ? acc[q + half] : acc[q];
+        acc[q] = cadd(keep, shfl_xor_c(send, o));
+      }
+    }
+    cnt = half;
+  }
+  acc[0] = cadd(acc[0], shfl_xor_c(acc[0], 2));
+  acc[0] = cadd(acc[0], shfl_xor_c(acc[0], 1));
+  return acc[0];
+}
+
+// Persistent forward/backward block sweeps over all subdomains.  Work items (subdomain, block
+// row, direction) are handed out by an atomic ticket in a fixed order in which every item comes
+// after all items it depends on (forward rows of a subdomain ascending, then backward rows
+// descending), so a workgroup only ever waits for tickets already taken by running workgroups.
+// Completion is published per block row with an epoch-tagged flag; waits are bounded.
+//   forward  : y_I = inv(L_II) (r_I - sum_{J<I} L_IJ y_J)
+//   backward : z_J = inv(L_JJ)^T (y_J / D_J - sum_{I>J} L_IJ^T z_I)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restrict__ pool,
+                                                const int32_t *__restrict__ sched_sub,
+                                                const int32_t *__restrict__ sched_blk, int n_items,
+                                                int n_fwd, const cx<T> *__restrict__ rvec,
+                                                cx<T> *yvec, cx<T> *zvec, int *flags_f,
+                                                int *flags_b, int *ctrl) {
+  __shared__ int s_item;
+  __shared__ int s_ok;
+  __shared__ cx<T> s_vec[kTile];
+  __shared__ cx<T> s_red[4][kTile];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int epoch = ctrl[0];
+  int *abort = &ctrl[2];
+  while (true) {
+    if (tid == 0) {
+      int t = __hip_atomic_fetch_add(&ctrl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = load_flag(abort) ? n_items : t;
+    }
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int l = sched_sub[item], B = sched_blk[item];
+    const int bb = v.brow_base[l];
+    const int64_t vb = v.vec_base[l];
+    if (item < n_fwd) {
+      // ---------------- forward block row B ----------------
+      const int f = v.bfirst[bb + B];
+      const cx<T> *row = pool + (v.tile_base[l] + v.brow_off[bb + B]) * (int64_t)kTileElems;
+      cx<T> acc[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = {0, 0};
+      int J = f;
+      while (J < B) {
+        // find the ready prefix [J, Jend) without waiting; wait only if it is empty
+        if (tid == 0) {
+          int Jend = J;
+          while (Jend < B && load_flag(&flags_f[bb + Jend]) == epoch) ++Jend;
+          if (Jend == J) {
+            s_ok = wait_flag(&flags_f[bb + J], epoch, abort) ? J + 1 : -1;
+          } else {
+            s_ok = Jend;
+          }
+        }
+        __syncthreads();
+        const int Jend = s_ok;
+        __syncthreads();
+        if (Jend < 0) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        for (; J < Jend; ++J) {
+          const cx<T> y = yvec[vb + (int64_t)J * kTile + lane];
+          const cx<T> *tp = row + (int64_t)(J - f) * kTileElems + (w * 16) * kTile + lane;
+          cx<T> a[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) a[r] = tp[r * kTile];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) cfma(acc[r], a[r], y);
+        }
+      }
+      cx<T> s = butterfly16(acc);
+      if ((lane & 3) == 0) {
+        const int i = w * 16 + (lane >> 2);
+        s_vec[i] = csub(rvec[vb + (int64_t)B * kTile + i], s);
+      }
+      __syncthreads();
+      // y_B = inv(L_BB) t  (unit lower: y_i = t_i + sum_{m<i} X[i][m] t_m)
+      const cx<T> *X = row + (int64_t)(B - f) * kTileElems;
+      const cx<T> tm = s_vec[lane];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = w * 16 + r;
+        acc[r] = lane < i ? cmul(X[i * kTile + lane], tm) : cx<T>{0, 0};
+      }
+      s = butterfly16(acc);
+      if ((lane & 3) == 0) {
+        const int i = w * 16 + (lane >> 2);
+        yvec[vb + (int64_t)B * kTile + i] = cadd(s_vec[i], s);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (tid == 0) store_flag(&flags_f[bb + B], epoch);
+    } else {
+      // ---------------- backward block column B ----------------
+      const int last = v.blast[bb + B];
+      // z_B depends on y_B (forward) and z_I, I in (B, last]
+      if (tid == 0) s_ok = wait_flag(&flags_f[bb + B], epoch, abort);
+      __syncthreads();
+      const int ready = s_ok;
+      __syncthreads();
+      if (!ready) return;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      cx<T> acc = {0, 0};
+      int I = B + 1;
+      while (I <= last) {
+        if (tid == 0) {
+          int Iend = I;
+          while (Iend <= last && load_flag(&flags_b[bb + Iend]) == epoch) ++Iend;
+          if (Iend == I) {
+            s_ok = wait_flag(&flags_b[bb + I], epoch, abort) ? I + 1 : -1;
+          } else {
+            s_ok = Iend;
+          }
+        }
+        __syncthreads();
+        const int Iend = s_ok;
+        __syncthreads();
+        if (Iend < 0) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        for (; I < Iend; ++I) {
+          const cx<T> *tp = tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + (w * 16) * kTile + lane;
+          const cx<T> *zi = zvec + vb + (int64_t)I * kTile + w * 16;
+          cx<T> a[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) a[r] = tp[r * kTile];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) cfma(acc, a[r], zi[r]);
+        }
+      }
+      s_red[w][lane] = acc;
+      __syncthreads();
+      const cx<T> *X = tile_ptr(const_cast<cx<T> *>(pool), v, l, B, B);
+      if (w == 0) {
+        cx<T> s = cadd(cadd(s_red[0][lane], s_red[1][lane]), cadd(s_red[2][lane], s_red[3][lane]));
+        const cx<T> d = X[lane * kTile + lane];
+        s_vec[lane] = csub(cdiv(yvec[vb + (int64_t)B * kTile + lane], d), s);
+      }
+      __syncthreads();
+      // z_B = inv(L_BB)^T s:  z_j = s_j + sum_{i>j} X[i][j] s_i
+      acc = {0, 0};
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = w * 16 + r;
+        if (i > lane) cfma(acc, X[i * kTile + lane], s_vec[i]);
+      }
+      s_red[w][lane] = acc;
+      __syncthreads();
+      if (w == 0) {
+        cx<T> s = cadd(cadd(s_red[0][lane], s_red[1][lane]), cadd(s_red[2][lane], s_red[3][lane]));
+        zvec[vb + (int64_t)B * kTile + lane] = cadd(s_vec[lane], s);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (tid == 0) store_flag(&flags_b[bb + B], epoch);
+    }
+  }
+}
+
+// ---- host side ------------------------------------------------------------------------------------
+static SubView view_of(const mx_precond *P) {
+  SubView v;
+  v.nb = P->d_sub_nb.as<int32_t>();
+  v.brow_base = P->d_sub_brow_base.as<int32_t>();
+  v.tile_base = P->d_sub_tile_base.as<int64_t>();
+  v.vec_base = P->d_sub_vec_base.as<int64_t>();
+  v.brow_off = P->d_brow_off.as<int64_t>();
+  v.bfirst = P->d_bfirst.as<int32_t>();
+  v.blast = P->d_blast.as<int32_t>();
+  return v;
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+static void factor_all(mx_precond *P, hipStream_t st) {
+  SubView v = view_of(P);
+  cx<T> *pool = P->pool.as<cx<T>>();
+  const int N = P->nsub;
+  for (int K = 0; K < P->max_nb; ++K) {
+    k_fac_diag<T><<<N, 256, 0, st>>>(K, v, pool, P->d_ctrl.as<int>());
+    const int32_t *pp = P->d_panel_pref.as<int32_t>() + (int64_t)K * (N + 1);
+    const int32_t *up = P->d_update_pref.as<int32_t>() + (int64_t)K * (N + 1);
+    int np = P->panel_pref[(int64_t)K * (N + 1) + N];
+    int nu = P->update_pref[(int64_t)K * (N + 1) + N];
+    if (np > 0) k_fac_panel<T><<<np, 256, 0, st>>>(K, v, pp, N, pool);
+    if (nu > 0) k_fac_update<T><<<nu, 256, 0, st>>>(K, v, up, N, pool);
+  }
+  MX_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
+  SubView v = view_of(P);
+  const int64_t n = P->vec_total;
+  k_restrict<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, P->d_glob.as<int32_t>(),
+                                                             (const cx<double> *)vin,
+                                                             P->d_r.as<cx<T>>(), P->d_ctrl.as<int>());
+  int *flags = P->d_flags.as<int>();
+  k_sweeps<T><<<P->trsv_grid, 256, 0, st>>>(
+      v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(),
+      P->n_items, P->n_items / 2, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), flags,
+      flags + P->blocks_total, P->d_ctrl.as<int>());
+  const int64_t E = P->E;
+  if (P->kind == MX_AS)
+    k_prolong_sum<T><<<(unsigned)((E + 255) / 256), 256, 0, st>>>(
+        E, P->d_sum_ptr.as<int64_t>(), P->d_sum_idx.as<int64_t>(), P->d_z.as<cx<T>>(),
+        (cx<double> *)zout);
+  else
+    k_prolong_owner<T><<<(unsigned)((E + 255) / 256), 256, 0, st>>>(
+        E, P->d_src.as<int64_t>(), P->d_z.as<cx<T>>(), (cx<double> *)zout);
+  MX_HIP(hipGetLastError());
+}
+
+void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
+  if (P->prec == MX_C128) apply_t<double>(P, vin, zout, st);
+  else apply_t<float>(P, vin, zout, st);
+}
+
+int precond_check(mx_precond *P) {
+  int h[4];
+  MX_HIP(hipMemcpy(h, P->d_ctrl.p, sizeof(h), hipMemcpyDeviceToHost));
+  if (h[3]) fail(MX_EPIVOT, "zero or non-finite pivot in a local factorisation");
+  if (h[2]) fail(MX_ESTALL, "a device-side wait in the block sweeps expired");
+  return MX_OK;
+}
+
+void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_partition *ph,
+                   const mx_precond_opts *opts, mx_precond *P) {
+  const Mesh &m = mh->m;
+  const Partition &part = ph->p;
+  if (A->h.n != m.ne) fail(MX_EINVAL, "matrix and mesh disagree");
+  if (opts->kind < MX_AS || opts->kind > MX_ORAS) fail(MX_EINVAL, "unknown preconditioner kind");
+  if (opts->precision != MX_C128 && opts->precision != MX_C64) fail(MX_EINVAL, "unknown precision");
+  const double t0 = now_s();
+  P->kind = opts->kind;
+  P->prec = opts->precision;
+  P->nsub = part.nsub;
+  P->E = m.ne;
+  P->device = ctx->device;
+  const int N = part.nsub;
+  const auto &sets = part.set(opts->kind);
+  // local matrices and their orderings
+  std::vector<LocalCSR> loc(N);
+  P->sky.assign(N, Skyline());
+  KuhnElements ke;
+  kuhn_elements(m.lx / m.nx, m.ly / m.ny, m.lz / m.nz, ke);
+  parallel_for(N, [&](int64_t a, int64_t b) {
+    std::vector<int32_t> g2l(m.ne, -1), tstamp;
+    if (opts->kind == MX_ORAS) tstamp.assign(m.nt, -1);
+    for (int64_t l = a; l < b; ++l) {
+      if (opts->kind == MX_ORAS)
+        local_impedance(m, ke, A->k, opts->xi_prec, A->bc, part.tets[l], sets[l], loc[l], g2l,
+                        tstamp, (int32_t)l);
+      else
+        local_minor(m, A->h, A->bc, sets[l], loc[l], g2l);
+      build_skyline(loc[l], P->sky[l]);
+    }
+  }, 1);
+  // layout
+  P->sub_nb.resize(N);
+  P->sub_brow_base.resize(N);
+  P->sub_tile_base.resize(N);
+  P->sub_vec_base.resize(N + 1);
+  int64_t tiles = 0, blocks = 0, vec = 0;
+  P->max_nb = 0;
+  for (int l = 0; l < N; ++l) {
+    const Skyline &s = P->sky[l];
+    P->sub_nb[l] = (int32_t)s.nb;
+    P->sub_brow_base[l] = (int32_t)blocks;
+    P->sub_tile_base[l] = tiles;
+    P->sub_vec_base[l] = vec;
+    tiles += s.tiles;
+    blocks += s.nb;
+    vec += s.nb * kTile;
+    P->max_nb = std::max<int>(P->max_nb, (int)s.nb);
+  }
+  P->sub_vec_base[N] = vec;
+  if (blocks > INT32_MAX) fail(MX_EINVAL, "too many block rows");
+  P->tiles_total = tiles;
+  P->blocks_total = blocks;
+  P->vec_total = vec;
+  std::vector<int64_t> brow_off(blocks);
+  std::vector<int32_t> bfirst(blocks), blast(blocks);
+  for (int l = 0; l < N; ++l) {
+    const Skyline &s = P->sky[l];
+    for (int64_t I = 0; I < s.nb; ++I) {
+      brow_off[P->sub_brow_base[l] + I] = s.brow_off[I];
+      bfirst[P->sub_brow_base[l] + I] = s.bfirst[I];
+      blast[P->sub_brow_base[l] + I] = s.blast[I];
+    }
+  }
+  // scatter list: lower-triangle entries of each permuted local matrix + unit diagonal padding
+  std::vector<int64_t> cnt(N + 1, 0);
+  for (int l = 0; l < N; ++l) {
+    const LocalCSR &a = loc[l];
+    const Skyline &s = P->sky[l];
+    int64_t c = 0;
+    for (int64_t r = 0; r < a.n; ++r)
+      for (int64_t q = a.rowptr[r]; q < a.rowptr[r + 1]; ++q) c += s.iperm[a.col[q]] <= s.iperm[r];
+    c += s.nb * kTile - s.n;
+    cnt[l + 1] = cnt[l] + c;
+  }
+  std::vector<int64_t> off(cnt[N]);
+  std::vector<double> val(2 * cnt[N]);
+  parallel_for(N, [&](int64_t a0, int64_t a1) {
+    for (int64_t l = a0; l < a1; ++l) {
+      const LocalCSR &a = loc[l];
+      const Skyline &s = P->sky[l];
+      int64_t w = cnt[l];
+      const int64_t tb = P->sub_tile_base[l];
+      auto pos = [&](int64_t i, int64_t j) {
+        int64_t I = i / kTile, J = j / kTile;
+        return (tb + s.brow_off[I] + (J - s.bfirst[I])) * (int64_t)kTileElems + (i % kTile) * kTile +
+               (j % kTile);
+      };
+      for (int64_t r = 0; r < a.n; ++r)
+        for (int64_t q = a.rowptr[r]; q < a.rowptr[r + 1]; ++q) {
+          int64_t i = s.iperm[r], j = s.iperm[a.col[q]];
+          if (j > i) continue;
+          off[w] = pos(i, j);
+          val[2 * w] = a.val[2 * q];
+          val[2 * w + 1] = a.val[2 * q + 1];
+          ++w;
+        }
+      for (int64_t i = s.n; i < s.nb * kTile; ++i) {
+        off[w] = pos(i, i);
+        val[2 * w] = 1.0;
+        val[2 * w + 1] = 0.0;
+        ++w;
+      }
+    }
+  }, 1);
+  // restriction / prolongation maps
+  std::vector<int32_t> glob(vec, -1);
+  for (int l = 0; l < N; ++l) {
+    const Skyline &s = P->sky[l];
+    for (int64_t i = 0; i < s.n; ++i) glob[P->sub_vec_base[l] + i] = sets[l][s.perm[i]];
+  }
+  std::vector<int64_t> src, sum_ptr, sum_idx;
+  if (opts->kind == MX_AS) {
+    sum_ptr.assign(m.ne + 1, 0);
+    for (int l = 0; l < N; ++l)
+      for (int32_t g : sets[l]) sum_ptr[g + 1]++;
+    for (int64_t e = 0; e < m.ne; ++e) sum_ptr[e + 1] += sum_ptr[e];
+    sum_idx.resize(sum_ptr[m.ne]);
+    std::vector<int64_t> fill(sum_ptr.begin(), sum_ptr.end() - 1);
+    for (int l = 0; l < N; ++l) {
+      const Skyline &s = P->sky[l];
+      for (int64_t r = 0; r < (int64_t)sets[l].size(); ++r)
+        sum_idx[fill[sets[l][r]]++] = P->sub_vec_base[l] + s.iperm[r];
+    }
+  } else {
+    src.assign(m.ne, -1);
+    for (int64_t e = 0; e < m.ne; ++e) {
+      int o = part.owner[e];
+      const auto &st = sets[o];
+      auto it = std::lower_bound(st.begin(), st.end(), (int32_t)e);
+      if (it == st.end() || *it != e) fail(MX_EINVAL, "internal: owner does not hold its DOF");
+      src[e] = P->sub_vec_base[o] + P->sky[o].iperm[it - st.begin()];
+    }
+  }
+  // factor step tables
+  P->panel_pref.assign((int64_t)P->max_nb * (N + 1), 0);
+  P->update_pref.assign((int64_t)P->max_nb * (N + 1), 0);
+  for (int K = 0; K < P->max_nb; ++K) {
+    int64_t ap = 0, au = 0;
+    for (int l = 0; l < N; ++l) {
+      P->panel_pref[(int64_t)K * (N + 1) + l] = (int32_t)ap;
+      P->update_pref[(int64_t)K * (N + 1) + l] = (int32_t)au;
+      if (K < P->sub_nb[l]) {
+        int64_t mK = P->sky[l].blast[K] - K;
+        ap += mK;
+        au += mK * (mK + 1) / 2;
+      }
+    }
+    if (au > INT32_MAX) fail(MX_EINVAL, "factor step too large");
+    P->panel_pref[(int64_t)K * (N + 1) + N] = (int32_t)ap;
+    P->update_pref[(int64_t)K * (N + 1) + N] = (int32_t)au;
+  }
+  // sweep schedule: forward rows by relative progress, then backward rows likewise
+  struct Item {
+    double key;
+    int32_t l, b;
+  };
+  std::vector<Item> fw, bw;
+  for (int l = 0; l < N; ++l) {
+    const int64_t nb = P->sub_nb[l];
+    for (int64_t I = 0; I < nb; ++I) {
+      fw.push_back({(I + 0.5) / nb, l, (int32_t)I});
+      bw.push_back({(I + 0.5) / nb, l, (int32_t)(nb - 1 - I)});
+    }
+  }
+  auto by_key = [](const Item &a, const Item &b) { return a.key != b.key ? a.key < b.key : a.l < b.l; };
+  std::sort(fw.begin(), fw.end(), by_key);
+  std::sort(bw.begin(), bw.end(), by_key);
+  std::vector<int32_t> sched_sub, sched_blk;
+  for (const auto *lst : {&fw, &bw})
+    for (const auto &it : *lst) {
+      sched_sub.push_back(it.l);
+      sched_blk.push_back(it.b);
+    }
+  P->n_items = (int)sched_sub.size();
+  P->trsv_grid = std::max(1, std::min(P->n_items / 2, 4 * ctx->cus));
+  const double t1 = now_s();
+
+  // device buffers
+  const size_t esz = P->prec == MX_C128 ? 16 : 8;
+  P->d_sub_nb.upload(P->sub_nb);
+  P->d_sub_brow_base.upload(P->sub_brow_base);
+  P->d_sub_tile_base.upload(P->sub_tile_base);
+  P->d_sub_vec_base.upload(P->sub_vec_base);
+  P->d_brow_off.upload(brow_off);
+  P->d_bfirst.upload(bfirst);
+  P->d_blast.upload(blast);
+  P->d_glob.upload(glob);
+  if (opts->kind == MX_AS) {
+    P->d_sum_ptr.upload(sum_ptr);
+    P->d_sum_idx.upload(sum_idx);
+  } else {
+    P->d_src.upload(src);
+  }
+  P->d_panel_pref.upload(P->panel_pref);
+  P->d_update_pref.upload(P->update_pref);
+  P->d_sched_sub.upload(sched_sub);
+  P->d_sched_blk.upload(sched_blk);
+  P->d_r.alloc(vec * esz);
+  P->d_y.alloc(vec * esz);
+  P->d_z.alloc(vec * esz);
+  P->d_flags.alloc(2 * blocks * sizeof(int));
+  P->d_ctrl.alloc(64);
+  MX_HIP(hipMemset(P->d_flags.p, 0, 2 * blocks * sizeof(int)));
+  MX_HIP(hipMemset(P->d_ctrl.p, 0, 64));
+  MX_HIP(hipMemset(P->d_y.p, 0, vec * esz));
+  MX_HIP(hipMemset(P->d_z.p, 0, vec * esz));
+  const size_t pool_bytes = (size_t)tiles * kTileElems * esz;
+  P->pool.alloc(pool_bytes);
+  hipStream_t st = nullptr;
+  k_zero<<<4096, 256, 0, st>>>((int64_t)(pool_bytes / 16), P->pool.as<uint4>());
+  {
+    DevBuf d_off, d_val;
+    d_off.upload(off);
+    d_val.upload(val);
+    const int64_t ne = (int64_t)off.size();
+    if (ne > 0) {
+      if (P->prec == MX_C128)
+        k_scatter<double><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(
+            ne, d_off.as<int64_t>(), d_val.as<cx<double>>(), P->pool.as<cx<double>>());
+      else
+        k_scatter<float><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(
+            ne, d_off.as<int64_t>(), d_val.as<cx<double>>(), P->pool.as<cx<float>>());
+    }
+    MX_HIP(hipGetLastError());
+    MX_HIP(hipDeviceSynchronize());
+  }
+  const double t2 = now_s();
+  if (P->prec == MX_C128) factor_all<double>(P, st);
+  else factor_all<float>(P, st);
+  MX_HIP(hipDeviceSynchronize());
+  const double t3 = now_s();
+  precond_check(P);
+  // info
+  mx_precond_info &in = P->info;
+  in.n_sub = N;
+  in.tile = kTile;
+  in.n_local_total = 0;
+  in.max_local = 0;
+  in.env_entries = 0;
+  in.env_flops = 0;
+  in.tile_flops = 0;
+  for (int l = 0; l < N; ++l) {
+    const Skyline &s = P->sky[l];
+    in.n_local_total += s.n;
+    in.max_local = std::max<int64_t>(in.max_local, s.n);
+    in.env_entries += s.env;
+    in.env_flops += s.env_flops;
+    in.tile_flops += s.tile_flops;
+  }
+  in.max_blocks = P->max_nb;
+  in.tiles = tiles;
+  in.factor_bytes = (int64_t)pool_bytes;
+  // algorithmic bytes per application: the envelope factor read twice, the local vectors
+  // (restricted input written and read, forward result written and read twice, backward result
+  // written and read), the global input gathered and output written, the 4-byte gather maps
+  const int64_t nloc = in.n_local_total;
+  in.apply_bytes = (int64_t)(2 * in.env_entries * esz + 6 * nloc * esz + 2 * m.ne * 16 + 4 * nloc +
+                             8 * m.ne);
+  in.t_host_setup = t1 - t0;
+  in.t_upload = t2 - t1;
+  in.t_factor = t3 - t2;
+}
+
+}  // namespace mx

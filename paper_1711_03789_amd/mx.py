@@ -1,0 +1,317 @@
+"""ctypes binding of libmx (include/mx.h): argument marshalling only.
+
+Every step of the solver runs inside libmx (host C++ for topology, gfx950 HIP kernels for all
+numerical work on the device).  Device buffers are torch tensors (complex128 / any dtype with the
+right byte size), passed by data pointer; streams are torch HIP streams.  If the library is not
+built, every entry point raises -- there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmx.so")
+
+MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EPIVOT, MX_ENAN, MX_ESTALL = 0, -1, -2, -3, -4, -5, -6
+MX_BC_PEC, MX_BC_IMPEDANCE = 0, 1
+MX_AS, MX_RAS, MX_ORAS = 0, 1, 2
+MX_C128, MX_C64 = 0, 1
+KINDS = {"as": MX_AS, "ras": MX_RAS, "oras": MX_ORAS}
+PRECISIONS = {"c128": MX_C128, "c64": MX_C64}
+
+# every symbol declared in include/mx.h
+SYMBOLS = [
+    "mx_last_error", "mx_version", "mx_ctx_create", "mx_ctx_destroy", "mx_mesh_box",
+    "mx_mesh_sizes", "mx_mesh_export", "mx_mesh_destroy", "mx_matrix_assemble", "mx_matrix_sizes",
+    "mx_matrix_export", "mx_matrix_destroy", "mx_spmv", "mx_rhs_gaussian", "mx_partition_box",
+    "mx_partition_sizes", "mx_partition_export", "mx_partition_destroy", "mx_precond_setup",
+    "mx_precond_apply", "mx_precond_get_info", "mx_precond_export_perm", "mx_precond_export_diag",
+    "mx_precond_check", "mx_precond_destroy", "mx_gmres", "mx_selftest", "mx_local_problem",
+]
+
+
+class MxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libmx error %d: %s" % (code, msg))
+        self.code = code
+
+
+class PrecondOpts(C.Structure):
+    _fields_ = [("kind", C.c_int), ("xi_prec", C.c_double), ("precision", C.c_int)]
+
+
+class PrecondInfo(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("tile", C.c_int32), ("n_local_total", C.c_int64),
+                ("max_local", C.c_int64), ("max_blocks", C.c_int64), ("tiles", C.c_int64),
+                ("factor_bytes", C.c_int64), ("env_entries", C.c_int64), ("env_flops", C.c_double),
+                ("tile_flops", C.c_double), ("apply_bytes", C.c_int64), ("t_host_setup", C.c_double),
+                ("t_upload", C.c_double), ("t_factor", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GmresOpts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("flexible", C.c_int),
+                ("fixed_iters", C.c_int), ("spmv_c64", C.c_int), ("rtol", C.c_double)]
+
+
+class GmresStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("converged", C.c_int),
+                ("relres_true", C.c_double), ("relres_est", C.c_double), ("t_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+P = C.c_void_p
+I32P = np.ctypeslib.ndpointer(np.int32, flags="C")
+I64P = np.ctypeslib.ndpointer(np.int64, flags="C")
+I8P = np.ctypeslib.ndpointer(np.int8, flags="C")
+F64P = np.ctypeslib.ndpointer(np.float64, flags="C")
+
+
+def load(path=LIB_PATH):
+    """Loads libmx.so (built by paper_1711_03789_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libmx.so not built: run `python -m paper_1711_03789_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = C.CDLL(path)
+    sig = {
+        "mx_last_error": (C.c_char_p, []),
+        "mx_version": (C.c_int, []),
+        "mx_ctx_create": (C.c_int, [C.c_int, C.POINTER(P)]),
+        "mx_ctx_destroy": (None, [P]),
+        "mx_mesh_box": (C.c_int, [C.c_int] * 3 + [C.c_double] * 3 + [C.POINTER(P)]),
+        "mx_mesh_sizes": (C.c_int, [P] + [C.POINTER(C.c_int64)] * 4),
+        "mx_mesh_export": (C.c_int, [P, P, P, P, P, P]),
+        "mx_mesh_destroy": (None, [P]),
+        "mx_matrix_assemble": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, C.POINTER(P)]),
+        "mx_matrix_sizes": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+        "mx_matrix_export": (C.c_int, [P, P, P, P]),
+        "mx_matrix_destroy": (None, [P]),
+        "mx_spmv": (C.c_int, [P, P, P, P, P]),
+        "mx_rhs_gaussian": (C.c_int, [P, C.c_int, F64P, F64P, C.c_double, P]),
+        "mx_partition_box": (C.c_int, [P, C.c_int, C.c_int, C.c_int, P, P, P, C.c_int, C.POINTER(P)]),
+        "mx_partition_sizes": (C.c_int, [P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+        "mx_partition_export": (C.c_int, [P, C.c_int, P, P, P, P]),
+        "mx_partition_destroy": (None, [P]),
+        "mx_precond_setup": (C.c_int, [P, P, P, P, C.POINTER(PrecondOpts), C.POINTER(P)]),
+        "mx_precond_apply": (C.c_int, [P, P, P, P, P]),
+        "mx_precond_get_info": (C.c_int, [P, C.POINTER(PrecondInfo)]),
+        "mx_precond_export_perm": (C.c_int, [P, C.c_int, P, P]),
+        "mx_precond_export_diag": (C.c_int, [P, C.c_int, P]),
+        "mx_precond_check": (C.c_int, [P]),
+        "mx_precond_destroy": (None, [P]),
+        "mx_gmres": (C.c_int, [P, P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresStats), P, P]),
+        "mx_selftest": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "mx_local_problem": (C.c_int, [P, P, P, C.POINTER(PrecondOpts), C.c_int,
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64), P, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != MX_OK:
+        raise MxError(rc, _lib.mx_last_error().decode())
+
+
+def _ptr(a):
+    """Raw pointer of a numpy array (host) or a torch tensor (host or device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    assert a.is_contiguous()
+    return a.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+class Context:
+    def __init__(self, device=0):
+        load()
+        h = P()
+        _check(_lib.mx_ctx_create(device, C.byref(h)))
+        self.h, self.device = h, device
+
+    def close(self):
+        if self.h:
+            _lib.mx_ctx_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def selftest(self):
+        e64, e32 = C.c_double(), C.c_double()
+        _check(_lib.mx_selftest(self.h, C.byref(e64), C.byref(e32)))
+        return e64.value, e32.value
+
+
+class Mesh:
+    def __init__(self, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0):
+        load()
+        h = P()
+        _check(_lib.mx_mesh_box(nx, ny, nz, lx, ly, lz, C.byref(h)))
+        self.h = h
+        a = [C.c_int64() for _ in range(4)]
+        _check(_lib.mx_mesh_sizes(h, *[C.byref(x) for x in a]))
+        self.n_vert, self.n_tet, self.n_edge, self.n_bface = [x.value for x in a]
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.mx_mesh_destroy(self.h)
+            self.h = None
+
+    def export(self):
+        tv = np.zeros((self.n_tet, 4), np.int32)
+        ev = np.zeros((self.n_edge, 2), np.int32)
+        te = np.zeros((self.n_tet, 6), np.int32)
+        ts = np.zeros((self.n_tet, 6), np.int8)
+        bf = np.zeros((self.n_bface, 3), np.int32)
+        _check(_lib.mx_mesh_export(self.h, _ptr(tv), _ptr(ev), _ptr(te), _ptr(ts), _ptr(bf)))
+        return {"tet_vert": tv, "edge_vert": ev, "tet_edge": te, "tet_edge_sign": ts, "bface_vert": bf}
+
+    def rhs_gaussian(self, center, pol, sigma, bc=MX_BC_IMPEDANCE):
+        f = np.zeros(self.n_edge, np.complex128)
+        _check(_lib.mx_rhs_gaussian(self.h, bc, np.asarray(center, np.float64),
+                                    np.asarray(pol, np.float64), sigma, _ptr(f)))
+        return f
+
+
+class Matrix:
+    def __init__(self, ctx, mesh, k, xi, bc=MX_BC_IMPEDANCE):
+        load()
+        h = P()
+        _check(_lib.mx_matrix_assemble(ctx.h if ctx is not None else None, mesh.h, k, xi, bc,
+                                       C.byref(h)))
+        self.h, self.k, self.xi, self.bc = h, k, xi, bc
+        n, nnz = C.c_int64(), C.c_int64()
+        _check(_lib.mx_matrix_sizes(h, C.byref(n), C.byref(nnz)))
+        self.n, self.nnz = n.value, nnz.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.mx_matrix_destroy(self.h)
+            self.h = None
+
+    def export(self):
+        rp = np.zeros(self.n + 1, np.int64)
+        col = np.zeros(self.nnz, np.int32)
+        val = np.zeros(self.nnz, np.complex128)
+        _check(_lib.mx_matrix_export(self.h, _ptr(rp), _ptr(col), _ptr(val)))
+        return rp, col, val
+
+    def spmv(self, ctx, x, y, stream=None):
+        _check(_lib.mx_spmv(ctx.h, self.h, _ptr(x), _ptr(y), _stream(stream)))
+
+
+class Partition:
+    def __init__(self, mesh, px, py, pz, layers, cx=None, cy=None, cz=None):
+        load()
+        h = P()
+        arrs = [None if c is None else np.ascontiguousarray(c, np.int32) for c in (cx, cy, cz)]
+        self._cuts = arrs
+        _check(_lib.mx_partition_box(mesh.h, px, py, pz, *[_ptr(a) for a in arrs], layers, C.byref(h)))
+        self.h = h
+        self.n_edge = mesh.n_edge
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.mx_partition_destroy(self.h)
+            self.h = None
+
+    def export(self, kind):
+        kind = KINDS.get(kind, kind)
+        n, tot = C.c_int32(), C.c_int64()
+        _check(_lib.mx_partition_sizes(self.h, kind, C.byref(n), C.byref(tot)))
+        off = np.zeros(n.value + 1, np.int64)
+        l2g = np.zeros(tot.value, np.int32)
+        owner = np.zeros(self.n_edge, np.int32)
+        nt = np.zeros(n.value, np.int64)
+        _check(_lib.mx_partition_export(self.h, kind, _ptr(off), _ptr(l2g), _ptr(owner), _ptr(nt)))
+        return {"offsets": off, "loc2glob": l2g, "owner": owner, "n_tet": nt,
+                "sets": [l2g[off[i]:off[i + 1]] for i in range(n.value)]}
+
+
+def local_problem(mesh, A, part, l, kind="oras", xi_prec=None):
+    """Host-only: local matrix of subdomain l (CSR in local numbering) and its RCM order."""
+    load()
+    o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec, MX_C128)
+    n, nnz = C.c_int64(), C.c_int64()
+    _check(_lib.mx_local_problem(mesh.h, A.h, part.h, C.byref(o), l, C.byref(n), C.byref(nnz),
+                                 None, None, None, None, None))
+    rp = np.zeros(n.value + 1, np.int64)
+    col = np.zeros(nnz.value, np.int32)
+    val = np.zeros(nnz.value, np.complex128)
+    perm = np.zeros(n.value, np.int32)
+    first = np.zeros(n.value, np.int32)
+    _check(_lib.mx_local_problem(mesh.h, A.h, part.h, C.byref(o), l, C.byref(n), C.byref(nnz),
+                                 _ptr(rp), _ptr(col), _ptr(val), _ptr(perm), _ptr(first)))
+    return {"rowptr": rp, "col": col, "val": val, "perm": perm, "first": first}
+
+
+class Precond:
+    def __init__(self, ctx, A, mesh, part, kind="oras", xi_prec=None, precision="c128"):
+        load()
+        o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec,
+                        PRECISIONS.get(precision, precision))
+        h = P()
+        _check(_lib.mx_precond_setup(ctx.h, A.h, mesh.h, part.h, C.byref(o), C.byref(h)))
+        self.h, self.ctx = h, ctx
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.mx_precond_destroy(self.h)
+            self.h = None
+
+    def info(self):
+        inf = PrecondInfo()
+        _check(_lib.mx_precond_get_info(self.h, C.byref(inf)))
+        return inf.as_dict()
+
+    def apply(self, v, z, stream=None):
+        _check(_lib.mx_precond_apply(self.ctx.h, self.h, _ptr(v), _ptr(z), _stream(stream)))
+
+    def check(self):
+        _check(_lib.mx_precond_check(self.h))
+
+    def perm(self, l, n_local):
+        perm = np.zeros(n_local, np.int32)
+        first = np.zeros(n_local, np.int32)
+        _check(_lib.mx_precond_export_perm(self.h, l, _ptr(perm), _ptr(first)))
+        return perm, first
+
+    def diag(self, l, n_local):
+        d = np.zeros(n_local, np.complex128)
+        _check(_lib.mx_precond_export_diag(self.h, l, _ptr(d)))
+        return d
+
+
+def gmres(ctx, A, Pc, b, x, restart=50, rtol=1e-6, max_iters=1000, flexible=False,
+          fixed_iters=0, spmv_c64=False, history=False, stream=None):
+    o = GmresOpts(restart, max_iters, int(flexible), fixed_iters, int(spmv_c64), rtol)
+    st = GmresStats()
+    hist = np.zeros(max(max_iters, fixed_iters) + 2, np.float64) if history else None
+    _check(_lib.mx_gmres(ctx.h, A.h, Pc.h if Pc is not None else None, _ptr(b), _ptr(x),
+                         C.byref(o), C.byref(st), _ptr(hist), _stream(stream)))
+    out = st.as_dict()
+    if history:
+        out["history"] = hist[: st.iters + 1].copy()
+    return out

@@ -1,0 +1,217 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle on the same seeded
+inputs.  Tolerances: FP64 path 1e-8 relative L2 for GMRES solutions (at the oracle's iteration
+count), iteration counts within +-1; single preconditioner applications and SpMV to rounding
+(1e-10 / 1e-13); complex64 factors 1e-4 per application and 1e-5 for FGMRES solutions."""
+import sys
+
+import numpy as np
+import pytest
+
+from mx_inputs import config_small, jittered_cuts, random_rhs
+from oracle import dd, fem, gmres
+from oracle.mesh import Mesh as OMesh
+
+pytestmark = pytest.mark.gpu
+
+OKIND = {"oras": dd.ORAS, "ras": dd.RAS, "as": dd.AS}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, np.complex128)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    return gpu_lib.Context(0)
+
+
+class Case:
+    """A problem built on both sides from the same description."""
+
+    def __init__(self, mx, ctx, n, parts, layers, k, xi, kind, cuts=(None, None, None),
+                 bc=fem.BC_IMPEDANCE, precision="c128", lengths=(1.0, 1.0, 1.0)):
+        self.om = OMesh(*n, *lengths)
+        self.oA = fem.assemble(self.om, k, xi, bc)
+        self.op = dd.Partition(self.om, *parts, layers, *cuts)
+        self.oB = dd.Schwarz(self.op, self.oA, OKIND[kind], k, xi, bc)
+        self.lm = mx.Mesh(*n, *lengths)
+        self.lA = mx.Matrix(ctx, self.lm, k, xi, bc)
+        self.lp = mx.Partition(self.lm, *parts, layers, *cuts)
+        self.lP = mx.Precond(ctx, self.lA, self.lm, self.lp, kind, precision=precision)
+        self.E = self.om.n_edge
+
+
+def test_selftest_matrix_cores(ctx):
+    say("selftest")
+    e64, e32 = ctx.selftest()
+    say("mfma rel err", e64, e32)
+    assert e64 < 1e-13 and e32 < 1e-5
+
+
+@pytest.mark.parametrize("n", [(8, 8, 8), (5, 7, 3)])
+def test_spmv(gpu_lib, ctx, n):
+    say("spmv", n)
+    om = OMesh(*n)
+    A = fem.assemble(om, 4.0, 16.0)
+    lm = gpu_lib.Mesh(*n)
+    lA = gpu_lib.Matrix(ctx, lm, 4.0, 16.0)
+    x = random_rhs(om.n_edge, 11)
+    xd, yd = dev(x), dev(np.zeros(om.n_edge))
+    lA.spmv(ctx, xd, yd)
+    y = host(yd)
+    ref = A @ x
+    assert np.linalg.norm(y - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("kind", ["oras", "ras", "as"])
+def test_apply_config_small(gpu_lib, ctx, kind):
+    say("apply cfg small", kind)
+    c = Case(gpu_lib, ctx, (8, 8, 8), (2, 2, 2), 2, 4.0, 16.0, kind)
+    v = random_rhs(c.E, 3)
+    vd, zd = dev(v), dev(np.zeros(c.E))
+    c.lP.apply(vd, zd)
+    c.lP.check()
+    z = host(zd)
+    ref = c.oB(v)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say("  rel err", err)
+    assert err <= 1e-10
+    # repeated application is bitwise deterministic
+    zd2 = dev(np.zeros(c.E))
+    c.lP.apply(vd, zd2)
+    assert np.array_equal(host(zd2), z)
+
+
+def test_apply_multi_tile_jittered(gpu_lib, ctx):
+    """Uneven jittered boxes with several 64-row blocks per subdomain and ragged last blocks."""
+    say("apply jittered")
+    n = (16, 14, 12)
+    cuts = (jittered_cuts(16, 3, 0.2, 7), jittered_cuts(14, 2, 0.2, 8), jittered_cuts(12, 2, 0.2, 9))
+    c = Case(gpu_lib, ctx, n, (3, 2, 2), 2, 5.0, 5.0, "oras", cuts)
+    info = c.lP.info()
+    say("  info", info)
+    assert info["max_blocks"] >= 20
+    v = random_rhs(c.E, 4)
+    vd, zd = dev(v), dev(np.zeros(c.E))
+    c.lP.apply(vd, zd)
+    c.lP.check()
+    ref = c.oB(v)
+    err = np.linalg.norm(host(zd) - ref) / np.linalg.norm(ref)
+    say("  rel err", err)
+    assert err <= 1e-10
+
+
+def test_apply_pec_and_negative_xi(gpu_lib, ctx):
+    say("apply pec")
+    c = Case(gpu_lib, ctx, (6, 6, 6), (2, 2, 1), 1, 3.0, -9.0, "oras", bc=fem.BC_PEC)
+    v = random_rhs(c.E, 5)
+    vd, zd = dev(v), dev(np.zeros(c.E))
+    c.lP.apply(vd, zd)
+    c.lP.check()
+    ref = c.oB(v)
+    assert np.linalg.norm(host(zd) - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_apply_complex64(gpu_lib, ctx):
+    say("apply c64")
+    c = Case(gpu_lib, ctx, (8, 8, 8), (2, 2, 2), 2, 4.0, 16.0, "oras", precision="c64")
+    v = random_rhs(c.E, 6)
+    vd, zd = dev(v), dev(np.zeros(c.E))
+    c.lP.apply(vd, zd)
+    c.lP.check()
+    ref = c.oB(v)
+    err = np.linalg.norm(host(zd) - ref) / np.linalg.norm(ref)
+    say("  rel err", err)
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("kind", ["oras", "ras", "as"])
+def test_gmres_config_small(gpu_lib, ctx, kind):
+    """8^3, k = 4, xi = k^2, impedance, Gaussian source, 2x2x2 subdomains, 2 layers, GMRES(50)."""
+    say("gmres cfg small", kind)
+    w = config_small(kind)
+    c = Case(gpu_lib, ctx, w.n, w.parts, w.layers, w.k, w.xi, kind)
+    f = fem.load_vector(c.om, fem.gaussian_source(w.center, w.pol, w.sigma))
+    fl = c.lm.rhs_gaussian(w.center, w.pol, w.sigma)
+    assert np.abs(fl - f).max() <= 1e-14 * np.abs(f).max()
+    ores = gmres.gmres(c.oA, f, c.oB, restart=w.restart, rtol=w.rtol)
+    bd, xd = dev(f), dev(np.zeros(c.E))
+    st = gpu_lib.gmres(ctx, c.lA, c.lP, bd, xd, restart=w.restart, rtol=w.rtol, history=True)
+    say("  iters gpu", st["iters"], "oracle", ores.iters, "relres", st["relres_true"])
+    assert st["converged"] and st["relres_true"] <= w.rtol
+    assert abs(st["iters"] - ores.iters) <= 1
+    # solution at the oracle's iteration count
+    xd2 = dev(np.zeros(c.E))
+    st2 = gpu_lib.gmres(ctx, c.lA, c.lP, bd, xd2, restart=w.restart, fixed_iters=ores.iters)
+    x = host(xd2)
+    err = np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x)
+    say("  fixed-iteration solution rel err", err)
+    assert st2["iters"] == ores.iters
+    assert err <= 1e-8
+
+
+def test_gmres_restart_and_flexible(gpu_lib, ctx):
+    """Small restart length (several cycles), flexible variant, nonzero initial guess."""
+    say("gmres restart")
+    c = Case(gpu_lib, ctx, (8, 6, 7), (2, 2, 1), 1, 3.0, 3.0, "ras")
+    f = random_rhs(c.E, 9)
+    x0 = random_rhs(c.E, 10) * 1e-3
+    for flex in (False, True):
+        ores = gmres.gmres(c.oA, f, c.oB, x0=x0, restart=5, rtol=1e-8, flexible=flex)
+        xd = dev(x0)
+        st = gpu_lib.gmres(ctx, c.lA, c.lP, dev(f), xd, restart=5, rtol=1e-8, flexible=flex)
+        say("  flex", flex, "iters", st["iters"], ores.iters, "cycles", st["cycles"], ores.cycles)
+        assert abs(st["iters"] - ores.iters) <= 1 and st["converged"]
+        xd = dev(x0)
+        gpu_lib.gmres(ctx, c.lA, c.lP, dev(f), xd, restart=5, fixed_iters=ores.iters, flexible=flex)
+        err = np.linalg.norm(host(xd) - ores.x) / np.linalg.norm(ores.x)
+        assert err <= 1e-8
+
+
+def test_gmres_degenerate(gpu_lib, ctx):
+    say("gmres degenerate")
+    # one subdomain: B^-1 = A^-1, one iteration
+    c = Case(gpu_lib, ctx, (5, 4, 4), (1, 1, 1), 2, 4.0, 4.0, "oras")
+    f = random_rhs(c.E, 12)
+    xd = dev(np.zeros(c.E))
+    st = gpu_lib.gmres(ctx, c.lA, c.lP, dev(f), xd, restart=10, rtol=1e-10)
+    assert st["iters"] == 1 and st["converged"]
+    x = host(xd)
+    assert np.linalg.norm(c.oA @ x - f) <= 1e-10 * np.linalg.norm(f)
+    # zero right-hand side: converged with no iteration, x stays 0
+    xd = dev(np.zeros(c.E))
+    st = gpu_lib.gmres(ctx, c.lA, c.lP, dev(np.zeros(c.E)), xd)
+    assert st["iters"] == 0 and st["converged"] and not host(xd).any()
+
+
+def test_fgmres_mixed_precision_config(gpu_lib, ctx):
+    """complex64 factors and complex64 SpMV values inside FP64 flexible GMRES: error against the
+    FP64 oracle solution reported and bounded by 1e-5."""
+    say("fgmres c64")
+    w = config_small("oras", precision="c64")
+    c = Case(gpu_lib, ctx, w.n, w.parts, w.layers, w.k, w.xi, "oras", precision="c64")
+    f = fem.load_vector(c.om, fem.gaussian_source(w.center, w.pol, w.sigma))
+    import scipy.sparse.linalg as spla
+    x_exact = spla.spsolve(c.oA.tocsc(), f)
+    ores = gmres.gmres(c.oA, f, c.oB, restart=w.restart, rtol=w.rtol)
+    xd = dev(np.zeros(c.E))
+    st = gpu_lib.gmres(ctx, c.lA, c.lP, dev(f), xd, restart=w.restart, rtol=w.rtol, flexible=True,
+                       spmv_c64=True)
+    x = host(xd)
+    err = np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x)
+    say("  iters", st["iters"], "oracle", ores.iters, "err vs oracle", err,
+        "err vs exact", np.linalg.norm(x - x_exact) / np.linalg.norm(x_exact))
+    assert st["converged"] and st["relres_true"] <= w.rtol
+    assert err <= 1e-5
