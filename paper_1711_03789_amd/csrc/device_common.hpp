@@ -50,8 +50,9 @@ __device__ __forceinline__ cx<T> shfl_xor_c(cx<T> v, int m) {
 }
 
 // ---- matrix cores --------------------------------------------------------------------------------
-// 16x16x4 products: lane l supplies A[l%16][l/16] and B[l/16][l%16]; the 4 accumulator values of
-// lane l are D[4*(l/16) + r][l%16], r = 0..3 (checked at run time by mx_selftest).
+// 16x16x4 products: lane l supplies A[l%16][l/16] and B[l/16][l%16].  Accumulator value r of lane
+// l holds D[row][l%16] with row = 4*(l/16) + r for the FP32 instruction and row = 4*r + l/16 for
+// the FP64 one (checked at run time by mx_selftest).
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -134,8 +135,15 @@ __device__ __forceinline__ void tile_nt_quadrant(const cx<T> *__restrict__ A,
 }
 
 // Row/column of accumulator element (rb, cb, r) of this lane inside the 64x64 tile.
-__device__ __forceinline__ int acc_row(int r0, int rb, int r) {
+template <typename T>
+__device__ __forceinline__ int acc_row(int r0, int rb, int r);
+template <>
+__device__ __forceinline__ int acc_row<float>(int r0, int rb, int r) {
   return r0 + rb * 16 + 4 * ((threadIdx.x & 63) >> 4) + r;
+}
+template <>
+__device__ __forceinline__ int acc_row<double>(int r0, int rb, int r) {
+  return r0 + rb * 16 + 4 * r + ((threadIdx.x & 63) >> 4);
 }
 __device__ __forceinline__ int acc_col(int c0, int cb) { return c0 + cb * 16 + (threadIdx.x & 15); }
 

@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256) void k_selftest_mfma(const cx<T> *A, const cx<
   for (int rb = 0; rb < 2; ++rb)
     for (int cb = 0; cb < 2; ++cb)
       for (int q = 0; q < 4; ++q)
-        out[acc_row(r0, rb, q) * kTile + acc_col(c0, cb)] = {acc[rb][cb][0][q], acc[rb][cb][1][q]};
+        out[acc_row<T>(r0, rb, q) * kTile + acc_col(c0, cb)] = {acc[rb][cb][0][q], acc[rb][cb][1][q]};
 }
 template <typename T>
 __global__ void k_selftest_ref(const cx<T> *A, const cx<T> *B, const cx<T> *s, cx<T> *out) {

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_fac_panel(int K, SubView v, const int32
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = acc_row(r0, rb, r);
+        const int row = acc_row<T>(r0, rb, r);
         A[row * kTile + col] = cmul(cx<T>{acc[rb][cb][0][r], acc[rb][cb][1][r]}, dinv);
       }
   }
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_fac_update(int K, SubView v, const int3
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = acc_row(r0, rb, q), col = acc_col(c0, cb);
+        const int row = acc_row<T>(r0, rb, q), col = acc_col(c0, cb);
         cx<T> cur = C[row * kTile + col];
         C[row * kTile + col] = {cur.re - acc[rb][cb][0][q], cur.im - acc[rb][cb][1][q]};
       }

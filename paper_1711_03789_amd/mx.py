@@ -152,9 +152,9 @@ class Context:
         self.h, self.device = h, device
 
     def close(self):
-        if self.h:
+        if getattr(self, "h", None) and _lib is not None:
             _lib.mx_ctx_destroy(self.h)
-            self.h = None
+        self.h = None
 
     __del__ = close
 
@@ -175,9 +175,9 @@ class Mesh:
         self.n_vert, self.n_tet, self.n_edge, self.n_bface = [x.value for x in a]
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.mx_mesh_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def export(self):
         tv = np.zeros((self.n_tet, 4), np.int32)
@@ -207,9 +207,9 @@ class Matrix:
         self.n, self.nnz = n.value, nnz.value
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.mx_matrix_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def export(self):
         rp = np.zeros(self.n + 1, np.int64)
@@ -233,9 +233,9 @@ class Partition:
         self.n_edge = mesh.n_edge
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.mx_partition_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def export(self, kind):
         kind = KINDS.get(kind, kind)
@@ -277,9 +277,9 @@ class Precond:
         self.h, self.ctx = h, ctx
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.mx_precond_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def info(self):
         inf = PrecondInfo()
