@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark: GMRES solves/sec at rtol 1e-6 for the one-level overlapping Schwarz (AS / ORAS)
+preconditioned GMRES solve of the lowest-order Nedelec discretisation of
+curl curl E - (k^2 + i xi) E = J on one MI355X.
+
+One step = the whole path for one batch of synthetic input: box mesh and edge numbering,
+partition with overlap, and for every (preconditioner, xi) instance of the batch: Galerkin
+assembly, local problems + reverse Cuthill-McKee + batched factorisation, right-preconditioned
+GMRES to rtol 1e-6 (true residual).  Right-hand sides are seeded per-DOF complex Gaussians,
+already resident in HBM when the timed region starts.
+
+Prints one JSON line.  Only one GPU is supported: --gpus N > 1 exits with a message.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3
+
+
+def instances(name):
+    """(kind, xi exponent, rhs seed) of one batch."""
+    if name == "scale":
+        return [(kind, e, s) for kind in ("oras", "as") for s, e in enumerate((1.0, 1.5, 2.0))]
+    if name == "scale-oras":
+        return [("oras", e, s) for s, e in enumerate((1.0, 1.5, 2.0))]
+    if name == "small":
+        return [("oras", 2.0, 0)]
+    raise SystemExit("unknown workload " + name)
+
+
+def workload_desc(name):
+    from mx_inputs import config_scale, config_small
+    if name.startswith("scale"):
+        w = config_scale()
+        return w, {"workload": "unit cube 64^3 cubes x 6 tets (1,872,064 complex DOFs), k=16, "
+                               "xi in {k, k^1.5, k^2}, 4x4x4 subdomains, 2-layer overlap, "
+                               + ("ORAS and AS" if name == "scale" else "ORAS")
+                               + ", GMRES(100) rtol 1e-6, complex128, seeded random complex "
+                                 "Gaussian J", "instances": len(instances(name))}
+    w = config_small()
+    return w, {"workload": "unit cube 8^3 cubes x 6 tets, k=4, xi=k^2, 2x2x2 subdomains, ORAS, "
+                           "GMRES(50), complex128", "instances": 1}
+
+
+def cpu_baseline(total_iters, n_inst):
+    """The oracle (NumPy/SciPy FP64, one thread) on a bounded sample of the same workload:
+    its global mesh + assembly + partition on the 32^3 box (1/8 of the 64^3 volume; scaled x8),
+    and one 16^3-cube ORAS local problem (local assembly, sparse LU, one local solve; scaled x64
+    subdomains).  Estimated seconds per solve = 8*T_global + 64*(T_local + T_lu)
+    + iterations*(64*T_solve); solves/s is its inverse."""
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    import scipy.sparse.linalg as spla
+
+    from mx_inputs import random_rhs
+    from oracle import dd, fem
+    from oracle.mesh import Mesh as OMesh
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        m = OMesh(32, 32, 32)
+        A = fem.assemble(m, 16.0, 256.0)
+        part = dd.Partition(m, 2, 2, 2, 2)
+        t1 = time.perf_counter()
+        idx = part.oras_sets[0]
+        tets = np.nonzero(part.tet_masks[0])[0]
+        K, M, Mb = fem.assemble_parts(m, tets, part.subdomain_boundary_faces(0))
+        Al = (K.astype(np.complex128) - (256.0 + 256.0j) * M - 16.0j * Mb).tocsr()[idx][:, idx].tocsc()
+        t2 = time.perf_counter()
+        lu = spla.splu(Al)
+        t3 = time.perf_counter()
+        lu.solve(random_rhs(len(idx), 0))
+        t4 = time.perf_counter()
+    t_global, t_local, t_lu, t_solve = t1 - t0, t2 - t1, t3 - t2, t4 - t3
+    per_solve = 8 * t_global + 64 * (t_local + t_lu) + (total_iters / max(n_inst, 1)) * 64 * t_solve
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle mesh+assembly+partition of the 32^3 box (x8) and one 16^3-cube ORAS "
+                      "local problem: assembly, SciPy SuperLU factorisation, one solve (x64 "
+                      "subdomains), GMRES iterations taken from the GPU run; measured %.1f s, "
+                      "per-solve estimate %.0f s (global %.2f s, local %.2f s, LU %.1f s, solve "
+                      "%.3f s)" % (t4 - t0, per_solve, t_global, t_local, t_lu, t_solve)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="scale")
+    ap.add_argument("--max-iters", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world > 1:
+        print("bench.py measures one MI355X: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from mx_inputs import random_rhs
+    from paper_1711_03789_amd import mx
+
+    w, cfg = workload_desc(args.workload)
+    inst = instances(args.workload)
+    ctx = mx.Context(0)
+    n = w.n
+    # inputs resident in HBM before the timed region
+    mesh0 = mx.Mesh(*n, *w.lengths)
+    E = mesh0.n_edge
+    del mesh0
+    rhs = {s: torch.from_numpy(random_rhs(E, s)).cuda() for _, _, s in inst}
+    if args.workload == "small":
+        m0 = mx.Mesh(*n, *w.lengths)
+        rhs[0] = torch.from_numpy(m0.rhs_gaussian(w.center, w.pol, w.sigma)).cuda()
+    x = torch.zeros(E, dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(record):
+        t = time.perf_counter()
+        mesh = mx.Mesh(*n, *w.lengths)
+        part = mx.Partition(mesh, *w.parts, w.layers)
+        t_topo = time.perf_counter() - t
+        rec = []
+        for kind, e, seed in inst:
+            xi = w.k ** e
+            t0 = time.perf_counter()
+            A = mx.Matrix(ctx, mesh, w.k, xi)
+            t1 = time.perf_counter()
+            P = mx.Precond(ctx, A, mesh, part, kind)
+            t2 = time.perf_counter()
+            if record:
+                P.sweep_timing(True)
+            x.zero_()
+            st = mx.gmres(ctx, A, P, rhs[seed], x, restart=w.restart, rtol=w.rtol,
+                          max_iters=args.max_iters)
+            t3 = time.perf_counter()
+            r = {"kind": kind, "xi": xi, "iters": st["iters"], "converged": st["converged"],
+                 "relres": st["relres_true"], "t_assemble": t1 - t0, "t_precond": t2 - t1,
+                 "t_gmres": t3 - t2}
+            inf = P.info()
+            r.update({"t_precond_host": inf["t_host_setup"], "t_upload": inf["t_upload"],
+                      "t_factor": inf["t_factor"], "env_flops": inf["env_flops"],
+                      "tile_flops": inf["tile_flops"], "sweep_bytes": inf["sweep_bytes"],
+                      "apply_bytes": inf["apply_bytes"], "factor_bytes": inf["factor_bytes"]})
+            if record:
+                r["sweep_launches"], r["sweep_ms"] = P.sweep_timing(False)
+            rec.append(r)
+            del P, A
+        return t_topo, rec
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = []
+    for _ in range(args.steps):
+        recs.append(step(True))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_solves = args.steps * len(inst)
+    all_r = [r for _, rr in recs for r in rr]
+    converged = all(r["converged"] for r in all_r)
+    launches = sum(r["sweep_launches"] for r in all_r)
+    sweep_ms = sum(r["sweep_ms"] for r in all_r)
+    sweep_bytes = sum(r["sweep_launches"] * r["sweep_bytes"] for r in all_r)
+    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
+    t_factor = sum(r["t_factor"] for r in all_r)
+    t_gmres = sum(r["t_gmres"] for r in all_r)
+    out = {
+        "metric": "GMRES solves/sec at rtol 1e-6",
+        "value": n_solves / elapsed if converged else 0.0,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "complex128 (fp64)",
+        "data": "synthetic: seeded per-DOF complex Gaussian right-hand sides",
+        "config": cfg,
+        "roofline": {"bound": "hbm", "kernel": "k_sweeps (block forward/backward sweeps of the "
+                                                "Schwarz application)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "launches": launches, "avg_launch_ms": sweep_ms / max(launches, 1),
+                     "bytes_per_launch_avg": sweep_bytes / max(launches, 1)},
+        "factor": {"bound": "mfma", "achieved_env": sum(r["env_flops"] for r in all_r) / t_factor / 1e12,
+                   "achieved_executed": sum(r["tile_flops"] for r in all_r) / t_factor / 1e12,
+                   "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "seconds_total": t_factor},
+        "phase_seconds_per_step": {
+            "mesh_partition": sum(t for t, _ in recs) / args.steps,
+            "assemble": sum(r["t_assemble"] for r in all_r) / args.steps,
+            "precond_host": sum(r["t_precond_host"] for r in all_r) / args.steps,
+            "precond_upload": sum(r["t_upload"] for r in all_r) / args.steps,
+            "factor": t_factor / args.steps,
+            "gmres": t_gmres / args.steps},
+        "solves": [{k: r[k] for k in ("kind", "xi", "iters", "converged", "relres", "t_gmres",
+                                      "t_factor")} for r in recs[0][1]],
+        "all_converged": converged,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sum(r["iters"] for r in recs[0][1]), len(inst))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -217,28 +217,49 @@ __global__ void k_prolong_sum(int64_t E, const int64_t *__restrict__ ptr,
 }
 
 // Reduce 16 per-lane complex partial sums (one per row r of this wave's 16 rows) across the 64
-// lanes; afterwards lanes with (lane & 3) == 0 hold the total of row (lane >> 2).
+// lanes; afterwards lanes with (lane & 3) == 0 hold the total of row (lane >> 2).  Each halving
+// step exchanges the half of the rows the partner keeps (compile-time indices throughout, so the
+// partial sums stay in registers).
+template <typename T, int O, int CNT>
+__device__ __forceinline__ void butterfly_step(cx<T> acc[16]) {
+  constexpr int half = CNT / 2;
+  const bool upper = ((threadIdx.x & 63) & O) != 0;
+#pragma unroll
+  for (int q = 0; q < half; ++q) {
+    cx<T> send = upper ? acc[q] : acc[q + half];
+    cx<T> keep = upper ? acc[q + half] : acc[q];
+    acc[q] = cadd(keep, shfl_xor_c(send, O));
+  }
+}
 template <typename T>
 __device__ __forceinline__ cx<T> butterfly16(cx<T> acc[16]) {
-  const int lane = threadIdx.x & 63;
-  int cnt = 16;
-#pragma unroll
-  for (int o = 32; o >= 4; o >>= 1) {
-    const int half = cnt >> 1;
-    const bool upper = (lane & o) != 0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      if (q < half) {
-        cx<T> send = upper ? acc[q] : acc[q + half];
-        cx<T> keep = upper ? acc[q + half] : acc[q];
-        acc[q] = cadd(keep, shfl_xor_c(send, o));
-      }
-    }
-    cnt = half;
-  }
+  butterfly_step<T, 32, 16>(acc);
+  butterfly_step<T, 16, 8>(acc);
+  butterfly_step<T, 8, 4>(acc);
+  butterfly_step<T, 4, 2>(acc);
   acc[0] = cadd(acc[0], shfl_xor_c(acc[0], 2));
   acc[0] = cadd(acc[0], shfl_xor_c(acc[0], 1));
   return acc[0];
+}
+
+// Wave 0 finds how many consecutive block rows from J (below Jlimit) have published `epoch`:
+// one flag per lane, then a ballot.  When none is ready yet, lane 0 waits (bounded) on flags[J].
+// Returns the end of the ready prefix (> J), or -1 after an expired wait or an abort.
+__device__ inline int ready_prefix(const int *flags, int J, int Jlimit, int epoch, int *abort) {
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    const int cnt = min(64, Jlimit - J);
+    const bool ok = lane < cnt && load_flag(&flags[J + lane]) == epoch;
+    const uint64_t m = __ballot(ok);
+    const uint64_t valid = cnt == 64 ? ~0ull : ((1ull << cnt) - 1);
+    const uint64_t bad = ~m & valid;
+    const int first_bad = bad ? __ffsll((long long)bad) - 1 : cnt;
+    if (first_bad > 0) return J + first_bad;
+    int okw = 1;
+    if (lane == 0) okw = wait_flag(&flags[J], epoch, abort) ? 1 : 0;
+    okw = __shfl(okw, 0);
+    if (!okw) return -1;
+  }
 }
 
 // Persistent forward/backward block sweeps over all subdomains.  Work items (subdomain, block
@@ -248,6 +269,10 @@ __device__ __forceinline__ cx<T> butterfly16(cx<T> acc[16]) {
 // Completion is published per block row with an epoch-tagged flag; waits are bounded.
 //   forward  : y_I = inv(L_II) (r_I - sum_{J<I} L_IJ y_J)
 //   backward : z_J = inv(L_JJ)^T (y_J / D_J - sum_{I>J} L_IJ^T z_I)
+// Memory: tiles are read row by row (lanes along a tile row, coalesced) in both sweeps.
+// Publication: the results of a block are written by wave 0 only, which then performs the
+// agent-scope release and stores the flag; consumers take an agent-scope acquire after seeing
+// the flag.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restrict__ pool,
                                                 const int32_t *__restrict__ sched_sub,
@@ -258,6 +283,7 @@ __global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restri
   __shared__ int s_item;
   __shared__ int s_ok;
   __shared__ cx<T> s_vec[kTile];
+  __shared__ cx<T> s_out[kTile];
   __shared__ cx<T> s_red[4][kTile];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int epoch = ctrl[0];
@@ -283,15 +309,9 @@ __global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restri
       for (int r = 0; r < 16; ++r) acc[r] = {0, 0};
       int J = f;
       while (J < B) {
-        // find the ready prefix [J, Jend) without waiting; wait only if it is empty
-        if (tid == 0) {
-          int Jend = J;
-          while (Jend < B && load_flag(&flags_f[bb + Jend]) == epoch) ++Jend;
-          if (Jend == J) {
-            s_ok = wait_flag(&flags_f[bb + J], epoch, abort) ? J + 1 : -1;
-          } else {
-            s_ok = Jend;
-          }
+        if (w == 0) {
+          const int e = ready_prefix(flags_f + bb, J, B, epoch, abort);
+          if (lane == 0) s_ok = e;
         }
         __syncthreads();
         const int Jend = s_ok;
@@ -301,11 +321,14 @@ __global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restri
         for (; J < Jend; ++J) {
           const cx<T> y = yvec[vb + (int64_t)J * kTile + lane];
           const cx<T> *tp = row + (int64_t)(J - f) * kTileElems + (w * 16) * kTile + lane;
-          cx<T> a[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) a[r] = tp[r * kTile];
+          for (int h = 0; h < 2; ++h) {
+            cx<T> a[8];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) cfma(acc[r], a[r], y);
+            for (int r = 0; r < 8; ++r) a[r] = tp[(h * 8 + r) * kTile];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) cfma(acc[h * 8 + r], a[r], y);
+          }
         }
       }
       cx<T> s = butterfly16(acc);
@@ -318,39 +341,46 @@ __global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restri
       const cx<T> *X = row + (int64_t)(B - f) * kTileElems;
       const cx<T> tm = s_vec[lane];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = w * 16 + r;
-        acc[r] = lane < i ? cmul(X[i * kTile + lane], tm) : cx<T>{0, 0};
+      for (int h = 0; h < 2; ++h) {
+        cx<T> a[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a[r] = X[(w * 16 + h * 8 + r) * kTile + lane];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int i = w * 16 + h * 8 + r;
+          acc[h * 8 + r] = lane < i ? cmul(a[r], tm) : cx<T>{0, 0};
+        }
       }
       s = butterfly16(acc);
       if ((lane & 3) == 0) {
         const int i = w * 16 + (lane >> 2);
-        yvec[vb + (int64_t)B * kTile + i] = cadd(s_vec[i], s);
+        s_out[i] = cadd(s_vec[i], s);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
-      if (tid == 0) store_flag(&flags_f[bb + B], epoch);
+      if (w == 0) {
+        yvec[vb + (int64_t)B * kTile + lane] = s_out[lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) store_flag(&flags_f[bb + B], epoch);
+      }
     } else {
       // ---------------- backward block column B ----------------
       const int last = v.blast[bb + B];
       // z_B depends on y_B (forward) and z_I, I in (B, last]
-      if (tid == 0) s_ok = wait_flag(&flags_f[bb + B], epoch, abort);
+      if (w == 0) {
+        const int e = ready_prefix(flags_f + bb, B, B + 1, epoch, abort);
+        if (lane == 0) s_ok = e;
+      }
       __syncthreads();
       const int ready = s_ok;
       __syncthreads();
-      if (!ready) return;
+      if (ready < 0) return;
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       cx<T> acc = {0, 0};
       int I = B + 1;
       while (I <= last) {
-        if (tid == 0) {
-          int Iend = I;
-          while (Iend <= last && load_flag(&flags_b[bb + Iend]) == epoch) ++Iend;
-          if (Iend == I) {
-            s_ok = wait_flag(&flags_b[bb + I], epoch, abort) ? I + 1 : -1;
-          } else {
-            s_ok = Iend;
-          }
+        if (w == 0) {
+          const int e = ready_prefix(flags_b + bb, I, last + 1, epoch, abort);
+          if (lane == 0) s_ok = e;
         }
         __syncthreads();
         const int Iend = s_ok;
@@ -360,20 +390,23 @@ __global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restri
         for (; I < Iend; ++I) {
           const cx<T> *tp = tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + (w * 16) * kTile + lane;
           const cx<T> *zi = zvec + vb + (int64_t)I * kTile + w * 16;
-          cx<T> a[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) a[r] = tp[r * kTile];
+          for (int h = 0; h < 2; ++h) {
+            cx<T> a[8];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) cfma(acc, a[r], zi[r]);
+            for (int r = 0; r < 8; ++r) a[r] = tp[(h * 8 + r) * kTile];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) cfma(acc, a[r], zi[h * 8 + r]);
+          }
         }
       }
       s_red[w][lane] = acc;
       __syncthreads();
       const cx<T> *X = tile_ptr(const_cast<cx<T> *>(pool), v, l, B, B);
       if (w == 0) {
-        cx<T> s = cadd(cadd(s_red[0][lane], s_red[1][lane]), cadd(s_red[2][lane], s_red[3][lane]));
+        cx<T> t = cadd(cadd(s_red[0][lane], s_red[1][lane]), cadd(s_red[2][lane], s_red[3][lane]));
         const cx<T> d = X[lane * kTile + lane];
-        s_vec[lane] = csub(cdiv(yvec[vb + (int64_t)B * kTile + lane], d), s);
+        s_vec[lane] = csub(cdiv(yvec[vb + (int64_t)B * kTile + lane], d), t);
       }
       __syncthreads();
       // z_B = inv(L_BB)^T s:  z_j = s_j + sum_{i>j} X[i][j] s_i
@@ -386,12 +419,11 @@ __global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restri
       s_red[w][lane] = acc;
       __syncthreads();
       if (w == 0) {
-        cx<T> s = cadd(cadd(s_red[0][lane], s_red[1][lane]), cadd(s_red[2][lane], s_red[3][lane]));
-        zvec[vb + (int64_t)B * kTile + lane] = cadd(s_vec[lane], s);
+        cx<T> t = cadd(cadd(s_red[0][lane], s_red[1][lane]), cadd(s_red[2][lane], s_red[3][lane]));
+        zvec[vb + (int64_t)B * kTile + lane] = cadd(s_vec[lane], t);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) store_flag(&flags_b[bb + B], epoch);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __syncthreads();
-      if (tid == 0) store_flag(&flags_b[bb + B], epoch);
     }
   }
 }
@@ -438,10 +470,21 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
                                                              (const cx<double> *)vin,
                                                              P->d_r.as<cx<T>>(), P->d_ctrl.as<int>());
   int *flags = P->d_flags.as<int>();
+  if (P->timing) {
+    if (P->n_timed == P->ev_start.size()) {
+      hipEvent_t a, b;
+      MX_HIP(hipEventCreate(&a));
+      MX_HIP(hipEventCreate(&b));
+      P->ev_start.push_back(a);
+      P->ev_stop.push_back(b);
+    }
+    MX_HIP(hipEventRecord(P->ev_start[P->n_timed], st));
+  }
   k_sweeps<T><<<P->trsv_grid, 256, 0, st>>>(
       v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(),
       P->n_items, P->n_items / 2, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), flags,
       flags + P->blocks_total, P->d_ctrl.as<int>());
+  if (P->timing) MX_HIP(hipEventRecord(P->ev_stop[P->n_timed++], st));
   const int64_t E = P->E;
   if (P->kind == MX_AS)
     k_prolong_sum<T><<<(unsigned)((E + 255) / 256), 256, 0, st>>>(
@@ -456,6 +499,25 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
   if (P->prec == MX_C128) apply_t<double>(P, vin, zout, st);
   else apply_t<float>(P, vin, zout, st);
+}
+
+void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_total) {
+  if (enable) {
+    P->timing = true;
+    P->n_timed = 0;
+    return;
+  }
+  double tot = 0;
+  for (size_t i = 0; i < P->n_timed; ++i) {
+    MX_HIP(hipEventSynchronize(P->ev_stop[i]));
+    float ms = 0;
+    MX_HIP(hipEventElapsedTime(&ms, P->ev_start[i], P->ev_stop[i]));
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)P->n_timed;
+  if (ms_total) *ms_total = tot;
+  P->timing = false;
+  P->n_timed = 0;
 }
 
 int precond_check(mx_precond *P) {
@@ -726,6 +788,8 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   const int64_t nloc = in.n_local_total;
   in.apply_bytes = (int64_t)(2 * in.env_entries * esz + 6 * nloc * esz + 2 * m.ne * 16 + 4 * nloc +
                              8 * m.ne);
+  // the block-sweep kernel alone: envelope read twice; r read, y written and read, z written
+  in.sweep_bytes = (int64_t)(2 * in.env_entries * esz + 4 * nloc * esz);
   in.t_host_setup = t1 - t0;
   in.t_upload = t2 - t1;
   in.t_factor = t3 - t2;

@@ -28,6 +28,7 @@ SYMBOLS = [
     "mx_partition_sizes", "mx_partition_export", "mx_partition_destroy", "mx_precond_setup",
     "mx_precond_apply", "mx_precond_get_info", "mx_precond_export_perm", "mx_precond_export_diag",
     "mx_precond_check", "mx_precond_destroy", "mx_gmres", "mx_selftest", "mx_local_problem",
+    "mx_precond_sweep_timing",
 ]
 
 
@@ -45,7 +46,8 @@ class PrecondInfo(C.Structure):
     _fields_ = [("n_sub", C.c_int32), ("tile", C.c_int32), ("n_local_total", C.c_int64),
                 ("max_local", C.c_int64), ("max_blocks", C.c_int64), ("tiles", C.c_int64),
                 ("factor_bytes", C.c_int64), ("env_entries", C.c_int64), ("env_flops", C.c_double),
-                ("tile_flops", C.c_double), ("apply_bytes", C.c_int64), ("t_host_setup", C.c_double),
+                ("tile_flops", C.c_double), ("apply_bytes", C.c_int64), ("sweep_bytes", C.c_int64),
+                ("t_host_setup", C.c_double),
                 ("t_upload", C.c_double), ("t_factor", C.c_double)]
 
     def as_dict(self):
@@ -107,6 +109,8 @@ def load(path=LIB_PATH):
         "mx_precond_export_perm": (C.c_int, [P, C.c_int, P, P]),
         "mx_precond_export_diag": (C.c_int, [P, C.c_int, P]),
         "mx_precond_check": (C.c_int, [P]),
+        "mx_precond_sweep_timing": (C.c_int, [P, C.c_int, C.POINTER(C.c_int64),
+                                              C.POINTER(C.c_double)]),
         "mx_precond_destroy": (None, [P]),
         "mx_gmres": (C.c_int, [P, P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresStats), P, P]),
         "mx_selftest": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -291,6 +295,13 @@ class Precond:
 
     def check(self):
         _check(_lib.mx_precond_check(self.h))
+
+    def sweep_timing(self, enable):
+        """enable=True starts per-launch event timing of the sweep kernel; enable=False stops
+        and returns (launches, total_ms)."""
+        n, ms = C.c_int64(), C.c_double()
+        _check(_lib.mx_precond_sweep_timing(self.h, 1 if enable else 0, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
 
     def perm(self, l, n_local):
         perm = np.zeros(n_local, np.int32)
