@@ -13,6 +13,7 @@
 // conjugation; no pivoting is needed for xi != 0 because every principal submatrix of
 // Theta A^l has positive definite imaginary part (coercivity lemma of Sec. 2.3).
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -190,7 +191,8 @@ __global__ void k_restrict(int64_t n, const int32_t *__restrict__ glob,
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p == 0) {
     ctrl[0] += 1;  // epoch of this application
-    ctrl[1] = 0;   // ticket counter
+    ctrl[1] = 0;   // ticket counters of the forward and backward sweeps
+    ctrl[4] = 0;
   }
   if (p < n) {
     int32_t g = glob[p];
@@ -216,12 +218,12 @@ __global__ void k_prolong_sum(int64_t E, const int64_t *__restrict__ ptr,
   out[e] = s;
 }
 
-// Reduce 16 per-lane complex partial sums (one per row r of this wave's 16 rows) across the 64
-// lanes; afterwards lanes with (lane & 3) == 0 hold the total of row (lane >> 2).  Each halving
+// Reduce 8 per-lane complex partial sums (one per row r of this wave's 8 rows) across the 64
+// lanes; afterwards lanes with (lane & 7) == 0 hold the total of row (lane >> 3).  Each halving
 // step exchanges the half of the rows the partner keeps (compile-time indices throughout, so the
 // partial sums stay in registers).
 template <typename T, int O, int CNT>
-__device__ __forceinline__ void butterfly_step(cx<T> acc[16]) {
+__device__ __forceinline__ void butterfly_step(cx<T> acc[8]) {
   constexpr int half = CNT / 2;
   const bool upper = ((threadIdx.x & 63) & O) != 0;
 #pragma unroll
@@ -232,65 +234,80 @@ __device__ __forceinline__ void butterfly_step(cx<T> acc[16]) {
   }
 }
 template <typename T>
-__device__ __forceinline__ cx<T> butterfly16(cx<T> acc[16]) {
-  butterfly_step<T, 32, 16>(acc);
-  butterfly_step<T, 16, 8>(acc);
-  butterfly_step<T, 8, 4>(acc);
-  butterfly_step<T, 4, 2>(acc);
+__device__ __forceinline__ cx<T> butterfly8(cx<T> acc[8]) {
+  butterfly_step<T, 32, 8>(acc);
+  butterfly_step<T, 16, 4>(acc);
+  butterfly_step<T, 8, 2>(acc);
+  acc[0] = cadd(acc[0], shfl_xor_c(acc[0], 4));
   acc[0] = cadd(acc[0], shfl_xor_c(acc[0], 2));
   acc[0] = cadd(acc[0], shfl_xor_c(acc[0], 1));
   return acc[0];
 }
 
-// Wave 0 finds how many consecutive block rows from J (below Jlimit) have published `epoch`:
-// one flag per lane, then a ballot.  When none is ready yet, lane 0 waits (bounded) on flags[J].
-// Returns the end of the ready prefix (> J), or -1 after an expired wait or an abort.
-__device__ inline int ready_prefix(const int *flags, int J, int Jlimit, int epoch, int *abort) {
+// Wave-level scan of completion flags.  Starting at J and moving by `step` (+1 or -1) towards
+// (exclusive) Jlimit, finds how many consecutive block rows have published `epoch`: one flag per
+// lane, then a ballot.  When none is ready yet, lane 0 waits (bounded) on flags[J].  Returns the
+// first not-yet-checked row (!= J), or INT_MIN after an expired wait or an abort.
+__device__ inline int ready_run(const int *flags, int J, int Jlimit, int step, int epoch, int *abort) {
   const int lane = threadIdx.x & 63;
   while (true) {
-    const int cnt = min(64, Jlimit - J);
-    const bool ok = lane < cnt && load_flag(&flags[J + lane]) == epoch;
+    const int cnt = min(64, (Jlimit - J) * step);
+    const bool ok = lane < cnt && load_flag(&flags[J + step * lane]) == epoch;
     const uint64_t m = __ballot(ok);
     const uint64_t valid = cnt == 64 ? ~0ull : ((1ull << cnt) - 1);
     const uint64_t bad = ~m & valid;
     const int first_bad = bad ? __ffsll((long long)bad) - 1 : cnt;
-    if (first_bad > 0) return J + first_bad;
+    if (first_bad > 0) return J + step * first_bad;
     int okw = 1;
     if (lane == 0) okw = wait_flag(&flags[J], epoch, abort) ? 1 : 0;
     okw = __shfl(okw, 0);
-    if (!okw) return -1;
+    if (!okw) return INT_MIN;
   }
 }
 
-// Persistent forward/backward block sweeps over all subdomains.  Work items (subdomain, block
-// row, direction) are handed out by an atomic ticket in a fixed order in which every item comes
-// after all items it depends on (forward rows of a subdomain ascending, then backward rows
-// descending), so a workgroup only ever waits for tickets already taken by running workgroups.
-// Completion is published per block row with an epoch-tagged flag; waits are bounded.
-//   forward  : y_I = inv(L_II) (r_I - sum_{J<I} L_IJ y_J)
-//   backward : z_J = inv(L_JJ)^T (y_J / D_J - sum_{I>J} L_IJ^T z_I)
-// Memory: tiles are read row by row (lanes along a tile row, coalesced) in both sweeps.
-// Publication: the results of a block are written by wave 0 only, which then performs the
-// agent-scope release and stores the flag; consumers take an agent-scope acquire after seeing
-// the flag.
+constexpr int kSweepWaves = 8;              // 512-thread workgroups, 8 tile rows per wave
+constexpr int kSweepThreads = 64 * kSweepWaves;
+constexpr int kRows = kTile / kSweepWaves;  // = 8
+// complex double sweeps keep their prefetched tiles in up to 256 registers (one workgroup per
+// CU); complex float ones fit two workgroups per CU
 template <typename T>
-__global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restrict__ pool,
-                                                const int32_t *__restrict__ sched_sub,
-                                                const int32_t *__restrict__ sched_blk, int n_items,
-                                                int n_fwd, const cx<T> *__restrict__ rvec,
-                                                cx<T> *yvec, cx<T> *zvec, int *flags_f,
-                                                int *flags_b, int *ctrl) {
+struct SweepMinWaves {
+  static constexpr int value = sizeof(T) == 8 ? 2 : 4;
+};
+
+// Block sweeps of all subdomains in one persistent launch per direction.  Work items
+// (subdomain, block row) are handed out by an atomic ticket in an order in which every item
+// comes after all items it depends on (a subdomain's rows ascending for the forward sweep,
+// descending for the backward one), so a workgroup only ever waits for tickets already taken by
+// running workgroups.  Completion is published per block row with an epoch-tagged flag; all waits
+// are bounded.
+//   forward  (FWD): y_I = inv(L_II) (r_I - sum_{J<I} L_IJ y_J)
+//   backward      : z_J = inv(L_JJ)^T (y_J / D_J - sum_{I>J} L_IJ^T z_I)
+// Tiles are read row by row with the lanes along a tile row (coalesced) in both directions.  The
+// tiles needed right after the last dependency (the neighbour tile and the diagonal tile) are
+// loaded into registers before waiting for it, so the dependency chain carries no tile loads.
+// Results of a block are written by wave 0 only, which performs the agent-scope release and stores
+// the flag; readers take an agent-scope acquire after seeing a flag.
+template <typename T, bool FWD>
+__global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_sweep(SubView v, const cx<T> *__restrict__ pool,
+                                                         const int32_t *__restrict__ sched_sub,
+                                                         const int32_t *__restrict__ sched_blk,
+                                                         int n_items, const cx<T> *__restrict__ rvec,
+                                                         cx<T> *yvec, cx<T> *zvec, int *flags,
+                                                         int *ctrl) {
   __shared__ int s_item;
   __shared__ int s_ok;
   __shared__ cx<T> s_vec[kTile];
   __shared__ cx<T> s_out[kTile];
-  __shared__ cx<T> s_red[4][kTile];
+  __shared__ cx<T> s_red[kSweepWaves][kTile];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int row0 = w * kRows;  // this wave's first row inside a tile
   const int epoch = ctrl[0];
   int *abort = &ctrl[2];
+  int *ticket = &ctrl[FWD ? 1 : 4];
   while (true) {
     if (tid == 0) {
-      int t = __hip_atomic_fetch_add(&ctrl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       s_item = load_flag(abort) ? n_items : t;
     }
     __syncthreads();
@@ -300,129 +317,183 @@ __global__ __launch_bounds__(256) void k_sweeps(SubView v, const cx<T> *__restri
     const int l = sched_sub[item], B = sched_blk[item];
     const int bb = v.brow_base[l];
     const int64_t vb = v.vec_base[l];
-    if (item < n_fwd) {
-      // ---------------- forward block row B ----------------
+    int *fl = flags + bb;
+    if (FWD) {
       const int f = v.bfirst[bb + B];
       const cx<T> *row = pool + (v.tile_base[l] + v.brow_off[bb + B]) * (int64_t)kTileElems;
-      cx<T> acc[16];
+      const cx<T> *X = row + (int64_t)(B - f) * kTileElems + row0 * kTile + lane;
+      const bool has_prev = B - 1 >= f;
+      const cx<T> *Lp = row + (int64_t)(B - 1 - f) * kTileElems + row0 * kTile + lane;
+      cx<T> aX[kRows], aL[kRows], acc[kRows];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = {0, 0};
+      for (int r = 0; r < kRows; ++r) {
+        aX[r] = X[r * kTile];
+        aL[r] = has_prev ? Lp[r * kTile] : cx<T>{0, 0};
+        acc[r] = {0, 0};
+      }
+      const cx<T> rB = rvec[vb + (int64_t)B * kTile + (lane & 63)];
       int J = f;
-      while (J < B) {
+      while (J < B - 1) {
         if (w == 0) {
-          const int e = ready_prefix(flags_f + bb, J, B, epoch, abort);
+          const int e = ready_run(fl, J, B - 1, 1, epoch, abort);
           if (lane == 0) s_ok = e;
         }
         __syncthreads();
         const int Jend = s_ok;
         __syncthreads();
-        if (Jend < 0) return;
+        if (Jend == INT_MIN) return;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        for (; J < Jend; ++J) {
-          const cx<T> y = yvec[vb + (int64_t)J * kTile + lane];
-          const cx<T> *tp = row + (int64_t)(J - f) * kTileElems + (w * 16) * kTile + lane;
+        for (; J + 1 < Jend; J += 2) {
+          const cx<T> y0 = yvec[vb + (int64_t)J * kTile + lane];
+          const cx<T> y1 = yvec[vb + (int64_t)(J + 1) * kTile + lane];
+          const cx<T> *tp = row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane;
+          cx<T> a0[kRows], a1[kRows];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            cx<T> a[8];
+          for (int r = 0; r < kRows; ++r) {
+            a0[r] = tp[r * kTile];
+            a1[r] = tp[kTileElems + r * kTile];
+          }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) a[r] = tp[(h * 8 + r) * kTile];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) cfma(acc[h * 8 + r], a[r], y);
+          for (int r = 0; r < kRows; ++r) {
+            cfma(acc[r], a0[r], y0);
+            cfma(acc[r], a1[r], y1);
           }
         }
-      }
-      cx<T> s = butterfly16(acc);
-      if ((lane & 3) == 0) {
-        const int i = w * 16 + (lane >> 2);
-        s_vec[i] = csub(rvec[vb + (int64_t)B * kTile + i], s);
-      }
-      __syncthreads();
-      // y_B = inv(L_BB) t  (unit lower: y_i = t_i + sum_{m<i} X[i][m] t_m)
-      const cx<T> *X = row + (int64_t)(B - f) * kTileElems;
-      const cx<T> tm = s_vec[lane];
+        if (J < Jend) {
+          const cx<T> y0 = yvec[vb + (int64_t)J * kTile + lane];
+          const cx<T> *tp = row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane;
+          cx<T> a0[kRows];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        cx<T> a[8];
+          for (int r = 0; r < kRows; ++r) a0[r] = tp[r * kTile];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) a[r] = X[(w * 16 + h * 8 + r) * kTile + lane];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int i = w * 16 + h * 8 + r;
-          acc[h * 8 + r] = lane < i ? cmul(a[r], tm) : cx<T>{0, 0};
+          for (int r = 0; r < kRows; ++r) cfma(acc[r], a0[r], y0);
+          ++J;
         }
       }
-      s = butterfly16(acc);
-      if ((lane & 3) == 0) {
-        const int i = w * 16 + (lane >> 2);
-        s_out[i] = cadd(s_vec[i], s);
+      if (has_prev) {
+        if (w == 0) {
+          const int e = ready_run(fl, B - 1, B, 1, epoch, abort);
+          if (lane == 0) s_ok = e;
+        }
+        __syncthreads();
+        const int ok = s_ok;
+        __syncthreads();
+        if (ok == INT_MIN) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const cx<T> y0 = yvec[vb + (int64_t)(B - 1) * kTile + lane];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) cfma(acc[r], aL[r], y0);
       }
+      cx<T> s = butterfly8(acc);
+      if ((lane & 7) == 0) s_vec[row0 + (lane >> 3)] = s;
+      __syncthreads();
+      // t = r_B - s;  y_B = inv(L_BB) t  (unit lower: y_i = t_i + sum_{m<i} X[i][m] t_m)
+      const cx<T> tm = csub(rB, s_vec[lane]);
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) acc[r] = lane < row0 + r ? cmul(aX[r], tm) : cx<T>{0, 0};
+      s = butterfly8(acc);
+      if ((lane & 7) == 0) s_out[row0 + (lane >> 3)] = s;
       __syncthreads();
       if (w == 0) {
-        yvec[vb + (int64_t)B * kTile + lane] = s_out[lane];
+        yvec[vb + (int64_t)B * kTile + lane] = cadd(tm, s_out[lane]);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) store_flag(&flags_f[bb + B], epoch);
+        if (lane == 0) store_flag(&fl[B], epoch);
       }
     } else {
-      // ---------------- backward block column B ----------------
       const int last = v.blast[bb + B];
-      // z_B depends on y_B (forward) and z_I, I in (B, last]
-      if (w == 0) {
-        const int e = ready_prefix(flags_f + bb, B, B + 1, epoch, abort);
-        if (lane == 0) s_ok = e;
+      const cx<T> *X = tile_ptr(const_cast<cx<T> *>(pool), v, l, B, B);
+      const bool has_next = B + 1 <= last;
+      cx<T> aX[kRows], aL[kRows];
+      {
+        const cx<T> *xp = X + row0 * kTile + lane;
+        const cx<T> *lp = has_next ? tile_ptr(const_cast<cx<T> *>(pool), v, l, B + 1, B) + row0 * kTile + lane
+                                   : xp;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+          aX[r] = xp[r * kTile];
+          aL[r] = has_next ? lp[r * kTile] : cx<T>{0, 0};
+        }
       }
-      __syncthreads();
-      const int ready = s_ok;
-      __syncthreads();
-      if (ready < 0) return;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const cx<T> dB = X[lane * kTile + lane];
+      const cx<T> yB = yvec[vb + (int64_t)B * kTile + lane];
       cx<T> acc = {0, 0};
-      int I = B + 1;
-      while (I <= last) {
+      // rows far below B finish first: consume I = last, last-1, ..., B+2 as they become ready
+      int I = last;
+      while (I > B + 1) {
         if (w == 0) {
-          const int e = ready_prefix(flags_b + bb, I, last + 1, epoch, abort);
+          const int e = ready_run(fl, I, B + 1, -1, epoch, abort);
           if (lane == 0) s_ok = e;
         }
         __syncthreads();
         const int Iend = s_ok;
         __syncthreads();
-        if (Iend < 0) return;
+        if (Iend == INT_MIN) return;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        for (; I < Iend; ++I) {
-          const cx<T> *tp = tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + (w * 16) * kTile + lane;
-          const cx<T> *zi = zvec + vb + (int64_t)I * kTile + w * 16;
+        for (; I - 1 > Iend; I -= 2) {
+          const cx<T> *t0 = tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + row0 * kTile + lane;
+          const cx<T> *t1 = tile_ptr(const_cast<cx<T> *>(pool), v, l, I - 1, B) + row0 * kTile + lane;
+          const cx<T> *z0 = zvec + vb + (int64_t)I * kTile + row0;
+          const cx<T> *z1 = zvec + vb + (int64_t)(I - 1) * kTile + row0;
+          cx<T> a0[kRows], a1[kRows];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            cx<T> a[8];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) a[r] = tp[(h * 8 + r) * kTile];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) cfma(acc, a[r], zi[h * 8 + r]);
+          for (int r = 0; r < kRows; ++r) {
+            a0[r] = t0[r * kTile];
+            a1[r] = t1[r * kTile];
           }
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) cfma(acc, a0[r], z0[r]);
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) cfma(acc, a1[r], z1[r]);
         }
+        if (I > Iend) {
+          const cx<T> *t0 = tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + row0 * kTile + lane;
+          const cx<T> *z0 = zvec + vb + (int64_t)I * kTile + row0;
+          cx<T> a0[kRows];
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) a0[r] = t0[r * kTile];
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) cfma(acc, a0[r], z0[r]);
+          --I;
+        }
+      }
+      if (has_next) {
+        if (w == 0) {
+          const int e = ready_run(fl, B + 1, B, -1, epoch, abort);
+          if (lane == 0) s_ok = e;
+        }
+        __syncthreads();
+        const int ok = s_ok;
+        __syncthreads();
+        if (ok == INT_MIN) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const cx<T> *z0 = zvec + vb + (int64_t)(B + 1) * kTile + row0;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) cfma(acc, aL[r], z0[r]);
       }
       s_red[w][lane] = acc;
       __syncthreads();
-      const cx<T> *X = tile_ptr(const_cast<cx<T> *>(pool), v, l, B, B);
       if (w == 0) {
-        cx<T> t = cadd(cadd(s_red[0][lane], s_red[1][lane]), cadd(s_red[2][lane], s_red[3][lane]));
-        const cx<T> d = X[lane * kTile + lane];
-        s_vec[lane] = csub(cdiv(yvec[vb + (int64_t)B * kTile + lane], d), t);
+        cx<T> t = s_red[0][lane];
+#pragma unroll
+        for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
+        s_vec[lane] = csub(cdiv(yB, dB), t);
       }
       __syncthreads();
       // z_B = inv(L_BB)^T s:  z_j = s_j + sum_{i>j} X[i][j] s_i
       acc = {0, 0};
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = w * 16 + r;
-        if (i > lane) cfma(acc, X[i * kTile + lane], s_vec[i]);
-      }
+      for (int r = 0; r < kRows; ++r)
+        if (row0 + r > lane) cfma(acc, aX[r], s_vec[row0 + r]);
+      __syncthreads();
       s_red[w][lane] = acc;
       __syncthreads();
       if (w == 0) {
-        cx<T> t = cadd(cadd(s_red[0][lane], s_red[1][lane]), cadd(s_red[2][lane], s_red[3][lane]));
+        cx<T> t = s_red[0][lane];
+#pragma unroll
+        for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
         zvec[vb + (int64_t)B * kTile + lane] = cadd(s_vec[lane], t);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) store_flag(&flags_b[bb + B], epoch);
+        if (lane == 0) store_flag(&fl[B], epoch);
       }
     }
   }
@@ -480,10 +551,14 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
     }
     MX_HIP(hipEventRecord(P->ev_start[P->n_timed], st));
   }
-  k_sweeps<T><<<P->trsv_grid, 256, 0, st>>>(
-      v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(),
-      P->n_items, P->n_items / 2, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), flags,
-      flags + P->blocks_total, P->d_ctrl.as<int>());
+  const int half = P->n_items / 2;
+  k_sweep<T, true><<<P->trsv_grid, kSweepThreads, 0, st>>>(
+      v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(), half,
+      P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), flags, P->d_ctrl.as<int>());
+  k_sweep<T, false><<<P->trsv_grid, kSweepThreads, 0, st>>>(
+      v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>() + half,
+      P->d_sched_blk.as<int32_t>() + half, half, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
+      P->d_z.as<cx<T>>(), flags + P->blocks_total, P->d_ctrl.as<int>());
   if (P->timing) MX_HIP(hipEventRecord(P->ev_stop[P->n_timed++], st));
   const int64_t E = P->E;
   if (P->kind == MX_AS)
@@ -704,7 +779,15 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
       sched_blk.push_back(it.b);
     }
   P->n_items = (int)sched_sub.size();
-  P->trsv_grid = std::max(1, std::min(P->n_items / 2, 4 * ctx->cus));
+  {
+    // persistent sweeps: as many workgroups as can be resident at once
+    int per_cu = 1;
+    if (P->prec == MX_C128)
+      MX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<double, true>, kSweepThreads, 0));
+    else
+      MX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<float, true>, kSweepThreads, 0));
+    P->trsv_grid = std::max(1, std::min(P->n_items / 2, std::max(1, per_cu) * ctx->cus));
+  }
   const double t1 = now_s();
 
   // device buffers
