@@ -268,8 +268,8 @@ __device__ inline int ready_run(const int *flags, int J, int Jlimit, int step, i
 constexpr int kSweepWaves = 8;              // 512-thread workgroups, 8 tile rows per wave
 constexpr int kSweepThreads = 64 * kSweepWaves;
 constexpr int kRows = kTile / kSweepWaves;  // = 8
-// complex double sweeps keep their prefetched tiles in up to 256 registers (one workgroup per
-// CU); complex float ones fit two workgroups per CU
+// complex double sweeps stage 128 KB of tiles in LDS and run one workgroup per CU; complex
+// float ones (64 KB) fit two workgroups per CU
 template <typename T>
 struct SweepMinWaves {
   static constexpr int value = sizeof(T) == 8 ? 2 : 4;
@@ -283,20 +283,60 @@ struct SweepMinWaves {
 // are bounded.
 //   forward  (FWD): y_I = inv(L_II) (r_I - sum_{J<I} L_IJ y_J)
 //   backward      : z_J = inv(L_JJ)^T (y_J / D_J - sum_{I>J} L_IJ^T z_I)
-// Tiles are read row by row with the lanes along a tile row (coalesced) in both directions.  The
-// tiles needed right after the last dependency (the neighbour tile and the diagonal tile) are
-// loaded into registers before waiting for it, so the dependency chain carries no tile loads.
-// Results of a block are written by wave 0 only, which performs the agent-scope release and stores
-// the flag; readers take an agent-scope acquire after seeing a flag.
+// Tiles are read row by row with the lanes along a tile row (coalesced) in both directions, up to
+// four tiles per wave in flight.  The two tiles needed right after the last dependency (the
+// neighbour tile and the diagonal tile) are staged in LDS when the item starts, so the dependency
+// chain itself carries no tile loads.  Results of a block are written by wave 0 only, which
+// performs the agent-scope release and stores the flag; readers take an agent-scope acquire after
+// seeing a flag.
+template <typename T, int NT>
+__device__ __forceinline__ void stream_fwd(const cx<T> *tp, const cx<T> *yp, cx<T> acc[kRows]) {
+  // NT consecutive tiles of a block row starting at tp; yp = y of the first one (lane's column)
+  cx<T> a[NT][kRows], y[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    y[t] = yp[t * kTile];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) a[t][r] = tp[(int64_t)t * kTileElems + r * kTile];
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) cfma(acc[r], a[t][r], y[t]);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> bcast(cx<T> v, int src) {
+  return {__shfl(v.re, src), __shfl(v.im, src)};
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void stream_bwd(const cx<T> *const tp[NT], const cx<T> *const zp[NT],
+                                           cx<T> &acc) {
+  // NT tiles of a block column; zp[t] = z rows of this wave (8 values, lanes 0..7 load them)
+  const int lane = threadIdx.x & 63;
+  cx<T> a[NT][kRows], z[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    z[t] = zp[t][lane & (kRows - 1)];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) a[t][r] = tp[t][r * kTile];
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) cfma(acc, a[t][r], bcast(z[t], r));
+}
+
 template <typename T, bool FWD>
-__global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_sweep(SubView v, const cx<T> *__restrict__ pool,
-                                                         const int32_t *__restrict__ sched_sub,
-                                                         const int32_t *__restrict__ sched_blk,
-                                                         int n_items, const cx<T> *__restrict__ rvec,
-                                                         cx<T> *yvec, cx<T> *zvec, int *flags,
-                                                         int *ctrl) {
+__global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_sweep(
+    SubView v, const cx<T> *__restrict__ pool, const int32_t *__restrict__ sched_sub,
+    const int32_t *__restrict__ sched_blk, int n_items, const cx<T> *__restrict__ rvec, cx<T> *yvec,
+    cx<T> *zvec, int *flags, int *ctrl) {
   __shared__ int s_item;
   __shared__ int s_ok;
+  __shared__ cx<T> sL[kTile][kTile];  // neighbour tile of the last dependency
+  __shared__ cx<T> sX[kTile][kTile];  // diagonal tile (inverse unit-lower factor, D on the diagonal)
   __shared__ cx<T> s_vec[kTile];
   __shared__ cx<T> s_out[kTile];
   __shared__ cx<T> s_red[kSweepWaves][kTile];
@@ -321,17 +361,20 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
     if (FWD) {
       const int f = v.bfirst[bb + B];
       const cx<T> *row = pool + (v.tile_base[l] + v.brow_off[bb + B]) * (int64_t)kTileElems;
-      const cx<T> *X = row + (int64_t)(B - f) * kTileElems + row0 * kTile + lane;
       const bool has_prev = B - 1 >= f;
-      const cx<T> *Lp = row + (int64_t)(B - 1 - f) * kTileElems + row0 * kTile + lane;
-      cx<T> aX[kRows], aL[kRows], acc[kRows];
+      {  // stage the diagonal tile and the (B, B-1) tile
+        const cx<T> *xp = row + (int64_t)(B - f) * kTileElems + row0 * kTile + lane;
+        const cx<T> *lp = row + (int64_t)(B - 1 - f) * kTileElems + row0 * kTile + lane;
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) {
-        aX[r] = X[r * kTile];
-        aL[r] = has_prev ? Lp[r * kTile] : cx<T>{0, 0};
-        acc[r] = {0, 0};
+        for (int r = 0; r < kRows; ++r) {
+          sX[row0 + r][lane] = xp[r * kTile];
+          sL[row0 + r][lane] = has_prev ? lp[r * kTile] : cx<T>{0, 0};
+        }
       }
-      const cx<T> rB = rvec[vb + (int64_t)B * kTile + (lane & 63)];
+      cx<T> acc[kRows];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) acc[r] = {0, 0};
+      const cx<T> rB = rvec[vb + (int64_t)B * kTile + lane];
       int J = f;
       while (J < B - 1) {
         if (w == 0) {
@@ -343,46 +386,27 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
         __syncthreads();
         if (Jend == INT_MIN) return;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        for (; J + 1 < Jend; J += 2) {
-          const cx<T> y0 = yvec[vb + (int64_t)J * kTile + lane];
-          const cx<T> y1 = yvec[vb + (int64_t)(J + 1) * kTile + lane];
-          const cx<T> *tp = row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane;
-          cx<T> a0[kRows], a1[kRows];
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) {
-            a0[r] = tp[r * kTile];
-            a1[r] = tp[kTileElems + r * kTile];
-          }
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) {
-            cfma(acc[r], a0[r], y0);
-            cfma(acc[r], a1[r], y1);
-          }
-        }
-        if (J < Jend) {
-          const cx<T> y0 = yvec[vb + (int64_t)J * kTile + lane];
-          const cx<T> *tp = row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane;
-          cx<T> a0[kRows];
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) a0[r] = tp[r * kTile];
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) cfma(acc[r], a0[r], y0);
-          ++J;
-        }
+        for (; J + 3 < Jend; J += 4)
+          stream_fwd<T, 4>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
+                           yvec + vb + (int64_t)J * kTile + lane, acc);
+        for (; J < Jend; ++J)
+          stream_fwd<T, 1>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
+                           yvec + vb + (int64_t)J * kTile + lane, acc);
       }
       if (has_prev) {
         if (w == 0) {
           const int e = ready_run(fl, B - 1, B, 1, epoch, abort);
           if (lane == 0) s_ok = e;
         }
-        __syncthreads();
+      }
+      __syncthreads();  // also makes the staged tiles visible
+      if (has_prev) {
         const int ok = s_ok;
-        __syncthreads();
         if (ok == INT_MIN) return;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const cx<T> y0 = yvec[vb + (int64_t)(B - 1) * kTile + lane];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) cfma(acc[r], aL[r], y0);
+        for (int r = 0; r < kRows; ++r) cfma(acc[r], sL[row0 + r][lane], y0);
       }
       cx<T> s = butterfly8(acc);
       if ((lane & 7) == 0) s_vec[row0 + (lane >> 3)] = s;
@@ -390,7 +414,8 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       // t = r_B - s;  y_B = inv(L_BB) t  (unit lower: y_i = t_i + sum_{m<i} X[i][m] t_m)
       const cx<T> tm = csub(rB, s_vec[lane]);
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) acc[r] = lane < row0 + r ? cmul(aX[r], tm) : cx<T>{0, 0};
+      for (int r = 0; r < kRows; ++r)
+        acc[r] = lane < row0 + r ? cmul(sX[row0 + r][lane], tm) : cx<T>{0, 0};
       s = butterfly8(acc);
       if ((lane & 7) == 0) s_out[row0 + (lane >> 3)] = s;
       __syncthreads();
@@ -403,15 +428,14 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       const int last = v.blast[bb + B];
       const cx<T> *X = tile_ptr(const_cast<cx<T> *>(pool), v, l, B, B);
       const bool has_next = B + 1 <= last;
-      cx<T> aX[kRows], aL[kRows];
-      {
+      {  // stage the diagonal tile and the (B+1, B) tile
         const cx<T> *xp = X + row0 * kTile + lane;
         const cx<T> *lp = has_next ? tile_ptr(const_cast<cx<T> *>(pool), v, l, B + 1, B) + row0 * kTile + lane
                                    : xp;
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-          aX[r] = xp[r * kTile];
-          aL[r] = has_next ? lp[r * kTile] : cx<T>{0, 0};
+          sX[row0 + r][lane] = xp[r * kTile];
+          sL[row0 + r][lane] = has_next ? lp[r * kTile] : cx<T>{0, 0};
         }
       }
       const cx<T> dB = X[lane * kTile + lane];
@@ -429,31 +453,19 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
         __syncthreads();
         if (Iend == INT_MIN) return;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        for (; I - 1 > Iend; I -= 2) {
-          const cx<T> *t0 = tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + row0 * kTile + lane;
-          const cx<T> *t1 = tile_ptr(const_cast<cx<T> *>(pool), v, l, I - 1, B) + row0 * kTile + lane;
-          const cx<T> *z0 = zvec + vb + (int64_t)I * kTile + row0;
-          const cx<T> *z1 = zvec + vb + (int64_t)(I - 1) * kTile + row0;
-          cx<T> a0[kRows], a1[kRows];
+        for (; I - 3 > Iend; I -= 4) {
+          const cx<T> *tp[4], *zp[4];
 #pragma unroll
-          for (int r = 0; r < kRows; ++r) {
-            a0[r] = t0[r * kTile];
-            a1[r] = t1[r * kTile];
+          for (int t = 0; t < 4; ++t) {
+            tp[t] = tile_ptr(const_cast<cx<T> *>(pool), v, l, I - t, B) + row0 * kTile + lane;
+            zp[t] = zvec + vb + (int64_t)(I - t) * kTile + row0;
           }
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) cfma(acc, a0[r], z0[r]);
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) cfma(acc, a1[r], z1[r]);
+          stream_bwd<T, 4>(tp, zp, acc);
         }
-        if (I > Iend) {
-          const cx<T> *t0 = tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + row0 * kTile + lane;
-          const cx<T> *z0 = zvec + vb + (int64_t)I * kTile + row0;
-          cx<T> a0[kRows];
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) a0[r] = t0[r * kTile];
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) cfma(acc, a0[r], z0[r]);
-          --I;
+        for (; I > Iend; --I) {
+          const cx<T> *tp[1] = {tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + row0 * kTile + lane};
+          const cx<T> *zp[1] = {zvec + vb + (int64_t)I * kTile + row0};
+          stream_bwd<T, 1>(tp, zp, acc);
         }
       }
       if (has_next) {
@@ -461,14 +473,15 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
           const int e = ready_run(fl, B + 1, B, -1, epoch, abort);
           if (lane == 0) s_ok = e;
         }
-        __syncthreads();
+      }
+      __syncthreads();  // also makes the staged tiles visible
+      if (has_next) {
         const int ok = s_ok;
-        __syncthreads();
         if (ok == INT_MIN) return;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const cx<T> *z0 = zvec + vb + (int64_t)(B + 1) * kTile + row0;
+        const cx<T> zv = zvec[vb + (int64_t)(B + 1) * kTile + row0 + (lane & (kRows - 1))];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) cfma(acc, aL[r], z0[r]);
+        for (int r = 0; r < kRows; ++r) cfma(acc, sL[row0 + r][lane], bcast(zv, r));
       }
       s_red[w][lane] = acc;
       __syncthreads();
@@ -483,8 +496,7 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       acc = {0, 0};
 #pragma unroll
       for (int r = 0; r < kRows; ++r)
-        if (row0 + r > lane) cfma(acc, aX[r], s_vec[row0 + r]);
-      __syncthreads();
+        if (row0 + r > lane) cfma(acc, sX[row0 + r][lane], s_vec[row0 + r]);
       s_red[w][lane] = acc;
       __syncthreads();
       if (w == 0) {
