@@ -119,6 +119,7 @@ typedef struct {
   int kind;        /* MX_AS | MX_RAS | MX_ORAS                                                */
   double xi_prec;  /* absorption of the local problems (ORAS local assembly; AS/RAS use A's)  */
   int precision;   /* MX_C128 | MX_C64 (local factors and local solves)                       */
+  int sweep_grid;  /* workgroups of the persistent sweep kernels; 0 = as many as fit at once  */
 } mx_precond_opts;
 
 /* Host-only view of one local problem, as mx_precond_setup builds it (for inspection and

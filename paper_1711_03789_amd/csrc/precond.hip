@@ -798,7 +798,8 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
       MX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<double, true>, kSweepThreads, 0));
     else
       MX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<float, true>, kSweepThreads, 0));
-    P->trsv_grid = std::max(1, std::min(P->n_items / 2, std::max(1, per_cu) * ctx->cus));
+    int grid = opts->sweep_grid > 0 ? opts->sweep_grid : std::max(1, per_cu) * ctx->cus;
+    P->trsv_grid = std::max(1, std::min(P->n_items / 2, grid));
   }
   const double t1 = now_s();
 
