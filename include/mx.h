@@ -119,7 +119,7 @@ typedef struct {
   int kind;        /* MX_AS | MX_RAS | MX_ORAS                                                */
   double xi_prec;  /* absorption of the local problems (ORAS local assembly; AS/RAS use A's)  */
   int precision;   /* MX_C128 | MX_C64 (local factors and local solves)                       */
-  int sweep_grid;  /* workgroups of the persistent sweep kernels; 0 = as many as fit at once  */
+  int sweep_grid;  /* workgroups of the persistent sweep kernels; 0 = one per compute unit      */
 } mx_precond_opts;
 
 /* Host-only view of one local problem, as mx_precond_setup builds it (for inspection and
@@ -142,8 +142,8 @@ typedef struct {
   double env_flops;             /* 8 * sum_i w_i^2 / 2 real flops (envelope LDL^T)             */
   double tile_flops;            /* real flops of the blocked factorisation as executed         */
   int64_t apply_bytes;          /* algorithmic bytes of one application (see mx_precond_apply)*/
-  int64_t sweep_bytes;          /* algorithmic bytes of one block-sweep launch: the envelope    */
-                                /* factor read twice, local r read, y written and read, z written*/
+  int64_t sweep_bytes;          /* algorithmic bytes of one block-sweep launch (either direction):*/
+                                /* the envelope factor read once and three local-vector passes   */
   double t_host_setup, t_upload, t_factor; /* seconds of the last mx_precond_setup phases      */
 } mx_precond_info;
 
@@ -165,11 +165,13 @@ int mx_precond_get_info(const mx_precond *P, mx_precond_info *info);
 int mx_precond_export_perm(const mx_precond *P, int l, int32_t *perm, int32_t *first);
 /* Host copy of the factored diagonal D of subdomain l (complex128[n_l], permuted order). */
 int mx_precond_export_diag(const mx_precond *P, int l, double *d);
-/* Per-launch timing of the block-sweep kernel (the dominant kernel of an application) with HIP
- * events recorded on the launch stream around each launch.  enable = 1 clears earlier records
- * and starts recording; enable = 0 stops, waits for the recorded events and returns the number
- * of timed launches and their summed duration in milliseconds.  Errors: MX_EINVAL, MX_EDEVICE. */
-int mx_precond_sweep_timing(mx_precond *P, int enable, int64_t *launches, double *ms_total);
+/* Per-launch timing of the two block-sweep kernels (forward and backward; together the dominant
+ * work of an application) with HIP events recorded on the launch stream around each launch.
+ * enable = 1 clears earlier records and starts recording; enable = 0 stops, waits for the
+ * recorded events and returns the number of timed applications and the summed durations of the
+ * forward and of the backward launches, in milliseconds.  Errors: MX_EINVAL, MX_EDEVICE. */
+int mx_precond_sweep_timing(mx_precond *P, int enable, int64_t *launches, double *ms_forward,
+                            double *ms_backward);
 /* Checks the device error word of P (set by a failed pivot or an expired wait). */
 int mx_precond_check(mx_precond *P);
 void mx_precond_destroy(mx_precond *P);

@@ -302,11 +302,12 @@ int mx_precond_export_diag(const mx_precond *P, int l, double *d) {
   });
 }
 
-int mx_precond_sweep_timing(mx_precond *P, int enable, int64_t *launches, double *ms_total) {
+int mx_precond_sweep_timing(mx_precond *P, int enable, int64_t *launches, double *ms_forward,
+                            double *ms_backward) {
   MX_GUARD({
     MX_REQUIRE(P, "NULL argument");
     bind_device(P->device);
-    mx::precond_timing(P, enable, launches, ms_total);
+    mx::precond_timing(P, enable, launches, ms_forward, ms_backward);
   });
 }
 

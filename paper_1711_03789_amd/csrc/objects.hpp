@@ -101,10 +101,11 @@ struct mx_precond {
   mx_precond_info info{};
   // optional per-launch timing of the sweep kernel
   bool timing = false;
-  std::vector<hipEvent_t> ev_start, ev_stop;
+  std::vector<hipEvent_t> ev_start, ev_mid, ev_stop;
   size_t n_timed = 0;
   ~mx_precond() {
     for (auto e : ev_start) (void)hipEventDestroy(e);
+    for (auto e : ev_mid) (void)hipEventDestroy(e);
     for (auto e : ev_stop) (void)hipEventDestroy(e);
   }
 };
@@ -115,7 +116,7 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_p
                    const mx_precond_opts *opts, mx_precond *P);
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st);
 int precond_check(mx_precond *P);
-void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_total);
+void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd, double *ms_bwd);
 void spmv_run(const mx_matrix *A, const void *x, void *y, bool c64, hipStream_t st);
 void matrix_upload(mx_matrix *A);
 void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,

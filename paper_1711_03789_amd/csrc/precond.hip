@@ -555,11 +555,13 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
   int *flags = P->d_flags.as<int>();
   if (P->timing) {
     if (P->n_timed == P->ev_start.size()) {
-      hipEvent_t a, b;
+      hipEvent_t a, b, c;
       MX_HIP(hipEventCreate(&a));
       MX_HIP(hipEventCreate(&b));
+      MX_HIP(hipEventCreate(&c));
       P->ev_start.push_back(a);
-      P->ev_stop.push_back(b);
+      P->ev_mid.push_back(b);
+      P->ev_stop.push_back(c);
     }
     MX_HIP(hipEventRecord(P->ev_start[P->n_timed], st));
   }
@@ -567,6 +569,7 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
   k_sweep<T, true><<<P->trsv_grid, kSweepThreads, 0, st>>>(
       v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(), half,
       P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), flags, P->d_ctrl.as<int>());
+  if (P->timing) MX_HIP(hipEventRecord(P->ev_mid[P->n_timed], st));
   k_sweep<T, false><<<P->trsv_grid, kSweepThreads, 0, st>>>(
       v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>() + half,
       P->d_sched_blk.as<int32_t>() + half, half, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
@@ -588,21 +591,24 @@ void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
   else apply_t<float>(P, vin, zout, st);
 }
 
-void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_total) {
+void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd, double *ms_bwd) {
   if (enable) {
     P->timing = true;
     P->n_timed = 0;
     return;
   }
-  double tot = 0;
+  double tf = 0, tb = 0;
   for (size_t i = 0; i < P->n_timed; ++i) {
     MX_HIP(hipEventSynchronize(P->ev_stop[i]));
-    float ms = 0;
-    MX_HIP(hipEventElapsedTime(&ms, P->ev_start[i], P->ev_stop[i]));
-    tot += ms;
+    float a = 0, b = 0;
+    MX_HIP(hipEventElapsedTime(&a, P->ev_start[i], P->ev_mid[i]));
+    MX_HIP(hipEventElapsedTime(&b, P->ev_mid[i], P->ev_stop[i]));
+    tf += a;
+    tb += b;
   }
   if (launches) *launches = (int64_t)P->n_timed;
-  if (ms_total) *ms_total = tot;
+  if (ms_fwd) *ms_fwd = tf;
+  if (ms_bwd) *ms_bwd = tb;
   P->timing = false;
   P->n_timed = 0;
 }
@@ -798,7 +804,10 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
       MX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<double, true>, kSweepThreads, 0));
     else
       MX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<float, true>, kSweepThreads, 0));
-    int grid = opts->sweep_grid > 0 ? opts->sweep_grid : std::max(1, per_cu) * ctx->cus;
+    // one workgroup per CU: a second co-resident workgroup streaming tiles delays the
+    // dependency chain of the first one more than it adds bandwidth (measured)
+    (void)per_cu;
+    int grid = opts->sweep_grid > 0 ? opts->sweep_grid : ctx->cus;
     P->trsv_grid = std::max(1, std::min(P->n_items / 2, grid));
   }
   const double t1 = now_s();
@@ -884,8 +893,9 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   const int64_t nloc = in.n_local_total;
   in.apply_bytes = (int64_t)(2 * in.env_entries * esz + 6 * nloc * esz + 2 * m.ne * 16 + 4 * nloc +
                              8 * m.ne);
-  // the block-sweep kernel alone: envelope read twice; r read, y written and read, z written
-  in.sweep_bytes = (int64_t)(2 * in.env_entries * esz + 4 * nloc * esz);
+  // one block-sweep launch: the envelope read once; forward: r read, y written, y read once
+  // (backward: y read, z written, z read once)
+  in.sweep_bytes = (int64_t)(in.env_entries * esz + 3 * nloc * esz);
   in.t_host_setup = t1 - t0;
   in.t_upload = t2 - t1;
   in.t_factor = t3 - t2;

@@ -111,7 +111,7 @@ def load(path=LIB_PATH):
         "mx_precond_export_diag": (C.c_int, [P, C.c_int, P]),
         "mx_precond_check": (C.c_int, [P]),
         "mx_precond_sweep_timing": (C.c_int, [P, C.c_int, C.POINTER(C.c_int64),
-                                              C.POINTER(C.c_double)]),
+                                              C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "mx_precond_destroy": (None, [P]),
         "mx_gmres": (C.c_int, [P, P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresStats), P, P]),
         "mx_selftest": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -299,11 +299,12 @@ class Precond:
         _check(_lib.mx_precond_check(self.h))
 
     def sweep_timing(self, enable):
-        """enable=True starts per-launch event timing of the sweep kernel; enable=False stops
-        and returns (launches, total_ms)."""
-        n, ms = C.c_int64(), C.c_double()
-        _check(_lib.mx_precond_sweep_timing(self.h, 1 if enable else 0, C.byref(n), C.byref(ms)))
-        return n.value, ms.value
+        """enable=True starts per-launch event timing of the sweep kernels; enable=False stops
+        and returns (applications, forward_ms_total, backward_ms_total)."""
+        n, a, b = C.c_int64(), C.c_double(), C.c_double()
+        _check(_lib.mx_precond_sweep_timing(self.h, 1 if enable else 0, C.byref(n), C.byref(a),
+                                            C.byref(b)))
+        return n.value, a.value, b.value
 
     def perm(self, l, n_local):
         perm = np.zeros(n_local, np.int32)
