@@ -34,6 +34,8 @@ def instances(name):
         return [("oras", e, s) for s, e in enumerate((1.0, 1.5, 2.0))]
     if name == "small":
         return [("oras", 2.0, 0)]
+    if name == "small-mixed":
+        return [("oras", 2.0, 0)]
     raise SystemExit("unknown workload " + name)
 
 
@@ -89,6 +91,67 @@ def cpu_baseline(total_iters, n_inst):
                       "%.3f s)" % (t4 - t0, per_solve, t_global, t_local, t_lu, t_solve)}
 
 
+def run_batching(args):
+    """Resident share of the 96x96x192 jittered-box problem (6x6x12 subdomains, complex64
+    factors): the first three z-layers of boxes (108 subdomains) are factored together and their
+    Schwarz application is timed; the full problem's complex64 factors exceed one GPU's HBM."""
+    import torch
+
+    from mx_inputs import config_batching
+    from paper_1711_03789_amd import mx
+    w = config_batching(0)
+    ctx = mx.Context(0)
+    t0 = time.perf_counter()
+    mesh = mx.Mesh(*w.n, *w.lengths)
+    A = mx.Matrix(ctx, mesh, w.k, w.xi)
+    part = mx.Partition(mesh, *w.parts, w.layers, *w.cuts)
+    t1 = time.perf_counter()
+    share = (0, w.parts[0] * w.parts[1] * 3)
+    P = mx.Precond(ctx, A, mesh, part, "oras", precision="c64", share=share)
+    t2 = time.perf_counter()
+    inf = P.info()
+    grid, tuned_ms = P.autotune()
+    E = mesh.n_edge
+    v = torch.randn(E, dtype=torch.complex128, device="cuda")
+    z = torch.zeros_like(v)
+    P.apply(v, z)
+    torch.cuda.synchronize()
+    P.sweep_timing(True)
+    t3 = time.perf_counter()
+    for _ in range(args.reps):
+        P.apply(v, z)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    nl, fms, bms = P.sweep_timing(False)
+    P.check()
+    sb = inf["sweep_bytes"]
+    ach = sb / (fms / nl * 1e-3) / 1e9
+    return {
+        "metric": "Schwarz-apply HBM GB/s", "value": inf["apply_bytes"] / ((t4 - t3) / args.reps) / 1e9,
+        "unit": "GB/s", "n_gpus": 1, "steps": args.reps, "warmup": 1,
+        "ms_per_step": (t4 - t3) / args.reps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "complex64 factors (fp32)", "data": "synthetic",
+        "config": {"workload": "box [0,1]x[0,1]x[0,2], 96x96x192 cubes x 6 tets (%d DOFs), k=xi=24, "
+                               "6x6x12 subdomains with +-20%% jittered cut planes, resident share "
+                               "= subdomains %d..%d (3 of 12 z-layers), ORAS, complex64" % (E, share[0], share[1] - 1),
+                   "share_subdomains": share[1] - share[0], "tuned_sweep_grid": grid},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep<float, true> (forward block sweep)",
+                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": None, "launches": nl, "avg_launch_ms": fms / nl,
+                     "bytes_per_launch": sb,
+                     "backward": {"avg_launch_ms": bms / nl, "achieved": sb / (bms / nl * 1e-3) / 1e9}},
+        "factor": {"bound": "mfma", "achieved_env": inf["env_flops"] / inf["t_factor"] / 1e12,
+                   "achieved_executed": inf["tile_flops"] / inf["t_factor"] / 1e12,
+                   "peak": FP32_PEAK_TFS, "unit": "TFLOP/s", "seconds": inf["t_factor"],
+                   "factor_bytes": inf["factor_bytes"]},
+        "setup_seconds": {"mesh_assemble_partition": t1 - t0, "precond_total": t2 - t1,
+                          "precond_host": inf["t_host_setup"], "upload": inf["t_upload"],
+                          "factor": inf["t_factor"]},
+        "share": {"n_local_total": inf["n_local_total"], "max_local": inf["max_local"],
+                  "tiles": inf["tiles"], "max_blocks": inf["max_blocks"]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +160,9 @@ def main():
     ap.add_argument("--workload", default="scale")
     ap.add_argument("--max-iters", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="c128", choices=["c128", "c64"],
+                    help="c64: complex64 factors and SpMV values inside FP64 flexible GMRES")
+    ap.add_argument("--reps", type=int, default=10, help="applications timed (batching)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world > 1:
@@ -110,8 +176,12 @@ def main():
     from mx_inputs import random_rhs
     from paper_1711_03789_amd import mx
 
+    if args.workload == "batching":
+        print(json.dumps(run_batching(args)), flush=True)
+        return
     w, cfg = workload_desc(args.workload)
     inst = instances(args.workload)
+    mixed = args.precision == "c64"
     ctx = mx.Context(0)
     n = w.n
     # inputs resident in HBM before the timed region
@@ -125,6 +195,8 @@ def main():
     x = torch.zeros(E, dtype=torch.complex128, device="cuda")
     torch.cuda.synchronize()
 
+    refs = {}
+
     def step(record):
         t = time.perf_counter()
         mesh = mx.Mesh(*n, *w.lengths)
@@ -136,13 +208,15 @@ def main():
             t0 = time.perf_counter()
             A = mx.Matrix(ctx, mesh, w.k, xi)
             t1 = time.perf_counter()
-            P = mx.Precond(ctx, A, mesh, part, kind)
+            P = mx.Precond(ctx, A, mesh, part, kind, precision=args.precision)
             t2 = time.perf_counter()
             if record:
                 P.sweep_timing(True)
             x.zero_()
             st = mx.gmres(ctx, A, P, rhs[seed], x, restart=w.restart, rtol=w.rtol,
-                          max_iters=args.max_iters)
+                          max_iters=args.max_iters, flexible=mixed, spmv_c64=mixed)
+            if record and mixed and "x_mixed" not in refs:
+                refs["x_mixed"] = (kind, e, seed, x.clone())
             t3 = time.perf_counter()
             r = {"kind": kind, "xi": xi, "iters": st["iters"], "converged": st["converged"],
                  "relres": st["relres_true"], "t_assemble": t1 - t0, "t_precond": t2 - t1,
@@ -215,6 +289,20 @@ def main():
                                       "t_factor")} for r in recs[0][1]],
         "all_converged": converged,
     }
+    if mixed and "x_mixed" in refs:
+        # accuracy of the mixed path against the complex128 path on the first instance
+        kind, e, seed, xm = refs["x_mixed"]
+        mesh = mx.Mesh(*n, *w.lengths)
+        part = mx.Partition(mesh, *w.parts, w.layers)
+        A = mx.Matrix(ctx, mesh, w.k, w.k ** e)
+        P = mx.Precond(ctx, A, mesh, part, kind, precision="c128")
+        x.zero_()
+        st = mx.gmres(ctx, A, P, rhs[seed], x, restart=w.restart, rtol=w.rtol,
+                      max_iters=args.max_iters)
+        out["mixed_vs_c128"] = {"instance": [kind, w.k ** e], "c128_iters": st["iters"],
+                                "rel_l2_diff": float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))}
+        out["dtype"] = "complex64 factors + FP64 FGMRES"
+        del P, A
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sum(r["iters"] for r in recs[0][1]), len(inst))
     print(json.dumps(out), flush=True)

@@ -120,6 +120,8 @@ typedef struct {
   double xi_prec;  /* absorption of the local problems (ORAS local assembly; AS/RAS use A's)  */
   int precision;   /* MX_C128 | MX_C64 (local factors and local solves)                       */
   int sweep_grid;  /* workgroups of the persistent sweep kernels; 0 = one per compute unit      */
+  int sub_begin;   /* resident share: build only subdomains [sub_begin, sub_end) (both 0 = all); */
+  int sub_end;     /* the application then returns the share's part of the sum (zero elsewhere)*/
 } mx_precond_opts;
 
 /* Host-only view of one local problem, as mx_precond_setup builds it (for inspection and
@@ -172,6 +174,12 @@ int mx_precond_export_diag(const mx_precond *P, int l, double *d);
  * forward and of the backward launches, in milliseconds.  Errors: MX_EINVAL, MX_EDEVICE. */
 int mx_precond_sweep_timing(mx_precond *P, int enable, int64_t *launches, double *ms_forward,
                             double *ms_backward);
+/* Launch-shape tuner: times the application with several sweep grid sizes (fractions and
+ * multiples of the CU count) on `stream`, keeps the fastest in P and returns it (best_grid,
+ * best_ms per application).  Synchronous; allocates two temporary E-vectors.
+ * Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_ESTALL. */
+int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_grid,
+                        double *best_ms);
 /* Checks the device error word of P (set by a failed pivot or an expired wait). */
 int mx_precond_check(mx_precond *P);
 void mx_precond_destroy(mx_precond *P);

@@ -311,6 +311,15 @@ int mx_precond_sweep_timing(mx_precond *P, int enable, int64_t *launches, double
   });
 }
 
+int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_grid,
+                        double *best_ms) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && P, "NULL argument");
+    bind_device(ctx->device);
+    mx::precond_autotune(ctx, P, (hipStream_t)stream, best_grid, best_ms);
+  });
+}
+
 int mx_precond_check(mx_precond *P) {
   MX_GUARD({
     MX_REQUIRE(P, "NULL argument");

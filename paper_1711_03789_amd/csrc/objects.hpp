@@ -81,7 +81,7 @@ struct mx_matrix {
 };
 
 struct mx_precond {
-  int kind = MX_ORAS, prec = MX_C128, nsub = 0, device = 0;
+  int kind = MX_ORAS, prec = MX_C128, nsub = 0, device = 0, sub_begin = 0;
   int64_t E = 0;
   int max_nb = 0;
   int64_t vec_total = 0, blocks_total = 0, tiles_total = 0;
@@ -116,6 +116,7 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_p
                    const mx_precond_opts *opts, mx_precond *P);
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st);
 int precond_check(mx_precond *P);
+void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_grid, double *best_ms);
 void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd, double *ms_bwd);
 void spmv_run(const mx_matrix *A, const void *x, void *y, bool c64, hipStream_t st);
 void matrix_upload(mx_matrix *A);

@@ -204,7 +204,10 @@ template <typename T>
 __global__ void k_prolong_owner(int64_t E, const int64_t *__restrict__ src,
                                 const cx<T> *__restrict__ z, cx<double> *__restrict__ out) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < E) out[e] = ccast<double>(z[src[e]]);
+  if (e < E) {
+    const int64_t q = src[e];
+    out[e] = q >= 0 ? ccast<double>(z[q]) : cx<double>{0, 0};
+  }
 }
 
 template <typename T>
@@ -613,6 +616,40 @@ void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd
   P->n_timed = 0;
 }
 
+void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_grid, double *best_ms) {
+  DevBuf vin, zout;
+  vin.alloc((size_t)P->E * 16);
+  zout.alloc((size_t)P->E * 16);
+  MX_HIP(hipMemsetAsync(vin.p, 0, (size_t)P->E * 16, st));
+  const int cus = ctx->cus;
+  std::vector<int> cand = {cus / 2, (3 * cus) / 4, cus, (5 * cus) / 4};
+  if (P->prec == MX_C64) cand.push_back(2 * cus);
+  const int saved = P->trsv_grid;
+  hipEvent_t a, b;
+  MX_HIP(hipEventCreate(&a));
+  MX_HIP(hipEventCreate(&b));
+  int best = saved;
+  double best_t = 1e300;
+  for (int g : cand) {
+    if (g < 1) continue;
+    P->trsv_grid = std::min(g, std::max(1, P->n_items / 2));
+    precond_apply(P, vin.p, zout.p, st);  // warm-up
+    MX_HIP(hipEventRecord(a, st));
+    for (int r = 0; r < 3; ++r) precond_apply(P, vin.p, zout.p, st);
+    MX_HIP(hipEventRecord(b, st));
+    MX_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    MX_HIP(hipEventElapsedTime(&ms, a, b));
+    if (ms / 3 < best_t) best_t = ms / 3, best = P->trsv_grid;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  P->trsv_grid = best;
+  precond_check(P);
+  if (best_grid) *best_grid = best;
+  if (best_ms) *best_ms = best_t;
+}
+
 int precond_check(mx_precond *P) {
   int h[4];
   MX_HIP(hipMemcpy(h, P->d_ctrl.p, sizeof(h), hipMemcpyDeviceToHost));
@@ -631,11 +668,18 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   const double t0 = now_s();
   P->kind = opts->kind;
   P->prec = opts->precision;
-  P->nsub = part.nsub;
   P->E = m.ne;
   P->device = ctx->device;
-  const int N = part.nsub;
-  const auto &sets = part.set(opts->kind);
+  int s0 = opts->sub_begin, s1 = opts->sub_end;
+  if (s0 == 0 && s1 == 0) s1 = part.nsub;
+  if (s0 < 0 || s1 > part.nsub || s0 >= s1) fail(MX_EINVAL, "subdomain share out of range");
+  P->sub_begin = s0;
+  P->nsub = s1 - s0;
+  const int N = P->nsub;
+  // subdomain j of this preconditioner is subdomain s0 + j of the partition
+  std::vector<std::vector<int32_t>> sets_share(part.set(opts->kind).begin() + s0,
+                                               part.set(opts->kind).begin() + s1);
+  const auto &sets = sets_share;
   // local matrices and their orderings
   std::vector<LocalCSR> loc(N);
   P->sky.assign(N, Skyline());
@@ -646,7 +690,7 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
     if (opts->kind == MX_ORAS) tstamp.assign(m.nt, -1);
     for (int64_t l = a; l < b; ++l) {
       if (opts->kind == MX_ORAS)
-        local_impedance(m, ke, A->k, opts->xi_prec, A->bc, part.tets[l], sets[l], loc[l], g2l,
+        local_impedance(m, ke, A->k, opts->xi_prec, A->bc, part.tets[s0 + l], sets[l], loc[l], g2l,
                         tstamp, (int32_t)l);
       else
         local_minor(m, A->h, A->bc, sets[l], loc[l], g2l);
@@ -749,7 +793,8 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   } else {
     src.assign(m.ne, -1);
     for (int64_t e = 0; e < m.ne; ++e) {
-      int o = part.owner[e];
+      int o = part.owner[e] - s0;
+      if (o < 0 || o >= N) continue;  // owned outside the resident share
       const auto &st = sets[o];
       auto it = std::lower_bound(st.begin(), st.end(), (int32_t)e);
       if (it == st.end() || *it != e) fail(MX_EINVAL, "internal: owner does not hold its DOF");

@@ -28,7 +28,7 @@ SYMBOLS = [
     "mx_partition_sizes", "mx_partition_export", "mx_partition_destroy", "mx_precond_setup",
     "mx_precond_apply", "mx_precond_get_info", "mx_precond_export_perm", "mx_precond_export_diag",
     "mx_precond_check", "mx_precond_destroy", "mx_gmres", "mx_selftest", "mx_local_problem",
-    "mx_precond_sweep_timing",
+    "mx_precond_sweep_timing", "mx_precond_autotune",
 ]
 
 
@@ -40,7 +40,7 @@ class MxError(RuntimeError):
 
 class PrecondOpts(C.Structure):
     _fields_ = [("kind", C.c_int), ("xi_prec", C.c_double), ("precision", C.c_int),
-                ("sweep_grid", C.c_int)]
+                ("sweep_grid", C.c_int), ("sub_begin", C.c_int), ("sub_end", C.c_int)]
 
 
 class PrecondInfo(C.Structure):
@@ -110,6 +110,7 @@ def load(path=LIB_PATH):
         "mx_precond_export_perm": (C.c_int, [P, C.c_int, P, P]),
         "mx_precond_export_diag": (C.c_int, [P, C.c_int, P]),
         "mx_precond_check": (C.c_int, [P]),
+        "mx_precond_autotune": (C.c_int, [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "mx_precond_sweep_timing": (C.c_int, [P, C.c_int, C.POINTER(C.c_int64),
                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "mx_precond_destroy": (None, [P]),
@@ -258,7 +259,7 @@ class Partition:
 def local_problem(mesh, A, part, l, kind="oras", xi_prec=None):
     """Host-only: local matrix of subdomain l (CSR in local numbering) and its RCM order."""
     load()
-    o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec, MX_C128, 0)
+    o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec, MX_C128, 0, 0, 0)
     n, nnz = C.c_int64(), C.c_int64()
     _check(_lib.mx_local_problem(mesh.h, A.h, part.h, C.byref(o), l, C.byref(n), C.byref(nnz),
                                  None, None, None, None, None))
@@ -274,10 +275,11 @@ def local_problem(mesh, A, part, l, kind="oras", xi_prec=None):
 
 class Precond:
     def __init__(self, ctx, A, mesh, part, kind="oras", xi_prec=None, precision="c128",
-                 sweep_grid=0):
+                 sweep_grid=0, share=None):
         load()
+        s0, s1 = share if share is not None else (0, 0)
         o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec,
-                        PRECISIONS.get(precision, precision), sweep_grid)
+                        PRECISIONS.get(precision, precision), sweep_grid, s0, s1)
         h = P()
         _check(_lib.mx_precond_setup(ctx.h, A.h, mesh.h, part.h, C.byref(o), C.byref(h)))
         self.h, self.ctx = h, ctx
@@ -297,6 +299,12 @@ class Precond:
 
     def check(self):
         _check(_lib.mx_precond_check(self.h))
+
+    def autotune(self, stream=None):
+        """Picks the fastest sweep grid; returns (grid, ms per application)."""
+        g, ms = C.c_int32(), C.c_double()
+        _check(_lib.mx_precond_autotune(self.ctx.h, self.h, _stream(stream), C.byref(g), C.byref(ms)))
+        return g.value, ms.value
 
     def sweep_timing(self, enable):
         """enable=True starts per-launch event timing of the sweep kernels; enable=False stops

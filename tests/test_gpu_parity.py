@@ -215,3 +215,40 @@ def test_fgmres_mixed_precision_config(gpu_lib, ctx):
         "err vs exact", np.linalg.norm(x - x_exact) / np.linalg.norm(x_exact))
     assert st["converged"] and st["relres_true"] <= w.rtol
     assert err <= 1e-5
+
+
+def test_resident_share_and_autotune(gpu_lib, ctx):
+    """A preconditioner built on a share of the subdomains returns the share's part of the sum
+    (zero on DOFs owned elsewhere); the launch-shape tuner keeps the result bit-identical."""
+    say("share")
+    n = (14, 12, 16)
+    cuts = (jittered_cuts(14, 2, 0.2, 21), jittered_cuts(12, 2, 0.2, 22), jittered_cuts(16, 3, 0.2, 23))
+    k, xi = 4.0, 4.0
+    om = OMesh(*n)
+    oA = fem.assemble(om, k, xi)
+    op = dd.Partition(om, 2, 2, 3, 2, *cuts)
+    oB = dd.Schwarz(op, oA, dd.ORAS, k, xi)
+    lm = gpu_lib.Mesh(*n)
+    lA = gpu_lib.Matrix(ctx, lm, k, xi)
+    lp = gpu_lib.Partition(lm, 2, 2, 3, 2, *cuts)
+    s0, s1 = 4, 8  # the middle z-layer of boxes
+    P = gpu_lib.Precond(ctx, lA, lm, lp, "oras", precision="c64", share=(s0, s1))
+    v = random_rhs(om.n_edge, 31)
+    ref = np.zeros(om.n_edge, np.complex128)
+    for l in range(s0, s1):
+        idx = op.oras_sets[l]
+        ref[idx] += op.pou(l, dd.ORAS) * oB.lu[l].solve(v[idx])
+    vd, zd = dev(v), dev(np.zeros(om.n_edge))
+    P.apply(vd, zd)
+    P.check()
+    z = host(zd)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say("  share rel err (c64)", err)
+    assert err <= 1e-4
+    assert not z[(op.owner < s0) | (op.owner >= s1)].any()
+    g, ms = P.autotune()
+    say("  autotune grid", g, "ms", ms)
+    zd2 = dev(np.zeros(om.n_edge))
+    P.apply(vd, zd2)
+    P.check()
+    assert np.array_equal(host(zd2), z)
