@@ -35,6 +35,8 @@ extern "C" {
 #define MX_EPIVOT (-4)    /* zero or non-finite pivot in a local LDL^T factorisation           */
 #define MX_ENAN (-5)      /* non-finite residual norm in GMRES                                 */
 #define MX_ESTALL (-6)    /* a bounded device-side wait expired (dependency never satisfied)   */
+#define MX_EHBM (-7)      /* a server request whose footprint can never fit the HBM budget      */
+#define MX_ETIMEOUT (-8)  /* a server request is not finished within the given time             */
 
 /* ---- enums -------------------------------------------------------------------------------- */
 #define MX_BC_PEC 0        /* E x n = 0 on the boundary (eq:PECcond)                          */
@@ -52,6 +54,7 @@ typedef struct mx_mesh mx_mesh;
 typedef struct mx_matrix mx_matrix;
 typedef struct mx_partition mx_partition;
 typedef struct mx_precond mx_precond;
+typedef struct mx_server mx_server;
 
 const char *mx_last_error(void);
 int mx_version(void);
@@ -207,6 +210,57 @@ typedef struct {
  * Synchronous.  Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_ENAN, MX_ESTALL. */
 int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
              const mx_gmres_opts *opts, mx_gmres_stats *stats, double *res_hist, void *stream);
+
+/* ---- solve server: continuous batching of independent solves -------------------------------- */
+/* Requests are unit-cube problems solved by the path above (Sec. 6.1 workloads).  `slots` worker
+ * threads, each with its own HIP stream, pull requests in submission order; a slot first does the
+ * request's host work (mesh, assembly, partition, local problems, orderings), which fixes its exact
+ * device footprint, then waits until the footprint fits in what is left of `hbm_budget`, runs the
+ * device work (upload, factorisation, GMRES) on its stream concurrently with the other admitted
+ * requests and returns its memory.  Results do not depend on what else is running (deterministic
+ * kernels).  A server is driven from any number of host threads. */
+typedef struct {
+  uint64_t hbm_budget;  /* device bytes the server may hold; 0 = 85% of the free memory          */
+  int slots;            /* requests in flight (worker threads / streams)                           */
+  int kind, precision;  /* preconditioner (MX_AS/MX_RAS/MX_ORAS) and factor precision             */
+  int layers;           /* overlap sweeps                                                          */
+  int restart, max_iters, flexible, spmv_c64;
+  double rtol;
+} mx_server_opts;
+
+typedef struct {
+  int n;                                     /* cubes per side of the unit cube                  */
+  int p;                                     /* subdomains per side (p^3 boxes)                   */
+  double k, xi;                              /* wavenumber and absorption                        */
+  double center[3], pol[3], sigma;           /* Gaussian source, as mx_rhs_gaussian              */
+} mx_request;
+
+typedef struct {
+  int status;                  /* MX_OK or the request's error code (message: mx_last_error)    */
+  int iters, converged;
+  double relres_true;
+  int64_t n_dof;
+  uint64_t footprint_bytes;    /* device bytes reserved for the request                          */
+  double t_queue, t_host, t_device, t_total; /* s: submit->admitted, submit->host work done,
+                                                admitted->done, submit->done                     */
+} mx_result;
+
+/* Errors: MX_EINVAL, MX_EDEVICE. */
+int mx_server_create(int device, const mx_server_opts *opts, mx_server **out);
+/* Non-blocking; *ticket identifies the request.  Errors: MX_EINVAL. */
+int mx_server_submit(mx_server *s, const mx_request *req, uint64_t *ticket);
+/* Blocks until the request is done (timeout_s < 0: no limit) and copies its result; a request
+ * whose footprint exceeds the budget finishes with status MX_EHBM.  Errors: MX_EINVAL,
+ * MX_ETIMEOUT. */
+int mx_server_wait(mx_server *s, uint64_t ticket, double timeout_s, mx_result *res);
+/* Copies the solution (complex128[n], host) of a finished, successful request. */
+int mx_server_solution(mx_server *s, uint64_t ticket, double *x_host, int64_t n);
+/* Forgets a finished request (its stored solution). */
+int mx_server_release(mx_server *s, uint64_t ticket);
+/* Budget, peak reserved bytes and the largest number of simultaneously admitted requests. */
+int mx_server_stats(mx_server *s, uint64_t *budget, uint64_t *peak_used, int *max_admitted);
+/* Finishes every submitted request, then stops the workers. */
+void mx_server_destroy(mx_server *s);
 
 /* ---- device self-check -------------------------------------------------------------------- */
 /* Runs the matrix-core tile product used by the factorisation on random 64x64 complex tiles in

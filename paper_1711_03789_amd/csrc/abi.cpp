@@ -9,6 +9,7 @@
 #include "objects.hpp"
 
 namespace mx {
+thread_local hipStream_t t_alloc_stream = nullptr;
 static thread_local std::string g_last_error;
 void set_error(int code, const std::string &msg) {
   (void)code;
@@ -245,7 +246,7 @@ int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx
     MX_REQUIRE(ctx && A && m && p && opts && out, "NULL argument");
     bind_device(ctx->device);
     auto P = std::make_unique<mx_precond>();
-    mx::precond_setup(ctx, A, m, p, opts, P.get());
+    mx::precond_setup(ctx, A, m, p, opts, P.get(), nullptr);
     *out = P.release();
   });
 }

@@ -241,6 +241,17 @@ void spmv_run(const mx_matrix *A, const void *x, void *y, bool c64, hipStream_t 
   MX_HIP(hipGetLastError());
 }
 
+size_t matrix_device_bytes(const mx_matrix *A) {
+  return 8 * (size_t)(A->h.n + 1) + (4 + 16 + 8) * (size_t)A->h.nnz() + 4096;
+}
+
+size_t gmres_device_bytes(int64_t n, int restart, bool flexible) {
+  const size_t vb = ((size_t)n * 16 + 255) & ~(size_t)255;
+  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 1023) / 1024));
+  return vb * (restart + 1 + (flexible ? restart : 0) + 4) + (size_t)G * (restart + 1) * 16 +
+         (size_t)(restart + 1) * restart * 16 + 64 * (size_t)(restart + 1) + 8192;
+}
+
 void matrix_upload(mx_matrix *A) {
   A->rowptr.upload(A->h.rowptr);
   A->col.upload(A->h.col);
@@ -376,7 +387,7 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
       }
       beta = residual();
       if (!std::isfinite(beta)) fail(MX_ENAN, "non-finite residual");
-      if (P) precond_check(P);
+      if (P) precond_check(P, st);
     }
   }
   stats->iters = total;

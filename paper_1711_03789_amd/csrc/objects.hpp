@@ -19,10 +19,22 @@
 
 namespace mx {
 
+// Stream used for device allocations and uploads made by this host thread: when set (by an
+// AllocScope) buffers come from the stream-ordered allocator and are freed on that stream, so
+// concurrent requests on different streams do not synchronise the whole device.
+extern thread_local hipStream_t t_alloc_stream;
+struct AllocScope {
+  hipStream_t prev;
+  explicit AllocScope(hipStream_t s) : prev(t_alloc_stream) { t_alloc_stream = s; }
+  ~AllocScope() { t_alloc_stream = prev; }
+};
+
 // Owning device buffer.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  hipStream_t st = nullptr;
+  bool async = false;
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
@@ -30,11 +42,21 @@ struct DevBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) n = 16;
-    MX_HIP(hipMalloc(&p, n));
+    if (t_alloc_stream) {
+      MX_HIP(hipMallocAsync(&p, n, t_alloc_stream));
+      st = t_alloc_stream;
+      async = true;
+    } else {
+      MX_HIP(hipMalloc(&p, n));
+      async = false;
+    }
     bytes = n;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (async) (void)hipFreeAsync(p, st);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
   }
@@ -43,7 +65,10 @@ struct DevBuf {
   template <class T>
   void upload(const std::vector<T> &v) {
     alloc(v.size() * sizeof(T));
-    if (!v.empty()) MX_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!v.empty()) {
+      MX_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, t_alloc_stream));
+      MX_HIP(hipStreamSynchronize(t_alloc_stream));
+    }
   }
 };
 
@@ -80,6 +105,21 @@ struct mx_matrix {
   mx::DevBuf rowptr, col, val, val32;
 };
 
+namespace mx {
+// Host-side product of a preconditioner setup: everything needed to materialise it on a device,
+// and its exact device footprint.
+struct PrecondPlan {
+  std::vector<int64_t> brow_off;
+  std::vector<int32_t> bfirst, blast;
+  std::vector<int64_t> off;   // scatter of the permuted lower-triangle entries into the tile pool
+  std::vector<double> val;
+  std::vector<int32_t> glob;
+  std::vector<int64_t> src, sum_ptr, sum_idx;
+  std::vector<int32_t> sched_sub, sched_blk;
+  size_t device_bytes = 0;    // peak device bytes of materialising and holding the preconditioner
+};
+}  // namespace mx
+
 struct mx_precond {
   int kind = MX_ORAS, prec = MX_C128, nsub = 0, device = 0, sub_begin = 0;
   int64_t E = 0;
@@ -113,9 +153,14 @@ struct mx_precond {
 namespace mx {
 // implemented in precond.hip / krylov.hip
 void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
-                   const mx_precond_opts *opts, mx_precond *P);
+                   const mx_precond_opts *opts, mx_precond *P, hipStream_t st);
+void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
+                  const mx_precond_opts *opts, mx_precond *P, PrecondPlan &plan);
+void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st);
+size_t matrix_device_bytes(const mx_matrix *A);
+size_t gmres_device_bytes(int64_t n, int restart, bool flexible);
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st);
-int precond_check(mx_precond *P);
+int precond_check(mx_precond *P, hipStream_t st = nullptr);
 void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_grid, double *best_ms);
 void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd, double *ms_bwd);
 void spmv_run(const mx_matrix *A, const void *x, void *y, bool c64, hipStream_t st);

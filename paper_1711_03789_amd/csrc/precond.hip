@@ -650,16 +650,24 @@ void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_
   if (best_ms) *best_ms = best_t;
 }
 
-int precond_check(mx_precond *P) {
+int precond_check(mx_precond *P, hipStream_t st) {
   int h[4];
-  MX_HIP(hipMemcpy(h, P->d_ctrl.p, sizeof(h), hipMemcpyDeviceToHost));
+  MX_HIP(hipMemcpyAsync(h, P->d_ctrl.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  MX_HIP(hipStreamSynchronize(st));
   if (h[3]) fail(MX_EPIVOT, "zero or non-finite pivot in a local factorisation");
   if (h[2]) fail(MX_ESTALL, "a device-side wait in the block sweeps expired");
   return MX_OK;
 }
 
 void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_partition *ph,
-                   const mx_precond_opts *opts, mx_precond *P) {
+                   const mx_precond_opts *opts, mx_precond *P, hipStream_t st) {
+  PrecondPlan plan;
+  precond_plan(ctx, A, mh, ph, opts, P, plan);
+  precond_materialize(P, plan, st);
+}
+
+void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_partition *ph,
+                  const mx_precond_opts *opts, mx_precond *P, PrecondPlan &plan) {
   const Mesh &m = mh->m;
   const Partition &part = ph->p;
   if (A->h.n != m.ne) fail(MX_EINVAL, "matrix and mesh disagree");
@@ -720,8 +728,11 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   P->tiles_total = tiles;
   P->blocks_total = blocks;
   P->vec_total = vec;
-  std::vector<int64_t> brow_off(blocks);
-  std::vector<int32_t> bfirst(blocks), blast(blocks);
+  std::vector<int64_t> &brow_off = plan.brow_off;
+  std::vector<int32_t> &bfirst = plan.bfirst, &blast = plan.blast;
+  brow_off.assign(blocks, 0);
+  bfirst.assign(blocks, 0);
+  blast.assign(blocks, 0);
   for (int l = 0; l < N; ++l) {
     const Skyline &s = P->sky[l];
     for (int64_t I = 0; I < s.nb; ++I) {
@@ -741,8 +752,10 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
     c += s.nb * kTile - s.n;
     cnt[l + 1] = cnt[l] + c;
   }
-  std::vector<int64_t> off(cnt[N]);
-  std::vector<double> val(2 * cnt[N]);
+  std::vector<int64_t> &off = plan.off;
+  std::vector<double> &val = plan.val;
+  off.assign(cnt[N], 0);
+  val.assign(2 * cnt[N], 0.0);
   parallel_for(N, [&](int64_t a0, int64_t a1) {
     for (int64_t l = a0; l < a1; ++l) {
       const LocalCSR &a = loc[l];
@@ -772,12 +785,13 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
     }
   }, 1);
   // restriction / prolongation maps
-  std::vector<int32_t> glob(vec, -1);
+  std::vector<int32_t> &glob = plan.glob;
+  glob.assign(vec, -1);
   for (int l = 0; l < N; ++l) {
     const Skyline &s = P->sky[l];
     for (int64_t i = 0; i < s.n; ++i) glob[P->sub_vec_base[l] + i] = sets[l][s.perm[i]];
   }
-  std::vector<int64_t> src, sum_ptr, sum_idx;
+  std::vector<int64_t> &src = plan.src, &sum_ptr = plan.sum_ptr, &sum_idx = plan.sum_idx;
   if (opts->kind == MX_AS) {
     sum_ptr.assign(m.ne + 1, 0);
     for (int l = 0; l < N; ++l)
@@ -835,7 +849,7 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   auto by_key = [](const Item &a, const Item &b) { return a.key != b.key ? a.key < b.key : a.l < b.l; };
   std::sort(fw.begin(), fw.end(), by_key);
   std::sort(bw.begin(), bw.end(), by_key);
-  std::vector<int32_t> sched_sub, sched_blk;
+  std::vector<int32_t> &sched_sub = plan.sched_sub, &sched_blk = plan.sched_blk;
   for (const auto *lst : {&fw, &bw})
     for (const auto &it : *lst) {
       sched_sub.push_back(it.l);
@@ -856,7 +870,27 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
     P->trsv_grid = std::max(1, std::min(P->n_items / 2, grid));
   }
   const double t1 = now_s();
+  P->info.t_host_setup = t1 - t0;
+  const size_t esz = P->prec == MX_C128 ? 16 : 8;
+  plan.device_bytes = (size_t)tiles * kTileElems * esz + 3 * (size_t)vec * esz +
+                      2 * (size_t)blocks * 4 + 16 * (size_t)blocks +
+                      4 * (size_t)vec + 8 * (size_t)std::max(src.size(), sum_idx.size() + sum_ptr.size()) +
+                      8 * (size_t)sched_sub.size() + 8 * P->panel_pref.size() +
+                      24 * off.size() + (1 << 20);
+}
 
+void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
+  const double t1 = now_s();
+  const int N = P->nsub;
+  const int64_t blocks = P->blocks_total, vec = P->vec_total, tiles = P->tiles_total;
+  std::vector<int64_t> &brow_off = plan.brow_off;
+  std::vector<int32_t> &bfirst = plan.bfirst, &blast = plan.blast;
+  std::vector<int64_t> &off = plan.off;
+  std::vector<double> &val = plan.val;
+  std::vector<int32_t> &glob = plan.glob;
+  std::vector<int64_t> &src = plan.src, &sum_ptr = plan.sum_ptr, &sum_idx = plan.sum_idx;
+  std::vector<int32_t> &sched_sub = plan.sched_sub, &sched_blk = plan.sched_blk;
+  AllocScope scope(st);
   // device buffers
   const size_t esz = P->prec == MX_C128 ? 16 : 8;
   P->d_sub_nb.upload(P->sub_nb);
@@ -867,7 +901,7 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   P->d_bfirst.upload(bfirst);
   P->d_blast.upload(blast);
   P->d_glob.upload(glob);
-  if (opts->kind == MX_AS) {
+  if (P->kind == MX_AS) {
     P->d_sum_ptr.upload(sum_ptr);
     P->d_sum_idx.upload(sum_idx);
   } else {
@@ -882,13 +916,12 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   P->d_z.alloc(vec * esz);
   P->d_flags.alloc(2 * blocks * sizeof(int));
   P->d_ctrl.alloc(64);
-  MX_HIP(hipMemset(P->d_flags.p, 0, 2 * blocks * sizeof(int)));
-  MX_HIP(hipMemset(P->d_ctrl.p, 0, 64));
-  MX_HIP(hipMemset(P->d_y.p, 0, vec * esz));
-  MX_HIP(hipMemset(P->d_z.p, 0, vec * esz));
+  MX_HIP(hipMemsetAsync(P->d_flags.p, 0, 2 * blocks * sizeof(int), st));
+  MX_HIP(hipMemsetAsync(P->d_ctrl.p, 0, 64, st));
+  MX_HIP(hipMemsetAsync(P->d_y.p, 0, vec * esz, st));
+  MX_HIP(hipMemsetAsync(P->d_z.p, 0, vec * esz, st));
   const size_t pool_bytes = (size_t)tiles * kTileElems * esz;
   P->pool.alloc(pool_bytes);
-  hipStream_t st = nullptr;
   k_zero<<<4096, 256, 0, st>>>((int64_t)(pool_bytes / 16), P->pool.as<uint4>());
   {
     DevBuf d_off, d_val;
@@ -904,14 +937,17 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
             ne, d_off.as<int64_t>(), d_val.as<cx<double>>(), P->pool.as<cx<float>>());
     }
     MX_HIP(hipGetLastError());
-    MX_HIP(hipDeviceSynchronize());
+    MX_HIP(hipStreamSynchronize(st));
   }
+  // host staging no longer needed
+  std::vector<int64_t>().swap(off);
+  std::vector<double>().swap(val);
   const double t2 = now_s();
   if (P->prec == MX_C128) factor_all<double>(P, st);
   else factor_all<float>(P, st);
-  MX_HIP(hipDeviceSynchronize());
+  MX_HIP(hipStreamSynchronize(st));
   const double t3 = now_s();
-  precond_check(P);
+  precond_check(P, st);
   // info
   mx_precond_info &in = P->info;
   in.n_sub = N;
@@ -936,12 +972,11 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   // (restricted input written and read, forward result written and read twice, backward result
   // written and read), the global input gathered and output written, the 4-byte gather maps
   const int64_t nloc = in.n_local_total;
-  in.apply_bytes = (int64_t)(2 * in.env_entries * esz + 6 * nloc * esz + 2 * m.ne * 16 + 4 * nloc +
-                             8 * m.ne);
+  in.apply_bytes = (int64_t)(2 * in.env_entries * esz + 6 * nloc * esz + 2 * P->E * 16 + 4 * nloc +
+                             8 * P->E);
   // one block-sweep launch: the envelope read once; forward: r read, y written, y read once
   // (backward: y read, z written, z read once)
   in.sweep_bytes = (int64_t)(in.env_entries * esz + 3 * nloc * esz);
-  in.t_host_setup = t1 - t0;
   in.t_upload = t2 - t1;
   in.t_factor = t3 - t2;
 }

@@ -1,0 +1,329 @@
+// Solve server: continuous batching of independent absorptive-Maxwell solves on one GPU.
+//
+// Each request is a unit-cube problem (n cubes per side, wavenumber k, absorption xi, p^3
+// subdomains, Gaussian source) solved by the one-level Schwarz-preconditioned (F)GMRES path.  A
+// fixed number of slots (worker threads, each with its own HIP stream and GMRES workspace) pull
+// requests in arrival order.  A slot first does the host work of a request (mesh, assembly,
+// partition, local problems and orderings), which fixes the request's exact device footprint;
+// the request is then admitted when that footprint fits in what the budget has left, runs its
+// device work (upload, batched factorisation, GMRES) on the slot's stream concurrently with the
+// other admitted requests, and returns its memory.  Device memory comes from the stream-ordered
+// allocator of the slot's stream, so requests never synchronise each other.  All kernels are
+// deterministic (fixed reduction orders, schedule-independent sweep accumulation), so a request
+// returns the same solution whether it runs alone or among others.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "objects.hpp"
+
+namespace mx {
+
+static double wall() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct SrvRequest {
+  mx_request req;
+  double t_submit = 0, t_admit = 0, t_host_done = 0, t_done = 0;
+  bool done = false;
+  mx_result res{};
+  std::string msg;
+  std::vector<double> x;  // interleaved complex128 solution
+};
+
+struct Server {
+  mx_server_opts opts{};
+  int device = 0;
+  int cus = 256;
+  uint64_t budget = 0, used = 0, peak = 0;
+  std::mutex mu;
+  std::condition_variable cv_queue, cv_mem, cv_done;
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, std::unique_ptr<SrvRequest>> reqs;
+  uint64_t next_id = 1;
+  bool stop = false;
+  int admitted = 0, max_admitted = 0;
+  std::vector<std::thread> workers;
+
+  void run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R);
+  void worker();
+};
+
+void Server::run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
+  const mx_request &q = R->req;
+  // ---- host phase (no device memory) ----
+  auto mesh = std::make_unique<mx_mesh>();
+  build_mesh(mesh->m, q.n, q.n, q.n, 1.0, 1.0, 1.0);
+  auto A = std::make_unique<mx_matrix>();
+  A->k = q.k, A->xi = q.xi, A->bc = MX_BC_IMPEDANCE, A->device = device;
+  assemble_global(mesh->m, q.k, q.xi, MX_BC_IMPEDANCE, A->h);
+  auto part = std::make_unique<mx_partition>();
+  build_partition(mesh->m, q.p, q.p, q.p, nullptr, nullptr, nullptr, opts.layers, part->p);
+  mx_precond_opts po{};
+  po.kind = opts.kind;
+  po.xi_prec = q.xi;
+  po.precision = opts.precision;
+  auto P = std::make_unique<mx_precond>();
+  PrecondPlan plan;
+  precond_plan(ctx, A.get(), mesh.get(), part.get(), &po, P.get(), plan);
+  const int64_t E = mesh->m.ne;
+  std::vector<double> f(2 * E);
+  rhs_gaussian(mesh->m, MX_BC_IMPEDANCE, q.center, q.pol, q.sigma, f.data());
+  const uint64_t need = plan.device_bytes + matrix_device_bytes(A.get()) +
+                        gmres_device_bytes(E, opts.restart, opts.flexible != 0) + 2 * 16 * (uint64_t)E;
+  R->res.n_dof = E;
+  R->res.footprint_bytes = need;
+  R->t_host_done = wall();
+  if (need > budget) fail(MX_EHBM, "request footprint exceeds the server's HBM budget");
+  // ---- admission by footprint ----
+  {
+    std::unique_lock<std::mutex> lk(mu);
+    cv_mem.wait(lk, [&] { return used + need <= budget; });
+    used += need;
+    peak = std::max(peak, used);
+    ++admitted;
+    max_admitted = std::max(max_admitted, admitted);
+    R->t_admit = wall();
+  }
+  struct Release {
+    Server *s;
+    uint64_t n;
+    ~Release() {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->used -= n;
+      --s->admitted;
+      s->cv_mem.notify_all();
+    }
+  } rel{this, need};
+  // ---- device phase, all on this slot's stream ----
+  {
+    AllocScope scope(st);
+    matrix_upload(A.get());
+    precond_materialize(P.get(), plan, st);
+    DevBuf b, x;
+    b.alloc(16 * (size_t)E);
+    x.alloc(16 * (size_t)E);
+    MX_HIP(hipMemcpyAsync(b.p, f.data(), 16 * (size_t)E, hipMemcpyHostToDevice, st));
+    MX_HIP(hipMemsetAsync(x.p, 0, 16 * (size_t)E, st));
+    mx_gmres_opts go{};
+    go.restart = opts.restart;
+    go.max_iters = opts.max_iters;
+    go.flexible = opts.flexible;
+    go.spmv_c64 = opts.spmv_c64;
+    go.rtol = opts.rtol;
+    mx_gmres_stats gs{};
+    gmres_run(ctx, A.get(), P.get(), b.p, x.p, &go, &gs, nullptr, st);
+    R->x.resize(2 * E);
+    MX_HIP(hipMemcpyAsync(R->x.data(), x.p, 16 * (size_t)E, hipMemcpyDeviceToHost, st));
+    MX_HIP(hipStreamSynchronize(st));
+    R->res.iters = gs.iters;
+    R->res.converged = gs.converged;
+    R->res.relres_true = gs.relres_true;
+    P.reset();
+    A.reset();
+    ctx->krylov.buf.release();
+    b.release();
+    x.release();
+    MX_HIP(hipStreamSynchronize(st));
+  }
+}
+
+void Server::worker() {
+  hipSetDevice(device);
+  hipStream_t st = nullptr;
+  mx_ctx ctx;
+  ctx.device = device;
+  ctx.cus = cus;
+  bool ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+            hipHostMalloc((void **)&ctx.pinned, 4096, hipHostMallocDefault) == hipSuccess;
+  while (true) {
+    uint64_t id;
+    SrvRequest *R;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_queue.wait(lk, [&] { return stop || !queue.empty(); });
+      if (queue.empty()) break;
+      id = queue.front();
+      queue.pop_front();
+      R = reqs[id].get();
+    }
+    int code = MX_OK;
+    std::string msg;
+    if (!ok) {
+      code = MX_EDEVICE;
+      msg = "server slot could not create its stream";
+    } else {
+      try {
+        run_request(&ctx, st, R);
+      } catch (const Error &e) {
+        code = e.code;
+        msg = e.msg;
+      } catch (const std::bad_alloc &) {
+        code = MX_ENOMEM;
+        msg = "host allocation failed";
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      R->res.status = code;
+      R->t_done = wall();
+      R->res.t_host = R->t_host_done - R->t_submit;
+      R->res.t_queue = (R->t_admit > 0 ? R->t_admit : R->t_done) - R->t_submit;
+      R->res.t_device = R->t_admit > 0 ? R->t_done - R->t_admit : 0.0;
+      R->res.t_total = R->t_done - R->t_submit;
+      R->done = true;
+      R->msg = msg;
+    }
+    cv_done.notify_all();
+  }
+  ctx.krylov.buf.release();
+  if (ctx.pinned) (void)hipHostFree(ctx.pinned);
+  ctx.pinned = nullptr;
+  if (st) (void)hipStreamDestroy(st);
+}
+
+}  // namespace mx
+
+struct mx_server {
+  mx::Server s;
+};
+
+using mx::Error;
+
+extern "C" {
+
+int mx_server_create(int device, const mx_server_opts *opts, mx_server **out) {
+  try {
+    if (!opts || !out) mx::fail(MX_EINVAL, "NULL argument");
+    if (opts->slots < 1 || opts->restart < 1 || opts->max_iters < 1 || !(opts->rtol > 0))
+      mx::fail(MX_EINVAL, "bad server options");
+    if (opts->kind < MX_AS || opts->kind > MX_ORAS) mx::fail(MX_EINVAL, "unknown kind");
+    if (opts->precision != MX_C128 && opts->precision != MX_C64) mx::fail(MX_EINVAL, "unknown precision");
+    MX_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    MX_HIP(hipGetDeviceProperties(&prop, device));
+    auto S = std::make_unique<mx_server>();
+    S->s.opts = *opts;
+    S->s.device = device;
+    S->s.cus = prop.multiProcessorCount;
+    size_t free_b = 0, total_b = 0;
+    MX_HIP(hipMemGetInfo(&free_b, &total_b));
+    S->s.budget = opts->hbm_budget ? opts->hbm_budget : (uint64_t)(0.85 * (double)free_b);
+    for (int i = 0; i < opts->slots; ++i) S->s.workers.emplace_back([p = &S->s] { p->worker(); });
+    *out = S.release();
+    return MX_OK;
+  } catch (const Error &e) {
+    mx::set_error(e.code, e.msg);
+    return e.code;
+  }
+}
+
+int mx_server_submit(mx_server *S, const mx_request *req, uint64_t *ticket) {
+  try {
+    if (!S || !req || !ticket) mx::fail(MX_EINVAL, "NULL argument");
+    if (req->n < 1 || req->p < 1 || req->p > req->n || !(req->k > 0) || !(req->sigma > 0))
+      mx::fail(MX_EINVAL, "bad request");
+    auto R = std::make_unique<mx::SrvRequest>();
+    R->req = *req;
+    R->t_submit = mx::wall();
+    std::lock_guard<std::mutex> lk(S->s.mu);
+    if (S->s.stop) mx::fail(MX_EINVAL, "server is shutting down");
+    uint64_t id = S->s.next_id++;
+    S->s.reqs[id] = std::move(R);
+    S->s.queue.push_back(id);
+    *ticket = id;
+    S->s.cv_queue.notify_one();
+    return MX_OK;
+  } catch (const Error &e) {
+    mx::set_error(e.code, e.msg);
+    return e.code;
+  }
+}
+
+int mx_server_wait(mx_server *S, uint64_t ticket, double timeout_s, mx_result *res) {
+  try {
+    if (!S || !res) mx::fail(MX_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(S->s.mu);
+    auto it = S->s.reqs.find(ticket);
+    if (it == S->s.reqs.end()) mx::fail(MX_EINVAL, "unknown ticket");
+    mx::SrvRequest *R = it->second.get();
+    auto pred = [&] { return R->done; };
+    if (timeout_s < 0) S->s.cv_done.wait(lk, pred);
+    else if (!S->s.cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred))
+      mx::fail(MX_ETIMEOUT, "request not finished yet");
+    *res = R->res;
+    if (R->res.status != MX_OK) mx::set_error(R->res.status, R->msg);
+    return MX_OK;
+  } catch (const Error &e) {
+    mx::set_error(e.code, e.msg);
+    return e.code;
+  }
+}
+
+int mx_server_solution(mx_server *S, uint64_t ticket, double *x_host, int64_t n) {
+  try {
+    if (!S || !x_host) mx::fail(MX_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->s.mu);
+    auto it = S->s.reqs.find(ticket);
+    if (it == S->s.reqs.end()) mx::fail(MX_EINVAL, "unknown ticket");
+    mx::SrvRequest *R = it->second.get();
+    if (!R->done) mx::fail(MX_ETIMEOUT, "request not finished yet");
+    if (R->res.status != MX_OK) mx::fail(R->res.status, "request failed");
+    if ((int64_t)R->x.size() != 2 * n) mx::fail(MX_EINVAL, "n does not match the request's DOF count");
+    std::memcpy(x_host, R->x.data(), 16 * (size_t)n);
+    return MX_OK;
+  } catch (const Error &e) {
+    mx::set_error(e.code, e.msg);
+    return e.code;
+  }
+}
+
+int mx_server_release(mx_server *S, uint64_t ticket) {
+  try {
+    if (!S) mx::fail(MX_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->s.mu);
+    auto it = S->s.reqs.find(ticket);
+    if (it == S->s.reqs.end()) mx::fail(MX_EINVAL, "unknown ticket");
+    if (!it->second->done) mx::fail(MX_EINVAL, "request still running");
+    S->s.reqs.erase(it);
+    return MX_OK;
+  } catch (const Error &e) {
+    mx::set_error(e.code, e.msg);
+    return e.code;
+  }
+}
+
+int mx_server_stats(mx_server *S, uint64_t *budget, uint64_t *peak_used, int *max_admitted) {
+  try {
+    if (!S) mx::fail(MX_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->s.mu);
+    if (budget) *budget = S->s.budget;
+    if (peak_used) *peak_used = S->s.peak;
+    if (max_admitted) *max_admitted = S->s.max_admitted;
+    return MX_OK;
+  } catch (const Error &e) {
+    mx::set_error(e.code, e.msg);
+    return e.code;
+  }
+}
+
+void mx_server_destroy(mx_server *S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->s.mu);
+    S->s.stop = true;
+  }
+  S->s.cv_queue.notify_all();
+  for (auto &t : S->s.workers) t.join();
+  delete S;
+}
+
+}  // extern "C"

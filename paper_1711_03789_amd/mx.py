@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmx.so")
 
 MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EPIVOT, MX_ENAN, MX_ESTALL = 0, -1, -2, -3, -4, -5, -6
+MX_EHBM, MX_ETIMEOUT = -7, -8
 MX_BC_PEC, MX_BC_IMPEDANCE = 0, 1
 MX_AS, MX_RAS, MX_ORAS = 0, 1, 2
 MX_C128, MX_C64 = 0, 1
@@ -28,7 +29,9 @@ SYMBOLS = [
     "mx_partition_sizes", "mx_partition_export", "mx_partition_destroy", "mx_precond_setup",
     "mx_precond_apply", "mx_precond_get_info", "mx_precond_export_perm", "mx_precond_export_diag",
     "mx_precond_check", "mx_precond_destroy", "mx_gmres", "mx_selftest", "mx_local_problem",
-    "mx_precond_sweep_timing", "mx_precond_autotune",
+    "mx_precond_sweep_timing", "mx_precond_autotune", "mx_server_create", "mx_server_submit",
+    "mx_server_wait", "mx_server_solution", "mx_server_release", "mx_server_stats",
+    "mx_server_destroy",
 ]
 
 
@@ -63,6 +66,28 @@ class GmresOpts(C.Structure):
 class GmresStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("converged", C.c_int),
                 ("relres_true", C.c_double), ("relres_est", C.c_double), ("t_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("slots", C.c_int), ("kind", C.c_int),
+                ("precision", C.c_int), ("layers", C.c_int), ("restart", C.c_int),
+                ("max_iters", C.c_int), ("flexible", C.c_int), ("spmv_c64", C.c_int),
+                ("rtol", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("n", C.c_int), ("p", C.c_int), ("k", C.c_double), ("xi", C.c_double),
+                ("center", C.c_double * 3), ("pol", C.c_double * 3), ("sigma", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int), ("converged", C.c_int),
+                ("relres_true", C.c_double), ("n_dof", C.c_int64), ("footprint_bytes", C.c_uint64),
+                ("t_queue", C.c_double), ("t_host", C.c_double), ("t_device", C.c_double),
+                ("t_total", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +136,14 @@ def load(path=LIB_PATH):
         "mx_precond_export_diag": (C.c_int, [P, C.c_int, P]),
         "mx_precond_check": (C.c_int, [P]),
         "mx_precond_autotune": (C.c_int, [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+        "mx_server_create": (C.c_int, [C.c_int, C.POINTER(ServerOpts), C.POINTER(P)]),
+        "mx_server_submit": (C.c_int, [P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+        "mx_server_wait": (C.c_int, [P, C.c_uint64, C.c_double, C.POINTER(Result)]),
+        "mx_server_solution": (C.c_int, [P, C.c_uint64, P, C.c_int64]),
+        "mx_server_release": (C.c_int, [P, C.c_uint64]),
+        "mx_server_stats": (C.c_int, [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                      C.POINTER(C.c_int)]),
+        "mx_server_destroy": (None, [P]),
         "mx_precond_sweep_timing": (C.c_int, [P, C.c_int, C.POINTER(C.c_int64),
                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "mx_precond_destroy": (None, [P]),
@@ -337,3 +370,51 @@ def gmres(ctx, A, Pc, b, x, restart=50, rtol=1e-6, max_iters=1000, flexible=Fals
     if history:
         out["history"] = hist[: st.iters + 1].copy()
     return out
+
+
+class Server:
+    """Continuous-batching solve server (include/mx.h, mx_server_*)."""
+
+    def __init__(self, device=0, slots=4, hbm_budget=0, kind="oras", precision="c64", layers=2,
+                 restart=50, max_iters=1000, flexible=True, spmv_c64=False, rtol=1e-6):
+        load()
+        o = ServerOpts(hbm_budget, slots, KINDS.get(kind, kind), PRECISIONS.get(precision, precision),
+                       layers, restart, max_iters, int(flexible), int(spmv_c64), rtol)
+        h = P()
+        _check(_lib.mx_server_create(device, C.byref(o), C.byref(h)))
+        self.h = h
+        self.sizes = {}
+
+    def submit(self, n, p, k, xi, center=(0.5, 0.5, 0.5), pol=(1.0, 0.0, 0.0), sigma=0.1):
+        r = Request(n, p, k, xi, (C.c_double * 3)(*center), (C.c_double * 3)(*pol), sigma)
+        t = C.c_uint64()
+        _check(_lib.mx_server_submit(self.h, C.byref(r), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        res = Result()
+        _check(_lib.mx_server_wait(self.h, ticket, timeout, C.byref(res)))
+        out = res.as_dict()
+        if res.status != MX_OK:
+            out["error"] = _lib.mx_last_error().decode()
+        return out
+
+    def solution(self, ticket, n_dof):
+        x = np.zeros(n_dof, np.complex128)
+        _check(_lib.mx_server_solution(self.h, ticket, _ptr(x), n_dof))
+        return x
+
+    def release(self, ticket):
+        _check(_lib.mx_server_release(self.h, ticket))
+
+    def stats(self):
+        b, pk, ma = C.c_uint64(), C.c_uint64(), C.c_int()
+        _check(_lib.mx_server_stats(self.h, C.byref(b), C.byref(pk), C.byref(ma)))
+        return {"budget": b.value, "peak_used": pk.value, "max_admitted": ma.value}
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mx_server_destroy(self.h)
+        self.h = None
+
+    __del__ = close

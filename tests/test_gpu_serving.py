@@ -1,0 +1,70 @@
+"""Solve server (continuous batching): results are the same alone and in the mix, requests that
+can never fit the HBM budget are refused, and a served solution matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import dd, fem, gmres
+from oracle.mesh import Mesh as OMesh
+
+pytestmark = pytest.mark.gpu
+
+REQ = dict(n=10, p=2, k=5.0, xi=25.0, center=(0.45, 0.5, 0.55), pol=(0.6, 0.8, 0.0), sigma=0.1)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_alone_vs_in_the_mix(gpu_lib):
+    say("serve alone")
+    srv = gpu_lib.Server(slots=3, precision="c64", restart=50)
+    t = srv.submit(**REQ)
+    r = srv.wait(t, 120.0)
+    assert r["status"] == 0 and r["converged"], r
+    x_alone = srv.solution(t, r["n_dof"])
+    say("  alone", r)
+    # the same request among others of different sizes, k and xi, all in flight together
+    others = [dict(n=14, p=2, k=7.0, xi=7.0), dict(n=9, p=3, k=4.0, xi=16.0),
+              dict(n=16, p=2, k=8.0, xi=64.0), dict(n=12, p=2, k=6.0, xi=6.0)]
+    tickets = [srv.submit(**o) for o in others[:2]]
+    tm = srv.submit(**REQ)
+    tickets += [srv.submit(**o) for o in others[2:]]
+    rm = srv.wait(tm, 300.0)
+    for tk in tickets:
+        ro = srv.wait(tk, 300.0)
+        assert ro["status"] == 0 and ro["converged"], ro
+    x_mix = srv.solution(tm, rm["n_dof"])
+    st = srv.stats()
+    say("  mix", rm, st)
+    assert rm["iters"] == r["iters"]
+    assert np.array_equal(x_mix, x_alone)
+    assert st["max_admitted"] >= 2  # work of several requests overlapped on the device
+    srv.close()
+
+
+def test_budget_refusal(gpu_lib):
+    say("serve budget")
+    srv = gpu_lib.Server(slots=1, hbm_budget=1 << 20, precision="c64")
+    t = srv.submit(**REQ)
+    r = srv.wait(t, 60.0)
+    assert r["status"] == gpu_lib.MX_EHBM and r["footprint_bytes"] > (1 << 20)
+    srv.close()
+
+
+def test_served_solution_vs_oracle(gpu_lib):
+    say("serve vs oracle")
+    srv = gpu_lib.Server(slots=2, precision="c64", restart=50)
+    t = srv.submit(**REQ)
+    r = srv.wait(t, 120.0)
+    x = srv.solution(t, r["n_dof"])
+    srv.close()
+    n = REQ["n"]
+    om = OMesh(n, n, n)
+    A = fem.assemble(om, REQ["k"], REQ["xi"])
+    f = fem.load_vector(om, fem.gaussian_source(REQ["center"], REQ["pol"], REQ["sigma"]))
+    part = dd.Partition(om, 2, 2, 2, 2)
+    B = dd.Schwarz(part, A, dd.ORAS, REQ["k"], REQ["xi"])
+    ores = gmres.gmres(A, f, B, restart=50, rtol=1e-6)
+    err = np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x)
+    say("  served err vs oracle", err, "iters", r["iters"], ores.iters)
+    assert err <= 1e-5
