@@ -116,6 +116,7 @@ struct PrecondPlan {
   std::vector<int32_t> glob;
   std::vector<int64_t> src, sum_ptr, sum_idx;
   std::vector<int32_t> sched_sub, sched_blk;
+  std::vector<int32_t> csched_sub, csched_blk;  // streaming items of the chained sweeps
   size_t device_bytes = 0;    // peak device bytes of materialising and holding the preconditioner
 };
 }  // namespace mx
@@ -137,7 +138,9 @@ struct mx_precond {
   mx::DevBuf d_glob, d_src, d_sum_ptr, d_sum_idx;
   mx::DevBuf d_flags, d_ctrl, d_sched_sub, d_sched_blk;
   mx::DevBuf d_panel_pref, d_update_pref;
+  mx::DevBuf d_part, d_cflags, d_csched_sub, d_csched_blk;  // chained sweeps
   int n_items = 0, trsv_grid = 0;
+  int chain = 0, n_cf = 0, n_cb = 0;  // chained sweeps on; streaming items forward / backward
   mx_precond_info info{};
   // optional per-launch timing of the sweep kernel
   bool timing = false;

@@ -514,6 +514,247 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
   }
 }
 
+// ---- chained sweeps: one resident chain workgroup per subdomain + streaming workgroups ----------
+// The block recurrences of the forward and backward sweeps are split in two:
+//   forward : y_B = inv(L_BB) (r_B - p_B - sum_{t=1..CL} L_{B,B-t} y_{B-t}),
+//             p_B = sum_{J < B-CL} L_BJ y_J
+//   backward: z_B = inv(L_BB)^T (y_B / D_B - q_B - sum_{t=1..CL} L_{B+t,B}^T z_{B+t}),
+//             q_B = sum_{I > B+CL} L_IB^T z_I
+// Workgroup l < nsub is the chain of subdomain l: it walks the block rows in order, keeps the
+// last CL solved blocks in LDS and the CL+1 tiles of the next step prefetched in registers, so
+// consecutive diagonal solves never cross compute units.  The other workgroups stream the far
+// parts p_B / q_B (almost all of the bytes) and publish them with epoch flags; they are handed out
+// by ticket in an order in which an item only depends on chain progress that itself only depends
+// on items with smaller tickets.  Chains are the lowest workgroup ids, so they are dispatched (and
+// resident) before any streaming workgroup.  All waits are bounded.
+constexpr int kChainLag = 2;  // CL
+
+template <typename T, bool FWD>
+__global__ __launch_bounds__(kSweepThreads, 2) void k_sweep_chain(
+    SubView v, const cx<T> *__restrict__ pool, int nsub, const int32_t *__restrict__ sched_sub,
+    const int32_t *__restrict__ sched_blk, int n_items, const cx<T> *__restrict__ in,
+    cx<T> *out, cx<T> *part, int *flags_out, int *flags_part, int *ctrl) {
+  constexpr int CL = kChainLag;
+  __shared__ int s_item;
+  __shared__ int s_ok;
+  __shared__ cx<T> ring[CL][kTile];
+  __shared__ cx<T> s_vec[kTile];
+  __shared__ cx<T> s_out[kTile];
+  __shared__ cx<T> s_red[kSweepWaves][kTile];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int row0 = w * kRows;
+  const int epoch = ctrl[0];
+  int *abort = &ctrl[2];
+  if ((int)blockIdx.x < nsub) {
+    // ======================= chain of subdomain l =======================
+    const int l = blockIdx.x;
+    const int nb = v.nb[l], bb = v.brow_base[l];
+    const int64_t vb = v.vec_base[l];
+    cx<T> *pl = const_cast<cx<T> *>(pool);
+    for (int q = tid; q < CL * kTile; q += kSweepThreads) ring[q / kTile][q % kTile] = {0, 0};
+    cx<T> cur[CL + 1][kRows], nxt[CL + 1][kRows];
+    cx<T> dcur = {1, 0}, dnxt = {1, 0};
+    auto load_tiles = [&](int B, cx<T>(&dst)[CL + 1][kRows], cx<T> &d) {
+      const cx<T> *X = tile_ptr(pl, v, l, B, B);
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) dst[0][r] = X[(row0 + r) * kTile + lane];
+      if (!FWD) d = X[lane * kTile + lane];
+      if (FWD) {
+        const int f = v.bfirst[bb + B];
+#pragma unroll
+        for (int t = 1; t <= CL; ++t) {
+          const bool ok = B - t >= f;
+          const cx<T> *Lt = ok ? tile_ptr(pl, v, l, B, B - t) : X;
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) dst[t][r] = ok ? Lt[(row0 + r) * kTile + lane] : cx<T>{0, 0};
+        }
+      } else {
+        const int last = v.blast[bb + B];
+#pragma unroll
+        for (int t = 1; t <= CL; ++t) {
+          const bool ok = B + t <= last;
+          const cx<T> *Lt = ok ? tile_ptr(pl, v, l, B + t, B) : X;
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) dst[t][r] = ok ? Lt[(row0 + r) * kTile + lane] : cx<T>{0, 0};
+        }
+      }
+    };
+    const int B0 = FWD ? 0 : nb - 1, step = FWD ? 1 : -1;
+    load_tiles(B0, cur, dcur);
+    __syncthreads();  // ring cleared
+    for (int it = 0; it < nb; ++it) {
+      const int B = B0 + step * it;
+      if (it + 1 < nb) load_tiles(B + step, nxt, dnxt);
+      const bool need_p = FWD ? v.bfirst[bb + B] <= B - CL - 1 : v.blast[bb + B] >= B + CL + 1;
+      const cx<T> inB = in[vb + (int64_t)B * kTile + lane];
+      cx<T> pB = {0, 0};
+      if (need_p) {
+        if (w == 0) {
+          const int e = ready_run(flags_part + bb, B, B + 1, 1, epoch, abort);
+          if (lane == 0) s_ok = e;
+        }
+        __syncthreads();
+        const int ok = s_ok;
+        __syncthreads();
+        if (ok == INT_MIN) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        pB = part[vb + (int64_t)B * kTile + lane];
+      }
+      if (FWD) {
+        cx<T> acc[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) acc[r] = {0, 0};
+#pragma unroll
+        for (int t = 1; t <= CL; ++t) {
+          const cx<T> yv = ring[(B - t + CL) % CL][lane];
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) cfma(acc[r], cur[t][r], yv);
+        }
+        cx<T> s = butterfly8(acc);
+        if ((lane & 7) == 0) s_vec[row0 + (lane >> 3)] = s;
+        __syncthreads();
+        const cx<T> tm = csub(csub(inB, pB), s_vec[lane]);
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) acc[r] = lane < row0 + r ? cmul(cur[0][r], tm) : cx<T>{0, 0};
+        s = butterfly8(acc);
+        if ((lane & 7) == 0) s_out[row0 + (lane >> 3)] = s;
+        __syncthreads();
+        if (w == 0) ring[B % CL][lane] = cadd(tm, s_out[lane]);
+      } else {
+        cx<T> acc = {0, 0};
+#pragma unroll
+        for (int t = 1; t <= CL; ++t)
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) cfma(acc, cur[t][r], ring[(B + t) % CL][row0 + r]);
+        s_red[w][lane] = acc;
+        __syncthreads();
+        if (w == 0) {
+          cx<T> t = s_red[0][lane];
+#pragma unroll
+          for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
+          s_vec[lane] = csub(csub(cdiv(inB, dcur), pB), t);
+        }
+        __syncthreads();
+        acc = {0, 0};
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+          if (row0 + r > lane) cfma(acc, cur[0][r], s_vec[row0 + r]);
+        s_red[w][lane] = acc;
+        __syncthreads();
+        if (w == 0) {
+          cx<T> t = s_red[0][lane];
+#pragma unroll
+          for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
+          ring[B % CL][lane] = cadd(s_vec[lane], t);
+        }
+      }
+      __syncthreads();  // ring[B] complete
+      if (w == 0) {
+        out[vb + (int64_t)B * kTile + lane] = ring[B % CL][lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) store_flag(&flags_out[bb + B], epoch);
+      }
+#pragma unroll
+      for (int t = 0; t <= CL; ++t)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) cur[t][r] = nxt[t][r];
+      dcur = dnxt;
+      if (load_flag(abort)) return;
+    }
+    return;
+  }
+  // ======================= streaming workgroups =======================
+  int *ticket = &ctrl[FWD ? 1 : 4];
+  while (true) {
+    if (tid == 0) {
+      int t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = load_flag(abort) ? n_items : t;
+    }
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int l = sched_sub[item], B = sched_blk[item];
+    const int bb = v.brow_base[l];
+    const int64_t vb = v.vec_base[l];
+    int *fl = flags_out + bb;
+    if (FWD) {
+      const int f = v.bfirst[bb + B];
+      const cx<T> *row = pool + (v.tile_base[l] + v.brow_off[bb + B]) * (int64_t)kTileElems;
+      cx<T> acc[kRows];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) acc[r] = {0, 0};
+      const int Jlim = B - CL;  // tiles f .. B-CL-1
+      int J = f;
+      while (J < Jlim) {
+        if (w == 0) {
+          const int e = ready_run(fl, J, Jlim, 1, epoch, abort);
+          if (lane == 0) s_ok = e;
+        }
+        __syncthreads();
+        const int Jend = s_ok;
+        __syncthreads();
+        if (Jend == INT_MIN) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        for (; J + 3 < Jend; J += 4)
+          stream_fwd<T, 4>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
+                           out + vb + (int64_t)J * kTile + lane, acc);
+        for (; J < Jend; ++J)
+          stream_fwd<T, 1>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
+                           out + vb + (int64_t)J * kTile + lane, acc);
+      }
+      cx<T> s = butterfly8(acc);
+      if ((lane & 7) == 0) s_out[row0 + (lane >> 3)] = s;
+      __syncthreads();
+      if (w == 0) {
+        part[vb + (int64_t)B * kTile + lane] = s_out[lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) store_flag(&flags_part[bb + B], epoch);
+      }
+    } else {
+      const int last = v.blast[bb + B];
+      const int Ilim = B + CL;  // tiles last .. B+CL+1
+      cx<T> acc = {0, 0};
+      int I = last;
+      while (I > Ilim) {
+        if (w == 0) {
+          const int e = ready_run(fl, I, Ilim, -1, epoch, abort);
+          if (lane == 0) s_ok = e;
+        }
+        __syncthreads();
+        const int Iend = s_ok;
+        __syncthreads();
+        if (Iend == INT_MIN) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        for (; I - 3 > Iend; I -= 4) {
+          const cx<T> *tp[4], *zp[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            tp[t] = tile_ptr(const_cast<cx<T> *>(pool), v, l, I - t, B) + row0 * kTile + lane;
+            zp[t] = out + vb + (int64_t)(I - t) * kTile + row0;
+          }
+          stream_bwd<T, 4>(tp, zp, acc);
+        }
+        for (; I > Iend; --I) {
+          const cx<T> *tp[1] = {tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + row0 * kTile + lane};
+          const cx<T> *zp[1] = {out + vb + (int64_t)I * kTile + row0};
+          stream_bwd<T, 1>(tp, zp, acc);
+        }
+      }
+      s_red[w][lane] = acc;
+      __syncthreads();
+      if (w == 0) {
+        cx<T> t = s_red[0][lane];
+#pragma unroll
+        for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
+        part[vb + (int64_t)B * kTile + lane] = t;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) store_flag(&flags_part[bb + B], epoch);
+      }
+    }
+  }
+}
+
 // ---- host side ------------------------------------------------------------------------------------
 static SubView view_of(const mx_precond *P) {
   SubView v;
@@ -569,6 +810,18 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
     MX_HIP(hipEventRecord(P->ev_start[P->n_timed], st));
   }
   const int half = P->n_items / 2;
+  if (P->chain) {
+    int *cfl = P->d_cflags.as<int>();
+    const int32_t *cs = P->d_csched_sub.as<int32_t>(), *cbk = P->d_csched_blk.as<int32_t>();
+    k_sweep_chain<T, true><<<P->trsv_grid, kSweepThreads, 0, st>>>(
+        v, P->pool.as<cx<T>>(), P->nsub, cs, cbk, P->n_cf, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
+        P->d_part.as<cx<T>>(), flags, cfl, P->d_ctrl.as<int>());
+    if (P->timing) MX_HIP(hipEventRecord(P->ev_mid[P->n_timed], st));
+    k_sweep_chain<T, false><<<P->trsv_grid, kSweepThreads, 0, st>>>(
+        v, P->pool.as<cx<T>>(), P->nsub, cs + P->n_cf, cbk + P->n_cf, P->n_cb, P->d_y.as<cx<T>>(),
+        P->d_z.as<cx<T>>(), P->d_part.as<cx<T>>(), flags + P->blocks_total, cfl + P->blocks_total,
+        P->d_ctrl.as<int>());
+  } else {
   k_sweep<T, true><<<P->trsv_grid, kSweepThreads, 0, st>>>(
       v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(), half,
       P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), flags, P->d_ctrl.as<int>());
@@ -577,6 +830,7 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
       v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>() + half,
       P->d_sched_blk.as<int32_t>() + half, half, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
       P->d_z.as<cx<T>>(), flags + P->blocks_total, P->d_ctrl.as<int>());
+  }
   if (P->timing) MX_HIP(hipEventRecord(P->ev_stop[P->n_timed++], st));
   const int64_t E = P->E;
   if (P->kind == MX_AS)
@@ -632,7 +886,8 @@ void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_
   double best_t = 1e300;
   for (int g : cand) {
     if (g < 1) continue;
-    P->trsv_grid = std::min(g, std::max(1, P->n_items / 2));
+    if (P->chain && g < 2 * P->nsub) continue;
+    P->trsv_grid = P->chain ? g : std::min(g, std::max(1, P->n_items / 2));
     precond_apply(P, vin.p, zout.p, st);  // warm-up
     MX_HIP(hipEventRecord(a, st));
     for (int r = 0; r < 3; ++r) precond_apply(P, vin.p, zout.p, st);
@@ -857,6 +1112,29 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     }
   P->n_items = (int)sched_sub.size();
   {
+    std::vector<Item> cf, cb;
+    for (int l = 0; l < N; ++l) {
+      const Skyline &sk = P->sky[l];
+      const int64_t nb = sk.nb;
+      for (int64_t I = 0; I < nb; ++I) {
+        if (sk.bfirst[I] <= I - kChainLag - 1) cf.push_back({(I + 0.5) / nb, l, (int32_t)I});
+        const int64_t J = nb - 1 - I;
+        if (sk.blast[J] >= J + kChainLag + 1) cb.push_back({(I + 0.5) / nb, l, (int32_t)J});
+      }
+    }
+    std::sort(cf.begin(), cf.end(), by_key);
+    std::sort(cb.begin(), cb.end(), by_key);
+    plan.csched_sub.clear();
+    plan.csched_blk.clear();
+    for (const auto *lst : {&cf, &cb})
+      for (const auto &it : *lst) {
+        plan.csched_sub.push_back(it.l);
+        plan.csched_blk.push_back(it.b);
+      }
+    P->n_cf = (int)cf.size();
+    P->n_cb = (int)cb.size();
+  }
+  {
     // persistent sweeps: as many workgroups as can be resident at once
     int per_cu = 1;
     if (P->prec == MX_C128)
@@ -867,7 +1145,10 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     // dependency chain of the first one more than it adds bandwidth (measured)
     (void)per_cu;
     int grid = opts->sweep_grid > 0 ? opts->sweep_grid : ctx->cus;
-    P->trsv_grid = std::max(1, std::min(P->n_items / 2, grid));
+    const bool can_chain = 2 * N <= grid;
+    if (opts->sweep_mode == 2 && !can_chain) fail(MX_EINVAL, "chained sweeps need subdomains <= grid / 2");
+    P->chain = (opts->sweep_mode == 2 || (opts->sweep_mode == 0 && can_chain)) ? 1 : 0;
+    P->trsv_grid = P->chain ? grid : std::max(1, std::min(P->n_items / 2, grid));
   }
   const double t1 = now_s();
   P->info.t_host_setup = t1 - t0;
@@ -876,7 +1157,8 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
                       2 * (size_t)blocks * 4 + 16 * (size_t)blocks +
                       4 * (size_t)vec + 8 * (size_t)std::max(src.size(), sum_idx.size() + sum_ptr.size()) +
                       8 * (size_t)sched_sub.size() + 8 * P->panel_pref.size() +
-                      24 * off.size() + (1 << 20);
+                      24 * off.size() + (1 << 20) +
+                      (P->chain ? (size_t)vec * esz + 8 * (size_t)blocks + 8 * plan.csched_sub.size() : 0);
 }
 
 void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
@@ -911,6 +1193,13 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   P->d_update_pref.upload(P->update_pref);
   P->d_sched_sub.upload(sched_sub);
   P->d_sched_blk.upload(sched_blk);
+  if (P->chain) {
+    P->d_csched_sub.upload(plan.csched_sub);
+    P->d_csched_blk.upload(plan.csched_blk);
+    P->d_part.alloc(vec * (P->prec == MX_C128 ? 16 : 8));
+    P->d_cflags.alloc(2 * blocks * sizeof(int));
+    MX_HIP(hipMemsetAsync(P->d_cflags.p, 0, 2 * blocks * sizeof(int), st));
+  }
   P->d_r.alloc(vec * esz);
   P->d_y.alloc(vec * esz);
   P->d_z.alloc(vec * esz);
