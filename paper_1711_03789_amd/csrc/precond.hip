@@ -648,18 +648,20 @@ __global__ __launch_bounds__(kSweepThreads, 2) void k_sweep_chain(
           ring[B % CL][lane] = cadd(s_vec[lane], t);
         }
       }
-      __syncthreads();  // ring[B] complete
+      if (tid == 0) s_item = load_flag(abort);
+      __syncthreads();  // ring[B] complete; abort word read once for the whole workgroup
+      const int stop = s_item;
       if (w == 0) {
         out[vb + (int64_t)B * kTile + lane] = ring[B % CL][lane];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (lane == 0) store_flag(&flags_out[bb + B], epoch);
       }
+      if (stop) return;
 #pragma unroll
       for (int t = 0; t <= CL; ++t)
 #pragma unroll
         for (int r = 0; r < kRows; ++r) cur[t][r] = nxt[t][r];
       dcur = dnxt;
-      if (load_flag(abort)) return;
     }
     return;
   }
