@@ -154,6 +154,26 @@ __device__ __forceinline__ int load_flag(const int *p) {
 __device__ __forceinline__ void store_flag(int *p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Cross-workgroup publication of small results (one 64-entry block) without cache-wide fences:
+// the producer writes with device-coherent atomic stores, waits until its stores are complete and
+// only then stores the flag; the consumer reads the flag and then the data with device-coherent
+// atomic loads, which cannot hit a stale line in a non-coherent cache.  Whole-cache writeback /
+// invalidate fences at agent scope would cost more than the data moved (measured: they halve the
+// streaming bandwidth of the sweeps).
+template <typename T>
+__device__ __forceinline__ void pub_store(cx<T> *p, cx<T> v) {
+  __hip_atomic_store(&p->re, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->im, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> pub_load(const cx<T> *p) {
+  return {__hip_atomic_load(&p->re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+          __hip_atomic_load(&p->im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+}
+// Wait until every memory operation issued by this wave has completed (vmcnt = 0; expcnt and
+// lgkmcnt left unconstrained).
+__device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Spins until *flag == want; returns false (and raises *abort) after kSpinLimit polls or when
 // another workgroup has raised *abort.
 __device__ inline bool wait_flag(const int *flag, int want, int *abort) {

@@ -298,7 +298,7 @@ __device__ __forceinline__ void stream_fwd(const cx<T> *tp, const cx<T> *yp, cx<
   cx<T> a[NT][kRows], y[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    y[t] = yp[t * kTile];
+    y[t] = pub_load(yp + t * kTile);
 #pragma unroll
     for (int r = 0; r < kRows; ++r) a[t][r] = tp[(int64_t)t * kTileElems + r * kTile];
   }
@@ -321,7 +321,7 @@ __device__ __forceinline__ void stream_bwd(const cx<T> *const tp[NT], const cx<T
   cx<T> a[NT][kRows], z[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    z[t] = zp[t][lane & (kRows - 1)];
+    z[t] = pub_load(zp[t] + (lane & (kRows - 1)));
 #pragma unroll
     for (int r = 0; r < kRows; ++r) a[t][r] = tp[t][r * kTile];
   }
@@ -388,7 +388,6 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
         const int Jend = s_ok;
         __syncthreads();
         if (Jend == INT_MIN) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         for (; J + 3 < Jend; J += 4)
           stream_fwd<T, 4>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
                            yvec + vb + (int64_t)J * kTile + lane, acc);
@@ -406,8 +405,7 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       if (has_prev) {
         const int ok = s_ok;
         if (ok == INT_MIN) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const cx<T> y0 = yvec[vb + (int64_t)(B - 1) * kTile + lane];
+        const cx<T> y0 = pub_load(yvec + vb + (int64_t)(B - 1) * kTile + lane);
 #pragma unroll
         for (int r = 0; r < kRows; ++r) cfma(acc[r], sL[row0 + r][lane], y0);
       }
@@ -423,8 +421,8 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       if ((lane & 7) == 0) s_out[row0 + (lane >> 3)] = s;
       __syncthreads();
       if (w == 0) {
-        yvec[vb + (int64_t)B * kTile + lane] = cadd(tm, s_out[lane]);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        pub_store(yvec + vb + (int64_t)B * kTile + lane, cadd(tm, s_out[lane]));
+        stores_complete();
         if (lane == 0) store_flag(&fl[B], epoch);
       }
     } else {
@@ -455,7 +453,6 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
         const int Iend = s_ok;
         __syncthreads();
         if (Iend == INT_MIN) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         for (; I - 3 > Iend; I -= 4) {
           const cx<T> *tp[4], *zp[4];
 #pragma unroll
@@ -481,8 +478,7 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       if (has_next) {
         const int ok = s_ok;
         if (ok == INT_MIN) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const cx<T> zv = zvec[vb + (int64_t)(B + 1) * kTile + row0 + (lane & (kRows - 1))];
+        const cx<T> zv = pub_load(zvec + vb + (int64_t)(B + 1) * kTile + row0 + (lane & (kRows - 1)));
 #pragma unroll
         for (int r = 0; r < kRows; ++r) cfma(acc, sL[row0 + r][lane], bcast(zv, r));
       }
@@ -506,8 +502,8 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
         cx<T> t = s_red[0][lane];
 #pragma unroll
         for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
-        zvec[vb + (int64_t)B * kTile + lane] = cadd(s_vec[lane], t);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        pub_store(zvec + vb + (int64_t)B * kTile + lane, cadd(s_vec[lane], t));
+        stores_complete();
         if (lane == 0) store_flag(&fl[B], epoch);
       }
     }
@@ -597,8 +593,7 @@ __global__ __launch_bounds__(kSweepThreads, 2) void k_sweep_chain(
         const int ok = s_ok;
         __syncthreads();
         if (ok == INT_MIN) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        pB = part[vb + (int64_t)B * kTile + lane];
+        pB = pub_load(part + vb + (int64_t)B * kTile + lane);
       }
       if (FWD) {
         cx<T> acc[kRows];
@@ -652,8 +647,8 @@ __global__ __launch_bounds__(kSweepThreads, 2) void k_sweep_chain(
       __syncthreads();  // ring[B] complete; abort word read once for the whole workgroup
       const int stop = s_item;
       if (w == 0) {
-        out[vb + (int64_t)B * kTile + lane] = ring[B % CL][lane];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        pub_store(out + vb + (int64_t)B * kTile + lane, ring[B % CL][lane]);
+        stores_complete();
         if (lane == 0) store_flag(&flags_out[bb + B], epoch);
       }
       if (stop) return;
@@ -697,7 +692,6 @@ __global__ __launch_bounds__(kSweepThreads, 2) void k_sweep_chain(
         const int Jend = s_ok;
         __syncthreads();
         if (Jend == INT_MIN) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         for (; J + 3 < Jend; J += 4)
           stream_fwd<T, 4>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
                            out + vb + (int64_t)J * kTile + lane, acc);
@@ -709,8 +703,8 @@ __global__ __launch_bounds__(kSweepThreads, 2) void k_sweep_chain(
       if ((lane & 7) == 0) s_out[row0 + (lane >> 3)] = s;
       __syncthreads();
       if (w == 0) {
-        part[vb + (int64_t)B * kTile + lane] = s_out[lane];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        pub_store(part + vb + (int64_t)B * kTile + lane, s_out[lane]);
+        stores_complete();
         if (lane == 0) store_flag(&flags_part[bb + B], epoch);
       }
     } else {
@@ -727,7 +721,6 @@ __global__ __launch_bounds__(kSweepThreads, 2) void k_sweep_chain(
         const int Iend = s_ok;
         __syncthreads();
         if (Iend == INT_MIN) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         for (; I - 3 > Iend; I -= 4) {
           const cx<T> *tp[4], *zp[4];
 #pragma unroll
@@ -749,8 +742,8 @@ __global__ __launch_bounds__(kSweepThreads, 2) void k_sweep_chain(
         cx<T> t = s_red[0][lane];
 #pragma unroll
         for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
-        part[vb + (int64_t)B * kTile + lane] = t;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        pub_store(part + vb + (int64_t)B * kTile + lane, t);
+        stores_complete();
         if (lane == 0) store_flag(&flags_part[bb + B], epoch);
       }
     }
