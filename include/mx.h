@@ -123,8 +123,8 @@ typedef struct {
   double xi_prec;  /* absorption of the local problems (ORAS local assembly; AS/RAS use A's)  */
   int precision;   /* MX_C128 | MX_C64 (local factors and local solves)                       */
   int sweep_grid;  /* workgroups of the persistent sweep kernels; 0 = one per compute unit      */
-  int sweep_mode;  /* 0 auto, 1 ticketed block rows only, 2 one resident chain workgroup per    */
-                   /* subdomain plus streaming workgroups (auto: 2 when subdomains <= grid/2)   */
+  int sweep_mode;  /* 0 or 1: ticketed block rows (default); 2: one resident chain workgroup per */
+                   /* subdomain plus streaming workgroups (needs subdomains <= grid / 2)        */
   int sub_begin;   /* resident share: build only subdomains [sub_begin, sub_end) (both 0 = all); */
   int sub_end;     /* the application then returns the share's part of the sum (zero elsewhere)*/
 } mx_precond_opts;

@@ -337,8 +337,8 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
     const int32_t *__restrict__ sched_blk, int n_items, const cx<T> *__restrict__ rvec, cx<T> *yvec,
     cx<T> *zvec, int *flags, int *ctrl) {
   __shared__ int s_item;
-  __shared__ int s_ok;
-  __shared__ cx<T> sL[kTile][kTile];  // neighbour tile of the last dependency
+  __shared__ int s_dead;
+  __shared__ cx<T> sL[kTile][kTile];  // neighbour tile of the last dependency (own wave's rows)
   __shared__ cx<T> sX[kTile][kTile];  // diagonal tile (inverse unit-lower factor, D on the diagonal)
   __shared__ cx<T> s_vec[kTile];
   __shared__ cx<T> s_out[kTile];
@@ -352,6 +352,7 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
     if (tid == 0) {
       int t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       s_item = load_flag(abort) ? n_items : t;
+      s_dead = 0;
     }
     __syncthreads();
     const int item = s_item;
@@ -361,11 +362,14 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
     const int bb = v.brow_base[l];
     const int64_t vb = v.vec_base[l];
     int *fl = flags + bb;
+    // Every wave streams its own 8 rows of each tile and checks the readiness of the rows it
+    // needs by itself (one ballot per 64 flags), so waves only meet at the final reductions.
+    bool dead = false;
     if (FWD) {
       const int f = v.bfirst[bb + B];
       const cx<T> *row = pool + (v.tile_base[l] + v.brow_off[bb + B]) * (int64_t)kTileElems;
       const bool has_prev = B - 1 >= f;
-      {  // stage the diagonal tile and the (B, B-1) tile
+      {  // stage this wave's rows of the diagonal tile and of the (B, B-1) tile
         const cx<T> *xp = row + (int64_t)(B - f) * kTileElems + row0 * kTile + lane;
         const cx<T> *lp = row + (int64_t)(B - 1 - f) * kTileElems + row0 * kTile + lane;
 #pragma unroll
@@ -380,14 +384,11 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       const cx<T> rB = rvec[vb + (int64_t)B * kTile + lane];
       int J = f;
       while (J < B - 1) {
-        if (w == 0) {
-          const int e = ready_run(fl, J, B - 1, 1, epoch, abort);
-          if (lane == 0) s_ok = e;
+        const int Jend = ready_run(fl, J, B - 1, 1, epoch, abort);
+        if (Jend == INT_MIN) {
+          dead = true;
+          break;
         }
-        __syncthreads();
-        const int Jend = s_ok;
-        __syncthreads();
-        if (Jend == INT_MIN) return;
         for (; J + 3 < Jend; J += 4)
           stream_fwd<T, 4>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
                            yvec + vb + (int64_t)J * kTile + lane, acc);
@@ -395,20 +396,16 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
           stream_fwd<T, 1>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
                            yvec + vb + (int64_t)J * kTile + lane, acc);
       }
-      if (has_prev) {
-        if (w == 0) {
-          const int e = ready_run(fl, B - 1, B, 1, epoch, abort);
-          if (lane == 0) s_ok = e;
+      if (has_prev && !dead) {
+        if (ready_run(fl, B - 1, B, 1, epoch, abort) == INT_MIN) {
+          dead = true;
+        } else {
+          const cx<T> y0 = pub_load(yvec + vb + (int64_t)(B - 1) * kTile + lane);
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) cfma(acc[r], sL[row0 + r][lane], y0);
         }
       }
-      __syncthreads();  // also makes the staged tiles visible
-      if (has_prev) {
-        const int ok = s_ok;
-        if (ok == INT_MIN) return;
-        const cx<T> y0 = pub_load(yvec + vb + (int64_t)(B - 1) * kTile + lane);
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) cfma(acc[r], sL[row0 + r][lane], y0);
-      }
+      if (dead && lane == 0) s_dead = 1;
       cx<T> s = butterfly8(acc);
       if ((lane & 7) == 0) s_vec[row0 + (lane >> 3)] = s;
       __syncthreads();
@@ -420,7 +417,7 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       s = butterfly8(acc);
       if ((lane & 7) == 0) s_out[row0 + (lane >> 3)] = s;
       __syncthreads();
-      if (w == 0) {
+      if (w == 0 && !s_dead) {
         pub_store(yvec + vb + (int64_t)B * kTile + lane, cadd(tm, s_out[lane]));
         stores_complete();
         if (lane == 0) store_flag(&fl[B], epoch);
@@ -429,7 +426,7 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       const int last = v.blast[bb + B];
       const cx<T> *X = tile_ptr(const_cast<cx<T> *>(pool), v, l, B, B);
       const bool has_next = B + 1 <= last;
-      {  // stage the diagonal tile and the (B+1, B) tile
+      {  // stage this wave's rows of the diagonal tile and of the (B+1, B) tile
         const cx<T> *xp = X + row0 * kTile + lane;
         const cx<T> *lp = has_next ? tile_ptr(const_cast<cx<T> *>(pool), v, l, B + 1, B) + row0 * kTile + lane
                                    : xp;
@@ -445,14 +442,11 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       // rows far below B finish first: consume I = last, last-1, ..., B+2 as they become ready
       int I = last;
       while (I > B + 1) {
-        if (w == 0) {
-          const int e = ready_run(fl, I, B + 1, -1, epoch, abort);
-          if (lane == 0) s_ok = e;
+        const int Iend = ready_run(fl, I, B + 1, -1, epoch, abort);
+        if (Iend == INT_MIN) {
+          dead = true;
+          break;
         }
-        __syncthreads();
-        const int Iend = s_ok;
-        __syncthreads();
-        if (Iend == INT_MIN) return;
         for (; I - 3 > Iend; I -= 4) {
           const cx<T> *tp[4], *zp[4];
 #pragma unroll
@@ -468,20 +462,16 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
           stream_bwd<T, 1>(tp, zp, acc);
         }
       }
-      if (has_next) {
-        if (w == 0) {
-          const int e = ready_run(fl, B + 1, B, -1, epoch, abort);
-          if (lane == 0) s_ok = e;
+      if (has_next && !dead) {
+        if (ready_run(fl, B + 1, B, -1, epoch, abort) == INT_MIN) {
+          dead = true;
+        } else {
+          const cx<T> zv = pub_load(zvec + vb + (int64_t)(B + 1) * kTile + row0 + (lane & (kRows - 1)));
+#pragma unroll
+          for (int r = 0; r < kRows; ++r) cfma(acc, sL[row0 + r][lane], bcast(zv, r));
         }
       }
-      __syncthreads();  // also makes the staged tiles visible
-      if (has_next) {
-        const int ok = s_ok;
-        if (ok == INT_MIN) return;
-        const cx<T> zv = pub_load(zvec + vb + (int64_t)(B + 1) * kTile + row0 + (lane & (kRows - 1)));
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) cfma(acc, sL[row0 + r][lane], bcast(zv, r));
-      }
+      if (dead && lane == 0) s_dead = 1;
       s_red[w][lane] = acc;
       __syncthreads();
       if (w == 0) {
@@ -498,7 +488,7 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
         if (row0 + r > lane) cfma(acc, sX[row0 + r][lane], s_vec[row0 + r]);
       s_red[w][lane] = acc;
       __syncthreads();
-      if (w == 0) {
+      if (w == 0 && !s_dead) {
         cx<T> t = s_red[0][lane];
 #pragma unroll
         for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
@@ -1142,7 +1132,10 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     int grid = opts->sweep_grid > 0 ? opts->sweep_grid : ctx->cus;
     const bool can_chain = 2 * N <= grid;
     if (opts->sweep_mode == 2 && !can_chain) fail(MX_EINVAL, "chained sweeps need subdomains <= grid / 2");
-    P->chain = (opts->sweep_mode == 2 || (opts->sweep_mode == 0 && can_chain)) ? 1 : 0;
+    // ticketed block rows are the default: measured faster than the chained schedule once the
+    // block results are published without cache-wide fences
+    P->chain = opts->sweep_mode == 2 ? 1 : 0;
+    (void)can_chain;
     P->trsv_grid = P->chain ? grid : std::max(1, std::min(P->n_items / 2, grid));
   }
   const double t1 = now_s();
