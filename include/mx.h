@@ -123,8 +123,6 @@ typedef struct {
   double xi_prec;  /* absorption of the local problems (ORAS local assembly; AS/RAS use A's)  */
   int precision;   /* MX_C128 | MX_C64 (local factors and local solves)                       */
   int sweep_grid;  /* workgroups of the persistent sweep kernels; 0 = one per compute unit      */
-  int sweep_mode;  /* 0 or 1: ticketed block rows (default); 2: one resident chain workgroup per */
-                   /* subdomain plus streaming workgroups (needs subdomains <= grid / 2)        */
   int sub_begin;   /* resident share: build only subdomains [sub_begin, sub_end) (both 0 = all); */
   int sub_end;     /* the application then returns the share's part of the sum (zero elsewhere)*/
 } mx_precond_opts;
@@ -144,7 +142,7 @@ typedef struct {
   int64_t n_local_total;        /* sum of local sizes                                          */
   int64_t max_local, max_blocks;
   int64_t tiles;                /* stored tiles (tile x tile complex each)                     */
-  int64_t factor_bytes;         /* device bytes of the factor tiles                            */
+  int64_t factor_bytes;         /* device bytes of the factor tiles (held during the factorisation)*/
   int64_t env_entries;          /* sum over subdomains of the exact lower envelope (diag incl.)*/
   double env_flops;             /* 8 * sum_i w_i^2 / 2 real flops (envelope LDL^T)             */
   double tile_flops;            /* real flops of the blocked factorisation as executed         */
@@ -152,6 +150,8 @@ typedef struct {
   int64_t sweep_bytes;          /* algorithmic bytes of one block-sweep launch (either direction):*/
                                 /* the envelope factor read once and three local-vector passes   */
   double t_host_setup, t_upload, t_factor; /* seconds of the last mx_precond_setup phases      */
+  int64_t pack_bytes;           /* device bytes of the packed row-envelope factor read by the    */
+                                /* sweeps (each row 8-entry aligned; diagonal blocks in full)    */
 } mx_precond_info;
 
 /* Builds the local matrices (AS/RAS: minors of A, so the matrix's k, xi and bc are used; ORAS:

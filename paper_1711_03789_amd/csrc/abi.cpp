@@ -283,23 +283,7 @@ int mx_precond_export_diag(const mx_precond *P, int l, double *d) {
     MX_REQUIRE(l >= 0 && l < P->nsub, "subdomain out of range");
     bind_device(P->device);
     const auto &s = P->sky[l];
-    const size_t esz = P->prec == MX_C128 ? 16 : 8;
-    std::vector<char> tile((mx::TILE * mx::TILE) * esz);
-    for (int64_t I = 0; I < s.nb; ++I) {
-      int64_t t = P->sub_tile_base[l] + s.brow_off[I] + (I - s.bfirst[I]);
-      MX_HIP(hipMemcpy(tile.data(), P->pool.as<char>() + t * (mx::TILE * mx::TILE) * esz, tile.size(),
-                       hipMemcpyDeviceToHost));
-      for (int i = 0; i < mx::TILE && I * mx::TILE + i < s.n; ++i) {
-        int64_t q = (int64_t)i * mx::TILE + i, o = I * mx::TILE + i;
-        if (P->prec == MX_C128) {
-          std::memcpy(d + 2 * o, tile.data() + q * 16, 16);
-        } else {
-          float f[2];
-          std::memcpy(f, tile.data() + q * 8, 8);
-          d[2 * o] = f[0], d[2 * o + 1] = f[1];
-        }
-      }
-    }
+    mx::precond_export_diag(P, l, d);
   });
 }
 

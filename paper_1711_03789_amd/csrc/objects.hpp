@@ -116,7 +116,8 @@ struct PrecondPlan {
   std::vector<int32_t> glob;
   std::vector<int64_t> src, sum_ptr, sum_idx;
   std::vector<int32_t> sched_sub, sched_blk;
-  std::vector<int32_t> csched_sub, csched_blk;  // streaming items of the chained sweeps
+  std::vector<int64_t> rmeta, cmeta;  // trimmed-tile (base, row mask) pairs: tile order, block-column order
+  std::vector<int64_t> cptr;          // start of each block column in cmeta
   size_t device_bytes = 0;    // peak device bytes of materialising and holding the preconditioner
 };
 }  // namespace mx
@@ -133,14 +134,14 @@ struct mx_precond {
   // device
   mx::DevBuf d_sub_nb, d_sub_brow_base, d_sub_tile_base, d_sub_vec_base;
   mx::DevBuf d_brow_off, d_bfirst, d_blast;
-  mx::DevBuf pool;
+  mx::DevBuf pool;                          // 64x64 tiles (factorisation only)
+  mx::DevBuf pack, d_rmeta, d_cmeta, d_cptr;  // trimmed tiles of the factor (sweeps)
+  int64_t pack_entries = 0;
   mx::DevBuf d_r, d_y, d_z;                 // local vectors (factor precision)
   mx::DevBuf d_glob, d_src, d_sum_ptr, d_sum_idx;
   mx::DevBuf d_flags, d_ctrl, d_sched_sub, d_sched_blk;
   mx::DevBuf d_panel_pref, d_update_pref;
-  mx::DevBuf d_part, d_cflags, d_csched_sub, d_csched_blk;  // chained sweeps
   int n_items = 0, trsv_grid = 0;
-  int chain = 0, n_cf = 0, n_cb = 0;  // chained sweeps on; streaming items forward / backward
   mx_precond_info info{};
   // optional per-launch timing of the sweep kernel
   bool timing = false;
@@ -165,6 +166,7 @@ size_t gmres_device_bytes(int64_t n, int restart, bool flexible);
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st);
 int precond_check(mx_precond *P, hipStream_t st = nullptr);
 void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_grid, double *best_ms);
+void precond_export_diag(const mx_precond *P, int l, double *d);
 void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd, double *ms_bwd);
 void spmv_run(const mx_matrix *A, const void *x, void *y, bool c64, hipStream_t st);
 void matrix_upload(mx_matrix *A);

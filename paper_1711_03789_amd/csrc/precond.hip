@@ -25,11 +25,28 @@
 namespace mx {
 
 // ---- tile addressing ---------------------------------------------------------------------------
+// After the factorisation a tile keeps only its rows that meet the envelope (row i of block row I
+// is kept in tile (I, J) iff first_i < 64 (J + 1); diagonal tiles keep all rows), packed as
+// consecutive 64-entry rows from pack[base]; the kept row with index r inside the tile is the
+// popcount(mask & (2^r - 1))-th one.
+struct TileMeta {
+  int64_t base;
+  uint64_t mask;
+};
+
+__device__ __forceinline__ int rank_below(uint64_t mask, int r) {
+  return __popcll(mask & ((1ull << r) - 1));
+}
+
 struct SubView {
   const int32_t *nb, *brow_base;
   const int64_t *tile_base, *vec_base;
   const int64_t *brow_off;
   const int32_t *bfirst, *blast;
+  // trimmed tiles read by the sweeps (see TileMeta): rmeta in tile order, cmeta by block column
+  // (tile (I, B) of a subdomain at cmeta[cptr[brow_base + B] + I - B] for B <= I <= blast(B))
+  const TileMeta *rmeta, *cmeta;
+  const int64_t *cptr;
 };
 
 template <typename T>
@@ -260,22 +277,23 @@ __device__ inline int ready_run(const int *flags, int J, int Jlimit, int step, i
     const uint64_t valid = cnt == 64 ? ~0ull : ((1ull << cnt) - 1);
     const uint64_t bad = ~m & valid;
     const int first_bad = bad ? __ffsll((long long)bad) - 1 : cnt;
-    if (first_bad > 0) return J + step * first_bad;
+    if (first_bad > 0) return __builtin_amdgcn_readfirstlane(J + step * first_bad);
     int okw = 1;
     if (lane == 0) okw = wait_flag(&flags[J], epoch, abort) ? 1 : 0;
-    okw = __shfl(okw, 0);
-    if (!okw) return INT_MIN;
+    // readfirstlane (not a shuffle) keeps the result, and the caller's loop bounds, scalar
+    if (!__builtin_amdgcn_readfirstlane(okw)) return INT_MIN;
   }
 }
 
 constexpr int kSweepWaves = 8;              // 512-thread workgroups, 8 tile rows per wave
 constexpr int kSweepThreads = 64 * kSweepWaves;
 constexpr int kRows = kTile / kSweepWaves;  // = 8
-// complex double sweeps stage 128 KB of tiles in LDS and run one workgroup per CU; complex
-// float ones (64 KB) fit two workgroups per CU
+// The sweeps run one workgroup per CU (a second co-resident workgroup delays the dependency
+// chain of the first more than it adds bandwidth), so both precisions get the full register
+// budget of two waves per SIMD.
 template <typename T>
 struct SweepMinWaves {
-  static constexpr int value = sizeof(T) == 8 ? 2 : 4;
+  static constexpr int value = 2;
 };
 
 // Block sweeps of all subdomains in one persistent launch per direction.  Work items
@@ -292,15 +310,31 @@ struct SweepMinWaves {
 // chain itself carries no tile loads.  Results of a block are written by wave 0 only, which
 // performs the agent-scope release and stores the flag; readers take an agent-scope acquire after
 // seeing a flag.
+// Streaming helpers over the trimmed tiles.  A wave owns 8 consecutive rows of a tile; a row
+// missing from a tile contributes zero and is not read.
+template <typename T>
+__device__ __forceinline__ void wave_rows(const cx<T> *__restrict__ pack, TileMeta m, int row0,
+                                          cx<T> a[kRows]) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t mb = (uint32_t)(m.mask >> row0) & 0xFFu;
+  const int k0 = rank_below(m.mask, row0);
+  const cx<T> *tp = pack + m.base + lane;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int k = k0 + __popc(mb & ((1u << r) - 1u));
+    a[r] = (mb >> r) & 1u ? tp[(int64_t)k * kTile] : cx<T>{0, 0};
+  }
+}
+
 template <typename T, int NT>
-__device__ __forceinline__ void stream_fwd(const cx<T> *tp, const cx<T> *yp, cx<T> acc[kRows]) {
-  // NT consecutive tiles of a block row starting at tp; yp = y of the first one (lane's column)
+__device__ __forceinline__ void stream_fwd(const cx<T> *__restrict__ pack, const TileMeta *rm,
+                                           int J, int row0, const cx<T> *yp, cx<T> acc[kRows]) {
+  // tiles (B, J..J+NT-1) of this wave's rows; rm[J] = meta of tile (B, J); yp = y of block J
   cx<T> a[NT][kRows], y[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     y[t] = pub_load(yp + t * kTile);
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) a[t][r] = tp[(int64_t)t * kTileElems + r * kTile];
+    wave_rows(pack, rm[J + t], row0, a[t]);
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t)
@@ -314,16 +348,16 @@ __device__ __forceinline__ cx<T> bcast(cx<T> v, int src) {
 }
 
 template <typename T, int NT>
-__device__ __forceinline__ void stream_bwd(const cx<T> *const tp[NT], const cx<T> *const zp[NT],
+__device__ __forceinline__ void stream_bwd(const cx<T> *__restrict__ pack, const TileMeta *cm,
+                                           int64_t vb, int I, int row0, const cx<T> *zvec,
                                            cx<T> &acc) {
-  // NT tiles of a block column; zp[t] = z rows of this wave (8 values, lanes 0..7 load them)
+  // tiles (I, B), (I-1, B), ...; cm[I] = meta of tile (I, B)
   const int lane = threadIdx.x & 63;
   cx<T> a[NT][kRows], z[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    z[t] = pub_load(zp[t] + (lane & (kRows - 1)));
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) a[t][r] = tp[t][r * kTile];
+    z[t] = pub_load(zvec + vb + (int64_t)(I - t) * kTile + row0 + (lane & (kRows - 1)));
+    wave_rows(pack, cm[I - t], row0, a[t]);
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t)
@@ -333,18 +367,19 @@ __device__ __forceinline__ void stream_bwd(const cx<T> *const tp[NT], const cx<T
 
 template <typename T, bool FWD>
 __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_sweep(
-    SubView v, const cx<T> *__restrict__ pool, const int32_t *__restrict__ sched_sub,
+    SubView v, const cx<T> *__restrict__ pack, const int32_t *__restrict__ sched_sub,
     const int32_t *__restrict__ sched_blk, int n_items, const cx<T> *__restrict__ rvec, cx<T> *yvec,
     cx<T> *zvec, int *flags, int *ctrl) {
   __shared__ int s_item;
   __shared__ int s_dead;
-  __shared__ cx<T> sL[kTile][kTile];  // neighbour tile of the last dependency (own wave's rows)
+  __shared__ cx<T> sL[kTile][kTile];  // neighbour tile of the last dependency
   __shared__ cx<T> sX[kTile][kTile];  // diagonal tile (inverse unit-lower factor, D on the diagonal)
   __shared__ cx<T> s_vec[kTile];
   __shared__ cx<T> s_out[kTile];
   __shared__ cx<T> s_red[kSweepWaves][kTile];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int row0 = w * kRows;  // this wave's first row inside a tile
+  // the wave index is uniform: keeping it scalar keeps the tile metadata in scalar registers
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int row0 = w * kRows;  // this wave's first row inside a block
   const int epoch = ctrl[0];
   int *abort = &ctrl[2];
   int *ticket = &ctrl[FWD ? 1 : 4];
@@ -355,27 +390,28 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       s_dead = 0;
     }
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (item >= n_items) break;
     const int l = sched_sub[item], B = sched_blk[item];
     const int bb = v.brow_base[l];
     const int64_t vb = v.vec_base[l];
     int *fl = flags + bb;
-    // Every wave streams its own 8 rows of each tile and checks the readiness of the rows it
-    // needs by itself (one ballot per 64 flags), so waves only meet at the final reductions.
+    // Every wave streams its own 8 rows and checks the readiness of the blocks it needs by
+    // itself (one ballot per 64 flags), so waves only meet at the final reductions.
     bool dead = false;
     if (FWD) {
       const int f = v.bfirst[bb + B];
-      const cx<T> *row = pool + (v.tile_base[l] + v.brow_off[bb + B]) * (int64_t)kTileElems;
       const bool has_prev = B - 1 >= f;
-      {  // stage this wave's rows of the diagonal tile and of the (B, B-1) tile
-        const cx<T> *xp = row + (int64_t)(B - f) * kTileElems + row0 * kTile + lane;
-        const cx<T> *lp = row + (int64_t)(B - 1 - f) * kTileElems + row0 * kTile + lane;
+      const TileMeta *rm = v.rmeta + (v.tile_base[l] + v.brow_off[bb + B] - f);  // rm[J]: (B, J)
+      {  // stage this wave's rows of the diagonal tile and of tile (B, B-1)
+        cx<T> x[kRows], p[kRows];
+        wave_rows(pack, rm[B], row0, x);
+        if (has_prev) wave_rows(pack, rm[B - 1], row0, p);
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-          sX[row0 + r][lane] = xp[r * kTile];
-          sL[row0 + r][lane] = has_prev ? lp[r * kTile] : cx<T>{0, 0};
+          sX[row0 + r][lane] = lane <= row0 + r ? x[r] : cx<T>{0, 0};
+          sL[row0 + r][lane] = has_prev ? p[r] : cx<T>{0, 0};
         }
       }
       cx<T> acc[kRows];
@@ -390,11 +426,9 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
           break;
         }
         for (; J + 3 < Jend; J += 4)
-          stream_fwd<T, 4>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
-                           yvec + vb + (int64_t)J * kTile + lane, acc);
+          stream_fwd<T, 4>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc);
         for (; J < Jend; ++J)
-          stream_fwd<T, 1>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
-                           yvec + vb + (int64_t)J * kTile + lane, acc);
+          stream_fwd<T, 1>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc);
       }
       if (has_prev && !dead) {
         if (ready_run(fl, B - 1, B, 1, epoch, abort) == INT_MIN) {
@@ -424,20 +458,22 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       }
     } else {
       const int last = v.blast[bb + B];
-      const cx<T> *X = tile_ptr(const_cast<cx<T> *>(pool), v, l, B, B);
       const bool has_next = B + 1 <= last;
-      {  // stage this wave's rows of the diagonal tile and of the (B+1, B) tile
-        const cx<T> *xp = X + row0 * kTile + lane;
-        const cx<T> *lp = has_next ? tile_ptr(const_cast<cx<T> *>(pool), v, l, B + 1, B) + row0 * kTile + lane
-                                   : xp;
+      const TileMeta *cm = v.cmeta + (v.cptr[bb + B] - B);  // cm[I]: tile (I, B)
+      const TileMeta md = cm[B];
+      {  // stage this wave's rows of the diagonal tile and of tile (B+1, B)
+        cx<T> x[kRows], p[kRows];
+        wave_rows(pack, md, row0, x);
+        if (has_next) wave_rows(pack, cm[B + 1], row0, p);
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-          sX[row0 + r][lane] = xp[r * kTile];
-          sL[row0 + r][lane] = has_next ? lp[r * kTile] : cx<T>{0, 0};
+          sX[row0 + r][lane] = lane <= row0 + r ? x[r] : cx<T>{0, 0};
+          sL[row0 + r][lane] = has_next ? p[r] : cx<T>{0, 0};
         }
       }
-      const cx<T> dB = X[lane * kTile + lane];
-      const cx<T> yB = yvec[vb + (int64_t)B * kTile + lane];
+      const int64_t pd = vb + (int64_t)B * kTile + lane;
+      const cx<T> dB = pack[md.base + (int64_t)lane * kTile + lane];  // diagonal tiles keep all rows
+      const cx<T> yB = yvec[pd];
       cx<T> acc = {0, 0};
       // rows far below B finish first: consume I = last, last-1, ..., B+2 as they become ready
       int I = last;
@@ -447,20 +483,8 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
           dead = true;
           break;
         }
-        for (; I - 3 > Iend; I -= 4) {
-          const cx<T> *tp[4], *zp[4];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            tp[t] = tile_ptr(const_cast<cx<T> *>(pool), v, l, I - t, B) + row0 * kTile + lane;
-            zp[t] = zvec + vb + (int64_t)(I - t) * kTile + row0;
-          }
-          stream_bwd<T, 4>(tp, zp, acc);
-        }
-        for (; I > Iend; --I) {
-          const cx<T> *tp[1] = {tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + row0 * kTile + lane};
-          const cx<T> *zp[1] = {zvec + vb + (int64_t)I * kTile + row0};
-          stream_bwd<T, 1>(tp, zp, acc);
-        }
+        for (; I - 3 > Iend; I -= 4) stream_bwd<T, 4>(pack, cm, vb, I, row0, zvec, acc);
+        for (; I > Iend; --I) stream_bwd<T, 1>(pack, cm, vb, I, row0, zvec, acc);
       }
       if (has_next && !dead) {
         if (ready_run(fl, B + 1, B, -1, epoch, abort) == INT_MIN) {
@@ -500,244 +524,19 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
   }
 }
 
-// ---- chained sweeps: one resident chain workgroup per subdomain + streaming workgroups ----------
-// The block recurrences of the forward and backward sweeps are split in two:
-//   forward : y_B = inv(L_BB) (r_B - p_B - sum_{t=1..CL} L_{B,B-t} y_{B-t}),
-//             p_B = sum_{J < B-CL} L_BJ y_J
-//   backward: z_B = inv(L_BB)^T (y_B / D_B - q_B - sum_{t=1..CL} L_{B+t,B}^T z_{B+t}),
-//             q_B = sum_{I > B+CL} L_IB^T z_I
-// Workgroup l < nsub is the chain of subdomain l: it walks the block rows in order, keeps the
-// last CL solved blocks in LDS and the CL+1 tiles of the next step prefetched in registers, so
-// consecutive diagonal solves never cross compute units.  The other workgroups stream the far
-// parts p_B / q_B (almost all of the bytes) and publish them with epoch flags; they are handed out
-// by ticket in an order in which an item only depends on chain progress that itself only depends
-// on items with smaller tickets.  Chains are the lowest workgroup ids, so they are dispatched (and
-// resident) before any streaming workgroup.  All waits are bounded.
-constexpr int kChainLag = 2;  // CL
-
-template <typename T, bool FWD>
-__global__ __launch_bounds__(kSweepThreads, 2) void k_sweep_chain(
-    SubView v, const cx<T> *__restrict__ pool, int nsub, const int32_t *__restrict__ sched_sub,
-    const int32_t *__restrict__ sched_blk, int n_items, const cx<T> *__restrict__ in,
-    cx<T> *out, cx<T> *part, int *flags_out, int *flags_part, int *ctrl) {
-  constexpr int CL = kChainLag;
-  __shared__ int s_item;
-  __shared__ int s_ok;
-  __shared__ cx<T> ring[CL][kTile];
-  __shared__ cx<T> s_vec[kTile];
-  __shared__ cx<T> s_out[kTile];
-  __shared__ cx<T> s_red[kSweepWaves][kTile];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int row0 = w * kRows;
-  const int epoch = ctrl[0];
-  int *abort = &ctrl[2];
-  if ((int)blockIdx.x < nsub) {
-    // ======================= chain of subdomain l =======================
-    const int l = blockIdx.x;
-    const int nb = v.nb[l], bb = v.brow_base[l];
-    const int64_t vb = v.vec_base[l];
-    cx<T> *pl = const_cast<cx<T> *>(pool);
-    for (int q = tid; q < CL * kTile; q += kSweepThreads) ring[q / kTile][q % kTile] = {0, 0};
-    cx<T> cur[CL + 1][kRows], nxt[CL + 1][kRows];
-    cx<T> dcur = {1, 0}, dnxt = {1, 0};
-    auto load_tiles = [&](int B, cx<T>(&dst)[CL + 1][kRows], cx<T> &d) {
-      const cx<T> *X = tile_ptr(pl, v, l, B, B);
-#pragma unroll
-      for (int r = 0; r < kRows; ++r) dst[0][r] = X[(row0 + r) * kTile + lane];
-      if (!FWD) d = X[lane * kTile + lane];
-      if (FWD) {
-        const int f = v.bfirst[bb + B];
-#pragma unroll
-        for (int t = 1; t <= CL; ++t) {
-          const bool ok = B - t >= f;
-          const cx<T> *Lt = ok ? tile_ptr(pl, v, l, B, B - t) : X;
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) dst[t][r] = ok ? Lt[(row0 + r) * kTile + lane] : cx<T>{0, 0};
-        }
-      } else {
-        const int last = v.blast[bb + B];
-#pragma unroll
-        for (int t = 1; t <= CL; ++t) {
-          const bool ok = B + t <= last;
-          const cx<T> *Lt = ok ? tile_ptr(pl, v, l, B + t, B) : X;
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) dst[t][r] = ok ? Lt[(row0 + r) * kTile + lane] : cx<T>{0, 0};
-        }
-      }
-    };
-    const int B0 = FWD ? 0 : nb - 1, step = FWD ? 1 : -1;
-    load_tiles(B0, cur, dcur);
-    __syncthreads();  // ring cleared
-    for (int it = 0; it < nb; ++it) {
-      const int B = B0 + step * it;
-      if (it + 1 < nb) load_tiles(B + step, nxt, dnxt);
-      const bool need_p = FWD ? v.bfirst[bb + B] <= B - CL - 1 : v.blast[bb + B] >= B + CL + 1;
-      const cx<T> inB = in[vb + (int64_t)B * kTile + lane];
-      cx<T> pB = {0, 0};
-      if (need_p) {
-        if (w == 0) {
-          const int e = ready_run(flags_part + bb, B, B + 1, 1, epoch, abort);
-          if (lane == 0) s_ok = e;
-        }
-        __syncthreads();
-        const int ok = s_ok;
-        __syncthreads();
-        if (ok == INT_MIN) return;
-        pB = pub_load(part + vb + (int64_t)B * kTile + lane);
-      }
-      if (FWD) {
-        cx<T> acc[kRows];
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) acc[r] = {0, 0};
-#pragma unroll
-        for (int t = 1; t <= CL; ++t) {
-          const cx<T> yv = ring[(B - t + CL) % CL][lane];
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) cfma(acc[r], cur[t][r], yv);
-        }
-        cx<T> s = butterfly8(acc);
-        if ((lane & 7) == 0) s_vec[row0 + (lane >> 3)] = s;
-        __syncthreads();
-        const cx<T> tm = csub(csub(inB, pB), s_vec[lane]);
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) acc[r] = lane < row0 + r ? cmul(cur[0][r], tm) : cx<T>{0, 0};
-        s = butterfly8(acc);
-        if ((lane & 7) == 0) s_out[row0 + (lane >> 3)] = s;
-        __syncthreads();
-        if (w == 0) ring[B % CL][lane] = cadd(tm, s_out[lane]);
-      } else {
-        cx<T> acc = {0, 0};
-#pragma unroll
-        for (int t = 1; t <= CL; ++t)
-#pragma unroll
-          for (int r = 0; r < kRows; ++r) cfma(acc, cur[t][r], ring[(B + t) % CL][row0 + r]);
-        s_red[w][lane] = acc;
-        __syncthreads();
-        if (w == 0) {
-          cx<T> t = s_red[0][lane];
-#pragma unroll
-          for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
-          s_vec[lane] = csub(csub(cdiv(inB, dcur), pB), t);
-        }
-        __syncthreads();
-        acc = {0, 0};
-#pragma unroll
-        for (int r = 0; r < kRows; ++r)
-          if (row0 + r > lane) cfma(acc, cur[0][r], s_vec[row0 + r]);
-        s_red[w][lane] = acc;
-        __syncthreads();
-        if (w == 0) {
-          cx<T> t = s_red[0][lane];
-#pragma unroll
-          for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
-          ring[B % CL][lane] = cadd(s_vec[lane], t);
-        }
-      }
-      if (tid == 0) s_item = load_flag(abort);
-      __syncthreads();  // ring[B] complete; abort word read once for the whole workgroup
-      const int stop = s_item;
-      if (w == 0) {
-        pub_store(out + vb + (int64_t)B * kTile + lane, ring[B % CL][lane]);
-        stores_complete();
-        if (lane == 0) store_flag(&flags_out[bb + B], epoch);
-      }
-      if (stop) return;
-#pragma unroll
-      for (int t = 0; t <= CL; ++t)
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) cur[t][r] = nxt[t][r];
-      dcur = dnxt;
-    }
-    return;
-  }
-  // ======================= streaming workgroups =======================
-  int *ticket = &ctrl[FWD ? 1 : 4];
-  while (true) {
-    if (tid == 0) {
-      int t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_item = load_flag(abort) ? n_items : t;
-    }
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    if (item >= n_items) break;
-    const int l = sched_sub[item], B = sched_blk[item];
-    const int bb = v.brow_base[l];
-    const int64_t vb = v.vec_base[l];
-    int *fl = flags_out + bb;
-    if (FWD) {
-      const int f = v.bfirst[bb + B];
-      const cx<T> *row = pool + (v.tile_base[l] + v.brow_off[bb + B]) * (int64_t)kTileElems;
-      cx<T> acc[kRows];
-#pragma unroll
-      for (int r = 0; r < kRows; ++r) acc[r] = {0, 0};
-      const int Jlim = B - CL;  // tiles f .. B-CL-1
-      int J = f;
-      while (J < Jlim) {
-        if (w == 0) {
-          const int e = ready_run(fl, J, Jlim, 1, epoch, abort);
-          if (lane == 0) s_ok = e;
-        }
-        __syncthreads();
-        const int Jend = s_ok;
-        __syncthreads();
-        if (Jend == INT_MIN) return;
-        for (; J + 3 < Jend; J += 4)
-          stream_fwd<T, 4>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
-                           out + vb + (int64_t)J * kTile + lane, acc);
-        for (; J < Jend; ++J)
-          stream_fwd<T, 1>(row + (int64_t)(J - f) * kTileElems + row0 * kTile + lane,
-                           out + vb + (int64_t)J * kTile + lane, acc);
-      }
-      cx<T> s = butterfly8(acc);
-      if ((lane & 7) == 0) s_out[row0 + (lane >> 3)] = s;
-      __syncthreads();
-      if (w == 0) {
-        pub_store(part + vb + (int64_t)B * kTile + lane, s_out[lane]);
-        stores_complete();
-        if (lane == 0) store_flag(&flags_part[bb + B], epoch);
-      }
-    } else {
-      const int last = v.blast[bb + B];
-      const int Ilim = B + CL;  // tiles last .. B+CL+1
-      cx<T> acc = {0, 0};
-      int I = last;
-      while (I > Ilim) {
-        if (w == 0) {
-          const int e = ready_run(fl, I, Ilim, -1, epoch, abort);
-          if (lane == 0) s_ok = e;
-        }
-        __syncthreads();
-        const int Iend = s_ok;
-        __syncthreads();
-        if (Iend == INT_MIN) return;
-        for (; I - 3 > Iend; I -= 4) {
-          const cx<T> *tp[4], *zp[4];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            tp[t] = tile_ptr(const_cast<cx<T> *>(pool), v, l, I - t, B) + row0 * kTile + lane;
-            zp[t] = out + vb + (int64_t)(I - t) * kTile + row0;
-          }
-          stream_bwd<T, 4>(tp, zp, acc);
-        }
-        for (; I > Iend; --I) {
-          const cx<T> *tp[1] = {tile_ptr(const_cast<cx<T> *>(pool), v, l, I, B) + row0 * kTile + lane};
-          const cx<T> *zp[1] = {out + vb + (int64_t)I * kTile + row0};
-          stream_bwd<T, 1>(tp, zp, acc);
-        }
-      }
-      s_red[w][lane] = acc;
-      __syncthreads();
-      if (w == 0) {
-        cx<T> t = s_red[0][lane];
-#pragma unroll
-        for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
-        pub_store(part + vb + (int64_t)B * kTile + lane, t);
-        stores_complete();
-        if (lane == 0) store_flag(&flags_part[bb + B], epoch);
-      }
-    }
-  }
+// Copies the kept rows of every factored tile into the trimmed layout: one workgroup per tile,
+// each wave 16 rows, lanes along the row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack(int64_t ntiles, const TileMeta *__restrict__ rmeta,
+                                              const cx<T> *__restrict__ pool, cx<T> *__restrict__ pack) {
+  const int64_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  const TileMeta m = rmeta[t];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const cx<T> *src = pool + t * (int64_t)kTileElems + lane;
+  cx<T> *dst = pack + m.base + lane;
+  for (int r = w * 16; r < w * 16 + 16; ++r)
+    if ((m.mask >> r) & 1ull) dst[(int64_t)rank_below(m.mask, r) * kTile] = src[r * kTile];
 }
 
 // ---- host side ------------------------------------------------------------------------------------
@@ -750,6 +549,9 @@ static SubView view_of(const mx_precond *P) {
   v.brow_off = P->d_brow_off.as<int64_t>();
   v.bfirst = P->d_bfirst.as<int32_t>();
   v.blast = P->d_blast.as<int32_t>();
+  v.rmeta = P->d_rmeta.as<TileMeta>();
+  v.cmeta = P->d_cmeta.as<TileMeta>();
+  v.cptr = P->d_cptr.as<int64_t>();
   return v;
 }
 
@@ -795,27 +597,14 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
     MX_HIP(hipEventRecord(P->ev_start[P->n_timed], st));
   }
   const int half = P->n_items / 2;
-  if (P->chain) {
-    int *cfl = P->d_cflags.as<int>();
-    const int32_t *cs = P->d_csched_sub.as<int32_t>(), *cbk = P->d_csched_blk.as<int32_t>();
-    k_sweep_chain<T, true><<<P->trsv_grid, kSweepThreads, 0, st>>>(
-        v, P->pool.as<cx<T>>(), P->nsub, cs, cbk, P->n_cf, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
-        P->d_part.as<cx<T>>(), flags, cfl, P->d_ctrl.as<int>());
-    if (P->timing) MX_HIP(hipEventRecord(P->ev_mid[P->n_timed], st));
-    k_sweep_chain<T, false><<<P->trsv_grid, kSweepThreads, 0, st>>>(
-        v, P->pool.as<cx<T>>(), P->nsub, cs + P->n_cf, cbk + P->n_cf, P->n_cb, P->d_y.as<cx<T>>(),
-        P->d_z.as<cx<T>>(), P->d_part.as<cx<T>>(), flags + P->blocks_total, cfl + P->blocks_total,
-        P->d_ctrl.as<int>());
-  } else {
   k_sweep<T, true><<<P->trsv_grid, kSweepThreads, 0, st>>>(
-      v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(), half,
+      v, P->pack.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(), half,
       P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), flags, P->d_ctrl.as<int>());
   if (P->timing) MX_HIP(hipEventRecord(P->ev_mid[P->n_timed], st));
   k_sweep<T, false><<<P->trsv_grid, kSweepThreads, 0, st>>>(
-      v, P->pool.as<cx<T>>(), P->d_sched_sub.as<int32_t>() + half,
+      v, P->pack.as<cx<T>>(), P->d_sched_sub.as<int32_t>() + half,
       P->d_sched_blk.as<int32_t>() + half, half, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
       P->d_z.as<cx<T>>(), flags + P->blocks_total, P->d_ctrl.as<int>());
-  }
   if (P->timing) MX_HIP(hipEventRecord(P->ev_stop[P->n_timed++], st));
   const int64_t E = P->E;
   if (P->kind == MX_AS)
@@ -831,6 +620,30 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
   if (P->prec == MX_C128) apply_t<double>(P, vin, zout, st);
   else apply_t<float>(P, vin, zout, st);
+}
+
+template <typename T>
+__global__ void k_gather_diag(SubView v, int l, int64_t n, const cx<T> *__restrict__ pack,
+                              cx<double> *__restrict__ d) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int I = (int)(i / kTile), r = (int)(i % kTile), bb = v.brow_base[l];
+  const int64_t t = v.tile_base[l] + v.brow_off[bb + I] + (I - v.bfirst[bb + I]);
+  d[i] = ccast<double>(pack[v.rmeta[t].base + (int64_t)r * kTile + r]);  // diagonal tiles keep all rows
+}
+
+void precond_export_diag(const mx_precond *P, int l, double *d) {
+  const int64_t n = P->sky[l].n;
+  if (n == 0) return;
+  DevBuf out;
+  out.alloc((size_t)n * 16);
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (P->prec == MX_C128)
+    k_gather_diag<double><<<g, 256>>>(view_of(P), l, n, P->pack.as<cx<double>>(), out.as<cx<double>>());
+  else
+    k_gather_diag<float><<<g, 256>>>(view_of(P), l, n, P->pack.as<cx<float>>(), out.as<cx<double>>());
+  MX_HIP(hipGetLastError());
+  MX_HIP(hipMemcpy(d, out.p, (size_t)n * 16, hipMemcpyDeviceToHost));
 }
 
 void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd, double *ms_bwd) {
@@ -861,8 +674,7 @@ void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_
   zout.alloc((size_t)P->E * 16);
   MX_HIP(hipMemsetAsync(vin.p, 0, (size_t)P->E * 16, st));
   const int cus = ctx->cus;
-  std::vector<int> cand = {cus / 2, (3 * cus) / 4, cus, (5 * cus) / 4};
-  if (P->prec == MX_C64) cand.push_back(2 * cus);
+  std::vector<int> cand = {cus / 4, cus / 2, (3 * cus) / 4, cus};
   const int saved = P->trsv_grid;
   hipEvent_t a, b;
   MX_HIP(hipEventCreate(&a));
@@ -871,8 +683,7 @@ void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_
   double best_t = 1e300;
   for (int g : cand) {
     if (g < 1) continue;
-    if (P->chain && g < 2 * P->nsub) continue;
-    P->trsv_grid = P->chain ? g : std::min(g, std::max(1, P->n_items / 2));
+    P->trsv_grid = std::min(g, std::max(1, P->n_items / 2));
     precond_apply(P, vin.p, zout.p, st);  // warm-up
     MX_HIP(hipEventRecord(a, st));
     for (int r = 0; r < 3; ++r) precond_apply(P, vin.p, zout.p, st);
@@ -980,6 +791,52 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
       bfirst[P->sub_brow_base[l] + I] = s.bfirst[I];
       blast[P->sub_brow_base[l] + I] = s.blast[I];
     }
+  }
+  // trimmed tiles read by the sweeps: row i of block row I is kept in tile (I, J) iff
+  // first_i < 64 (J + 1) (padding rows have first_i = i); kept rows are packed tile after tile
+  std::vector<int64_t> &rmeta = plan.rmeta, &cmeta = plan.cmeta, &cptr = plan.cptr;
+  rmeta.assign(2 * tiles, 0);
+  parallel_for(N, [&](int64_t a0, int64_t a1) {
+    for (int64_t l = a0; l < a1; ++l) {
+      const Skyline &s = P->sky[l];
+      for (int64_t I = 0; I < s.nb; ++I) {
+        const int64_t f = s.bfirst[I], t0 = P->sub_tile_base[l] + s.brow_off[I];
+        std::vector<uint64_t> bits(I - f + 1, 0);
+        for (int r = 0; r < kTile; ++r) {
+          const int64_t i = I * kTile + r, fi = i < s.n ? s.first[i] : i;
+          bits[std::max(f, fi / kTile) - f] |= 1ull << r;
+        }
+        uint64_t m = 0;
+        for (int64_t J = f; J <= I; ++J) {
+          m |= bits[J - f];
+          rmeta[2 * (t0 + J - f) + 1] = (int64_t)m;
+        }
+      }
+    }
+  }, 1);
+  int64_t packed = 0;
+  for (int64_t t = 0; t < tiles; ++t) {
+    rmeta[2 * t] = packed;
+    packed += (int64_t)__builtin_popcountll((uint64_t)rmeta[2 * t + 1]) * kTile;
+  }
+  P->pack_entries = packed;
+  cptr.assign(blocks, 0);
+  cmeta.assign(2 * tiles, 0);
+  {
+    int64_t c = 0;
+    for (int l = 0; l < N; ++l) {
+      const Skyline &s = P->sky[l];
+      const int64_t bb = P->sub_brow_base[l], tb = P->sub_tile_base[l];
+      for (int64_t B = 0; B < s.nb; ++B) {
+        cptr[bb + B] = c;
+        for (int64_t I = B; I <= s.blast[B]; ++I, ++c) {
+          const int64_t t = tb + s.brow_off[I] + (B - s.bfirst[I]);
+          cmeta[2 * c] = rmeta[2 * t];
+          cmeta[2 * c + 1] = rmeta[2 * t + 1];
+        }
+      }
+    }
+    if (c != tiles) fail(MX_EINVAL, "internal: block columns do not cover the stored tiles");
   }
   // scatter list: lower-triangle entries of each permuted local matrix + unit diagonal padding
   std::vector<int64_t> cnt(N + 1, 0);
@@ -1097,29 +954,6 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     }
   P->n_items = (int)sched_sub.size();
   {
-    std::vector<Item> cf, cb;
-    for (int l = 0; l < N; ++l) {
-      const Skyline &sk = P->sky[l];
-      const int64_t nb = sk.nb;
-      for (int64_t I = 0; I < nb; ++I) {
-        if (sk.bfirst[I] <= I - kChainLag - 1) cf.push_back({(I + 0.5) / nb, l, (int32_t)I});
-        const int64_t J = nb - 1 - I;
-        if (sk.blast[J] >= J + kChainLag + 1) cb.push_back({(I + 0.5) / nb, l, (int32_t)J});
-      }
-    }
-    std::sort(cf.begin(), cf.end(), by_key);
-    std::sort(cb.begin(), cb.end(), by_key);
-    plan.csched_sub.clear();
-    plan.csched_blk.clear();
-    for (const auto *lst : {&cf, &cb})
-      for (const auto &it : *lst) {
-        plan.csched_sub.push_back(it.l);
-        plan.csched_blk.push_back(it.b);
-      }
-    P->n_cf = (int)cf.size();
-    P->n_cb = (int)cb.size();
-  }
-  {
     // persistent sweeps: as many workgroups as can be resident at once
     int per_cu = 1;
     if (P->prec == MX_C128)
@@ -1130,23 +964,17 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     // dependency chain of the first one more than it adds bandwidth (measured)
     (void)per_cu;
     int grid = opts->sweep_grid > 0 ? opts->sweep_grid : ctx->cus;
-    const bool can_chain = 2 * N <= grid;
-    if (opts->sweep_mode == 2 && !can_chain) fail(MX_EINVAL, "chained sweeps need subdomains <= grid / 2");
-    // ticketed block rows are the default: measured faster than the chained schedule once the
-    // block results are published without cache-wide fences
-    P->chain = opts->sweep_mode == 2 ? 1 : 0;
-    (void)can_chain;
-    P->trsv_grid = P->chain ? grid : std::max(1, std::min(P->n_items / 2, grid));
+    P->trsv_grid = std::max(1, std::min(P->n_items / 2, grid));
   }
   const double t1 = now_s();
   P->info.t_host_setup = t1 - t0;
   const size_t esz = P->prec == MX_C128 ? 16 : 8;
-  plan.device_bytes = (size_t)tiles * kTileElems * esz + 3 * (size_t)vec * esz +
-                      2 * (size_t)blocks * 4 + 16 * (size_t)blocks +
-                      4 * (size_t)vec + 8 * (size_t)std::max(src.size(), sum_idx.size() + sum_ptr.size()) +
+  // peak: the tile pool and the packed factor coexist while packing
+  plan.device_bytes = (size_t)tiles * kTileElems * esz + (size_t)packed * esz + 3 * (size_t)vec * esz +
+                      2 * (size_t)blocks * 4 + 24 * (size_t)blocks + 32 * (size_t)tiles + 4 * (size_t)vec +
+                      8 * (size_t)std::max(src.size(), sum_idx.size() + sum_ptr.size()) +
                       8 * (size_t)sched_sub.size() + 8 * P->panel_pref.size() +
-                      24 * off.size() + (1 << 20) +
-                      (P->chain ? (size_t)vec * esz + 8 * (size_t)blocks + 8 * plan.csched_sub.size() : 0);
+                      24 * off.size() + (1 << 20);
 }
 
 void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
@@ -1181,13 +1009,9 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   P->d_update_pref.upload(P->update_pref);
   P->d_sched_sub.upload(sched_sub);
   P->d_sched_blk.upload(sched_blk);
-  if (P->chain) {
-    P->d_csched_sub.upload(plan.csched_sub);
-    P->d_csched_blk.upload(plan.csched_blk);
-    P->d_part.alloc(vec * (P->prec == MX_C128 ? 16 : 8));
-    P->d_cflags.alloc(2 * blocks * sizeof(int));
-    MX_HIP(hipMemsetAsync(P->d_cflags.p, 0, 2 * blocks * sizeof(int), st));
-  }
+  P->d_rmeta.upload(plan.rmeta);
+  P->d_cmeta.upload(plan.cmeta);
+  P->d_cptr.upload(plan.cptr);
   P->d_r.alloc(vec * esz);
   P->d_y.alloc(vec * esz);
   P->d_z.alloc(vec * esz);
@@ -1223,8 +1047,22 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   if (P->prec == MX_C128) factor_all<double>(P, st);
   else factor_all<float>(P, st);
   MX_HIP(hipStreamSynchronize(st));
-  const double t3 = now_s();
   precond_check(P, st);
+  // keep only the rows of each tile that meet the envelope, then free the full tiles
+  P->pack.alloc((size_t)P->pack_entries * esz);
+  if (tiles > 0) {
+    if (tiles > INT32_MAX) fail(MX_EINVAL, "too many tiles");
+    if (P->prec == MX_C128)
+      k_pack<double><<<(unsigned)tiles, 256, 0, st>>>(tiles, P->d_rmeta.as<TileMeta>(),
+                                                     P->pool.as<cx<double>>(), P->pack.as<cx<double>>());
+    else
+      k_pack<float><<<(unsigned)tiles, 256, 0, st>>>(tiles, P->d_rmeta.as<TileMeta>(),
+                                                    P->pool.as<cx<float>>(), P->pack.as<cx<float>>());
+    MX_HIP(hipGetLastError());
+  }
+  P->pool.release();
+  MX_HIP(hipStreamSynchronize(st));
+  const double t3 = now_s();
   // info
   mx_precond_info &in = P->info;
   in.n_sub = N;
@@ -1245,6 +1083,7 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   in.max_blocks = P->max_nb;
   in.tiles = tiles;
   in.factor_bytes = (int64_t)pool_bytes;
+  in.pack_bytes = (int64_t)(P->pack_entries * (int64_t)esz);
   // algorithmic bytes per application: the envelope factor read twice, the local vectors
   // (restricted input written and read, forward result written and read twice, backward result
   // written and read), the global input gathered and output written, the 4-byte gather maps

@@ -71,7 +71,6 @@ void Server::run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
   po.kind = opts.kind;
   po.xi_prec = q.xi;
   po.precision = opts.precision;
-  po.sweep_mode = 1;  // ticketed sweeps: no residency assumption while other requests' kernels run
   auto P = std::make_unique<mx_precond>();
   PrecondPlan plan;
   precond_plan(ctx, A.get(), mesh.get(), part.get(), &po, P.get(), plan);

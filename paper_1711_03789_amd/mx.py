@@ -43,7 +43,7 @@ class MxError(RuntimeError):
 
 class PrecondOpts(C.Structure):
     _fields_ = [("kind", C.c_int), ("xi_prec", C.c_double), ("precision", C.c_int),
-                ("sweep_grid", C.c_int), ("sweep_mode", C.c_int), ("sub_begin", C.c_int),
+                ("sweep_grid", C.c_int), ("sub_begin", C.c_int),
                 ("sub_end", C.c_int)]
 
 
@@ -53,7 +53,7 @@ class PrecondInfo(C.Structure):
                 ("factor_bytes", C.c_int64), ("env_entries", C.c_int64), ("env_flops", C.c_double),
                 ("tile_flops", C.c_double), ("apply_bytes", C.c_int64), ("sweep_bytes", C.c_int64),
                 ("t_host_setup", C.c_double),
-                ("t_upload", C.c_double), ("t_factor", C.c_double)]
+                ("t_upload", C.c_double), ("t_factor", C.c_double), ("pack_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -293,7 +293,7 @@ class Partition:
 def local_problem(mesh, A, part, l, kind="oras", xi_prec=None):
     """Host-only: local matrix of subdomain l (CSR in local numbering) and its RCM order."""
     load()
-    o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec, MX_C128, 0, 0, 0, 0)
+    o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec, MX_C128, 0, 0, 0)
     n, nnz = C.c_int64(), C.c_int64()
     _check(_lib.mx_local_problem(mesh.h, A.h, part.h, C.byref(o), l, C.byref(n), C.byref(nnz),
                                  None, None, None, None, None))
@@ -309,11 +309,11 @@ def local_problem(mesh, A, part, l, kind="oras", xi_prec=None):
 
 class Precond:
     def __init__(self, ctx, A, mesh, part, kind="oras", xi_prec=None, precision="c128",
-                 sweep_grid=0, share=None, sweep_mode=0):
+                 sweep_grid=0, share=None):
         load()
         s0, s1 = share if share is not None else (0, 0)
         o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec,
-                        PRECISIONS.get(precision, precision), sweep_grid, sweep_mode, s0, s1)
+                        PRECISIONS.get(precision, precision), sweep_grid, s0, s1)
         h = P()
         _check(_lib.mx_precond_setup(ctx.h, A.h, mesh.h, part.h, C.byref(o), C.byref(h)))
         self.h, self.ctx = h, ctx

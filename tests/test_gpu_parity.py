@@ -41,7 +41,7 @@ class Case:
     """A problem built on both sides from the same description."""
 
     def __init__(self, mx, ctx, n, parts, layers, k, xi, kind, cuts=(None, None, None),
-                 bc=fem.BC_IMPEDANCE, precision="c128", lengths=(1.0, 1.0, 1.0), sweep_mode=0):
+                 bc=fem.BC_IMPEDANCE, precision="c128", lengths=(1.0, 1.0, 1.0), sweep_grid=0):
         self.om = OMesh(*n, *lengths)
         self.oA = fem.assemble(self.om, k, xi, bc)
         self.op = dd.Partition(self.om, *parts, layers, *cuts)
@@ -50,7 +50,7 @@ class Case:
         self.lA = mx.Matrix(ctx, self.lm, k, xi, bc)
         self.lp = mx.Partition(self.lm, *parts, layers, *cuts)
         self.lP = mx.Precond(ctx, self.lA, self.lm, self.lp, kind, precision=precision,
-                             sweep_mode=sweep_mode)
+                             sweep_grid=sweep_grid)
         self.E = self.om.n_edge
 
 
@@ -76,11 +76,12 @@ def test_spmv(gpu_lib, ctx, n):
     assert np.linalg.norm(y - ref) <= 1e-13 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("kind,mode", [("oras", 2), ("ras", 2), ("as", 2), ("oras", 1), ("as", 1)])
-def test_apply_config_small(gpu_lib, ctx, kind, mode):
-    """mode 2: chained sweeps (chain workgroup per subdomain); mode 1: ticketed block rows."""
-    say("apply cfg small", kind, mode)
-    c = Case(gpu_lib, ctx, (8, 8, 8), (2, 2, 2), 2, 4.0, 16.0, kind, sweep_mode=mode)
+@pytest.mark.parametrize("kind,grid", [("oras", 0), ("ras", 0), ("as", 0), ("oras", 3), ("as", 1)])
+def test_apply_config_small(gpu_lib, ctx, kind, grid):
+    """grid 0: one sweep workgroup per compute unit; 3 and 1: few workgroups, so that most block
+    rows are claimed late and a single workgroup walks the whole ticket order."""
+    say("apply cfg small", kind, grid)
+    c = Case(gpu_lib, ctx, (8, 8, 8), (2, 2, 2), 2, 4.0, 16.0, kind, sweep_grid=grid)
     v = random_rhs(c.E, 3)
     vd, zd = dev(v), dev(np.zeros(c.E))
     c.lP.apply(vd, zd)
@@ -96,15 +97,15 @@ def test_apply_config_small(gpu_lib, ctx, kind, mode):
     assert np.array_equal(host(zd2), z)
 
 
-@pytest.mark.parametrize("mode,precision", [(2, "c128"), (1, "c128"), (2, "c64"), (1, "c64")])
-def test_apply_multi_tile_jittered(gpu_lib, ctx, mode, precision):
+@pytest.mark.parametrize("grid,precision", [(0, "c128"), (5, "c128"), (0, "c64"), (5, "c64")])
+def test_apply_multi_tile_jittered(gpu_lib, ctx, grid, precision):
     """Uneven jittered boxes with several 64-row blocks per subdomain and ragged last blocks,
-    both sweep schedules and both factor precisions."""
-    say("apply jittered", mode, precision)
+    two sweep grids and both factor precisions."""
+    say("apply jittered", grid, precision)
     n = (16, 14, 12)
     cuts = (jittered_cuts(16, 3, 0.2, 7), jittered_cuts(14, 2, 0.2, 8), jittered_cuts(12, 2, 0.2, 9))
     c = Case(gpu_lib, ctx, n, (3, 2, 2), 2, 5.0, 5.0, "oras", cuts, precision=precision,
-             sweep_mode=mode)
+             sweep_grid=grid)
     info = c.lP.info()
     say("  info", info)
     assert info["max_blocks"] >= 20
@@ -257,3 +258,43 @@ def test_resident_share_and_autotune(gpu_lib, ctx):
     P.apply(vd, zd2)
     P.check()
     assert np.array_equal(host(zd2), z)
+
+
+@pytest.mark.parametrize("kind,precision", [("oras", "c128"), ("as", "c128"), ("oras", "c64")])
+def test_factor_pivots(gpu_lib, ctx, kind, precision):
+    """The exported LDL^T pivots D of every local factor equal the pivots of an unpivoted LU
+    (natural column order, no row exchanges) of the oracle's local matrix in the exported
+    reverse Cuthill-McKee order: both are ratios of the same leading principal minors."""
+    import scipy.sparse.linalg as spla
+    say("factor pivots", kind, precision)
+    c = Case(gpu_lib, ctx, (8, 8, 8), (2, 2, 2), 2, 4.0, 16.0, kind, precision=precision)
+    tol = 1e-9 if precision == "c128" else 1e-4
+    for l in range(c.op.N):
+        Al = c.oB.local[l]
+        n = Al.shape[0]
+        perm, first = c.lP.perm(l, n)
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        Ap = Al[perm][:, perm].tocsc()
+        lu = spla.splu(Ap, permc_spec="NATURAL", diag_pivot_thresh=0.0,
+                       options={"SymmetricMode": True})
+        assert np.array_equal(lu.perm_r, np.arange(n)) and np.array_equal(lu.perm_c, np.arange(n))
+        ref = lu.U.diagonal()
+        d = c.lP.diag(l, n)
+        err = np.max(np.abs(d - ref) / np.abs(ref))
+        say("  sub", l, "n", n, "max rel pivot err", err)
+        assert err <= tol
+        # the envelope start of every row is its first nonzero column in the permuted matrix
+        lower = sp_lower_first(Ap)
+        assert np.array_equal(first, lower)
+
+
+def sp_lower_first(Ap):
+    """First nonzero column of each row of the lower triangle (diagonal included)."""
+    C = Ap.tocsr()
+    n = C.shape[0]
+    out = np.arange(n, dtype=np.int32)
+    for i in range(n):
+        cols = C.indices[C.indptr[i]:C.indptr[i + 1]]
+        if cols.size:
+            out[i] = min(i, int(cols.min()))
+    return out
