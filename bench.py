@@ -143,7 +143,7 @@ def run_batching(args):
         "factor": {"bound": "mfma", "achieved_env": inf["env_flops"] / inf["t_factor"] / 1e12,
                    "achieved_executed": inf["tile_flops"] / inf["t_factor"] / 1e12,
                    "peak": FP32_PEAK_TFS, "unit": "TFLOP/s", "seconds": inf["t_factor"],
-                   "factor_bytes": inf["factor_bytes"]},
+                   "factor_bytes": inf["factor_bytes"], "pack_bytes": inf["pack_bytes"]},
         "setup_seconds": {"mesh_assemble_partition": t1 - t0, "precond_total": t2 - t1,
                           "precond_host": inf["t_host_setup"], "upload": inf["t_upload"],
                           "factor": inf["t_factor"]},
@@ -276,7 +276,9 @@ def main():
             r.update({"t_precond_host": inf["t_host_setup"], "t_upload": inf["t_upload"],
                       "t_factor": inf["t_factor"], "env_flops": inf["env_flops"],
                       "tile_flops": inf["tile_flops"], "sweep_bytes": inf["sweep_bytes"],
-                      "apply_bytes": inf["apply_bytes"], "factor_bytes": inf["factor_bytes"]})
+                      "apply_bytes": inf["apply_bytes"], "factor_bytes": inf["factor_bytes"],
+                      "pack_bytes": inf["pack_bytes"], "env_bytes": inf["env_entries"] *
+                      (16 if args.precision == "c128" else 8)})
             if record:
                 r["sweep_launches"], r["fwd_ms"], r["bwd_ms"] = P.sweep_timing(False)
             rec.append(r)
@@ -324,6 +326,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "launches": launches, "avg_launch_ms": fwd_ms / max(launches, 1),
                      "bytes_per_launch_avg": sweep_bytes / max(launches, 1),
+                     "stored_factor_over_envelope": sum(r["pack_bytes"] for r in all_r) /
+                     max(sum(r["env_bytes"] for r in all_r), 1),
                      "backward": {"achieved": achieved_bwd, "frac": achieved_bwd / HBM_PEAK_GBS,
                                   "avg_launch_ms": bwd_ms / max(launches, 1)}},
         "factor": {"bound": "mfma", "achieved_env": sum(r["env_flops"] for r in all_r) / t_factor / 1e12,

@@ -60,7 +60,11 @@ const char *mx_last_error(void);
 int mx_version(void);
 
 /* ---- context ------------------------------------------------------------------------------ */
-/* Binds HIP device `device` (must be gfx950).  Errors: MX_EDEVICE. */
+/* Binds HIP device `device` (must be gfx950).  Large device blocks (64 MiB and up: factor tiles,
+ * trimmed factors) freed by the library stay mapped in a process-wide cache and are reused by
+ * later setups (remapping tens of GB costs seconds); mx_ctx_destroy waits for the device and
+ * returns the cached blocks and the stream-ordered pool's unused memory to HIP.  Objects must
+ * not be destroyed while work that uses them is still queued.  Errors: MX_EDEVICE. */
 int mx_ctx_create(int device, mx_ctx **out);
 void mx_ctx_destroy(mx_ctx *ctx);
 
@@ -150,8 +154,9 @@ typedef struct {
   int64_t sweep_bytes;          /* algorithmic bytes of one block-sweep launch (either direction):*/
                                 /* the envelope factor read once and three local-vector passes   */
   double t_host_setup, t_upload, t_factor; /* seconds of the last mx_precond_setup phases      */
-  int64_t pack_bytes;           /* device bytes of the packed row-envelope factor read by the    */
-                                /* sweeps (each row 8-entry aligned; diagonal blocks in full)    */
+  int64_t pack_bytes;           /* device bytes of the trimmed tiles read by the sweeps (the tile */
+                                /* rows that meet the envelope; diagonal tiles in full)          */
+  double t_pack;                /* seconds spent trimming the tiles and freeing the full ones    */
 } mx_precond_info;
 
 /* Builds the local matrices (AS/RAS: minors of A, so the matrix's k, xi and bc are used; ORAS:

@@ -10,6 +10,7 @@
 
 namespace mx {
 thread_local hipStream_t t_alloc_stream = nullptr;
+thread_local int t_alloc_scoped = 0;
 static thread_local std::string g_last_error;
 void set_error(int code, const std::string &msg) {
   (void)code;
@@ -66,6 +67,11 @@ int mx_ctx_create(int device, mx_ctx **out) {
 
 void mx_ctx_destroy(mx_ctx *ctx) {
   if (!ctx) return;
+  if (hipSetDevice(ctx->device) == hipSuccess && hipDeviceSynchronize() == hipSuccess) {
+    mx::big_trim(ctx->device);
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+  }
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
 }

@@ -19,22 +19,42 @@
 
 namespace mx {
 
-// Stream used for device allocations and uploads made by this host thread: when set (by an
-// AllocScope) buffers come from the stream-ordered allocator and are freed on that stream, so
-// concurrent requests on different streams do not synchronise the whole device.
+// Stream used for device allocations and uploads made by this host thread: inside an
+// AllocScope (the null stream included) buffers come from the stream-ordered allocator and are
+// freed on that stream, so concurrent requests on different streams do not synchronise the whole
+// device and freed memory stays mapped in the device's pool for the next setup.
 extern thread_local hipStream_t t_alloc_stream;
+extern thread_local int t_alloc_scoped;
 struct AllocScope {
   hipStream_t prev;
-  explicit AllocScope(hipStream_t s) : prev(t_alloc_stream) { t_alloc_stream = s; }
-  ~AllocScope() { t_alloc_stream = prev; }
+  int prev_scoped;
+  explicit AllocScope(hipStream_t s) : prev(t_alloc_stream), prev_scoped(t_alloc_scoped) {
+    t_alloc_stream = s;
+    t_alloc_scoped = 1;
+  }
+  ~AllocScope() {
+    t_alloc_stream = prev;
+    t_alloc_scoped = prev_scoped;
+  }
 };
+
+// Process-wide cache of large device blocks (factor tiles, trimmed factors, big vectors):
+// freed blocks stay mapped, tagged with an event recorded on their stream at release, and are
+// handed out again (best fit, after that event has completed) instead of being unmapped and
+// remapped, which costs seconds for the tens of GB of a factorisation.  A failed allocation
+// returns the cached blocks of the device to HIP and retries once.  Implemented in devcache.cpp.
+constexpr size_t kBigBlock = size_t(64) << 20;
+void *big_alloc(size_t n, size_t *capacity);
+void big_free(void *p, size_t capacity, hipStream_t st);
+void big_trim(int device);
 
 // Owning device buffer.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  size_t cap = 0;  // capacity of a cached large block
   hipStream_t st = nullptr;
-  bool async = false;
+  bool async = false, big = false;
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
@@ -42,7 +62,11 @@ struct DevBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) n = 16;
-    if (t_alloc_stream) {
+    if (n >= kBigBlock) {
+      p = big_alloc(n, &cap);
+      st = t_alloc_scoped ? t_alloc_stream : nullptr;
+      big = true;
+    } else if (t_alloc_scoped) {
       MX_HIP(hipMallocAsync(&p, n, t_alloc_stream));
       st = t_alloc_stream;
       async = true;
@@ -54,11 +78,13 @@ struct DevBuf {
   }
   void release() {
     if (p) {
-      if (async) (void)hipFreeAsync(p, st);
+      if (big) big_free(p, cap, st);
+      else if (async) (void)hipFreeAsync(p, st);
       else (void)hipFree(p);
     }
     p = nullptr;
-    bytes = 0;
+    bytes = cap = 0;
+    big = async = false;
   }
   template <class T>
   T *as() const { return (T *)p; }

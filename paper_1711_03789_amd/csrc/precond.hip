@@ -1048,6 +1048,7 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   else factor_all<float>(P, st);
   MX_HIP(hipStreamSynchronize(st));
   precond_check(P, st);
+  const double t3 = now_s();
   // keep only the rows of each tile that meet the envelope, then free the full tiles
   P->pack.alloc((size_t)P->pack_entries * esz);
   if (tiles > 0) {
@@ -1062,7 +1063,7 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   }
   P->pool.release();
   MX_HIP(hipStreamSynchronize(st));
-  const double t3 = now_s();
+  const double t4 = now_s();
   // info
   mx_precond_info &in = P->info;
   in.n_sub = N;
@@ -1095,6 +1096,7 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   in.sweep_bytes = (int64_t)(in.env_entries * esz + 3 * nloc * esz);
   in.t_upload = t2 - t1;
   in.t_factor = t3 - t2;
+  in.t_pack = t4 - t3;
 }
 
 }  // namespace mx

@@ -215,6 +215,13 @@ int mx_server_create(int device, const mx_server_opts *opts, mx_server **out) {
     S->s.device = device;
     S->s.cus = prop.multiProcessorCount;
     size_t free_b = 0, total_b = 0;
+    {  // memory parked in the block cache or the stream-ordered pool by earlier setups counts as free
+      MX_HIP(hipDeviceSynchronize());
+      mx::big_trim(device);
+      hipMemPool_t pool;
+      MX_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+      MX_HIP(hipMemPoolTrimTo(pool, 0));
+    }
     MX_HIP(hipMemGetInfo(&free_b, &total_b));
     S->s.budget = opts->hbm_budget ? opts->hbm_budget : (uint64_t)(0.85 * (double)free_b);
     for (int i = 0; i < opts->slots; ++i) S->s.workers.emplace_back([p = &S->s] { p->worker(); });

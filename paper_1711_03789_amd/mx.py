@@ -53,7 +53,8 @@ class PrecondInfo(C.Structure):
                 ("factor_bytes", C.c_int64), ("env_entries", C.c_int64), ("env_flops", C.c_double),
                 ("tile_flops", C.c_double), ("apply_bytes", C.c_int64), ("sweep_bytes", C.c_int64),
                 ("t_host_setup", C.c_double),
-                ("t_upload", C.c_double), ("t_factor", C.c_double), ("pack_bytes", C.c_int64)]
+                ("t_upload", C.c_double), ("t_factor", C.c_double), ("pack_bytes", C.c_int64),
+                ("t_pack", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
