@@ -81,61 +81,61 @@ __global__ void k_zero(int64_t n16, uint4 *__restrict__ p) {
 }
 
 // ---- factorisation: diagonal tile ----------------------------------------------------------------
-// One workgroup per subdomain: S = A_KK (lower triangle) is factored in LDS as L D L^T, then the
-// unit lower L is inverted in place; written back as inv(L) below the diagonal, D on it, 0 above.
+// One workgroup per subdomain.  The tile A_KK is held in LDS as a full symmetric matrix (rows
+// padded by one entry) and factored as L D L^T, right-looking, with the lanes along the columns
+// of the trailing matrix; row j of the upper triangle then holds column j of L.  The unit-lower
+// inverse X = inv(L) is formed row by row into the strict lower triangle, each wave owning 16
+// columns (four partial sums per column, reduced with lane shuffles).  Written back as X below
+// the diagonal, D on it, 0 above.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fac_diag(int K, SubView v, cx<T> *pool, int *ctrl) {
   const int l = blockIdx.x;
   if (K >= v.nb[l]) return;
-  __shared__ cx<T> S[kTile][kTile];
-  __shared__ cx<T> tmp[kTile];
+  __shared__ cx<T> S[kTile][kTile + 1];
   cx<T> *tile = tile_ptr(pool, v, l, K, K);
-  const int tid = threadIdx.x;
-  for (int q = tid; q < kTileElems; q += 256) {
-    int i = q / kTile, j = q % kTile;
-    S[i][j] = j <= i ? tile[q] : cx<T>{0, 0};
-  }
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = w; i < kTile; i += 4)
+    if (lane <= i) {
+      const cx<T> a = tile[i * kTile + lane];
+      S[i][lane] = a;
+      S[lane][i] = a;
+    }
   bool bad = false;
   for (int j = 0; j < kTile; ++j) {
     __syncthreads();
     cx<T> d = S[j][j];
-    T mag = d.re * d.re + d.im * d.im;
+    const T mag = d.re * d.re + d.im * d.im;
     if (!(mag > (T)0) || !isfinite(mag)) {
       bad = true;
       d = {(T)1, (T)0};
     }
-    cx<T> dinv = cinv(d);
-    // trailing update S[i][m] -= S[i][j] S[m][j] / d,  j < m <= i
-    const int i = tid & 63;
-    if (i > j) {
-      cx<T> lij = cmul(S[i][j], dinv);
-      for (int m = j + 1 + (tid >> 6); m <= i; m += 4) {
-        cx<T> t = cmul(lij, S[m][j]);
-        S[i][m] = csub(S[i][m], t);
-      }
+    // S[i][m] -= S[j][i] S[j][m] / d   for i, m > j  (row j is final and not written here)
+    if (lane > j) {
+      const cx<T> u = cmul(S[j][lane], cinv(d));
+      for (int i = j + 1 + w; i < kTile; i += 4) S[i][lane] = csub(S[i][lane], cmul(S[j][i], u));
     }
-    __syncthreads();
-    if (tid < kTile && tid > j) S[tid][j] = cmul(S[tid][j], dinv);
   }
   if (bad && tid == 0) atomicOr(&ctrl[3], 1);
-  // in-place inverse of the unit lower triangle, columns right to left:
-  // X[i][j] = -(L[i][j] + sum_{j<m<i} X[i][m] L[m][j])
-  for (int j = kTile - 2; j >= 0; --j) {
+  __syncthreads();
+  // upper row j := column j of L  (L[m][j] = S[j][m] / D_j)
+  for (int j = w; j < kTile; j += 4)
+    if (lane > j) S[j][lane] = cmul(S[j][lane], cinv(S[j][j]));
+  // X[i][c] = -(L[i][c] + sum_{c<m<i} L[i][m] X[m][c])  for c < i
+  const int c = 16 * w + (lane & 15), g = lane >> 4;
+  for (int i = 1; i < kTile; ++i) {
     __syncthreads();
-    if (tid < kTile && tid > j) {
-      const int i = tid;
-      cx<T> acc = S[i][j];
-      for (int m = j + 1; m < i; ++m) cfma(acc, S[i][m], S[m][j]);
-      tmp[i] = {-acc.re, -acc.im};
+    cx<T> acc = {(T)0, (T)0};
+    if (c < i) {
+      for (int m = c + 1 + g; m < i; m += 4) cfma(acc, S[m][i], S[m][c]);
+      if (g == 0) acc = cadd(acc, S[c][i]);
     }
-    __syncthreads();
-    if (tid < kTile && tid > j) S[tid][j] = tmp[tid];
+    acc = cadd(acc, shfl_xor_c(acc, 16));
+    acc = cadd(acc, shfl_xor_c(acc, 32));
+    if (c < i && g == 0) S[i][c] = {-acc.re, -acc.im};
   }
   __syncthreads();
-  for (int q = tid; q < kTileElems; q += 256) {
-    int i = q / kTile, j = q % kTile;
-    tile[q] = j <= i ? S[i][j] : cx<T>{0, 0};
-  }
+  for (int i = w; i < kTile; i += 4)
+    tile[i * kTile + lane] = lane <= i ? S[i][lane] : cx<T>{(T)0, (T)0};
 }
 
 // ---- factorisation: panel L_IK = A_IK inv(L_KK)^T D_K^-1 -------------------------------------------
