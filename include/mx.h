@@ -91,8 +91,12 @@ void mx_mesh_destroy(mx_mesh *m);
  * form.  The CSR (int64 row pointers, int32 columns sorted ascending, complex128 values, plus a
  * complex64 copy of the values) is built on the host and kept on the context's device.
  * Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE. */
+/* ctx may be NULL: the matrix is then host-only until mx_matrix_upload. */
 int mx_matrix_assemble(mx_ctx *ctx, const mx_mesh *m, double k, double xi, int bc,
                        mx_matrix **out);
+/* Device copy of a host-only matrix (assembled with ctx = NULL).  Errors: MX_EINVAL (already on
+ * a device), MX_ENOMEM, MX_EDEVICE. */
+int mx_matrix_upload(mx_ctx *ctx, mx_matrix *A);
 int mx_matrix_sizes(const mx_matrix *A, int64_t *n, int64_t *nnz);
 /* Host copies: rowptr[n+1], col[nnz], val[2*nnz] (complex128).  Any may be NULL. */
 int mx_matrix_export(const mx_matrix *A, int64_t *rowptr, int32_t *col, double *val);
@@ -167,6 +171,16 @@ typedef struct {
  * Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EPIVOT. */
 int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
                      const mx_precond_opts *opts, mx_precond **out);
+/* The two halves of mx_precond_setup, so that the host half of one preconditioner can run on
+ * another host thread while the device works on an earlier one.  mx_precond_plan does all host
+ * work (local matrices, orderings, tile layout, schedules; no device work, A needs no device
+ * copy) and returns the exact peak device bytes that materialising it will allocate;
+ * mx_precond_materialize uploads and factors on `stream` (NULL = null stream) and returns when
+ * done.  A planned, not yet materialised preconditioner may only be materialised or destroyed.
+ * Errors: as mx_precond_setup. */
+int mx_precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
+                    const mx_precond_opts *opts, mx_precond **out, uint64_t *device_bytes);
+int mx_precond_materialize(mx_ctx *ctx, mx_precond *P, void *stream);
 /* z = sum_l R_l^T D_l (A^l)^-1 R_l v (D_l = I for AS); v_dev, z_dev complex128[E], distinct.
  * Enqueued on `stream`; device-side failures surface at the next synchronising call.
  * apply_bytes = factors read twice (forward and backward sweep) + local vectors + gathers. */

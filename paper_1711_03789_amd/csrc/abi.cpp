@@ -130,6 +130,16 @@ int mx_matrix_assemble(mx_ctx *ctx, const mx_mesh *m, double k, double xi, int b
   });
 }
 
+int mx_matrix_upload(mx_ctx *ctx, mx_matrix *A) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && A, "NULL argument");
+    MX_REQUIRE(!A->rowptr.p, "matrix already has a device copy");
+    bind_device(ctx->device);
+    A->device = ctx->device;
+    mx::matrix_upload(A);
+  });
+}
+
 int mx_matrix_sizes(const mx_matrix *A, int64_t *n, int64_t *nnz) {
   MX_GUARD({
     MX_REQUIRE(A, "matrix is NULL");
@@ -257,9 +267,34 @@ int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx
   });
 }
 
+int mx_precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
+                    const mx_precond_opts *opts, mx_precond **out, uint64_t *device_bytes) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && A && m && p && opts && out, "NULL argument");
+    bind_device(ctx->device);
+    auto P = std::make_unique<mx_precond>();
+    P->plan = std::make_unique<mx::PrecondPlan>();
+    mx::precond_plan(ctx, A, m, p, opts, P.get(), *P->plan);
+    if (device_bytes) *device_bytes = P->plan->device_bytes;
+    *out = P.release();
+  });
+}
+
+int mx_precond_materialize(mx_ctx *ctx, mx_precond *P, void *stream) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && P, "NULL argument");
+    MX_REQUIRE(P->plan, "preconditioner is already materialised");
+    MX_REQUIRE(ctx->device == P->device, "preconditioner was planned for another device");
+    bind_device(ctx->device);
+    mx::precond_materialize(P, *P->plan, (hipStream_t)stream);
+    P->plan.reset();
+  });
+}
+
 int mx_precond_apply(mx_ctx *ctx, mx_precond *P, const void *v_dev, void *z_dev, void *stream) {
   MX_GUARD({
     MX_REQUIRE(ctx && P && v_dev && z_dev, "NULL argument");
+    MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
     MX_REQUIRE(v_dev != z_dev, "v and z must be distinct");
     bind_device(ctx->device);
     mx::precond_apply(P, v_dev, z_dev, (hipStream_t)stream);
@@ -286,6 +321,7 @@ int mx_precond_export_perm(const mx_precond *P, int l, int32_t *perm, int32_t *f
 int mx_precond_export_diag(const mx_precond *P, int l, double *d) {
   MX_GUARD({
     MX_REQUIRE(P && d, "NULL argument");
+    MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
     MX_REQUIRE(l >= 0 && l < P->nsub, "subdomain out of range");
     bind_device(P->device);
     const auto &s = P->sky[l];
@@ -297,6 +333,7 @@ int mx_precond_sweep_timing(mx_precond *P, int enable, int64_t *launches, double
                             double *ms_backward) {
   MX_GUARD({
     MX_REQUIRE(P, "NULL argument");
+    MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
     bind_device(P->device);
     mx::precond_timing(P, enable, launches, ms_forward, ms_backward);
   });
@@ -306,6 +343,7 @@ int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_
                         double *best_ms) {
   MX_GUARD({
     MX_REQUIRE(ctx && P, "NULL argument");
+    MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
     bind_device(ctx->device);
     mx::precond_autotune(ctx, P, (hipStream_t)stream, best_grid, best_ms);
   });
@@ -314,6 +352,7 @@ int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_
 int mx_precond_check(mx_precond *P) {
   MX_GUARD({
     MX_REQUIRE(P, "NULL argument");
+    MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
     bind_device(P->device);
     MX_HIP(hipDeviceSynchronize());
     mx::precond_check(P);
@@ -329,6 +368,7 @@ int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, 
     MX_REQUIRE(b_dev != x_dev, "b and x must be distinct");
     MX_REQUIRE(A->rowptr.p, "matrix has no device copy");
     MX_REQUIRE(!P || P->E == A->h.n, "preconditioner and matrix sizes differ");
+    MX_REQUIRE(!P || !P->plan, "preconditioner is planned but not materialised");
     bind_device(ctx->device);
     mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream);
   });

@@ -150,6 +150,7 @@ struct PrecondPlan {
 
 struct mx_precond {
   int kind = MX_ORAS, prec = MX_C128, nsub = 0, device = 0, sub_begin = 0;
+  std::unique_ptr<mx::PrecondPlan> plan;  // set between mx_precond_plan and mx_precond_materialize
   int64_t E = 0;
   int max_nb = 0;
   int64_t vec_total = 0, blocks_total = 0, tiles_total = 0;

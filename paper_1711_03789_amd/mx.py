@@ -31,7 +31,7 @@ SYMBOLS = [
     "mx_precond_check", "mx_precond_destroy", "mx_gmres", "mx_selftest", "mx_local_problem",
     "mx_precond_sweep_timing", "mx_precond_autotune", "mx_server_create", "mx_server_submit",
     "mx_server_wait", "mx_server_solution", "mx_server_release", "mx_server_stats",
-    "mx_server_destroy",
+    "mx_server_destroy", "mx_matrix_upload", "mx_precond_plan", "mx_precond_materialize",
 ]
 
 
@@ -132,6 +132,10 @@ def load(path=LIB_PATH):
         "mx_partition_export": (C.c_int, [P, C.c_int, P, P, P, P]),
         "mx_partition_destroy": (None, [P]),
         "mx_precond_setup": (C.c_int, [P, P, P, P, C.POINTER(PrecondOpts), C.POINTER(P)]),
+        "mx_precond_plan": (C.c_int, [P, P, P, P, C.POINTER(PrecondOpts), C.POINTER(P),
+                                      C.POINTER(C.c_uint64)]),
+        "mx_precond_materialize": (C.c_int, [P, P, P]),
+        "mx_matrix_upload": (C.c_int, [P, P]),
         "mx_precond_apply": (C.c_int, [P, P, P, P, P]),
         "mx_precond_get_info": (C.c_int, [P, C.POINTER(PrecondInfo)]),
         "mx_precond_export_perm": (C.c_int, [P, C.c_int, P, P]),
@@ -252,6 +256,9 @@ class Matrix:
             _lib.mx_matrix_destroy(self.h)
         self.h = None
 
+    def upload(self, ctx):
+        _check(_lib.mx_matrix_upload(ctx.h, self.h))
+
     def export(self):
         rp = np.zeros(self.n + 1, np.int64)
         col = np.zeros(self.nnz, np.int32)
@@ -309,15 +316,28 @@ def local_problem(mesh, A, part, l, kind="oras", xi_prec=None):
 
 
 class Precond:
+    """plan_only=True runs only the host half (mx_precond_plan); call materialize() before use."""
+
     def __init__(self, ctx, A, mesh, part, kind="oras", xi_prec=None, precision="c128",
-                 sweep_grid=0, share=None):
+                 sweep_grid=0, share=None, plan_only=False):
         load()
         s0, s1 = share if share is not None else (0, 0)
         o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec,
                         PRECISIONS.get(precision, precision), sweep_grid, s0, s1)
         h = P()
-        _check(_lib.mx_precond_setup(ctx.h, A.h, mesh.h, part.h, C.byref(o), C.byref(h)))
+        self.device_bytes = None
+        if plan_only:
+            nb = C.c_uint64()
+            _check(_lib.mx_precond_plan(ctx.h, A.h, mesh.h, part.h, C.byref(o), C.byref(h),
+                                        C.byref(nb)))
+            self.device_bytes = nb.value
+        else:
+            _check(_lib.mx_precond_setup(ctx.h, A.h, mesh.h, part.h, C.byref(o), C.byref(h)))
         self.h, self.ctx = h, ctx
+
+    def materialize(self, ctx, stream=None):
+        _check(_lib.mx_precond_materialize(ctx.h, self.h, _stream(stream)))
+        self.ctx = ctx
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -298,3 +298,38 @@ def sp_lower_first(Ap):
         if cols.size:
             out[i] = min(i, int(cols.min()))
     return out
+
+
+def test_plan_then_materialize(gpu_lib, ctx):
+    """The two halves of the setup (host plan on a host-only matrix, then device
+    materialisation) give the same preconditioner, bit for bit, as the one-call setup; a planned
+    preconditioner refuses to apply, and materialising twice is refused."""
+    say("plan + materialize")
+    n, parts = (9, 8, 7), (2, 2, 2)
+    lm = gpu_lib.Mesh(*n)
+    lp = gpu_lib.Partition(lm, *parts, 2)
+    A_dev = gpu_lib.Matrix(ctx, lm, 4.0, 16.0)
+    ref = gpu_lib.Precond(ctx, A_dev, lm, lp, "oras")
+    A_host = gpu_lib.Matrix(None, lm, 4.0, 16.0)
+    Pp = gpu_lib.Precond(ctx, A_host, lm, lp, "oras", plan_only=True)
+    assert Pp.device_bytes > 0
+    v = random_rhs(lm.n_edge, 21)
+    vd, z1, z2 = dev(v), dev(np.zeros(lm.n_edge)), dev(np.zeros(lm.n_edge))
+    with pytest.raises(gpu_lib.MxError):
+        Pp.apply(vd, z2)
+    Pp.materialize(ctx)
+    with pytest.raises(gpu_lib.MxError):
+        Pp.materialize(ctx)
+    ref.apply(vd, z1)
+    Pp.apply(vd, z2)
+    ref.check()
+    Pp.check()
+    assert np.array_equal(host(z1), host(z2))
+    A_host.upload(ctx)
+    with pytest.raises(gpu_lib.MxError):
+        A_host.upload(ctx)
+    b = dev(random_rhs(lm.n_edge, 22))
+    x1, x2 = dev(np.zeros(lm.n_edge)), dev(np.zeros(lm.n_edge))
+    s1 = gpu_lib.gmres(ctx, A_dev, ref, b, x1, restart=30, rtol=1e-8)
+    s2 = gpu_lib.gmres(ctx, A_host, Pp, b, x2, restart=30, rtol=1e-8)
+    assert s1["iters"] == s2["iters"] and np.array_equal(host(x1), host(x2))
