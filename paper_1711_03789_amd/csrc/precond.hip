@@ -167,17 +167,27 @@ __global__ __launch_bounds__(256) void k_fac_panel(int K, SubView v, const int32
 }
 
 // ---- factorisation: trailing update A_IJ -= L_IK D_K L_JK^T ---------------------------------------
-template <typename T>
+// Split in two launches so that the next diagonal tile and panel can start early (look-ahead):
+//   NEXT = true:  the tiles of block column K+1, (I, K+1) for K+1 <= I <= blast(K)  (pref: m per
+//                 subdomain, m = blast(K) - K);
+//   NEXT = false: all other tiles, (I, J) with K+2 <= J <= I <= blast(K)  (pref: m(m-1)/2).
+template <typename T, bool NEXT>
 __global__ __launch_bounds__(256) void k_fac_update(int K, SubView v, const int32_t *pref, int nsub,
                                                     cx<T> *pool) {
   const int g = blockIdx.x;
   const int l = find_sub(pref, nsub, g);
-  int t = g - pref[l];
-  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((r + 1) * (r + 2) / 2 <= t) ++r;
-  while (r * (r + 1) / 2 > t) --r;
-  const int c = t - r * (r + 1) / 2;
-  const int I = K + 1 + r, J = K + 1 + c;
+  const int t = g - pref[l];
+  int I, J;
+  if (NEXT) {
+    I = K + 1 + t;
+    J = K + 1;
+  } else {
+    int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    while (r * (r + 1) / 2 > t) --r;
+    I = K + 2 + r;
+    J = K + 2 + (t - r * (r + 1) / 2);
+  }
   __shared__ cx<T> dk[kTile];
   const cx<T> *Xk = tile_ptr(pool, v, l, K, K);
   if (threadIdx.x < kTile) dk[threadIdx.x] = Xk[threadIdx.x * kTile + threadIdx.x];
@@ -380,6 +390,8 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
   // the wave index is uniform: keeping it scalar keeps the tile metadata in scalar registers
   const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int row0 = w * kRows;  // this wave's first row inside a block
+  // tiles per wave in flight (eight for complex float measured slower than four)
+  constexpr int kBatch = 4;
   const int epoch = ctrl[0];
   int *abort = &ctrl[2];
   int *ticket = &ctrl[FWD ? 1 : 4];
@@ -425,8 +437,8 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
           dead = true;
           break;
         }
-        for (; J + 3 < Jend; J += 4)
-          stream_fwd<T, 4>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc);
+        for (; J + kBatch - 1 < Jend; J += kBatch)
+          stream_fwd<T, kBatch>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc);
         for (; J < Jend; ++J)
           stream_fwd<T, 1>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc);
       }
@@ -483,7 +495,7 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
           dead = true;
           break;
         }
-        for (; I - 3 > Iend; I -= 4) stream_bwd<T, 4>(pack, cm, vb, I, row0, zvec, acc);
+        for (; I - (kBatch - 1) > Iend; I -= kBatch) stream_bwd<T, kBatch>(pack, cm, vb, I, row0, zvec, acc);
         for (; I > Iend; --I) stream_bwd<T, 1>(pack, cm, vb, I, row0, zvec, acc);
       }
       if (has_next && !dead) {
@@ -559,21 +571,47 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Right-looking blocked LDL^T over all subdomains at once, one block step K after the other.  Two
+// streams overlap step K's bulk trailing update (aux stream) with the chain that gates step K+1
+// on the main stream: update of block column K+1, then diagonal tile K+1, then panel K+1.
 template <typename T>
 static void factor_all(mx_precond *P, hipStream_t st) {
   SubView v = view_of(P);
   cx<T> *pool = P->pool.as<cx<T>>();
   const int N = P->nsub;
-  for (int K = 0; K < P->max_nb; ++K) {
+  hipStream_t sx;
+  hipEvent_t ev_panel, ev_rest;
+  MX_HIP(hipStreamCreateWithFlags(&sx, hipStreamNonBlocking));
+  MX_HIP(hipEventCreateWithFlags(&ev_panel, hipEventDisableTiming));
+  MX_HIP(hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming));
+  auto diag_panel = [&](int K) {
     k_fac_diag<T><<<N, 256, 0, st>>>(K, v, pool, P->d_ctrl.as<int>());
+    const int np = P->panel_pref[(int64_t)K * (N + 1) + N];
+    if (np > 0)
+      k_fac_panel<T><<<np, 256, 0, st>>>(K, v, P->d_panel_pref.as<int32_t>() + (int64_t)K * (N + 1), N, pool);
+  };
+  MX_HIP(hipEventRecord(ev_rest, sx));  // nothing pending on the aux stream yet
+  diag_panel(0);
+  for (int K = 0; K < P->max_nb; ++K) {
     const int32_t *pp = P->d_panel_pref.as<int32_t>() + (int64_t)K * (N + 1);
     const int32_t *up = P->d_update_pref.as<int32_t>() + (int64_t)K * (N + 1);
-    int np = P->panel_pref[(int64_t)K * (N + 1) + N];
-    int nu = P->update_pref[(int64_t)K * (N + 1) + N];
-    if (np > 0) k_fac_panel<T><<<np, 256, 0, st>>>(K, v, pp, N, pool);
-    if (nu > 0) k_fac_update<T><<<nu, 256, 0, st>>>(K, v, up, N, pool);
+    const int np = P->panel_pref[(int64_t)K * (N + 1) + N];
+    const int nu = P->update_pref[(int64_t)K * (N + 1) + N];
+    // aux: tiles (I, J), J >= K+2, once panel K is done (and, in stream order, step K-1's rest)
+    MX_HIP(hipEventRecord(ev_panel, st));
+    MX_HIP(hipStreamWaitEvent(sx, ev_panel, 0));
+    if (nu > 0) k_fac_update<T, false><<<nu, 256, 0, sx>>>(K, v, up, N, pool);
+    // main: block column K+1 needs step K-1's rest (recorded before this step's rest is queued)
+    MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
+    if (np > 0) k_fac_update<T, true><<<np, 256, 0, st>>>(K, v, pp, N, pool);
+    MX_HIP(hipEventRecord(ev_rest, sx));
+    if (K + 1 < P->max_nb) diag_panel(K + 1);
   }
+  MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
   MX_HIP(hipGetLastError());
+  (void)hipEventDestroy(ev_panel);
+  (void)hipEventDestroy(ev_rest);
+  (void)hipStreamDestroy(sx);
 }
 
 template <typename T>
@@ -922,8 +960,8 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
       P->update_pref[(int64_t)K * (N + 1) + l] = (int32_t)au;
       if (K < P->sub_nb[l]) {
         int64_t mK = P->sky[l].blast[K] - K;
-        ap += mK;
-        au += mK * (mK + 1) / 2;
+        ap += mK;                 // panel tiles = block column K+1 tiles of the trailing update
+        au += mK * (mK - 1) / 2;  // the remaining trailing tiles
       }
     }
     if (au > INT32_MAX) fail(MX_EINVAL, "factor step too large");
