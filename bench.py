@@ -22,6 +22,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per forward-sweep launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of the same
+# command (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0: what the counters read for a 1 GiB
+# device copy), averaged over the launches; summaries in profiles/.  Valid for the sweep kernel
+# as it is now; None where not measured.
+SWEEP_TRAFFIC = {("scale", "c128"): 59.62e9, ("apply", "c128"): 66.69e9}
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
@@ -204,7 +209,8 @@ def run_apply(args):
                                "one Schwarz application per step"},
         "roofline": {"bound": "hbm", "kernel": "k_sweep<T, true> (forward block sweep)",
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                     "traffic": None, "launches": nl, "avg_launch_ms": fms / nl, "bytes_per_launch": sb,
+                     "traffic": SWEEP_TRAFFIC.get(("apply", args.precision)), "launches": nl,
+                     "avg_launch_ms": fms / nl, "bytes_per_launch": sb,
                      "stored_factor_over_envelope": inf["pack_bytes"] / (inf["env_entries"] *
                                                                         (16 if args.precision == "c128" else 8)),
                      "backward": {"avg_launch_ms": bms / nl, "achieved": sb / (bms / nl * 1e-3) / 1e9}},
@@ -404,7 +410,8 @@ def main():
                                                 "Schwarz application; the backward launch is "
                                                 "reported beside it)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": SWEEP_TRAFFIC.get((args.workload, args.precision)),
                      "launches": launches, "avg_launch_ms": fwd_ms / max(launches, 1),
                      "bytes_per_launch_avg": sweep_bytes / max(launches, 1),
                      "stored_factor_over_envelope": sum(r["pack_bytes"] for r in all_r) /
