@@ -112,29 +112,33 @@ def local_pattern(part, l, kind, bc=fem.BC_IMPEDANCE):
     return P
 
 
-def local_matrices(part, A, kind, k, xi, bc=fem.BC_IMPEDANCE):
-    """A^l for every subdomain: minors of A (AS, RAS) or impedance local problems (ORAS)."""
+def local_matrix(part, A, kind, k, xi, l, bc=fem.BC_IMPEDANCE):
+    """A^l of subdomain l: the minor of A (AS, RAS; eq:minor) or the impedance local problem
+    assembled on the tetrahedra of Omega_l (ORAS = ImpRAS, Sec. 6.3)."""
     mesh = part.mesh
-    out = []
     if kind in (AS, RAS):
-        for idx in part.as_sets:
-            out.append(A[idx][:, idx].tocsc())
-        return out
-    pec = mesh.boundary_edge_mask() if bc == fem.BC_PEC else None
-    gb = set(map(tuple, mesh.bface_vert)) if bc == fem.BC_PEC else None
-    for l, idx in enumerate(part.oras_sets):
-        tets = np.nonzero(part.tet_masks[l])[0]
-        faces = part.subdomain_boundary_faces(l)
-        if bc == fem.BC_PEC:  # PEC faces of the box keep PEC, only interface faces get impedance
-            faces = np.array([f for f in faces if tuple(f) not in gb]).reshape(-1, 3)
-        K, M, Mb = fem.assemble_parts(mesh, tets, faces)
-        Al = (K.astype(np.complex128) - (k * k + 1j * xi) * M
-              - 1j * fem.impedance_sign(xi) * k * Mb).tocsr()
-        if pec is not None and pec.any():
+        idx = part.as_sets[l]
+        return A[idx][:, idx].tocsc()
+    idx = part.oras_sets[l]
+    tets = np.nonzero(part.tet_masks[l])[0]
+    faces = part.subdomain_boundary_faces(l)
+    if bc == fem.BC_PEC:  # PEC faces of the box keep PEC, only interface faces get impedance
+        gb = set(map(tuple, mesh.bface_vert))
+        faces = np.array([f for f in faces if tuple(f) not in gb]).reshape(-1, 3)
+    K, M, Mb = fem.assemble_parts(mesh, tets, faces)
+    Al = (K.astype(np.complex128) - (k * k + 1j * xi) * M
+          - 1j * fem.impedance_sign(xi) * k * Mb).tocsr()
+    if bc == fem.BC_PEC:
+        pec = mesh.boundary_edge_mask()
+        if pec.any():
             keep = sp.diags((~pec).astype(np.float64))
             Al = (keep @ Al @ keep + sp.diags(pec.astype(np.float64))).tocsr()
-        out.append(Al[idx][:, idx].tocsc())
-    return out
+    return Al[idx][:, idx].tocsc()
+
+
+def local_matrices(part, A, kind, k, xi, bc=fem.BC_IMPEDANCE):
+    """A^l for every subdomain: minors of A (AS, RAS) or impedance local problems (ORAS)."""
+    return [local_matrix(part, A, kind, k, xi, l, bc) for l in range(part.N)]
 
 
 class Schwarz:

@@ -120,17 +120,25 @@ __device__ __forceinline__ void tile_nt_quadrant(const cx<T> *__restrict__ A,
         bv[cb][e] = v;
       }
     }
+    // two passes over the eight accumulators per k group, so that consecutive matrix-core
+    // instructions never depend on each other (a dependent one waits for the previous result)
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 4; ++e) {
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
           acc[rb][cb][0] = Mfma<T>::op(av[rb][e].re, bv[cb][e].re, acc[rb][cb][0]);
-          acc[rb][cb][0] = Mfma<T>::op(-av[rb][e].im, bv[cb][e].im, acc[rb][cb][0]);
           acc[rb][cb][1] = Mfma<T>::op(av[rb][e].re, bv[cb][e].im, acc[rb][cb][1]);
+        }
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          acc[rb][cb][0] = Mfma<T>::op(-av[rb][e].im, bv[cb][e].im, acc[rb][cb][0]);
           acc[rb][cb][1] = Mfma<T>::op(av[rb][e].im, bv[cb][e].re, acc[rb][cb][1]);
         }
+    }
   }
 }
 

@@ -171,10 +171,19 @@ __global__ __launch_bounds__(256) void k_fac_panel(int K, SubView v, const int32
 //   NEXT = true:  the tiles of block column K+1, (I, K+1) for K+1 <= I <= blast(K)  (pref: m per
 //                 subdomain, m = blast(K) - K);
 //   NEXT = false: all other tiles, (I, J) with K+2 <= J <= I <= blast(K)  (pref: m(m-1)/2).
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Remapping the
+// block index gives every XCD a contiguous range of tiles, so consecutive tiles (same block row I,
+// hence the same L_IK, and neighbouring L_JK) meet in one L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+  constexpr int kXcd = 8;
+  const int per = n / kXcd, rem = n % kXcd, x = b % kXcd, q = b / kXcd;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + q;
+}
+
 template <typename T, bool NEXT>
 __global__ __launch_bounds__(256) void k_fac_update(int K, SubView v, const int32_t *pref, int nsub,
                                                     cx<T> *pool) {
-  const int g = blockIdx.x;
+  const int g = xcd_contiguous(blockIdx.x, gridDim.x);
   const int l = find_sub(pref, nsub, g);
   const int t = g - pref[l];
   int I, J;
