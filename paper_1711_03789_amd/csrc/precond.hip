@@ -171,6 +171,82 @@ __global__ __launch_bounds__(256) void k_fac_panel(int K, SubView v, const int32
 //   NEXT = true:  the tiles of block column K+1, (I, K+1) for K+1 <= I <= blast(K)  (pref: m per
 //                 subdomain, m = blast(K) - K);
 //   NEXT = false: all other tiles, (I, J) with K+2 <= J <= I <= blast(K)  (pref: m(m-1)/2).
+// Staged complex tile product for the trailing update, one 32x32 quadrant per wave:
+//     acc[i][j] = sum_k A[i][k] * d[k] * B[j][k]      (A, B row-major 64x64 tiles)
+// The workgroup copies 16-wide k slabs of A and of d-scaled B into LDS (double-buffered, rows
+// padded by one entry so the 16 rows read by one instruction fall in different banks) while the
+// waves run the matrix-core products of the previous slab, so every tile entry is read from L2
+// once per workgroup instead of once per wave.
+template <typename T>
+struct UpdateStage {
+  cx<T> a[2][kTile][17];
+  cx<T> b[2][kTile][17];
+};
+
+template <typename T>
+__device__ __forceinline__ void update_product(const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
+                                               const cx<T> *__restrict__ d, UpdateStage<T> &st,
+                                               int r0, int c0, typename Mfma<T>::acc_t acc[2][2][2]) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int lrow = tid >> 2, lq = (tid & 3) * 4;  // staging: row, first of 4 consecutive k
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[a][b][c] = acc_t{0, 0, 0, 0};
+  cx<T> ra[4], rb[4];
+  auto fetch = [&](int kk) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ra[e] = A[lrow * kTile + kk + lq + e];
+      rb[e] = cmul(B[lrow * kTile + kk + lq + e], d[kk + lq + e]);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      st.a[buf][lrow][lq + e] = ra[e];
+      st.b[buf][lrow][lq + e] = rb[e];
+    }
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < kTile / 16; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < kTile / 16) fetch((s + 1) * 16);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      cx<T> av[2], bv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[q] = st.a[buf][r0 + q * 16 + li][4 * lk + e];
+        bv[q] = st.b[buf][c0 + q * 16 + li][4 * lk + e];
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          acc[q][p][0] = Mfma<T>::op(av[q].re, bv[p].re, acc[q][p][0]);
+          acc[q][p][1] = Mfma<T>::op(av[q].re, bv[p].im, acc[q][p][1]);
+        }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          acc[q][p][0] = Mfma<T>::op(-av[q].im, bv[p].im, acc[q][p][0]);
+          acc[q][p][1] = Mfma<T>::op(av[q].im, bv[p].re, acc[q][p][1]);
+        }
+    }
+    if (s + 1 < kTile / 16) stash(buf ^ 1);
+    __syncthreads();
+  }
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Remapping the
 // block index gives every XCD a contiguous range of tiles, so consecutive tiles (same block row I,
 // hence the same L_IK, and neighbouring L_JK) meet in one L2.
@@ -198,6 +274,7 @@ __global__ __launch_bounds__(256) void k_fac_update(int K, SubView v, const int3
     J = K + 2 + (t - r * (r + 1) / 2);
   }
   __shared__ cx<T> dk[kTile];
+  __shared__ UpdateStage<T> stage;
   const cx<T> *Xk = tile_ptr(pool, v, l, K, K);
   if (threadIdx.x < kTile) dk[threadIdx.x] = Xk[threadIdx.x * kTile + threadIdx.x];
   __syncthreads();
@@ -207,7 +284,7 @@ __global__ __launch_bounds__(256) void k_fac_update(int K, SubView v, const int3
   const int w = threadIdx.x >> 6;
   const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
   typename Mfma<T>::acc_t acc[2][2][2];
-  tile_nt_quadrant<T, true, false>(A, B, dk, r0, c0, acc);
+  update_product<T>(A, B, dk, stage, r0, c0, acc);
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
