@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # command (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0: what the counters read for a 1 GiB
 # device copy), averaged over the launches; summaries in profiles/.  Valid for the sweep kernel
 # as it is now; None where not measured.
-SWEEP_TRAFFIC = {("scale", "c128"): 59.62e9, ("apply", "c128"): 66.69e9}
+SWEEP_TRAFFIC = {}
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
@@ -420,7 +420,8 @@ def main():
                                   "avg_launch_ms": bwd_ms / max(launches, 1)}},
         "factor": {"bound": "mfma", "achieved_env": sum(r["env_flops"] for r in all_r) / t_factor / 1e12,
                    "achieved_executed": sum(r["tile_flops"] for r in all_r) / t_factor / 1e12,
-                   "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "seconds_total": t_factor},
+                   "peak": FP64_PEAK_TFS if args.precision == "c128" else FP32_PEAK_TFS,
+                   "unit": "TFLOP/s", "seconds_total": t_factor},
         "solve_phase_solves_per_s": n_solves / t_gmres if converged and t_gmres > 0 else 0.0,
         "phase_seconds_per_step": {
             "mesh_partition": sum(t for t, _ in recs) / args.steps,
