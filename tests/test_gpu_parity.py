@@ -333,3 +333,25 @@ def test_plan_then_materialize(gpu_lib, ctx):
     s1 = gpu_lib.gmres(ctx, A_dev, ref, b, x1, restart=30, rtol=1e-8)
     s2 = gpu_lib.gmres(ctx, A_host, Pp, b, x2, restart=30, rtol=1e-8)
     assert s1["iters"] == s2["iters"] and np.array_equal(host(x1), host(x2))
+
+
+@pytest.mark.parametrize("n,parts", [((1, 1, 1), (1, 1, 1)), ((2, 1, 1), (2, 1, 1)), ((3, 2, 1), (3, 2, 1))])
+def test_tiny_meshes(gpu_lib, ctx, n, parts):
+    """Subdomains far smaller than one 64-row tile (a single ragged block each), including the
+    single-cube mesh (19 edges)."""
+    say("tiny", n, parts)
+    for kind in ("oras", "as"):
+        c = Case(gpu_lib, ctx, n, parts, 1, 3.0, 9.0, kind)
+        v = random_rhs(c.E, 30)
+        vd, zd = dev(v), dev(np.zeros(c.E))
+        c.lP.apply(vd, zd)
+        c.lP.check()
+        ref = c.oB(v)
+        err = np.linalg.norm(host(zd) - ref) / np.linalg.norm(ref)
+        say("  ", kind, "E", c.E, "rel err", err)
+        assert err <= 1e-10
+        f = random_rhs(c.E, 31)
+        xd = dev(np.zeros(c.E))
+        st = gpu_lib.gmres(ctx, c.lA, c.lP, dev(f), xd, restart=20, rtol=1e-10)
+        ores = gmres.gmres(c.oA, f, c.oB, restart=20, rtol=1e-10)
+        assert st["converged"] and abs(st["iters"] - ores.iters) <= 1
