@@ -223,13 +223,27 @@ def run_serving(args):
     """Continuous-batching server: seeded Poisson arrivals of unit-cube requests (k ~ U[4,16],
     xi in {k, k^2}, n = ceil(k^1.5)+4 cubes per side, p = clamp(ceil(n/17),2,4) subdomains per
     side, Gaussian sources), mixed-precision ORAS FGMRES(50) rtol 1e-6, admission by exact HBM
-    footprint.  Reports throughput and p50/p99 latency (arrival to result)."""
+    footprint.  Unless --rate is given, the arrival rate is 0.8 x the saturated throughput of a
+    closed-loop calibration run (all calibration requests submitted at once).  Reports
+    throughput and p50/p99 latency (arrival to result)."""
     import numpy as np
 
     from mx_inputs import serving_requests
     from paper_1711_03789_amd import mx
-    reqs = serving_requests(args.requests, args.rate, args.seed)
     srv = mx.Server(slots=args.slots, precision="c64", restart=50, flexible=True, rtol=1e-6)
+    calib = None
+    rate = args.rate
+    if rate <= 0:
+        creqs = serving_requests(args.calib_requests, 1.0, args.seed + 1000)
+        c0 = time.perf_counter()
+        ts = [srv.submit(r["n"], r["p"], r["k"], r["xi"], r["center"], r["pol"], 0.1) for r in creqs]
+        for t in ts:
+            srv.wait(t, 600.0)
+            srv.release(t)
+        sat = len(creqs) / (time.perf_counter() - c0)
+        rate = 0.8 * sat
+        calib = {"requests": len(creqs), "saturated_solves_per_s": sat, "rate": rate}
+    reqs = serving_requests(args.requests, rate, args.seed)
     t0 = time.perf_counter()
     tickets = []
     for r in reqs:
@@ -254,11 +268,12 @@ def run_serving(args):
         "dtype": "complex64 factors + FP64 FGMRES", "data": "synthetic",
         "config": {"workload": "serving: %d requests, Poisson arrivals at %.2f/s, unit cube, "
                                "k~U[4,16], xi in {k,k^2}, n=ceil(k^1.5)+4, p=clamp(ceil(n/17),2,4), "
-                               "ORAS FGMRES(50) rtol 1e-6, %d slots" % (len(res), args.rate, args.slots)},
+                               "ORAS FGMRES(50) rtol 1e-6, %d slots" % (len(res), rate, args.slots)},
         "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
         "throughput_solves_per_s": len(res) / (t1 - t0), "all_converged": ok,
         "mean_iters": float(np.mean([x["iters"] for x in res])),
         "mean_queue_s": float(np.mean([x["t_queue"] for x in res])),
+        "calibration": calib,
         "server": st,
     }
 
@@ -274,8 +289,10 @@ def main():
     ap.add_argument("--precision", default="c128", choices=["c128", "c64"],
                     help="c64: complex64 factors and SpMV values inside FP64 flexible GMRES")
     ap.add_argument("--reps", type=int, default=10, help="applications timed (batching)")
-    ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
-    ap.add_argument("--rate", type=float, default=2.0, help="serving: arrivals per second")
+    ap.add_argument("--requests", type=int, default=120, help="serving: number of requests")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serving: arrivals per second (0 = 0.8 x calibrated saturated throughput)")
+    ap.add_argument("--calib-requests", type=int, default=24, help="serving: calibration requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: requests in flight")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
