@@ -50,10 +50,10 @@ void build_partition(const Mesh &m, int px, int py, int pz, const int32_t *cx, c
   p.as_set.assign(p.nsub, {});
   p.oras_set.assign(p.nsub, {});
   // one subdomain per task; per-thread stamp arrays for vertices, tetrahedra and edges
-  parallel_for(p.nsub, [&](int64_t s0, int64_t s1) {
+  parallel_items(p.nsub, [&](auto next) {
     std::vector<int32_t> vstamp(m.nv, -1), tstamp(m.nt, -1), estamp(m.ne, -1);
     int32_t gen = 0;
-    for (int64_t l = s0; l < s1; ++l) {
+    for (int64_t l; (l = next()) >= 0;) {
       int b[3] = {(int)(l % px), (int)((l / px) % py), (int)(l / ((int64_t)px * py))};
       int lo[3], hi[3], clo[3], chi[3];
       for (int a = 0; a < 3; ++a) {
@@ -106,7 +106,7 @@ void build_partition(const Mesh &m, int px, int py, int pz, const int32_t *cx, c
       p.oras_set[l].swap(oras);
       p.as_set[l].swap(as);
     }
-  }, 1);
+  });
   p.owner.assign(m.ne, 0);
   parallel_for(m.ne, [&](int64_t a, int64_t b) {
     for (int64_t e = a; e < b; ++e) {

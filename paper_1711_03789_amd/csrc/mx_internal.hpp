@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <string>
 #include <vector>
+#include <atomic>
 #include <thread>
 #include <algorithm>
 
@@ -35,6 +36,23 @@ void parallel_for(int64_t n, F &&f, int64_t grain = 4096) {
     if (a >= b) break;
     th.emplace_back([&f, a, b] { f(a, b); });
   }
+  for (auto &x : th) x.join();
+}
+
+// Items of very different cost (subdomains): f(next) runs once on each of up to 16 threads, so
+// it can set up per-thread scratch; next() hands out the unclaimed items in order, then -1.
+template <class F>
+void parallel_items(int64_t n, F &&f) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nt = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nt, n));
+  std::atomic<int64_t> counter(0);
+  auto next = [&counter, n]() -> int64_t {
+    const int64_t i = counter.fetch_add(1);
+    return i < n ? i : -1;
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt; ++t) th.emplace_back([&] { f(next); });
+  f(next);
   for (auto &x : th) x.join();
 }
 

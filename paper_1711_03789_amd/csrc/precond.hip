@@ -877,10 +877,10 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   P->sky.assign(N, Skyline());
   KuhnElements ke;
   kuhn_elements(m.lx / m.nx, m.ly / m.ny, m.lz / m.nz, ke);
-  parallel_for(N, [&](int64_t a, int64_t b) {
+  parallel_items(N, [&](auto next) {
     std::vector<int32_t> g2l(m.ne, -1), tstamp;
     if (opts->kind == MX_ORAS) tstamp.assign(m.nt, -1);
-    for (int64_t l = a; l < b; ++l) {
+    for (int64_t l; (l = next()) >= 0;) {
       if (opts->kind == MX_ORAS)
         local_impedance(m, ke, A->k, opts->xi_prec, A->bc, part.tets[s0 + l], sets[l], loc[l], g2l,
                         tstamp, (int32_t)l);
@@ -888,7 +888,7 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
         local_minor(m, A->h, A->bc, sets[l], loc[l], g2l);
       build_skyline(loc[l], P->sky[l]);
     }
-  }, 1);
+  });
   // layout
   P->sub_nb.resize(N);
   P->sub_brow_base.resize(N);
@@ -929,8 +929,8 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   // first_i < 64 (J + 1) (padding rows have first_i = i); kept rows are packed tile after tile
   std::vector<int64_t> &rmeta = plan.rmeta, &cmeta = plan.cmeta, &cptr = plan.cptr;
   rmeta.assign(2 * tiles, 0);
-  parallel_for(N, [&](int64_t a0, int64_t a1) {
-    for (int64_t l = a0; l < a1; ++l) {
+  parallel_items(N, [&](auto next) {
+    for (int64_t l; (l = next()) >= 0;) {
       const Skyline &s = P->sky[l];
       for (int64_t I = 0; I < s.nb; ++I) {
         const int64_t f = s.bfirst[I], t0 = P->sub_tile_base[l] + s.brow_off[I];
@@ -946,7 +946,7 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
         }
       }
     }
-  }, 1);
+  });
   int64_t packed = 0;
   for (int64_t t = 0; t < tiles; ++t) {
     rmeta[2 * t] = packed;
@@ -986,8 +986,8 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   std::vector<double> &val = plan.val;
   off.assign(cnt[N], 0);
   val.assign(2 * cnt[N], 0.0);
-  parallel_for(N, [&](int64_t a0, int64_t a1) {
-    for (int64_t l = a0; l < a1; ++l) {
+  parallel_items(N, [&](auto next) {
+    for (int64_t l; (l = next()) >= 0;) {
       const LocalCSR &a = loc[l];
       const Skyline &s = P->sky[l];
       int64_t w = cnt[l];
@@ -1013,7 +1013,7 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
         ++w;
       }
     }
-  }, 1);
+  });
   // restriction / prolongation maps
   std::vector<int32_t> &glob = plan.glob;
   glob.assign(vec, -1);
