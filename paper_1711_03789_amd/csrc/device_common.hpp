@@ -182,6 +182,29 @@ __device__ __forceinline__ cx<T> pub_load(const cx<T> *p) {
 // lgkmcnt left unconstrained).
 __device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Sentinel marking a not-yet-written result value: a NaN bit pattern that no computed value has
+// (a NaN result means a failed factorisation, which is reported anyway).  A result vector is
+// filled with it before each sweep; a consumer of the block it depends on last polls the values
+// themselves instead of a flag, which saves the producer's store acknowledgement and one round
+// trip on the critical path.  Each half of a complex value is written by one 4- or 8-byte store,
+// so a value is complete when neither half is the sentinel.
+__device__ __forceinline__ bool is_sentinel(double v) {
+  return __double_as_longlong(v) == (long long)0x7FF75EA700000001ull;
+}
+__device__ __forceinline__ bool is_sentinel(float v) { return __float_as_uint(v) == 0x7FB5EA71u; }
+template <typename T>
+__device__ __forceinline__ cx<T> sentinel();
+template <>
+__device__ __forceinline__ cx<double> sentinel<double>() {
+  const double s = __longlong_as_double((long long)0x7FF75EA700000001ull);
+  return {s, s};
+}
+template <>
+__device__ __forceinline__ cx<float> sentinel<float>() {
+  const float s = __uint_as_float(0x7FB5EA71u);
+  return {s, s};
+}
+
 // Spins until *flag == want; returns false (and raises *abort) after kSpinLimit polls or when
 // another workgroup has raised *abort.
 __device__ inline bool wait_flag(const int *flag, int want, int *abort) {
@@ -189,6 +212,22 @@ __device__ inline bool wait_flag(const int *flag, int want, int *abort) {
   for (long it = 0; it < kSpinLimit; ++it) {
     __builtin_amdgcn_s_sleep(1);
     if (load_flag(flag) == want) return true;
+    if ((it & 63) == 0 && load_flag(abort)) return false;
+  }
+  store_flag(abort, 1);
+  return false;
+}
+
+// Loads this wave's values at p, waiting (bounded) until no lane sees the sentinel in either half;
+// returns false (and raises *abort) after kSpinLimit polls or when another workgroup has raised it.
+template <typename T>
+__device__ inline bool wait_values(const cx<T> *p, cx<T> &v, int *abort) {
+  v = pub_load(p);
+  if (__all(!is_sentinel(v.re) && !is_sentinel(v.im))) return true;
+  for (long it = 0; it < kSpinLimit; ++it) {
+    __builtin_amdgcn_s_sleep(1);
+    v = pub_load(p);
+    if (__all(!is_sentinel(v.re) && !is_sentinel(v.im))) return true;
     if ((it & 63) == 0 && load_flag(abort)) return false;
   }
   store_flag(abort, 1);

@@ -300,7 +300,8 @@ __global__ __launch_bounds__(256) void k_fac_update(int K, SubView v, const int3
 // ---- application: restrict, persistent sweeps, prolong ---------------------------------------------
 template <typename T>
 __global__ void k_restrict(int64_t n, const int32_t *__restrict__ glob,
-                           const cx<double> *__restrict__ vin, cx<T> *__restrict__ r, int *ctrl) {
+                           const cx<double> *__restrict__ vin, cx<T> *__restrict__ r,
+                           cx<T> *__restrict__ y, cx<T> *__restrict__ z, int *ctrl) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p == 0) {
     ctrl[0] += 1;  // epoch of this application
@@ -310,6 +311,8 @@ __global__ void k_restrict(int64_t n, const int32_t *__restrict__ glob,
   if (p < n) {
     int32_t g = glob[p];
     r[p] = g >= 0 ? ccast<T>(vin[g]) : cx<T>{0, 0};
+    y[p] = sentinel<T>();  // results of the two sweeps: not yet written
+    z[p] = sentinel<T>();
   }
 }
 
@@ -538,10 +541,11 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
           stream_fwd<T, 1>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc);
       }
       if (has_prev && !dead) {
-        if (ready_run(fl, B - 1, B, 1, epoch, abort) == INT_MIN) {
+        // the last dependency is read directly (sentinel polling), not through its flag
+        cx<T> y0;
+        if (!wait_values(yvec + vb + (int64_t)(B - 1) * kTile + lane, y0, abort)) {
           dead = true;
         } else {
-          const cx<T> y0 = pub_load(yvec + vb + (int64_t)(B - 1) * kTile + lane);
 #pragma unroll
           for (int r = 0; r < kRows; ++r) cfma(acc[r], sL[row0 + r][lane], y0);
         }
@@ -594,10 +598,10 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
         for (; I > Iend; --I) stream_bwd<T, 1>(pack, cm, vb, I, row0, zvec, acc);
       }
       if (has_next && !dead) {
-        if (ready_run(fl, B + 1, B, -1, epoch, abort) == INT_MIN) {
+        cx<T> zv;  // the last dependency, read directly (sentinel polling)
+        if (!wait_values(zvec + vb + (int64_t)(B + 1) * kTile + row0 + (lane & (kRows - 1)), zv, abort)) {
           dead = true;
         } else {
-          const cx<T> zv = pub_load(zvec + vb + (int64_t)(B + 1) * kTile + row0 + (lane & (kRows - 1)));
 #pragma unroll
           for (int r = 0; r < kRows; ++r) cfma(acc, sL[row0 + r][lane], bcast(zv, r));
         }
@@ -713,9 +717,9 @@ template <typename T>
 static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
   SubView v = view_of(P);
   const int64_t n = P->vec_total;
-  k_restrict<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, P->d_glob.as<int32_t>(),
-                                                             (const cx<double> *)vin,
-                                                             P->d_r.as<cx<T>>(), P->d_ctrl.as<int>());
+  k_restrict<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+      n, P->d_glob.as<int32_t>(), (const cx<double> *)vin, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
+      P->d_z.as<cx<T>>(), P->d_ctrl.as<int>());
   int *flags = P->d_flags.as<int>();
   if (P->timing) {
     if (P->n_timed == P->ev_start.size()) {
