@@ -87,8 +87,18 @@ def cpu_baseline(total_iters, n_inst):
         lu.solve(random_rhs(len(idx), 0))
         t4 = time.perf_counter()
     t_global, t_local, t_lu, t_solve = t1 - t0, t2 - t1, t3 - t2, t4 - t3
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     per_solve = 8 * t_global + 64 * (t_local + t_lu) + (total_iters / max(n_inst, 1)) * 64 * t_solve
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host": {"cpu": model, "nproc": os.cpu_count(), "blas_threads": 1},
             "sample": "oracle mesh+assembly+partition of the 32^3 box (x8) and one 16^3-cube ORAS "
                       "local problem: assembly, SciPy SuperLU factorisation, one solve (x64 "
                       "subdomains), GMRES iterations taken from the GPU run; measured %.1f s, "
