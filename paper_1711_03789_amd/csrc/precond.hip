@@ -678,6 +678,25 @@ static void factor_all(mx_precond *P, hipStream_t st) {
   SubView v = view_of(P);
   cx<T> *pool = P->pool.as<cx<T>>();
   const int N = P->nsub;
+  int64_t total_updates = 0;
+  for (int K = 0; K < P->max_nb; ++K)
+    total_updates += P->update_pref[(int64_t)K * (N + 1) + N] + P->panel_pref[(int64_t)K * (N + 1) + N];
+  if (total_updates < 2048LL * std::max(1, P->max_nb)) {
+    // small steps (a few tiles per CU): launch latency dominates and the second stream's event
+    // traffic costs more than the overlap gains; one stream, four launches per step
+    for (int K = 0; K < P->max_nb; ++K) {
+      const int32_t *pp = P->d_panel_pref.as<int32_t>() + (int64_t)K * (N + 1);
+      const int32_t *up = P->d_update_pref.as<int32_t>() + (int64_t)K * (N + 1);
+      const int np = P->panel_pref[(int64_t)K * (N + 1) + N];
+      const int nu = P->update_pref[(int64_t)K * (N + 1) + N];
+      k_fac_diag<T><<<N, 256, 0, st>>>(K, v, pool, P->d_ctrl.as<int>());
+      if (np > 0) k_fac_panel<T><<<np, 256, 0, st>>>(K, v, pp, N, pool);
+      if (np > 0) k_fac_update<T, true><<<np, 256, 0, st>>>(K, v, pp, N, pool);
+      if (nu > 0) k_fac_update<T, false><<<nu, 256, 0, st>>>(K, v, up, N, pool);
+    }
+    MX_HIP(hipGetLastError());
+    return;
+  }
   hipStream_t sx;
   hipEvent_t ev_panel, ev_rest;
   MX_HIP(hipStreamCreateWithFlags(&sx, hipStreamNonBlocking));
