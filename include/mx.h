@@ -133,6 +133,8 @@ typedef struct {
   int sweep_grid;  /* workgroups of the persistent sweep kernels; 0 = one per compute unit      */
   int sub_begin;   /* resident share: build only subdomains [sub_begin, sub_end) (both 0 = all); */
   int sub_end;     /* the application then returns the share's part of the sum (zero elsewhere)*/
+  int64_t pool_limit; /* bytes of full factor tiles held at a time: the subdomains are factored in */
+                      /* consecutive groups that fit (0 = as many as free device memory allows)  */
 } mx_precond_opts;
 
 /* Host-only view of one local problem, as mx_precond_setup builds it (for inspection and
@@ -161,6 +163,7 @@ typedef struct {
   int64_t pack_bytes;           /* device bytes of the trimmed tiles read by the sweeps (the tile */
                                 /* rows that meet the envelope; diagonal tiles in full)          */
   double t_pack;                /* seconds spent trimming the tiles and freeing the full ones    */
+  int32_t factor_groups;        /* consecutive subdomain groups the factorisation ran in         */
 } mx_precond_info;
 
 /* Builds the local matrices (AS/RAS: minors of A, so the matrix's k, xi and bc are used; ORAS:

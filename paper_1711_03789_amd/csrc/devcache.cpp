@@ -76,6 +76,14 @@ void big_free(void *p, size_t capacity, hipStream_t st) {
   g_free.push_back({p, capacity, dev, ev});
 }
 
+size_t big_cached(int device) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  size_t n = 0;
+  for (const auto &b : g_free)
+    if (b.device == device) n += b.cap;
+  return n;
+}
+
 void big_trim(int device) {
   std::vector<Block> out;
   {

@@ -47,6 +47,7 @@ constexpr size_t kBigBlock = size_t(64) << 20;
 void *big_alloc(size_t n, size_t *capacity);
 void big_free(void *p, size_t capacity, hipStream_t st);
 void big_trim(int device);
+size_t big_cached(int device);  // bytes of the device's blocks held in the cache
 
 // Owning device buffer.
 struct DevBuf {
@@ -144,6 +145,7 @@ struct PrecondPlan {
   std::vector<int32_t> sched_sub, sched_blk;
   std::vector<int64_t> rmeta, cmeta;  // trimmed-tile (base, row mask) pairs: tile order, block-column order
   std::vector<int64_t> cptr;          // start of each block column in cmeta
+  std::vector<int64_t> scat;          // start of each subdomain's entries in off / val
   size_t device_bytes = 0;    // peak device bytes of materialising and holding the preconditioner
 };
 }  // namespace mx
@@ -151,6 +153,8 @@ struct PrecondPlan {
 struct mx_precond {
   int kind = MX_ORAS, prec = MX_C128, nsub = 0, device = 0, sub_begin = 0;
   std::unique_ptr<mx::PrecondPlan> plan;  // set between mx_precond_plan and mx_precond_materialize
+  int64_t pool_limit = 0;                 // bytes of full tiles at a time (0: what device memory allows)
+  int n_groups = 0;                       // subdomain groups the factorisation ran in
   int64_t E = 0;
   int max_nb = 0;
   int64_t vec_total = 0, blocks_total = 0, tiles_total = 0;

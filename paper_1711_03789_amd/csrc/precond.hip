@@ -47,12 +47,13 @@ struct SubView {
   // (tile (I, B) of a subdomain at cmeta[cptr[brow_base + B] + I - B] for B <= I <= blast(B))
   const TileMeta *rmeta, *cmeta;
   const int64_t *cptr;
+  int64_t tile_shift;  // factorisation: first tile of the group held in the tile pool
 };
 
 template <typename T>
 __device__ __forceinline__ cx<T> *tile_ptr(cx<T> *pool, const SubView &v, int l, int I, int J) {
   const int bb = v.brow_base[l];
-  const int64_t t = v.tile_base[l] + v.brow_off[bb + I] + (J - v.bfirst[bb + I]);
+  const int64_t t = v.tile_base[l] - v.tile_shift + v.brow_off[bb + I] + (J - v.bfirst[bb + I]);
   return pool + t * (int64_t)kTileElems;
 }
 
@@ -69,9 +70,9 @@ __device__ __forceinline__ int find_sub(const int32_t *pref, int nsub, int g) {
 // ---- setup kernels ------------------------------------------------------------------------------
 template <typename T>
 __global__ void k_scatter(int64_t n, const int64_t *__restrict__ off,
-                          const cx<double> *__restrict__ val, cx<T> *__restrict__ pool) {
+                          const cx<double> *__restrict__ val, int64_t shift, cx<T> *__restrict__ pool) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) pool[off[i]] = ccast<T>(val[i]);
+  if (i < n) pool[off[i] - shift] = ccast<T>(val[i]);
 }
 
 __global__ void k_zero(int64_t n16, uint4 *__restrict__ p) {
@@ -88,8 +89,8 @@ __global__ void k_zero(int64_t n16, uint4 *__restrict__ p) {
 // columns (four partial sums per column, reduced with lane shuffles).  Written back as X below
 // the diagonal, D on it, 0 above.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fac_diag(int K, SubView v, cx<T> *pool, int *ctrl) {
-  const int l = blockIdx.x;
+__global__ __launch_bounds__(256) void k_fac_diag(int K, int l0, SubView v, cx<T> *pool, int *ctrl) {
+  const int l = l0 + blockIdx.x;
   if (K >= v.nb[l]) return;
   __shared__ cx<T> S[kTile][kTile + 1];
   cx<T> *tile = tile_ptr(pool, v, l, K, K);
@@ -140,9 +141,9 @@ __global__ __launch_bounds__(256) void k_fac_diag(int K, SubView v, cx<T> *pool,
 
 // ---- factorisation: panel L_IK = A_IK inv(L_KK)^T D_K^-1 -------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_fac_panel(int K, SubView v, const int32_t *pref, int nsub,
+__global__ __launch_bounds__(256) void k_fac_panel(int K, int g0, SubView v, const int32_t *pref, int nsub,
                                                    cx<T> *pool) {
-  const int g = blockIdx.x;
+  const int g = g0 + blockIdx.x;
   const int l = find_sub(pref, nsub, g);
   const int I = K + 1 + (g - pref[l]);
   cx<T> *A = tile_ptr(pool, v, l, I, K);
@@ -257,9 +258,9 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
 }
 
 template <typename T, bool NEXT>
-__global__ __launch_bounds__(256) void k_fac_update(int K, SubView v, const int32_t *pref, int nsub,
-                                                    cx<T> *pool) {
-  const int g = xcd_contiguous(blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void k_fac_update(int K, int g0, SubView v, const int32_t *pref,
+                                                    int nsub, cx<T> *pool) {
+  const int g = g0 + xcd_contiguous(blockIdx.x, gridDim.x);
   const int l = find_sub(pref, nsub, g);
   const int t = g - pref[l];
   int I, J;
@@ -663,6 +664,7 @@ static SubView view_of(const mx_precond *P) {
   v.rmeta = P->d_rmeta.as<TileMeta>();
   v.cmeta = P->d_cmeta.as<TileMeta>();
   v.cptr = P->d_cptr.as<int64_t>();
+  v.tile_shift = 0;
   return v;
 }
 
@@ -670,29 +672,36 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Right-looking blocked LDL^T over all subdomains at once, one block step K after the other.  Two
-// streams overlap step K's bulk trailing update (aux stream) with the chain that gates step K+1
-// on the main stream: update of block column K+1, then diagonal tile K+1, then panel K+1.
+// Right-looking blocked LDL^T over the subdomains [l0, l1) at once (their tiles are in `pool`,
+// starting with tile v.tile_shift), one block step K after the other.  Two streams overlap step
+// K's bulk trailing update (aux stream) with the chain that gates step K+1 on the main stream:
+// update of block column K+1, then diagonal tile K+1, then panel K+1.
 template <typename T>
-static void factor_all(mx_precond *P, hipStream_t st) {
-  SubView v = view_of(P);
-  cx<T> *pool = P->pool.as<cx<T>>();
+static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView v, cx<T> *pool) {
   const int N = P->nsub;
+  int nb = 0;
+  for (int l = l0; l < l1; ++l) nb = std::max(nb, P->sub_nb[l]);
+  auto range = [&](const std::vector<int32_t> &pref, int K, int &g0) {
+    g0 = pref[(int64_t)K * (N + 1) + l0];
+    return pref[(int64_t)K * (N + 1) + l1] - g0;
+  };
+  const int32_t *dpp = P->d_panel_pref.as<int32_t>(), *dup = P->d_update_pref.as<int32_t>();
   int64_t total_updates = 0;
-  for (int K = 0; K < P->max_nb; ++K)
-    total_updates += P->update_pref[(int64_t)K * (N + 1) + N] + P->panel_pref[(int64_t)K * (N + 1) + N];
-  if (total_updates < 2048LL * std::max(1, P->max_nb)) {
+  for (int K = 0; K < nb; ++K) {
+    int g;
+    total_updates += range(P->update_pref, K, g) + range(P->panel_pref, K, g);
+  }
+  if (total_updates < 2048LL * std::max(1, nb)) {
     // small steps (a few tiles per CU): launch latency dominates and the second stream's event
     // traffic costs more than the overlap gains; one stream, four launches per step
-    for (int K = 0; K < P->max_nb; ++K) {
-      const int32_t *pp = P->d_panel_pref.as<int32_t>() + (int64_t)K * (N + 1);
-      const int32_t *up = P->d_update_pref.as<int32_t>() + (int64_t)K * (N + 1);
-      const int np = P->panel_pref[(int64_t)K * (N + 1) + N];
-      const int nu = P->update_pref[(int64_t)K * (N + 1) + N];
-      k_fac_diag<T><<<N, 256, 0, st>>>(K, v, pool, P->d_ctrl.as<int>());
-      if (np > 0) k_fac_panel<T><<<np, 256, 0, st>>>(K, v, pp, N, pool);
-      if (np > 0) k_fac_update<T, true><<<np, 256, 0, st>>>(K, v, pp, N, pool);
-      if (nu > 0) k_fac_update<T, false><<<nu, 256, 0, st>>>(K, v, up, N, pool);
+    for (int K = 0; K < nb; ++K) {
+      int gp, gu;
+      const int np = range(P->panel_pref, K, gp), nu = range(P->update_pref, K, gu);
+      const int32_t *pp = dpp + (int64_t)K * (N + 1), *up = dup + (int64_t)K * (N + 1);
+      k_fac_diag<T><<<l1 - l0, 256, 0, st>>>(K, l0, v, pool, P->d_ctrl.as<int>());
+      if (np > 0) k_fac_panel<T><<<np, 256, 0, st>>>(K, gp, v, pp, N, pool);
+      if (np > 0) k_fac_update<T, true><<<np, 256, 0, st>>>(K, gp, v, pp, N, pool);
+      if (nu > 0) k_fac_update<T, false><<<nu, 256, 0, st>>>(K, gu, v, up, N, pool);
     }
     MX_HIP(hipGetLastError());
     return;
@@ -703,27 +712,26 @@ static void factor_all(mx_precond *P, hipStream_t st) {
   MX_HIP(hipEventCreateWithFlags(&ev_panel, hipEventDisableTiming));
   MX_HIP(hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming));
   auto diag_panel = [&](int K) {
-    k_fac_diag<T><<<N, 256, 0, st>>>(K, v, pool, P->d_ctrl.as<int>());
-    const int np = P->panel_pref[(int64_t)K * (N + 1) + N];
-    if (np > 0)
-      k_fac_panel<T><<<np, 256, 0, st>>>(K, v, P->d_panel_pref.as<int32_t>() + (int64_t)K * (N + 1), N, pool);
+    k_fac_diag<T><<<l1 - l0, 256, 0, st>>>(K, l0, v, pool, P->d_ctrl.as<int>());
+    int gp;
+    const int np = range(P->panel_pref, K, gp);
+    if (np > 0) k_fac_panel<T><<<np, 256, 0, st>>>(K, gp, v, dpp + (int64_t)K * (N + 1), N, pool);
   };
   MX_HIP(hipEventRecord(ev_rest, sx));  // nothing pending on the aux stream yet
   diag_panel(0);
-  for (int K = 0; K < P->max_nb; ++K) {
-    const int32_t *pp = P->d_panel_pref.as<int32_t>() + (int64_t)K * (N + 1);
-    const int32_t *up = P->d_update_pref.as<int32_t>() + (int64_t)K * (N + 1);
-    const int np = P->panel_pref[(int64_t)K * (N + 1) + N];
-    const int nu = P->update_pref[(int64_t)K * (N + 1) + N];
+  for (int K = 0; K < nb; ++K) {
+    int gp, gu;
+    const int np = range(P->panel_pref, K, gp), nu = range(P->update_pref, K, gu);
+    const int32_t *pp = dpp + (int64_t)K * (N + 1), *up = dup + (int64_t)K * (N + 1);
     // aux: tiles (I, J), J >= K+2, once panel K is done (and, in stream order, step K-1's rest)
     MX_HIP(hipEventRecord(ev_panel, st));
     MX_HIP(hipStreamWaitEvent(sx, ev_panel, 0));
-    if (nu > 0) k_fac_update<T, false><<<nu, 256, 0, sx>>>(K, v, up, N, pool);
+    if (nu > 0) k_fac_update<T, false><<<nu, 256, 0, sx>>>(K, gu, v, up, N, pool);
     // main: block column K+1 needs step K-1's rest (recorded before this step's rest is queued)
     MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
-    if (np > 0) k_fac_update<T, true><<<np, 256, 0, st>>>(K, v, pp, N, pool);
+    if (np > 0) k_fac_update<T, true><<<np, 256, 0, st>>>(K, gp, v, pp, N, pool);
     MX_HIP(hipEventRecord(ev_rest, sx));
-    if (K + 1 < P->max_nb) diag_panel(K + 1);
+    if (K + 1 < nb) diag_panel(K + 1);
   }
   MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
   MX_HIP(hipGetLastError());
@@ -888,6 +896,8 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   int s0 = opts->sub_begin, s1 = opts->sub_end;
   if (s0 == 0 && s1 == 0) s1 = part.nsub;
   if (s0 < 0 || s1 > part.nsub || s0 >= s1) fail(MX_EINVAL, "subdomain share out of range");
+  if (opts->pool_limit < 0) fail(MX_EINVAL, "pool_limit must be >= 0");
+  P->pool_limit = opts->pool_limit;
   P->sub_begin = s0;
   P->nsub = s1 - s0;
   const int N = P->nsub;
@@ -1005,6 +1015,7 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     c += s.nb * kTile - s.n;
     cnt[l + 1] = cnt[l] + c;
   }
+  plan.scat = cnt;
   std::vector<int64_t> &off = plan.off;
   std::vector<double> &val = plan.val;
   off.assign(cnt[N], 0);
@@ -1139,8 +1150,6 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   const int64_t blocks = P->blocks_total, vec = P->vec_total, tiles = P->tiles_total;
   std::vector<int64_t> &brow_off = plan.brow_off;
   std::vector<int32_t> &bfirst = plan.bfirst, &blast = plan.blast;
-  std::vector<int64_t> &off = plan.off;
-  std::vector<double> &val = plan.val;
   std::vector<int32_t> &glob = plan.glob;
   std::vector<int64_t> &src = plan.src, &sum_ptr = plan.sum_ptr, &sum_idx = plan.sum_idx;
   std::vector<int32_t> &sched_sub = plan.sched_sub, &sched_blk = plan.sched_blk;
@@ -1177,49 +1186,98 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   MX_HIP(hipMemsetAsync(P->d_ctrl.p, 0, 64, st));
   MX_HIP(hipMemsetAsync(P->d_y.p, 0, vec * esz, st));
   MX_HIP(hipMemsetAsync(P->d_z.p, 0, vec * esz, st));
-  const size_t pool_bytes = (size_t)tiles * kTileElems * esz;
-  P->pool.alloc(pool_bytes);
-  k_zero<<<4096, 256, 0, st>>>((int64_t)(pool_bytes / 16), P->pool.as<uint4>());
-  {
-    DevBuf d_off, d_val;
-    d_off.upload(off);
-    d_val.upload(val);
-    const int64_t ne = (int64_t)off.size();
-    if (ne > 0) {
-      if (P->prec == MX_C128)
-        k_scatter<double><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(
-            ne, d_off.as<int64_t>(), d_val.as<cx<double>>(), P->pool.as<cx<double>>());
-      else
-        k_scatter<float><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(
-            ne, d_off.as<int64_t>(), d_val.as<cx<double>>(), P->pool.as<cx<float>>());
-    }
-    MX_HIP(hipGetLastError());
-    MX_HIP(hipStreamSynchronize(st));
-  }
-  // host staging no longer needed
-  std::vector<int64_t>().swap(off);
-  std::vector<double>().swap(val);
-  const double t2 = now_s();
-  if (P->prec == MX_C128) factor_all<double>(P, st);
-  else factor_all<float>(P, st);
-  MX_HIP(hipStreamSynchronize(st));
-  precond_check(P, st);
-  const double t3 = now_s();
-  // keep only the rows of each tile that meet the envelope, then free the full tiles
+  // Trimmed tiles (what the sweeps read) first; then the full tiles of as many consecutive
+  // subdomains at a time as fit (all of them unless memory or pool_limit says otherwise), each
+  // group scattered, factored and trimmed in turn.
   P->pack.alloc((size_t)P->pack_entries * esz);
-  if (tiles > 0) {
-    if (tiles > INT32_MAX) fail(MX_EINVAL, "too many tiles");
-    if (P->prec == MX_C128)
-      k_pack<double><<<(unsigned)tiles, 256, 0, st>>>(tiles, P->d_rmeta.as<TileMeta>(),
-                                                     P->pool.as<cx<double>>(), P->pack.as<cx<double>>());
-    else
-      k_pack<float><<<(unsigned)tiles, 256, 0, st>>>(tiles, P->d_rmeta.as<TileMeta>(),
-                                                    P->pool.as<cx<float>>(), P->pack.as<cx<float>>());
-    MX_HIP(hipGetLastError());
+  if (tiles > INT32_MAX) fail(MX_EINVAL, "too many tiles");
+  auto tile_end = [&](int l) { return l < N ? P->sub_tile_base[l] : tiles; };
+  auto group_bytes = [&](int l) {
+    return (size_t)(tile_end(l + 1) - P->sub_tile_base[l]) * kTileElems * esz +
+           (size_t)(plan.scat[l + 1] - plan.scat[l]) * 24;
+  };
+  size_t cap = (size_t)P->pool_limit;
+  if (cap == 0) {
+    size_t free_b = 0, total_b = 0;
+    MX_HIP(hipStreamSynchronize(st));
+    MX_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t avail = free_b + big_cached(P->device);
+    const size_t margin = (size_t)2 << 30;
+    cap = avail > margin ? avail - margin : 0;
   }
+  std::vector<int> groups = {0};
+  {
+    size_t acc = 0;
+    for (int l = 0; l < N; ++l) {
+      const size_t b = group_bytes(l);
+      if (b > cap) fail(MX_ENOMEM, "one subdomain's factor tiles exceed the memory available");
+      if (acc + b > cap && l > groups.back()) {
+        groups.push_back(l);
+        acc = 0;
+      }
+      acc += b;
+    }
+    groups.push_back(N);
+  }
+  int64_t max_group_tiles = 0;
+  for (size_t g = 0; g + 1 < groups.size(); ++g)
+    max_group_tiles = std::max(max_group_tiles, tile_end(groups[g + 1]) - P->sub_tile_base[groups[g]]);
+  const size_t pool_bytes = (size_t)max_group_tiles * kTileElems * esz;
+  P->pool.alloc(pool_bytes);
+  P->n_groups = (int)groups.size() - 1;
+  double t_upload = now_s() - t1, t_factor = 0, t_pack = 0;
+  for (size_t g = 0; g + 1 < groups.size(); ++g) {
+    const int l0 = groups[g], l1 = groups[g + 1];
+    const int64_t T0 = P->sub_tile_base[l0], T1 = tile_end(l1);
+    double ta = now_s();
+    k_zero<<<4096, 256, 0, st>>>((int64_t)((T1 - T0) * kTileElems * esz / 16), P->pool.as<uint4>());
+    {
+      const int64_t e0 = plan.scat[l0], ne = plan.scat[l1] - e0;
+      DevBuf d_off, d_val;
+      d_off.alloc((size_t)ne * 8);
+      d_val.alloc((size_t)ne * 16);
+      if (ne > 0) {
+        MX_HIP(hipMemcpyAsync(d_off.p, plan.off.data() + e0, (size_t)ne * 8, hipMemcpyHostToDevice, st));
+        MX_HIP(hipMemcpyAsync(d_val.p, plan.val.data() + 2 * e0, (size_t)ne * 16, hipMemcpyHostToDevice, st));
+        const int64_t shift = T0 * kTileElems;
+        if (P->prec == MX_C128)
+          k_scatter<double><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(
+              ne, d_off.as<int64_t>(), d_val.as<cx<double>>(), shift, P->pool.as<cx<double>>());
+        else
+          k_scatter<float><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(
+              ne, d_off.as<int64_t>(), d_val.as<cx<double>>(), shift, P->pool.as<cx<float>>());
+      }
+      MX_HIP(hipGetLastError());
+      MX_HIP(hipStreamSynchronize(st));
+    }
+    double tb = now_s();
+    SubView v = view_of(P);
+    v.tile_shift = T0;
+    if (P->prec == MX_C128) factor_group<double>(P, st, l0, l1, v, P->pool.as<cx<double>>());
+    else factor_group<float>(P, st, l0, l1, v, P->pool.as<cx<float>>());
+    MX_HIP(hipStreamSynchronize(st));
+    double tc = now_s();
+    if (T1 > T0) {
+      if (P->prec == MX_C128)
+        k_pack<double><<<(unsigned)(T1 - T0), 256, 0, st>>>(T1 - T0, P->d_rmeta.as<TileMeta>() + T0,
+                                                         P->pool.as<cx<double>>(), P->pack.as<cx<double>>());
+      else
+        k_pack<float><<<(unsigned)(T1 - T0), 256, 0, st>>>(T1 - T0, P->d_rmeta.as<TileMeta>() + T0,
+                                                        P->pool.as<cx<float>>(), P->pack.as<cx<float>>());
+      MX_HIP(hipGetLastError());
+    }
+    MX_HIP(hipStreamSynchronize(st));
+    double td = now_s();
+    t_upload += tb - ta;
+    t_factor += tc - tb;
+    t_pack += td - tc;
+  }
+  precond_check(P, st);
   P->pool.release();
   MX_HIP(hipStreamSynchronize(st));
-  const double t4 = now_s();
+  // host staging no longer needed
+  std::vector<int64_t>().swap(plan.off);
+  std::vector<double>().swap(plan.val);
   // info
   mx_precond_info &in = P->info;
   in.n_sub = N;
@@ -1250,9 +1308,10 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   // one block-sweep launch: the envelope read once; forward: r read, y written, y read once
   // (backward: y read, z written, z read once)
   in.sweep_bytes = (int64_t)(in.env_entries * esz + 3 * nloc * esz);
-  in.t_upload = t2 - t1;
-  in.t_factor = t3 - t2;
-  in.t_pack = t4 - t3;
+  in.t_upload = t_upload;
+  in.t_factor = t_factor;
+  in.t_pack = t_pack;
+  in.factor_groups = P->n_groups;
 }
 
 }  // namespace mx

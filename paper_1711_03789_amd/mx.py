@@ -44,7 +44,7 @@ class MxError(RuntimeError):
 class PrecondOpts(C.Structure):
     _fields_ = [("kind", C.c_int), ("xi_prec", C.c_double), ("precision", C.c_int),
                 ("sweep_grid", C.c_int), ("sub_begin", C.c_int),
-                ("sub_end", C.c_int)]
+                ("sub_end", C.c_int), ("pool_limit", C.c_int64)]
 
 
 class PrecondInfo(C.Structure):
@@ -54,7 +54,7 @@ class PrecondInfo(C.Structure):
                 ("tile_flops", C.c_double), ("apply_bytes", C.c_int64), ("sweep_bytes", C.c_int64),
                 ("t_host_setup", C.c_double),
                 ("t_upload", C.c_double), ("t_factor", C.c_double), ("pack_bytes", C.c_int64),
-                ("t_pack", C.c_double)]
+                ("t_pack", C.c_double), ("factor_groups", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -301,7 +301,7 @@ class Partition:
 def local_problem(mesh, A, part, l, kind="oras", xi_prec=None):
     """Host-only: local matrix of subdomain l (CSR in local numbering) and its RCM order."""
     load()
-    o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec, MX_C128, 0, 0, 0)
+    o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec, MX_C128, 0, 0, 0, 0)
     n, nnz = C.c_int64(), C.c_int64()
     _check(_lib.mx_local_problem(mesh.h, A.h, part.h, C.byref(o), l, C.byref(n), C.byref(nnz),
                                  None, None, None, None, None))
@@ -319,11 +319,11 @@ class Precond:
     """plan_only=True runs only the host half (mx_precond_plan); call materialize() before use."""
 
     def __init__(self, ctx, A, mesh, part, kind="oras", xi_prec=None, precision="c128",
-                 sweep_grid=0, share=None, plan_only=False):
+                 sweep_grid=0, share=None, plan_only=False, pool_limit=0):
         load()
         s0, s1 = share if share is not None else (0, 0)
         o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec,
-                        PRECISIONS.get(precision, precision), sweep_grid, s0, s1)
+                        PRECISIONS.get(precision, precision), sweep_grid, s0, s1, pool_limit)
         h = P()
         self.device_bytes = None
         if plan_only:

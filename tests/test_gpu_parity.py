@@ -355,3 +355,32 @@ def test_tiny_meshes(gpu_lib, ctx, n, parts):
         st = gpu_lib.gmres(ctx, c.lA, c.lP, dev(f), xd, restart=20, rtol=1e-10)
         ores = gmres.gmres(c.oA, f, c.oB, restart=20, rtol=1e-10)
         assert st["converged"] and abs(st["iters"] - ores.iters) <= 1
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_grouped_factorisation(gpu_lib, ctx, precision):
+    """A tile-pool limit makes the setup factor consecutive subdomain groups one after another
+    in a pool that holds one group; the factors, and so the applications, are bitwise those of
+    the one-group setup, and they still match the oracle."""
+    say("grouped factorisation", precision)
+    n = (16, 14, 12)
+    cuts = (jittered_cuts(16, 3, 0.2, 7), jittered_cuts(14, 2, 0.2, 8), jittered_cuts(12, 2, 0.2, 9))
+    c = Case(gpu_lib, ctx, n, (3, 2, 2), 2, 5.0, 5.0, "oras", cuts, precision=precision)
+    info = c.lP.info()
+    assert info["factor_groups"] == 1
+    limit = info["factor_bytes"] // 4
+    Pg = gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, pool_limit=limit)
+    ig = Pg.info()
+    say("  groups", ig["factor_groups"], "pool bytes", ig["factor_bytes"], "limit", limit)
+    assert ig["factor_groups"] >= 4 and ig["factor_bytes"] <= limit
+    v = random_rhs(c.E, 41)
+    vd, z1, z2 = dev(v), dev(np.zeros(c.E)), dev(np.zeros(c.E))
+    c.lP.apply(vd, z1)
+    Pg.apply(vd, z2)
+    Pg.check()
+    assert np.array_equal(host(z1), host(z2))
+    ref = c.oB(v)
+    err = np.linalg.norm(host(z2) - ref) / np.linalg.norm(ref)
+    assert err <= (1e-10 if precision == "c128" else 1e-4)
+    with pytest.raises(gpu_lib.MxError):
+        gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, pool_limit=1024)
