@@ -33,8 +33,10 @@ void *big_alloc(size_t n, size_t *capacity) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
     int best = -1;
+    // best fit, but never more than 1.5x the request: a small request must not pin a block that a
+    // later large one needs (it then gets fresh memory, emptying the cache first if need be)
     for (int i = 0; i < (int)g_free.size(); ++i)
-      if (g_free[i].device == dev && g_free[i].cap >= n &&
+      if (g_free[i].device == dev && g_free[i].cap >= n && g_free[i].cap - n <= n / 2 &&
           (best < 0 || g_free[i].cap < g_free[best].cap))
         best = i;
     if (best >= 0) {

@@ -40,8 +40,9 @@ struct AllocScope {
 
 // Process-wide cache of large device blocks (factor tiles, trimmed factors, big vectors):
 // freed blocks stay mapped, tagged with an event recorded on their stream at release, and are
-// handed out again (best fit, after that event has completed) instead of being unmapped and
-// remapped, which costs seconds for the tens of GB of a factorisation.  A failed allocation
+// handed out again (best fit within 1.5x of the request, after that event has completed)
+// instead of being unmapped and remapped, which costs seconds for the tens of GB of a
+// factorisation.  A failed allocation
 // returns the cached blocks of the device to HIP and retries once.  Implemented in devcache.cpp.
 constexpr size_t kBigBlock = size_t(64) << 20;
 void *big_alloc(size_t n, size_t *capacity);
