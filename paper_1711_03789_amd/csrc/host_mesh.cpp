@@ -95,21 +95,42 @@ void build_mesh(Mesh &m, int nx, int ny, int nz, double lx, double ly, double lz
       }
     }
   });
-  // edge -> tetrahedron incidence, tet ids ascending
+  // edge -> tetrahedron incidence, tet ids ascending: counted and filled in parallel (atomic
+  // cursors), then each edge's short list is sorted by tet id
   m.et_ptr.assign(m.ne + 1, 0);
-  for (int64_t t = 0; t < m.nt; ++t)
-    for (int e = 0; e < 6; ++e) m.et_ptr[m.tet_edge[6 * t + e] + 1]++;
+  parallel_for(m.nt, [&](int64_t a, int64_t b) {
+    for (int64_t t = a; t < b; ++t)
+      for (int e = 0; e < 6; ++e)
+        __atomic_fetch_add(&m.et_ptr[m.tet_edge[6 * t + e] + 1], (int64_t)1, __ATOMIC_RELAXED);
+  });
   for (int64_t e = 0; e < m.ne; ++e) m.et_ptr[e + 1] += m.et_ptr[e];
   m.et_tet.resize(m.et_ptr[m.ne]);
   m.et_loc.resize(m.et_ptr[m.ne]);
   {
-    std::vector<int64_t> pos(m.et_ptr.begin(), m.et_ptr.end() - 1);
-    for (int64_t t = 0; t < m.nt; ++t)
-      for (int e = 0; e < 6; ++e) {
-        int64_t q = pos[m.tet_edge[6 * t + e]]++;
-        m.et_tet[q] = (int32_t)t;
-        m.et_loc[q] = (int8_t)e;
-      }
+    std::vector<int32_t> cursor(m.ne, 0);
+    parallel_for(m.nt, [&](int64_t a, int64_t b) {
+      for (int64_t t = a; t < b; ++t)
+        for (int e = 0; e < 6; ++e) {
+          const int32_t g = m.tet_edge[6 * t + e];
+          const int64_t q = m.et_ptr[g] + __atomic_fetch_add(&cursor[g], 1, __ATOMIC_RELAXED);
+          m.et_tet[q] = (int32_t)t;
+          m.et_loc[q] = (int8_t)e;
+        }
+    });
+    parallel_for(m.ne, [&](int64_t a, int64_t b) {
+      for (int64_t g = a; g < b; ++g)
+        for (int64_t i = m.et_ptr[g] + 1; i < m.et_ptr[g + 1]; ++i) {
+          const int32_t t = m.et_tet[i];
+          const int8_t l = m.et_loc[i];
+          int64_t j = i - 1;
+          for (; j >= m.et_ptr[g] && m.et_tet[j] > t; --j) {
+            m.et_tet[j + 1] = m.et_tet[j];
+            m.et_loc[j + 1] = m.et_loc[j];
+          }
+          m.et_tet[j + 1] = t;
+          m.et_loc[j + 1] = l;
+        }
+    });
   }
   // boundary triangles: each boundary square (a, a+u, a+w, a+u+w), u < w axes, is split along
   // its diagonal a -> a+u+w into (a, a+u, a+u+w) and (a, a+w, a+u+w)
@@ -261,25 +282,30 @@ struct Entry {
   double re, im;
 };
 
-static void merge_entries(std::vector<Entry> &ent) {
-  std::stable_sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &b) { return a.col < b.col; });
+// Sums the contributions of equal columns in arrival order (slot[col] = position of the column's
+// entry while a row is built, -1 otherwise) and sorts the distinct columns.
+static void merge_entries(std::vector<Entry> &ent, std::vector<int32_t> &slot) {
   size_t w = 0;
   for (size_t r = 0; r < ent.size(); ++r) {
-    if (w > 0 && ent[w - 1].col == ent[r].col) {
-      ent[w - 1].re += ent[r].re;
-      ent[w - 1].im += ent[r].im;
+    const int32_t c = ent[r].col;
+    if (slot[c] >= 0) {
+      ent[slot[c]].re += ent[r].re;
+      ent[slot[c]].im += ent[r].im;
     } else {
+      slot[c] = (int32_t)w;
       ent[w++] = ent[r];
     }
   }
   ent.resize(w);
+  for (const Entry &x : ent) slot[x.col] = -1;
+  std::sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &b) { return a.col < b.col; });
 }
 
 static double imp_sign(double xi) { return xi >= 0 ? 1.0 : -1.0; }
 
 // Row e of the global matrix: tetrahedra in ascending id, then boundary triangles.
 static void global_row(const Mesh &m, const KuhnElements &ke, double k, double xi, int bc,
-                       int64_t e, std::vector<Entry> &ent) {
+                       int64_t e, std::vector<Entry> &ent, std::vector<int32_t> &slot) {
   ent.clear();
   const double sre = -k * k, sim = -xi;  // coefficient -(k^2 + i xi) of M
   for (int64_t q = m.et_ptr[e]; q < m.et_ptr[e + 1]; ++q) {
@@ -306,7 +332,7 @@ static void global_row(const Mesh &m, const KuhnElements &ke, double k, double x
       for (int b = 0; b < 3; ++b) ent.push_back({m.bface_edge[3 * (int64_t)f + b], 0.0, cb * Mb[a][b]});
     }
   }
-  merge_entries(ent);
+  merge_entries(ent, slot);
   if (bc == MX_BC_PEC) {
     bool row_pec = m.edge_on_boundary[e];
     for (auto &x : ent) {
@@ -323,28 +349,41 @@ void assemble_global(const Mesh &m, double k, double xi, int bc, HostCSR &A) {
   kuhn_elements(m.lx / m.nx, m.ly / m.ny, m.lz / m.nz, ke);
   A.n = m.ne;
   A.rowptr.assign(m.ne + 1, 0);
-  parallel_for(m.ne, [&](int64_t a, int64_t b) {
+  // one pass: each thread assembles a contiguous range of rows into its own buffer, then the
+  // buffers are copied into place once the row offsets are known
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t chunk = (m.ne + nt - 1) / nt;
+  std::vector<std::vector<Entry>> part(nt);
+  parallel_for(nt, [&](int64_t t0, int64_t t1) {
     std::vector<Entry> ent;
-    for (int64_t e = a; e < b; ++e) {
-      global_row(m, ke, k, xi, bc, e, ent);
-      A.rowptr[e + 1] = (int64_t)ent.size();
+    std::vector<int32_t> slot(m.ne, -1);
+    for (int64_t t = t0; t < t1; ++t) {
+      const int64_t a = t * chunk, b = std::min<int64_t>(m.ne, a + chunk);
+      std::vector<Entry> &out = part[t];
+      out.reserve((size_t)std::max<int64_t>(0, b - a) * 17);  // about 16.3 entries per row
+      for (int64_t e = a; e < b; ++e) {
+        global_row(m, ke, k, xi, bc, e, ent, slot);
+        A.rowptr[e + 1] = (int64_t)ent.size();
+        out.insert(out.end(), ent.begin(), ent.end());
+      }
     }
-  });
+  }, 1);
   for (int64_t e = 0; e < m.ne; ++e) A.rowptr[e + 1] += A.rowptr[e];
   A.col.resize(A.rowptr[m.ne]);
   A.val.resize(2 * A.rowptr[m.ne]);
-  parallel_for(m.ne, [&](int64_t a, int64_t b) {
-    std::vector<Entry> ent;
-    for (int64_t e = a; e < b; ++e) {
-      global_row(m, ke, k, xi, bc, e, ent);
-      int64_t o = A.rowptr[e];
-      for (size_t i = 0; i < ent.size(); ++i) {
-        A.col[o + i] = ent[i].col;
-        A.val[2 * (o + i)] = ent[i].re;
-        A.val[2 * (o + i) + 1] = ent[i].im;
+  parallel_for(nt, [&](int64_t t0, int64_t t1) {
+    for (int64_t t = t0; t < t1; ++t) {
+      const int64_t a = std::min<int64_t>(m.ne, t * chunk);
+      std::vector<Entry> &in = part[t];
+      int64_t o = A.rowptr[a];
+      for (size_t i = 0; i < in.size(); ++i, ++o) {
+        A.col[o] = in[i].col;
+        A.val[2 * o] = in[i].re;
+        A.val[2 * o + 1] = in[i].im;
       }
+      std::vector<Entry>().swap(in);
     }
-  });
+  }, 1);
 }
 
 // ---- load vector ------------------------------------------------------------------------------------

@@ -256,7 +256,10 @@ void matrix_upload(mx_matrix *A) {
   A->rowptr.upload(A->h.rowptr);
   A->col.upload(A->h.col);
   A->val.upload(A->h.val);
-  std::vector<float> v32(A->h.val.begin(), A->h.val.end());
+  raw_vector<float> v32(A->h.val.size());
+  parallel_for((int64_t)v32.size(), [&](int64_t a, int64_t b) {
+    for (int64_t i = a; i < b; ++i) v32[i] = (float)A->h.val[i];
+  });
   A->val32.upload(v32);
 }
 

@@ -4,6 +4,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <memory>
+#include <utility>
 #include <vector>
 #include <atomic>
 #include <thread>
@@ -105,11 +107,34 @@ void triangle_mass(const double x0[3], const double x1[3], const double x2[3], d
 void tet_element(const double X[4][3], double K[6][6], double M[6][6], double *vol);
 
 // ---- complex CSR ---------------------------------------------------------------------------------
+// std::vector whose resize leaves new elements uninitialised (for arrays filled right after, where
+// zero-filling gigabytes single-threaded would cost seconds)
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+  template <class U>
+  void construct(U *p) noexcept {
+    ::new ((void *)p) U;
+  }
+  template <class U, class... Args>
+  void construct(U *p, Args &&...args) {
+    ::new ((void *)p) U(std::forward<Args>(args)...);
+  }
+};
+template <class T>
+using raw_vector = std::vector<T, NoInitAlloc<T>>;
+
 struct HostCSR {
   int64_t n = 0;
   std::vector<int64_t> rowptr;
-  std::vector<int32_t> col;
-  std::vector<double> val;  // interleaved complex, 2 * nnz
+  raw_vector<int32_t> col;
+  raw_vector<double> val;  // interleaved complex, 2 * nnz
   int64_t nnz() const { return (int64_t)col.size(); }
 };
 void assemble_global(const Mesh &m, double k, double xi, int bc, HostCSR &A);

@@ -90,8 +90,9 @@ struct DevBuf {
   }
   template <class T>
   T *as() const { return (T *)p; }
-  template <class T>
-  void upload(const std::vector<T> &v) {
+  template <class V>
+  void upload(const V &v) {
+    typedef typename V::value_type T;
     alloc(v.size() * sizeof(T));
     if (!v.empty()) {
       MX_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, t_alloc_stream));

@@ -989,32 +989,40 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   cptr.assign(blocks, 0);
   cmeta.assign(2 * tiles, 0);
   {
-    int64_t c = 0;
-    for (int l = 0; l < N; ++l) {
-      const Skyline &s = P->sky[l];
-      const int64_t bb = P->sub_brow_base[l], tb = P->sub_tile_base[l];
-      for (int64_t B = 0; B < s.nb; ++B) {
-        cptr[bb + B] = c;
-        for (int64_t I = B; I <= s.blast[B]; ++I, ++c) {
-          const int64_t t = tb + s.brow_off[I] + (B - s.bfirst[I]);
-          cmeta[2 * c] = rmeta[2 * t];
-          cmeta[2 * c + 1] = rmeta[2 * t + 1];
+    // a subdomain's block columns cover exactly its tiles, so its column-ordered entries start
+    // where its tiles start
+    std::atomic<int> bad(0);
+    parallel_items(N, [&](auto next) {
+      for (int64_t l; (l = next()) >= 0;) {
+        const Skyline &s = P->sky[l];
+        const int64_t bb = P->sub_brow_base[l], tb = P->sub_tile_base[l];
+        int64_t c = tb;
+        for (int64_t B = 0; B < s.nb; ++B) {
+          cptr[bb + B] = c;
+          for (int64_t I = B; I <= s.blast[B]; ++I, ++c) {
+            const int64_t t = tb + s.brow_off[I] + (B - s.bfirst[I]);
+            cmeta[2 * c] = rmeta[2 * t];
+            cmeta[2 * c + 1] = rmeta[2 * t + 1];
+          }
         }
+        if (c != tb + s.tiles) bad = 1;
       }
-    }
-    if (c != tiles) fail(MX_EINVAL, "internal: block columns do not cover the stored tiles");
+    });
+    if (bad) fail(MX_EINVAL, "internal: block columns do not cover the stored tiles");
   }
   // scatter list: lower-triangle entries of each permuted local matrix + unit diagonal padding
   std::vector<int64_t> cnt(N + 1, 0);
-  for (int l = 0; l < N; ++l) {
-    const LocalCSR &a = loc[l];
-    const Skyline &s = P->sky[l];
-    int64_t c = 0;
-    for (int64_t r = 0; r < a.n; ++r)
-      for (int64_t q = a.rowptr[r]; q < a.rowptr[r + 1]; ++q) c += s.iperm[a.col[q]] <= s.iperm[r];
-    c += s.nb * kTile - s.n;
-    cnt[l + 1] = cnt[l] + c;
-  }
+  parallel_items(N, [&](auto next) {
+    for (int64_t l; (l = next()) >= 0;) {
+      const LocalCSR &a = loc[l];
+      const Skyline &s = P->sky[l];
+      int64_t c = 0;
+      for (int64_t r = 0; r < a.n; ++r)
+        for (int64_t q = a.rowptr[r]; q < a.rowptr[r + 1]; ++q) c += s.iperm[a.col[q]] <= s.iperm[r];
+      cnt[l + 1] = c + (s.nb * kTile - s.n);
+    }
+  });
+  for (int l = 0; l < N; ++l) cnt[l + 1] += cnt[l];
   plan.scat = cnt;
   std::vector<int64_t> &off = plan.off;
   std::vector<double> &val = plan.val;
@@ -1051,10 +1059,12 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   // restriction / prolongation maps
   std::vector<int32_t> &glob = plan.glob;
   glob.assign(vec, -1);
-  for (int l = 0; l < N; ++l) {
-    const Skyline &s = P->sky[l];
-    for (int64_t i = 0; i < s.n; ++i) glob[P->sub_vec_base[l] + i] = sets[l][s.perm[i]];
-  }
+  parallel_items(N, [&](auto next) {
+    for (int64_t l; (l = next()) >= 0;) {
+      const Skyline &s = P->sky[l];
+      for (int64_t i = 0; i < s.n; ++i) glob[P->sub_vec_base[l] + i] = sets[l][s.perm[i]];
+    }
+  });
   std::vector<int64_t> &src = plan.src, &sum_ptr = plan.sum_ptr, &sum_idx = plan.sum_idx;
   if (opts->kind == MX_AS) {
     sum_ptr.assign(m.ne + 1, 0);
@@ -1070,14 +1080,21 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     }
   } else {
     src.assign(m.ne, -1);
-    for (int64_t e = 0; e < m.ne; ++e) {
-      int o = part.owner[e] - s0;
-      if (o < 0 || o >= N) continue;  // owned outside the resident share
-      const auto &st = sets[o];
-      auto it = std::lower_bound(st.begin(), st.end(), (int32_t)e);
-      if (it == st.end() || *it != e) fail(MX_EINVAL, "internal: owner does not hold its DOF");
-      src[e] = P->sub_vec_base[o] + P->sky[o].iperm[it - st.begin()];
-    }
+    std::atomic<int> bad(0);
+    parallel_for(m.ne, [&](int64_t a0, int64_t a1) {
+      for (int64_t e = a0; e < a1; ++e) {
+        int o = part.owner[e] - s0;
+        if (o < 0 || o >= N) continue;  // owned outside the resident share
+        const auto &st = sets[o];
+        auto it = std::lower_bound(st.begin(), st.end(), (int32_t)e);
+        if (it == st.end() || *it != e) {
+          bad = 1;
+          continue;
+        }
+        src[e] = P->sub_vec_base[o] + P->sky[o].iperm[it - st.begin()];
+      }
+    });
+    if (bad) fail(MX_EINVAL, "internal: owner does not hold its DOF");
   }
   // factor step tables
   P->panel_pref.assign((int64_t)P->max_nb * (N + 1), 0);
