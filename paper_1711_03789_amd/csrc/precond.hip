@@ -184,31 +184,37 @@ struct UpdateStage {
   cx<T> b[2][kTile][17];
 };
 
+// Waves per trailing-update workgroup: each wave owns 32 rows x (128 / kUpdWaves) columns of the
+// 64x64 tile, so two 70 KB workgroups per CU keep 16 waves resident to hide LDS and L2 latency.
+constexpr int kUpdWaves = 8;
+constexpr int kUpdCB = 8 / kUpdWaves;  // 16-column blocks per wave
+
 template <typename T>
 __device__ __forceinline__ void update_product(const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
                                                const cx<T> *__restrict__ d, UpdateStage<T> &st,
-                                               int r0, int c0, typename Mfma<T>::acc_t acc[2][2][2]) {
+                                               int r0, int c0, typename Mfma<T>::acc_t acc[2][kUpdCB][2]) {
   typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int kPer = 1024 / (64 * kUpdWaves);  // staged entries per thread and operand
   const int tid = threadIdx.x, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int lrow = tid >> 2, lq = (tid & 3) * 4;  // staging: row, first of 4 consecutive k
+  const int lrow = tid / (16 / kPer), lq = (tid % (16 / kPer)) * kPer;  // staging: row, first k
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < kUpdCB; ++b)
 #pragma unroll
       for (int c = 0; c < 2; ++c) acc[a][b][c] = acc_t{0, 0, 0, 0};
-  cx<T> ra[4], rb[4];
+  cx<T> ra[kPer], rb[kPer];
   auto fetch = [&](int kk) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kPer; ++e) {
       ra[e] = A[lrow * kTile + kk + lq + e];
       rb[e] = cmul(B[lrow * kTile + kk + lq + e], d[kk + lq + e]);
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kPer; ++e) {
       st.a[buf][lrow][lq + e] = ra[e];
       st.b[buf][lrow][lq + e] = rb[e];
     }
@@ -222,23 +228,22 @@ __device__ __forceinline__ void update_product(const cx<T> *__restrict__ A, cons
     if (s + 1 < kTile / 16) fetch((s + 1) * 16);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      cx<T> av[2], bv[2];
+      cx<T> av[2], bv[kUpdCB];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        av[q] = st.a[buf][r0 + q * 16 + li][4 * lk + e];
-        bv[q] = st.b[buf][c0 + q * 16 + li][4 * lk + e];
-      }
+      for (int q = 0; q < 2; ++q) av[q] = st.a[buf][r0 + q * 16 + li][4 * lk + e];
+#pragma unroll
+      for (int p = 0; p < kUpdCB; ++p) bv[p] = st.b[buf][c0 + p * 16 + li][4 * lk + e];
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < kUpdCB; ++p) {
           acc[q][p][0] = Mfma<T>::op(av[q].re, bv[p].re, acc[q][p][0]);
           acc[q][p][1] = Mfma<T>::op(av[q].re, bv[p].im, acc[q][p][1]);
         }
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < kUpdCB; ++p) {
           acc[q][p][0] = Mfma<T>::op(-av[q].im, bv[p].im, acc[q][p][0]);
           acc[q][p][1] = Mfma<T>::op(av[q].im, bv[p].re, acc[q][p][1]);
         }
@@ -258,7 +263,7 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
 }
 
 template <typename T, bool NEXT>
-__global__ __launch_bounds__(256) void k_fac_update(int K, int g0, SubView v, const int32_t *pref,
+__global__ __launch_bounds__(64 * kUpdWaves) void k_fac_update(int K, int g0, SubView v, const int32_t *pref,
                                                     int nsub, cx<T> *pool) {
   const int g = g0 + xcd_contiguous(blockIdx.x, gridDim.x);
   const int l = find_sub(pref, nsub, g);
@@ -283,13 +288,14 @@ __global__ __launch_bounds__(256) void k_fac_update(int K, int g0, SubView v, co
   const cx<T> *A = tile_ptr(pool, v, l, I, K);
   const cx<T> *B = tile_ptr(pool, v, l, J, K);
   const int w = threadIdx.x >> 6;
-  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
-  typename Mfma<T>::acc_t acc[2][2][2];
+  constexpr int kColWaves = kUpdWaves / 2;
+  const int r0 = (w / kColWaves) * 32, c0 = (w % kColWaves) * (16 * kUpdCB);
+  typename Mfma<T>::acc_t acc[2][kUpdCB][2];
   update_product<T>(A, B, dk, stage, r0, c0, acc);
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < kUpdCB; ++cb)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int row = acc_row<T>(r0, rb, q), col = acc_col(c0, cb);
@@ -700,8 +706,8 @@ static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView 
       const int32_t *pp = dpp + (int64_t)K * (N + 1), *up = dup + (int64_t)K * (N + 1);
       k_fac_diag<T><<<l1 - l0, 256, 0, st>>>(K, l0, v, pool, P->d_ctrl.as<int>());
       if (np > 0) k_fac_panel<T><<<np, 256, 0, st>>>(K, gp, v, pp, N, pool);
-      if (np > 0) k_fac_update<T, true><<<np, 256, 0, st>>>(K, gp, v, pp, N, pool);
-      if (nu > 0) k_fac_update<T, false><<<nu, 256, 0, st>>>(K, gu, v, up, N, pool);
+      if (np > 0) k_fac_update<T, true><<<np, 64 * kUpdWaves, 0, st>>>(K, gp, v, pp, N, pool);
+      if (nu > 0) k_fac_update<T, false><<<nu, 64 * kUpdWaves, 0, st>>>(K, gu, v, up, N, pool);
     }
     MX_HIP(hipGetLastError());
     return;
@@ -726,10 +732,10 @@ static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView 
     // aux: tiles (I, J), J >= K+2, once panel K is done (and, in stream order, step K-1's rest)
     MX_HIP(hipEventRecord(ev_panel, st));
     MX_HIP(hipStreamWaitEvent(sx, ev_panel, 0));
-    if (nu > 0) k_fac_update<T, false><<<nu, 256, 0, sx>>>(K, gu, v, up, N, pool);
+    if (nu > 0) k_fac_update<T, false><<<nu, 64 * kUpdWaves, 0, sx>>>(K, gu, v, up, N, pool);
     // main: block column K+1 needs step K-1's rest (recorded before this step's rest is queued)
     MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
-    if (np > 0) k_fac_update<T, true><<<np, 256, 0, st>>>(K, gp, v, pp, N, pool);
+    if (np > 0) k_fac_update<T, true><<<np, 64 * kUpdWaves, 0, st>>>(K, gp, v, pp, N, pool);
     MX_HIP(hipEventRecord(ev_rest, sx));
     if (K + 1 < nb) diag_panel(K + 1);
   }
