@@ -311,11 +311,25 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
     k_dot_partial<<<G, 256, 0, st>>>(n, nullptr, 0, 0, vec, part, 1);
     k_reduce<<<1, 256, 0, st>>>(G, part, nullptr, nullptr, nrm, 2);
   };
-  auto sync_status = [&]() {
-    MX_HIP(hipMemcpyAsync(hst, dst, sizeof(GmresStatus), hipMemcpyDeviceToHost, st));
-    MX_HIP(hipStreamSynchronize(st));
-    if (hst->pivot) fail(MX_EPIVOT, "zero or non-finite pivot in a local factorisation");
-    if (hst->abort) fail(MX_ESTALL, "a device-side wait in the block sweeps expired");
+  // Arnoldi steps are enqueued one ahead of the host: step j+1 is queued before the status of
+  // step j is read, so the device never waits for the host between steps. The status of step j
+  // lands in its own pinned slot (two alternate) and is read after that step's event.  A step
+  // queued past the one that ends the cycle only touches column j+1 of H, g[j+1..j+2], V[j+2]
+  // and the scratch vectors, none of which the cycle's update reads.
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  for (auto &x : ev.e) MX_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+  auto read_status = [&](int slot) -> const GmresStatus & {
+    MX_HIP(hipEventSynchronize(ev.e[slot]));
+    const GmresStatus &s = hst[slot];
+    if (s.pivot) fail(MX_EPIVOT, "zero or non-finite pivot in a local factorisation");
+    if (s.abort) fail(MX_ESTALL, "a device-side wait in the block sweeps expired");
+    return s;
   };
   auto residual = [&]() {  // r = b - A x, beta -> status
     spmv_run(A, x, tmp, false, st);
@@ -337,6 +351,7 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
   const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
   if (hist) hist[0] = 1.0;
   double est = 1.0, beta = beta0;
+  double last = beta0, rate = 1.0;  // last residual estimate and its last contraction factor
   bool converged = false;
   if (!std::isfinite(beta0)) fail(MX_ENAN, "non-finite initial residual");
   if (beta0 == 0.0) {
@@ -355,7 +370,7 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
       k_scale<<<nblk(n), 256, 0, st>>>(n, r, nrm, V);
       k_init_g<<<1, 64, 0, st>>>(m, nrm, g, dst);
       int jend = 0;
-      for (int j = 0; j < m; ++j) {
+      auto arnoldi_step = [&](int j) {
         cx<double> *z = flex ? Z + (int64_t)j * ldv : tmp;
         apply_prec(V + (int64_t)j * ldv, z);
         spmv_run(A, z, w, c64, st);
@@ -370,14 +385,31 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
         k_givens<<<1, 64, 0, st>>>(j, m + 1, h1, nrm, H, cs, sn, g, dst, pctrl);
         k_scale<<<nblk(n), 256, 0, st>>>(n, w, nrm, V + (int64_t)(j + 1) * ldv);
         MX_HIP(hipGetLastError());
-        sync_status();
+        MX_HIP(hipMemcpyAsync(hst + (j & 1), dst, sizeof(GmresStatus), hipMemcpyDeviceToHost, st));
+        MX_HIP(hipEventRecord(ev.e[j & 1], st));
+      };
+      const int total0 = total;
+      arnoldi_step(0);
+      for (int j = 0; j < m; ++j) {
+        // Step j+1 is queued before step j's status only if it is inside the cycle and the
+        // iteration limit and, with a tolerance, if the residual estimate two steps on, at the
+        // last contraction rate, is still above it (so the step is almost surely needed; a
+        // wasted step costs a whole preconditioner application on large problems).
+        const bool inside = j + 1 < m && total0 + j + 2 <= limit;
+        const double pred = last * rate * rate;
+        const bool queued = inside && (o->fixed_iters > 0 || pred > o->rtol * beta0);
+        if (queued) arnoldi_step(j + 1);
+        const GmresStatus &s = read_status(j & 1);
         ++total;
         jend = j + 1;
-        est = hst->est / beta0;
+        est = s.est / beta0;
         if (hist) hist[total] = est;
-        if (!std::isfinite(hst->est) || !std::isfinite(hst->hn)) fail(MX_ENAN, "non-finite Arnoldi value");
-        if (o->fixed_iters == 0 && hst->est <= o->rtol * beta0) break;
-        if (total >= limit || hst->hn == 0.0) break;
+        if (!std::isfinite(s.est) || !std::isfinite(s.hn)) fail(MX_ENAN, "non-finite Arnoldi value");
+        if (s.est > 0.0 && last > 0.0) rate = std::min(1.0, s.est / last);
+        last = s.est;
+        if (o->fixed_iters == 0 && s.est <= o->rtol * beta0) break;
+        if (!inside || s.hn == 0.0) break;
+        if (!queued) arnoldi_step(j + 1);
       }
       k_trisolve<<<1, 64, 0, st>>>(jend, m + 1, H, g, y);
       if (flex) {
@@ -389,6 +421,7 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
         k_add<<<nblk(n), 256, 0, st>>>(n, x, tmp);
       }
       beta = residual();
+      last = beta;
       if (!std::isfinite(beta)) fail(MX_ENAN, "non-finite residual");
       if (P) precond_check(P, st);
     }

@@ -12,6 +12,7 @@
 // The local matrices are complex symmetric (A = A^T, Sec. 2.2), so A^l = L D L^T with no
 // conjugation; no pivoting is needed for xi != 0 because every principal submatrix of
 // Theta A^l has positive definite imaginary part (coercivity lemma of Sec. 2.3).
+#include <utility>
 #include <algorithm>
 #include <climits>
 #include <chrono>
@@ -82,61 +83,81 @@ __global__ void k_zero(int64_t n16, uint4 *__restrict__ p) {
 }
 
 // ---- factorisation: diagonal tile ----------------------------------------------------------------
-// One workgroup per subdomain.  The tile A_KK is held in LDS as a full symmetric matrix (rows
-// padded by one entry) and factored as L D L^T, right-looking, with the lanes along the columns
-// of the trailing matrix; row j of the upper triangle then holds column j of L.  The unit-lower
-// inverse X = inv(L) is formed row by row into the strict lower triangle, each wave owning 16
-// columns (four partial sums per column, reduced with lane shuffles).  Written back as X below
-// the diagonal, D on it, 0 above.
+// One workgroup of four waves per subdomain.  Thread (w, c) keeps column c of rows i = 4q + w
+// (q = 0..15) of two 64x64 matrices in registers: S, the symmetric tile being reduced, and X,
+// which starts as the identity.  Pivot j is eliminated right-looking: the wave holding row j
+// publishes, through LDS, row j of S, the same row divided by the pivot d_j (column j of L, by
+// symmetry) and row j of X; after one barrier every thread updates its rows i > j,
+//   S_i -= L_ij S_j,   X_i -= L_ij X_j,
+// i.e. Gauss elimination applied to [A | I], which ends with X = inv(L).  The published rows are
+// double-buffered, so a step costs one barrier.  Written back as X below the diagonal, D on it,
+// 0 above.
+// Pivots 4Q .. 4Q+3 (held in register Q of waves 0..3).  Q is a template argument so that every
+// register index is static and the arrays stay in registers.
+template <typename T, int Q>
+__device__ __forceinline__ void diag_pivots(cx<T> (&s)[16], cx<T> (&x)[16], cx<T> (*R)[3][kTile], int w,
+                                            int c, bool &bad) {
+#pragma unroll 1
+  for (int p = 0; p < 4; ++p) {
+    const int j = 4 * Q + p;
+    cx<T>(*B)[kTile] = R[j & 1];
+    if (w == p) {
+      cx<T> d = {__shfl(s[Q].re, j), __shfl(s[Q].im, j)};
+      const T mag = d.re * d.re + d.im * d.im;
+      if (!(mag > (T)0) || !isfinite(mag)) {
+        bad = true;
+        d = {(T)1, (T)0};
+      }
+      B[0][c] = s[Q];
+      B[1][c] = cmul(s[Q], cinv(d));
+      B[2][c] = x[Q];
+    }
+    __syncthreads();
+    const cx<T> sj = B[0][c], xj = B[2][c];
+#pragma unroll
+    for (int r = Q; r < 16; ++r) {
+      if (r == Q && w <= p) continue;  // only rows 4r + w > j
+      const cx<T> lij = B[1][4 * r + w];
+      s[r] = csub(s[r], cmul(lij, sj));
+      x[r] = csub(x[r], cmul(lij, xj));
+    }
+  }
+}
+template <typename T, int... Q>
+__device__ __forceinline__ void diag_all_pivots(cx<T> (&s)[16], cx<T> (&x)[16], cx<T> (*R)[3][kTile], int w,
+                                                int c, bool &bad, std::integer_sequence<int, Q...>) {
+  (diag_pivots<T, Q>(s, x, R, w, c, bad), ...);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fac_diag(int K, int l0, SubView v, cx<T> *pool, int *ctrl) {
   const int l = l0 + blockIdx.x;
   if (K >= v.nb[l]) return;
-  __shared__ cx<T> S[kTile][kTile + 1];
+  __shared__ cx<T> S[kTile][kTile + 1];  // the symmetric input, staged once
+  __shared__ cx<T> R[2][3][kTile];       // published row j: S_j, S_j / d_j, X_j
   cx<T> *tile = tile_ptr(pool, v, l, K, K);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, c = tid & 63, w = tid >> 6;
   for (int i = w; i < kTile; i += 4)
-    if (lane <= i) {
-      const cx<T> a = tile[i * kTile + lane];
-      S[i][lane] = a;
-      S[lane][i] = a;
+    if (c <= i) {
+      const cx<T> a = tile[i * kTile + c];
+      S[i][c] = a;
+      S[c][i] = a;
     }
+  __syncthreads();
+  cx<T> s[16], x[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    s[q] = S[4 * q + w][c];
+    x[q] = {(T)(4 * q + w == c ? 1 : 0), (T)0};
+  }
   bool bad = false;
-  for (int j = 0; j < kTile; ++j) {
-    __syncthreads();
-    cx<T> d = S[j][j];
-    const T mag = d.re * d.re + d.im * d.im;
-    if (!(mag > (T)0) || !isfinite(mag)) {
-      bad = true;
-      d = {(T)1, (T)0};
-    }
-    // S[i][m] -= S[j][i] S[j][m] / d   for i, m > j  (row j is final and not written here)
-    if (lane > j) {
-      const cx<T> u = cmul(S[j][lane], cinv(d));
-      for (int i = j + 1 + w; i < kTile; i += 4) S[i][lane] = csub(S[i][lane], cmul(S[j][i], u));
-    }
+  diag_all_pivots<T>(s, x, R, w, c, bad, std::make_integer_sequence<int, 16>());
+  if (bad) atomicOr(&ctrl[3], 1);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = 4 * q + w;
+    tile[i * kTile + c] = c < i ? x[q] : c == i ? s[q] : cx<T>{(T)0, (T)0};
   }
-  if (bad && tid == 0) atomicOr(&ctrl[3], 1);
-  __syncthreads();
-  // upper row j := column j of L  (L[m][j] = S[j][m] / D_j)
-  for (int j = w; j < kTile; j += 4)
-    if (lane > j) S[j][lane] = cmul(S[j][lane], cinv(S[j][j]));
-  // X[i][c] = -(L[i][c] + sum_{c<m<i} L[i][m] X[m][c])  for c < i
-  const int c = 16 * w + (lane & 15), g = lane >> 4;
-  for (int i = 1; i < kTile; ++i) {
-    __syncthreads();
-    cx<T> acc = {(T)0, (T)0};
-    if (c < i) {
-      for (int m = c + 1 + g; m < i; m += 4) cfma(acc, S[m][i], S[m][c]);
-      if (g == 0) acc = cadd(acc, S[c][i]);
-    }
-    acc = cadd(acc, shfl_xor_c(acc, 16));
-    acc = cadd(acc, shfl_xor_c(acc, 32));
-    if (c < i && g == 0) S[i][c] = {-acc.re, -acc.im};
-  }
-  __syncthreads();
-  for (int i = w; i < kTile; i += 4)
-    tile[i * kTile + lane] = lane <= i ? S[i][lane] : cx<T>{(T)0, (T)0};
 }
 
 // ---- factorisation: panel L_IK = A_IK inv(L_KK)^T D_K^-1 -------------------------------------------
