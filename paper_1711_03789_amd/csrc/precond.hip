@@ -12,6 +12,7 @@
 // The local matrices are complex symmetric (A = A^T, Sec. 2.2), so A^l = L D L^T with no
 // conjugation; no pivoting is needed for xi != 0 because every principal submatrix of
 // Theta A^l has positive definite imaginary part (coercivity lemma of Sec. 2.3).
+#include <type_traits>
 #include <utility>
 #include <algorithm>
 #include <climits>
@@ -210,15 +211,29 @@ struct UpdateStage {
 constexpr int kUpdWaves = 8;
 constexpr int kUpdCB = 8 / kUpdWaves;  // 16-column blocks per wave
 
+// Operands of one trailing-update tile: up to two source block columns q = 0, 1, each a pair of
+// tiles (Aq = L_IK, Bq = L_JK) and the pivots dq = D_K in LDS; `slabs` 16-wide k slabs in all
+// (4 per source).  Passed as scalars so that they stay in scalar registers.
 template <typename T>
-__device__ __forceinline__ void update_product(const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
-                                               const cx<T> *__restrict__ d, UpdateStage<T> &st,
-                                               int r0, int c0, typename Mfma<T>::acc_t acc[2][kUpdCB][2]) {
+struct UpdSources {
+  const cx<T> *A0, *B0, *d0, *A1, *B1, *d1;
+  int slabs;
+};
+
+// acc = sum over the sources of A diag(d) B^T for this wave's 32 x (16 kUpdCB) part of the tile.
+// The 16-wide k slabs of A and B (B already scaled by d) are staged through LDS, double-buffered:
+// slab s+1 is loaded into registers while slab s feeds the matrix cores, across the boundary
+// between the two sources too.  SLABS = 4 per source column.
+template <typename T, int SLABS>
+__device__ __forceinline__ void update_product(const UpdSources<T> src, UpdateStage<T> &st, int r0, int c0,
+                                               typename Mfma<T>::acc_t acc[2][kUpdCB][2]) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int kPer = 1024 / (64 * kUpdWaves);  // staged entries per thread and operand
   const int tid = threadIdx.x, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int lrow = tid / (16 / kPer), lq = (tid % (16 / kPer)) * kPer;  // staging: row, first k
+  static_assert(SLABS == 4 || SLABS == 8, "one or two source columns");
+  constexpr int ns = SLABS;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -226,7 +241,9 @@ __device__ __forceinline__ void update_product(const cx<T> *__restrict__ A, cons
 #pragma unroll
       for (int c = 0; c < 2; ++c) acc[a][b][c] = acc_t{0, 0, 0, 0};
   cx<T> ra[kPer], rb[kPer];
-  auto fetch = [&](int kk) {
+  auto fetch = [&](int slab) {
+    const int q = slab >> 2, kk = (slab & 3) * 16;
+    const cx<T> *A = q ? src.A1 : src.A0, *B = q ? src.B1 : src.B0, *d = q ? src.d1 : src.d0;
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       ra[e] = A[lrow * kTile + kk + lq + e];
@@ -240,13 +257,10 @@ __device__ __forceinline__ void update_product(const cx<T> *__restrict__ A, cons
       st.b[buf][lrow][lq + e] = rb[e];
     }
   };
-  fetch(0);
-  stash(0);
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < kTile / 16; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < kTile / 16) fetch((s + 1) * 16);
+  // one slab: feed buffer BUF to the matrix cores while slab s+1 is loaded into the other buffer
+  auto step = [&](int s, auto bufc) {
+    constexpr int buf = decltype(bufc)::value;
+    if (s + 1 < ns) fetch(s + 1);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       cx<T> av[2], bv[kUpdCB];
@@ -269,9 +283,39 @@ __device__ __forceinline__ void update_product(const cx<T> *__restrict__ A, cons
           acc[q][p][1] = Mfma<T>::op(av[q].im, bv[p].re, acc[q][p][1]);
         }
     }
-    if (s + 1 < kTile / 16) stash(buf ^ 1);
+    if (s + 1 < ns) stash(buf ^ 1);
     __syncthreads();
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < ns; s += 2) {
+    step(s, std::integral_constant<int, 0>());
+    step(s + 1, std::integral_constant<int, 1>());
   }
+}
+
+// C -= the sources' product for one 64x64 tile (one workgroup).
+template <typename T, int SLABS>
+__device__ __forceinline__ void update_tile(const UpdSources<T> src, UpdateStage<T> &stage, cx<T> *C) {
+  const int w = threadIdx.x >> 6;
+  constexpr int kColWaves = kUpdWaves / 2;
+  const int r0 = (w / kColWaves) * 32, c0 = (w % kColWaves) * (16 * kUpdCB);
+  typename Mfma<T>::acc_t acc[2][kUpdCB][2];
+  if constexpr (SLABS > 0) update_product<T, SLABS>(src, stage, r0, c0, acc);
+  else if (src.slabs == 8) update_product<T, 8>(src, stage, r0, c0, acc);
+  else update_product<T, 4>(src, stage, r0, c0, acc);
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < kUpdCB; ++cb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = acc_row<T>(r0, rb, q), col = acc_col(c0, cb);
+        cx<T> cur = C[row * kTile + col];
+        C[row * kTile + col] = {cur.re - acc[rb][cb][0][q], cur.im - acc[rb][cb][1][q]};
+      }
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Remapping the
@@ -305,24 +349,54 @@ __global__ __launch_bounds__(64 * kUpdWaves) void k_fac_update(int K, int g0, Su
   const cx<T> *Xk = tile_ptr(pool, v, l, K, K);
   if (threadIdx.x < kTile) dk[threadIdx.x] = Xk[threadIdx.x * kTile + threadIdx.x];
   __syncthreads();
-  cx<T> *C = tile_ptr(pool, v, l, I, J);
-  const cx<T> *A = tile_ptr(pool, v, l, I, K);
-  const cx<T> *B = tile_ptr(pool, v, l, J, K);
-  const int w = threadIdx.x >> 6;
-  constexpr int kColWaves = kUpdWaves / 2;
-  const int r0 = (w / kColWaves) * 32, c0 = (w % kColWaves) * (16 * kUpdCB);
-  typename Mfma<T>::acc_t acc[2][kUpdCB][2];
-  update_product<T>(A, B, dk, stage, r0, c0, acc);
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < kUpdCB; ++cb)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = acc_row<T>(r0, rb, q), col = acc_col(c0, cb);
-        cx<T> cur = C[row * kTile + col];
-        C[row * kTile + col] = {cur.re - acc[rb][cb][0][q], cur.im - acc[rb][cb][1][q]};
-      }
+  const cx<T> *A = tile_ptr(pool, v, l, I, K), *B = tile_ptr(pool, v, l, J, K);
+  update_tile<T, 4>(UpdSources<T>{A, B, dk, A, B, dk, 4}, stage, tile_ptr(pool, v, l, I, J));
+}
+
+// Trailing update from two block columns at once, K and K+1 (both factored): every tile gets
+//   A_IJ -= L_I,K+1 D_K+1 L_J,K+1^T  (+ L_IK D_K L_JK^T when block row I meets column K)
+// in one pass over A_IJ, so the tile is read and written once per two columns.
+//   NEXT: block columns K+2 and K+3 (the next pair's panel columns), rows I <= blast(K+1);
+//   otherwise: tiles K+4 <= J <= I <= blast(K+1).
+template <typename T, bool NEXT>
+__global__ __launch_bounds__(64 * kUpdWaves) void k_fac_update2(int K, int g0, SubView v, const int32_t *pref,
+                                                     int nsub, cx<T> *pool) {
+  const int g = g0 + xcd_contiguous(blockIdx.x, gridDim.x);
+  const int l = find_sub(pref, nsub, g);
+  const int t = g - pref[l];
+  const int bb = v.brow_base[l];
+  const int b0 = v.blast[bb + K], b1 = v.blast[bb + K + 1];
+  int I, J;
+  if (NEXT) {
+    const int na = b1 - K - 1;  // tiles of block column K+2: rows K+2 .. b1
+    if (t < na) {
+      I = K + 2 + t;
+      J = K + 2;
+    } else {
+      I = K + 3 + (t - na);
+      J = K + 3;
+    }
+  } else {
+    int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    while (r * (r + 1) / 2 > t) --r;
+    I = K + 4 + r;
+    J = K + 4 + (t - r * (r + 1) / 2);
+  }
+  __shared__ cx<T> dk[2][kTile];
+  __shared__ UpdateStage<T> stage;
+  const bool both = I <= b0;  // block row I (hence J <= I) meets column K too
+  if (threadIdx.x < 2 * kTile) {
+    const int q = threadIdx.x >> 6, i = threadIdx.x & 63;
+    const cx<T> *Xk = tile_ptr(pool, v, l, K + q, K + q);
+    dk[q][i] = Xk[i * kTile + i];
+  }
+  __syncthreads();
+  // the K+1 column first: it is present for every tile
+  const cx<T> *A1 = tile_ptr(pool, v, l, I, K + 1), *B1 = tile_ptr(pool, v, l, J, K + 1);
+  const cx<T> *A0 = both ? tile_ptr(pool, v, l, I, K) : A1, *B0 = both ? tile_ptr(pool, v, l, J, K) : B1;
+  update_tile<T, 0>(UpdSources<T>{A1, B1, dk[1], A0, B0, dk[0], both ? 8 : 4}, stage,
+                    tile_ptr(pool, v, l, I, J));
 }
 
 // ---- application: restrict, persistent sweeps, prolong ---------------------------------------------
@@ -718,7 +792,9 @@ static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView 
     int g;
     total_updates += range(P->update_pref, K, g) + range(P->panel_pref, K, g);
   }
-  if (total_updates < 2048LL * std::max(1, nb)) {
+  int sched = P->schedule;
+  if (sched == MX_FACTOR_AUTO) sched = total_updates < 2048LL * std::max(1, nb) ? MX_FACTOR_ONE_STREAM : MX_FACTOR_PAIRS;
+  if (sched == MX_FACTOR_ONE_STREAM) {
     // small steps (a few tiles per CU): launch latency dominates and the second stream's event
     // traffic costs more than the overlap gains; one stream, four launches per step
     for (int K = 0; K < nb; ++K) {
@@ -733,6 +809,11 @@ static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView 
     MX_HIP(hipGetLastError());
     return;
   }
+  // Look-ahead on two streams.  The main stream carries the critical path (the next block
+  // columns' updates, diagonal tiles and panels); the aux stream applies the rest of each trailing
+  // update as soon as the panels it reads are done.  An aux update must finish before the main
+  // stream updates the columns it also touches (event ev_rest, waited on before it is recorded
+  // again).
   hipStream_t sx;
   hipEvent_t ev_panel, ev_rest;
   MX_HIP(hipStreamCreateWithFlags(&sx, hipStreamNonBlocking));
@@ -744,21 +825,51 @@ static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView 
     const int np = range(P->panel_pref, K, gp);
     if (np > 0) k_fac_panel<T><<<np, 256, 0, st>>>(K, gp, v, dpp + (int64_t)K * (N + 1), N, pool);
   };
-  MX_HIP(hipEventRecord(ev_rest, sx));  // nothing pending on the aux stream yet
-  diag_panel(0);
-  for (int K = 0; K < nb; ++K) {
-    int gp, gu;
-    const int np = range(P->panel_pref, K, gp), nu = range(P->update_pref, K, gu);
-    const int32_t *pp = dpp + (int64_t)K * (N + 1), *up = dup + (int64_t)K * (N + 1);
-    // aux: tiles (I, J), J >= K+2, once panel K is done (and, in stream order, step K-1's rest)
+  auto next_column = [&](int K) {  // block column K+1 from column K (main stream)
+    int gp;
+    const int np = range(P->panel_pref, K, gp);
+    if (np > 0) k_fac_update<T, true><<<np, 64 * kUpdWaves, 0, st>>>(K, gp, v, dpp + (int64_t)K * (N + 1), N, pool);
+  };
+  auto aux_after_panels = [&]() {
     MX_HIP(hipEventRecord(ev_panel, st));
     MX_HIP(hipStreamWaitEvent(sx, ev_panel, 0));
-    if (nu > 0) k_fac_update<T, false><<<nu, 64 * kUpdWaves, 0, sx>>>(K, gu, v, up, N, pool);
-    // main: block column K+1 needs step K-1's rest (recorded before this step's rest is queued)
-    MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
-    if (np > 0) k_fac_update<T, true><<<np, 64 * kUpdWaves, 0, st>>>(K, gp, v, pp, N, pool);
-    MX_HIP(hipEventRecord(ev_rest, sx));
-    if (K + 1 < nb) diag_panel(K + 1);
+  };
+  MX_HIP(hipEventRecord(ev_rest, sx));  // nothing pending on the aux stream yet
+  diag_panel(0);
+  if (sched == MX_FACTOR_COLUMNS) {
+    for (int K = 0; K < nb; ++K) {
+      int gu;
+      const int nu = range(P->update_pref, K, gu);
+      // aux: tiles (I, J), J >= K+2, once panel K is done (and, in stream order, step K-1's rest)
+      aux_after_panels();
+      if (nu > 0) k_fac_update<T, false><<<nu, 64 * kUpdWaves, 0, sx>>>(K, gu, v, dup + (int64_t)K * (N + 1), N, pool);
+      // main: block column K+1 needs step K-1's rest (recorded before this step's rest is queued)
+      MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
+      next_column(K);
+      MX_HIP(hipEventRecord(ev_rest, sx));
+      if (K + 1 < nb) diag_panel(K + 1);
+    }
+  } else {
+    // Two block columns per trailing update: each pass over a tile applies columns K and K+1
+    // together, so the bulk update reads and writes every tile half as often.  At the start of
+    // pair (K, K+1) columns K and K+1 hold every update from the columns before K, and column K
+    // is factored.
+    const int32_t *dnp = P->d_pair_next_pref.as<int32_t>(), *drp = P->d_pair_rest_pref.as<int32_t>();
+    for (int K = 0; K + 1 < nb; K += 2) {
+      next_column(K);
+      diag_panel(K + 1);
+      int gn, gr;
+      const int nn = range(P->pair_next_pref, K, gn), nr = range(P->pair_rest_pref, K, gr);
+      // aux: tiles K+4 <= J <= I from both columns, after both panels (and the previous pair's rest)
+      aux_after_panels();
+      // main: columns K+2, K+3 overlap the previous pair's rest, so wait for it first
+      MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
+      if (nr > 0) k_fac_update2<T, false><<<nr, 64 * kUpdWaves, 0, sx>>>(K, gr, v, drp + (int64_t)K * (N + 1), N, pool);
+      MX_HIP(hipEventRecord(ev_rest, sx));
+      if (nn > 0) k_fac_update2<T, true><<<nn, 64 * kUpdWaves, 0, st>>>(K, gn, v, dnp + (int64_t)K * (N + 1), N, pool);
+      if (K + 2 < nb) diag_panel(K + 2);
+    }
+    // an odd last column was factored by the last pair's diag_panel(K + 2) and updates nothing
   }
   MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
   MX_HIP(hipGetLastError());
@@ -925,6 +1036,9 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   if (s0 < 0 || s1 > part.nsub || s0 >= s1) fail(MX_EINVAL, "subdomain share out of range");
   if (opts->pool_limit < 0) fail(MX_EINVAL, "pool_limit must be >= 0");
   P->pool_limit = opts->pool_limit;
+  if (opts->factor_schedule < 0 || opts->factor_schedule > MX_FACTOR_PAIRS)
+    fail(MX_EINVAL, "unknown factor_schedule");
+  P->schedule = opts->factor_schedule;
   P->sub_begin = s0;
   P->nsub = s1 - s0;
   const int N = P->nsub;
@@ -1141,6 +1255,26 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     P->panel_pref[(int64_t)K * (N + 1) + N] = (int32_t)ap;
     P->update_pref[(int64_t)K * (N + 1) + N] = (int32_t)au;
   }
+  // two-column steps (K, K+1): block columns K+2, K+3 and the tiles K+4 <= J <= I, all for rows up
+  // to blast(K+1) (blast is nondecreasing, so this covers the rows of column K too)
+  P->pair_next_pref.assign((int64_t)P->max_nb * (N + 1), 0);
+  P->pair_rest_pref.assign((int64_t)P->max_nb * (N + 1), 0);
+  for (int K = 0; K < P->max_nb; ++K) {
+    int64_t an = 0, ar = 0;
+    for (int l = 0; l < N; ++l) {
+      P->pair_next_pref[(int64_t)K * (N + 1) + l] = (int32_t)an;
+      P->pair_rest_pref[(int64_t)K * (N + 1) + l] = (int32_t)ar;
+      if (K + 1 < P->sub_nb[l]) {
+        const int64_t b1 = P->sky[l].blast[K + 1];
+        an += std::max<int64_t>(0, b1 - K - 1) + std::max<int64_t>(0, b1 - K - 2);
+        const int64_t m = std::max<int64_t>(0, b1 - K - 3);
+        ar += m * (m + 1) / 2;
+      }
+    }
+    if (ar > INT32_MAX) fail(MX_EINVAL, "factor step too large");
+    P->pair_next_pref[(int64_t)K * (N + 1) + N] = (int32_t)an;
+    P->pair_rest_pref[(int64_t)K * (N + 1) + N] = (int32_t)ar;
+  }
   // sweep schedule: forward rows by relative progress, then backward rows likewise
   struct Item {
     double key;
@@ -1184,7 +1318,7 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   plan.device_bytes = (size_t)tiles * kTileElems * esz + (size_t)packed * esz + 3 * (size_t)vec * esz +
                       2 * (size_t)blocks * 4 + 24 * (size_t)blocks + 32 * (size_t)tiles + 4 * (size_t)vec +
                       8 * (size_t)std::max(src.size(), sum_idx.size() + sum_ptr.size()) +
-                      8 * (size_t)sched_sub.size() + 8 * P->panel_pref.size() +
+                      8 * (size_t)sched_sub.size() + 16 * P->panel_pref.size() +
                       24 * off.size() + (1 << 20);
 }
 
@@ -1216,6 +1350,8 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   }
   P->d_panel_pref.upload(P->panel_pref);
   P->d_update_pref.upload(P->update_pref);
+  P->d_pair_next_pref.upload(P->pair_next_pref);
+  P->d_pair_rest_pref.upload(P->pair_rest_pref);
   P->d_sched_sub.upload(sched_sub);
   P->d_sched_blk.upload(sched_blk);
   P->d_rmeta.upload(plan.rmeta);

@@ -384,3 +384,33 @@ def test_grouped_factorisation(gpu_lib, ctx, precision):
     assert err <= (1e-10 if precision == "c128" else 1e-4)
     with pytest.raises(gpu_lib.MxError):
         gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, pool_limit=1024)
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_factor_schedules(gpu_lib, ctx, precision):
+    """The three launch orders of the blocked LDL^T (one stream; look-ahead with one block column
+    per trailing update; look-ahead with two) compute the same factors up to rounding: their
+    applications agree with the oracle, and with each other to rounding.  Subdomains of unequal
+    block counts (jittered cuts) cover pairs that end on an odd last column."""
+    say("factor schedules", precision)
+    n = (16, 14, 12)
+    cuts = (jittered_cuts(16, 3, 0.2, 7), jittered_cuts(14, 2, 0.2, 8), jittered_cuts(12, 2, 0.2, 9))
+    c = Case(gpu_lib, ctx, n, (3, 2, 2), 2, 5.0, 5.0, "oras", cuts, precision=precision)
+    v = random_rhs(c.E, 43)
+    vd = dev(v)
+    ref = c.oB(v)
+    out = {}
+    for sched in ("one_stream", "columns", "pairs"):
+        P = gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, schedule=sched)
+        z = dev(np.zeros(c.E))
+        P.apply(vd, z)
+        P.check()
+        out[sched] = host(z)
+        err = np.linalg.norm(out[sched] - ref) / np.linalg.norm(ref)
+        say("  ", sched, "rel err vs oracle", err)
+        assert err <= (1e-10 if precision == "c128" else 1e-4)
+    for sched in ("columns", "pairs"):
+        d = np.linalg.norm(out[sched] - out["one_stream"]) / np.linalg.norm(out["one_stream"])
+        assert d <= (1e-12 if precision == "c128" else 1e-5)
+    with pytest.raises(gpu_lib.MxError):
+        gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, schedule=7)
