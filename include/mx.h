@@ -137,13 +137,16 @@ typedef struct {
                       /* consecutive groups that fit (0 = as many as free device memory allows)  */
   int32_t factor_schedule; /* MX_FACTOR_*: order of the blocked factorisation's launches; every */
                            /* schedule computes the same LDL^T up to rounding (0 = automatic)   */
+  int32_t factor_width;    /* look-ahead: block columns applied per pass of the trailing update */
+                           /* (1 .. 4; 0 = 4)                                                  */
 } mx_precond_opts;
 
 /* factor_schedule values.  ONE_STREAM: diagonal tile, panel and trailing update of one block
  * column after another on one stream (the automatic choice when steps are a few tiles per CU).
- * COLUMNS: look-ahead on two streams, one block column per trailing update.  PAIRS: look-ahead
- * with two block columns per trailing update (the automatic choice otherwise). */
-enum { MX_FACTOR_AUTO = 0, MX_FACTOR_ONE_STREAM = 1, MX_FACTOR_COLUMNS = 2, MX_FACTOR_PAIRS = 3 };
+ * LOOKAHEAD: two streams; the next block columns are updated and factored on one while the rest
+ * of the trailing update runs on the other, factor_width block columns per pass over each tile
+ * (the automatic choice otherwise). */
+enum { MX_FACTOR_AUTO = 0, MX_FACTOR_ONE_STREAM = 1, MX_FACTOR_LOOKAHEAD = 2 };
 
 /* Host-only view of one local problem, as mx_precond_setup builds it (for inspection and
  * tests): A^l in local numbering (local DOFs sorted by global id) as CSR rowptr[n+1],

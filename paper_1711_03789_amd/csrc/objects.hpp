@@ -157,6 +157,7 @@ struct mx_precond {
   std::unique_ptr<mx::PrecondPlan> plan;  // set between mx_precond_plan and mx_precond_materialize
   int64_t pool_limit = 0;                 // bytes of full tiles at a time (0: what device memory allows)
   int schedule = 0;                       // factorisation schedule (MX_FACTOR_*; 0 = automatic)
+  int width = 4;                          // block columns per look-ahead trailing update
   int n_groups = 0;                       // subdomain groups the factorisation ran in
   int64_t E = 0;
   int max_nb = 0;
@@ -165,7 +166,7 @@ struct mx_precond {
   std::vector<int64_t> sub_vec_base, sub_tile_base;
   std::vector<int32_t> sub_brow_base, sub_nb;
   std::vector<int32_t> panel_pref, update_pref;  // [max_nb][nsub+1]
-  std::vector<int32_t> pair_next_pref, pair_rest_pref;  // two-column steps K, K+1: [max_nb][nsub+1]
+  std::vector<int32_t> intra_pref, next_pref, rest_pref;  // look-ahead groups: [max_nb][nsub+1]
   // device
   mx::DevBuf d_sub_nb, d_sub_brow_base, d_sub_tile_base, d_sub_vec_base;
   mx::DevBuf d_brow_off, d_bfirst, d_blast;
@@ -175,7 +176,7 @@ struct mx_precond {
   mx::DevBuf d_r, d_y, d_z;                 // local vectors (factor precision)
   mx::DevBuf d_glob, d_src, d_sum_ptr, d_sum_idx;
   mx::DevBuf d_flags, d_ctrl, d_sched_sub, d_sched_blk;
-  mx::DevBuf d_panel_pref, d_update_pref, d_pair_next_pref, d_pair_rest_pref;
+  mx::DevBuf d_panel_pref, d_update_pref, d_intra_pref, d_next_pref, d_rest_pref;
   int n_items = 0, trsv_grid = 0;
   mx_precond_info info{};
   // optional per-launch timing of the sweep kernel

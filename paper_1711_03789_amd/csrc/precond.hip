@@ -211,19 +211,21 @@ struct UpdateStage {
 constexpr int kUpdWaves = 8;
 constexpr int kUpdCB = 8 / kUpdWaves;  // 16-column blocks per wave
 
-// Operands of one trailing-update tile: up to two source block columns q = 0, 1, each a pair of
-// tiles (Aq = L_IK, Bq = L_JK) and the pivots dq = D_K in LDS; `slabs` 16-wide k slabs in all
-// (4 per source).  Passed as scalars so that they stay in scalar registers.
+// Operands of one trailing-update tile: up to kMaxWidth source block columns q, each a pair of
+// tiles (A[q] = L_IK, B[q] = L_JK) and the pivots d[q] = D_K in LDS; 4 16-wide k slabs per source.
+// The slab loop is unrolled, so every index into these arrays is a constant.
+constexpr int kMaxWidth = 4;
+constexpr int kDefaultWidth = 4;  // block columns per look-ahead trailing update unless asked
 template <typename T>
 struct UpdSources {
-  const cx<T> *A0, *B0, *d0, *A1, *B1, *d1;
-  int slabs;
+  const cx<T> *A[kMaxWidth], *B[kMaxWidth], *d[kMaxWidth];
+  int n;  // sources in use
 };
 
 // acc = sum over the sources of A diag(d) B^T for this wave's 32 x (16 kUpdCB) part of the tile.
 // The 16-wide k slabs of A and B (B already scaled by d) are staged through LDS, double-buffered:
-// slab s+1 is loaded into registers while slab s feeds the matrix cores, across the boundary
-// between the two sources too.  SLABS = 4 per source column.
+// slab s+1 is loaded into registers while slab s feeds the matrix cores, across the boundaries
+// between sources too.  SLABS = 4 per source column.
 template <typename T, int SLABS>
 __device__ __forceinline__ void update_product(const UpdSources<T> src, UpdateStage<T> &st, int r0, int c0,
                                                typename Mfma<T>::acc_t acc[2][kUpdCB][2]) {
@@ -232,7 +234,7 @@ __device__ __forceinline__ void update_product(const UpdSources<T> src, UpdateSt
   const int tid = threadIdx.x, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int lrow = tid / (16 / kPer), lq = (tid % (16 / kPer)) * kPer;  // staging: row, first k
-  static_assert(SLABS == 4 || SLABS == 8, "one or two source columns");
+  static_assert(SLABS % 4 == 0 && SLABS / 4 <= kMaxWidth, "whole source columns");
   constexpr int ns = SLABS;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -243,7 +245,7 @@ __device__ __forceinline__ void update_product(const UpdSources<T> src, UpdateSt
   cx<T> ra[kPer], rb[kPer];
   auto fetch = [&](int slab) {
     const int q = slab >> 2, kk = (slab & 3) * 16;
-    const cx<T> *A = q ? src.A1 : src.A0, *B = q ? src.B1 : src.B0, *d = q ? src.d1 : src.d0;
+    const cx<T> *A = src.A[q], *B = src.B[q], *d = src.d[q];
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       ra[e] = A[lrow * kTile + kk + lq + e];
@@ -304,7 +306,9 @@ __device__ __forceinline__ void update_tile(const UpdSources<T> src, UpdateStage
   const int r0 = (w / kColWaves) * 32, c0 = (w % kColWaves) * (16 * kUpdCB);
   typename Mfma<T>::acc_t acc[2][kUpdCB][2];
   if constexpr (SLABS > 0) update_product<T, SLABS>(src, stage, r0, c0, acc);
-  else if (src.slabs == 8) update_product<T, 8>(src, stage, r0, c0, acc);
+  else if (src.n == 4) update_product<T, 16>(src, stage, r0, c0, acc);
+  else if (src.n == 3) update_product<T, 12>(src, stage, r0, c0, acc);
+  else if (src.n == 2) update_product<T, 8>(src, stage, r0, c0, acc);
   else update_product<T, 4>(src, stage, r0, c0, acc);
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
@@ -349,54 +353,69 @@ __global__ __launch_bounds__(64 * kUpdWaves) void k_fac_update(int K, int g0, Su
   const cx<T> *Xk = tile_ptr(pool, v, l, K, K);
   if (threadIdx.x < kTile) dk[threadIdx.x] = Xk[threadIdx.x * kTile + threadIdx.x];
   __syncthreads();
-  const cx<T> *A = tile_ptr(pool, v, l, I, K), *B = tile_ptr(pool, v, l, J, K);
-  update_tile<T, 4>(UpdSources<T>{A, B, dk, A, B, dk, 4}, stage, tile_ptr(pool, v, l, I, J));
+  UpdSources<T> src;
+  src.A[0] = tile_ptr(pool, v, l, I, K);
+  src.B[0] = tile_ptr(pool, v, l, J, K);
+  src.d[0] = dk;
+  src.n = 1;
+  update_tile<T, 4>(src, stage, tile_ptr(pool, v, l, I, J));
 }
 
-// Trailing update from two block columns at once, K and K+1 (both factored): every tile gets
-//   A_IJ -= L_I,K+1 D_K+1 L_J,K+1^T  (+ L_IK D_K L_JK^T when block row I meets column K)
-// in one pass over A_IJ, so the tile is read and written once per two columns.
-//   NEXT: block columns K+2 and K+3 (the next pair's panel columns), rows I <= blast(K+1);
-//   otherwise: tiles K+4 <= J <= I <= blast(K+1).
-template <typename T, bool NEXT>
-__global__ __launch_bounds__(64 * kUpdWaves) void k_fac_update2(int K, int g0, SubView v, const int32_t *pref,
-                                                     int nsub, cx<T> *pool) {
+// Trailing updates from a group of W <= kMaxWidth factored block columns G .. G+W-1 at once:
+//   A_IJ -= sum over the group's columns S with I <= blast(S) of L_IS D_S L_JS^T
+// in one pass over A_IJ, so each tile is read and written once per group instead of once per
+// column (blast is nondecreasing, so the columns present for row I are the group's last ones).
+//   UpdIntra: block column Kc of the group (G < Kc < G+W) from the group's columns before it.
+//   UpdNext:  the next group's columns G+W .. G+2W-1, rows up to b = blast(G+W-1).
+//   UpdRest:  tiles G+2W <= J <= I <= b.
+enum UpdMode { UpdIntra, UpdNext, UpdRest };
+template <typename T, int MODE>
+__global__ __launch_bounds__(64 * kUpdWaves) void k_fac_update_group(int G, int W, int Kc, int g0, SubView v,
+                                                          const int32_t *pref, int nsub, cx<T> *pool) {
   const int g = g0 + xcd_contiguous(blockIdx.x, gridDim.x);
   const int l = find_sub(pref, nsub, g);
-  const int t = g - pref[l];
+  int t = g - pref[l];
   const int bb = v.brow_base[l];
-  const int b0 = v.blast[bb + K], b1 = v.blast[bb + K + 1];
+  const int send = MODE == UpdIntra ? Kc : min(G + W, v.nb[l]);  // sources G .. send-1
+  const int b = v.blast[bb + send - 1];
   int I, J;
-  if (NEXT) {
-    const int na = b1 - K - 1;  // tiles of block column K+2: rows K+2 .. b1
-    if (t < na) {
-      I = K + 2 + t;
-      J = K + 2;
-    } else {
-      I = K + 3 + (t - na);
-      J = K + 3;
+  if (MODE == UpdIntra) {
+    I = Kc + t;
+    J = Kc;
+  } else if (MODE == UpdNext) {
+    J = G + W;
+    while (t >= b - J + 1) {  // column J holds rows J .. b
+      t -= b - J + 1;
+      ++J;
     }
+    I = J + t;
   } else {
     int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((r + 1) * (r + 2) / 2 <= t) ++r;
     while (r * (r + 1) / 2 > t) --r;
-    I = K + 4 + r;
-    J = K + 4 + (t - r * (r + 1) / 2);
+    I = G + 2 * W + r;
+    J = G + 2 * W + (t - r * (r + 1) / 2);
   }
-  __shared__ cx<T> dk[2][kTile];
+  int s0 = G;  // first source column that reaches row I
+  while (v.blast[bb + s0] < I) ++s0;
+  const int n = send - s0;
+  __shared__ cx<T> dk[kMaxWidth][kTile];
   __shared__ UpdateStage<T> stage;
-  const bool both = I <= b0;  // block row I (hence J <= I) meets column K too
-  if (threadIdx.x < 2 * kTile) {
-    const int q = threadIdx.x >> 6, i = threadIdx.x & 63;
-    const cx<T> *Xk = tile_ptr(pool, v, l, K + q, K + q);
-    dk[q][i] = Xk[i * kTile + i];
+  for (int x = threadIdx.x; x < n * kTile; x += blockDim.x) {
+    const int q = x >> 6, i = x & 63;
+    dk[q][i] = tile_ptr(pool, v, l, s0 + q, s0 + q)[i * kTile + i];
   }
   __syncthreads();
-  // the K+1 column first: it is present for every tile
-  const cx<T> *A1 = tile_ptr(pool, v, l, I, K + 1), *B1 = tile_ptr(pool, v, l, J, K + 1);
-  const cx<T> *A0 = both ? tile_ptr(pool, v, l, I, K) : A1, *B0 = both ? tile_ptr(pool, v, l, J, K) : B1;
-  update_tile<T, 0>(UpdSources<T>{A1, B1, dk[1], A0, B0, dk[0], both ? 8 : 4}, stage,
-                    tile_ptr(pool, v, l, I, J));
+  UpdSources<T> src;
+#pragma unroll
+  for (int q = 0; q < kMaxWidth; ++q) {
+    const int S = s0 + min(q, n - 1);
+    src.A[q] = tile_ptr(pool, v, l, I, S);
+    src.B[q] = tile_ptr(pool, v, l, J, S);
+    src.d[q] = dk[min(q, n - 1)];
+  }
+  src.n = n;
+  update_tile<T, 0>(src, stage, tile_ptr(pool, v, l, I, J));
 }
 
 // ---- application: restrict, persistent sweeps, prolong ---------------------------------------------
@@ -793,7 +812,7 @@ static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView 
     total_updates += range(P->update_pref, K, g) + range(P->panel_pref, K, g);
   }
   int sched = P->schedule;
-  if (sched == MX_FACTOR_AUTO) sched = total_updates < 2048LL * std::max(1, nb) ? MX_FACTOR_ONE_STREAM : MX_FACTOR_PAIRS;
+  if (sched == MX_FACTOR_AUTO) sched = total_updates < 2048LL * std::max(1, nb) ? MX_FACTOR_ONE_STREAM : MX_FACTOR_LOOKAHEAD;
   if (sched == MX_FACTOR_ONE_STREAM) {
     // small steps (a few tiles per CU): launch latency dominates and the second stream's event
     // traffic costs more than the overlap gains; one stream, four launches per step
@@ -836,7 +855,7 @@ static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView 
   };
   MX_HIP(hipEventRecord(ev_rest, sx));  // nothing pending on the aux stream yet
   diag_panel(0);
-  if (sched == MX_FACTOR_COLUMNS) {
+  if (P->width == 1) {
     for (int K = 0; K < nb; ++K) {
       int gu;
       const int nu = range(P->update_pref, K, gu);
@@ -850,26 +869,34 @@ static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView 
       if (K + 1 < nb) diag_panel(K + 1);
     }
   } else {
-    // Two block columns per trailing update: each pass over a tile applies columns K and K+1
-    // together, so the bulk update reads and writes every tile half as often.  At the start of
-    // pair (K, K+1) columns K and K+1 hold every update from the columns before K, and column K
-    // is factored.
-    const int32_t *dnp = P->d_pair_next_pref.as<int32_t>(), *drp = P->d_pair_rest_pref.as<int32_t>();
-    for (int K = 0; K + 1 < nb; K += 2) {
-      next_column(K);
-      diag_panel(K + 1);
+    // W block columns per trailing update: each pass over a tile applies a whole group of W
+    // columns, so the bulk update reads and writes every tile W times less often.  At the start
+    // of group G the columns G .. G+W-1 hold every update from the columns before G, and column
+    // G is factored.
+    const int W = P->width;
+    const int32_t *dip = P->d_intra_pref.as<int32_t>(), *dnp = P->d_next_pref.as<int32_t>();
+    const int32_t *drp = P->d_rest_pref.as<int32_t>();
+    for (int G = 0; G < nb; G += W) {
+      for (int Kc = G + 1; Kc < std::min(G + W, nb); ++Kc) {  // the group's own columns, in turn
+        int gi;
+        const int ni = range(P->intra_pref, Kc, gi);
+        if (ni > 0)
+          k_fac_update_group<T, UpdIntra><<<ni, 64 * kUpdWaves, 0, st>>>(G, W, Kc, gi, v, dip + (int64_t)Kc * (N + 1), N, pool);
+        diag_panel(Kc);
+      }
       int gn, gr;
-      const int nn = range(P->pair_next_pref, K, gn), nr = range(P->pair_rest_pref, K, gr);
-      // aux: tiles K+4 <= J <= I from both columns, after both panels (and the previous pair's rest)
+      const int nn = range(P->next_pref, G, gn), nr = range(P->rest_pref, G, gr);
+      // aux: tiles G+2W <= J <= I from the whole group, after its panels (and the previous rest)
       aux_after_panels();
-      // main: columns K+2, K+3 overlap the previous pair's rest, so wait for it first
+      // main: the next group's columns overlap the previous group's rest, so wait for it first
       MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
-      if (nr > 0) k_fac_update2<T, false><<<nr, 64 * kUpdWaves, 0, sx>>>(K, gr, v, drp + (int64_t)K * (N + 1), N, pool);
+      if (nr > 0)
+        k_fac_update_group<T, UpdRest><<<nr, 64 * kUpdWaves, 0, sx>>>(G, W, 0, gr, v, drp + (int64_t)G * (N + 1), N, pool);
       MX_HIP(hipEventRecord(ev_rest, sx));
-      if (nn > 0) k_fac_update2<T, true><<<nn, 64 * kUpdWaves, 0, st>>>(K, gn, v, dnp + (int64_t)K * (N + 1), N, pool);
-      if (K + 2 < nb) diag_panel(K + 2);
+      if (nn > 0)
+        k_fac_update_group<T, UpdNext><<<nn, 64 * kUpdWaves, 0, st>>>(G, W, 0, gn, v, dnp + (int64_t)G * (N + 1), N, pool);
+      if (G + W < nb) diag_panel(G + W);
     }
-    // an odd last column was factored by the last pair's diag_panel(K + 2) and updates nothing
   }
   MX_HIP(hipStreamWaitEvent(st, ev_rest, 0));
   MX_HIP(hipGetLastError());
@@ -1036,9 +1063,12 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   if (s0 < 0 || s1 > part.nsub || s0 >= s1) fail(MX_EINVAL, "subdomain share out of range");
   if (opts->pool_limit < 0) fail(MX_EINVAL, "pool_limit must be >= 0");
   P->pool_limit = opts->pool_limit;
-  if (opts->factor_schedule < 0 || opts->factor_schedule > MX_FACTOR_PAIRS)
+  if (opts->factor_schedule < 0 || opts->factor_schedule > MX_FACTOR_LOOKAHEAD)
     fail(MX_EINVAL, "unknown factor_schedule");
+  if (opts->factor_width < 0 || opts->factor_width > kMaxWidth)
+    fail(MX_EINVAL, "factor_width must be 0 .. 4");
   P->schedule = opts->factor_schedule;
+  P->width = opts->factor_width > 0 ? opts->factor_width : kDefaultWidth;
   P->sub_begin = s0;
   P->nsub = s1 - s0;
   const int N = P->nsub;
@@ -1255,25 +1285,39 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     P->panel_pref[(int64_t)K * (N + 1) + N] = (int32_t)ap;
     P->update_pref[(int64_t)K * (N + 1) + N] = (int32_t)au;
   }
-  // two-column steps (K, K+1): block columns K+2, K+3 and the tiles K+4 <= J <= I, all for rows up
-  // to blast(K+1) (blast is nondecreasing, so this covers the rows of column K too)
-  P->pair_next_pref.assign((int64_t)P->max_nb * (N + 1), 0);
-  P->pair_rest_pref.assign((int64_t)P->max_nb * (N + 1), 0);
-  for (int K = 0; K < P->max_nb; ++K) {
-    int64_t an = 0, ar = 0;
-    for (int l = 0; l < N; ++l) {
-      P->pair_next_pref[(int64_t)K * (N + 1) + l] = (int32_t)an;
-      P->pair_rest_pref[(int64_t)K * (N + 1) + l] = (int32_t)ar;
-      if (K + 1 < P->sub_nb[l]) {
-        const int64_t b1 = P->sky[l].blast[K + 1];
-        an += std::max<int64_t>(0, b1 - K - 1) + std::max<int64_t>(0, b1 - K - 2);
-        const int64_t m = std::max<int64_t>(0, b1 - K - 3);
-        ar += m * (m + 1) / 2;
+  // look-ahead groups of W block columns (group G = 0, W, 2W, ...; rows up to b = blast of the
+  // group's last column, blast being nondecreasing): column Kc of a group from the group's
+  // columns before it; the next group's W columns; the remaining tiles G+2W <= J <= I <= b
+  {
+    const int W = P->width;
+    const size_t sz = (size_t)P->max_nb * (N + 1);
+    P->intra_pref.assign(sz, 0);
+    P->next_pref.assign(sz, 0);
+    P->rest_pref.assign(sz, 0);
+    for (int K = 0; K < P->max_nb; ++K) {
+      int64_t ai = 0, an = 0, ar = 0;
+      const bool start = K % W == 0;
+      for (int l = 0; l < N; ++l) {
+        const int64_t row = (int64_t)K * (N + 1) + l;
+        P->intra_pref[row] = (int32_t)ai;
+        P->next_pref[row] = (int32_t)an;
+        P->rest_pref[row] = (int32_t)ar;
+        const int nbl = P->sub_nb[l];
+        if (K >= nbl) continue;
+        const auto &bl = P->sky[l].blast;
+        if (!start) ai += std::max<int64_t>(0, bl[K - 1] - K + 1);
+        if (start) {
+          const int64_t b = bl[std::min(K + W, nbl) - 1];
+          for (int64_t J = K + W; J < K + 2 * W; ++J) an += std::max<int64_t>(0, b - J + 1);
+          const int64_t m = std::max<int64_t>(0, b - (K + 2 * W) + 1);
+          ar += m * (m + 1) / 2;
+        }
       }
+      if (ar > INT32_MAX || an > INT32_MAX) fail(MX_EINVAL, "factor step too large");
+      P->intra_pref[(int64_t)K * (N + 1) + N] = (int32_t)ai;
+      P->next_pref[(int64_t)K * (N + 1) + N] = (int32_t)an;
+      P->rest_pref[(int64_t)K * (N + 1) + N] = (int32_t)ar;
     }
-    if (ar > INT32_MAX) fail(MX_EINVAL, "factor step too large");
-    P->pair_next_pref[(int64_t)K * (N + 1) + N] = (int32_t)an;
-    P->pair_rest_pref[(int64_t)K * (N + 1) + N] = (int32_t)ar;
   }
   // sweep schedule: forward rows by relative progress, then backward rows likewise
   struct Item {
@@ -1318,7 +1362,7 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   plan.device_bytes = (size_t)tiles * kTileElems * esz + (size_t)packed * esz + 3 * (size_t)vec * esz +
                       2 * (size_t)blocks * 4 + 24 * (size_t)blocks + 32 * (size_t)tiles + 4 * (size_t)vec +
                       8 * (size_t)std::max(src.size(), sum_idx.size() + sum_ptr.size()) +
-                      8 * (size_t)sched_sub.size() + 16 * P->panel_pref.size() +
+                      8 * (size_t)sched_sub.size() + 20 * P->panel_pref.size() +
                       24 * off.size() + (1 << 20);
 }
 
@@ -1350,8 +1394,9 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   }
   P->d_panel_pref.upload(P->panel_pref);
   P->d_update_pref.upload(P->update_pref);
-  P->d_pair_next_pref.upload(P->pair_next_pref);
-  P->d_pair_rest_pref.upload(P->pair_rest_pref);
+  P->d_intra_pref.upload(P->intra_pref);
+  P->d_next_pref.upload(P->next_pref);
+  P->d_rest_pref.upload(P->rest_pref);
   P->d_sched_sub.upload(sched_sub);
   P->d_sched_blk.upload(sched_blk);
   P->d_rmeta.upload(plan.rmeta);

@@ -42,13 +42,14 @@ class MxError(RuntimeError):
 
 
 # factor_schedule values of mx_precond_opts (mx.h)
-FACTOR_SCHEDULES = {"auto": 0, "one_stream": 1, "columns": 2, "pairs": 3}
+FACTOR_SCHEDULES = {"auto": 0, "one_stream": 1, "lookahead": 2}
 
 
 class PrecondOpts(C.Structure):
     _fields_ = [("kind", C.c_int), ("xi_prec", C.c_double), ("precision", C.c_int),
                 ("sweep_grid", C.c_int), ("sub_begin", C.c_int),
-                ("sub_end", C.c_int), ("pool_limit", C.c_int64), ("factor_schedule", C.c_int32)]
+                ("sub_end", C.c_int), ("pool_limit", C.c_int64), ("factor_schedule", C.c_int32),
+                ("factor_width", C.c_int32)]
 
 
 class PrecondInfo(C.Structure):
@@ -323,12 +324,13 @@ class Precond:
     """plan_only=True runs only the host half (mx_precond_plan); call materialize() before use."""
 
     def __init__(self, ctx, A, mesh, part, kind="oras", xi_prec=None, precision="c128",
-                 sweep_grid=0, share=None, plan_only=False, pool_limit=0, schedule="auto"):
+                 sweep_grid=0, share=None, plan_only=False, pool_limit=0, schedule="auto",
+                 width=0):
         load()
         s0, s1 = share if share is not None else (0, 0)
         o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec,
                         PRECISIONS.get(precision, precision), sweep_grid, s0, s1, pool_limit,
-                        FACTOR_SCHEDULES.get(schedule, schedule))
+                        FACTOR_SCHEDULES.get(schedule, schedule), width)
         h = P()
         self.device_bytes = None
         if plan_only:

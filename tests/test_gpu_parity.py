@@ -388,10 +388,10 @@ def test_grouped_factorisation(gpu_lib, ctx, precision):
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 def test_factor_schedules(gpu_lib, ctx, precision):
-    """The three launch orders of the blocked LDL^T (one stream; look-ahead with one block column
-    per trailing update; look-ahead with two) compute the same factors up to rounding: their
+    """The launch orders of the blocked LDL^T (one stream; look-ahead with 1, 2, 3 or 4 block
+    columns per pass of the trailing update) compute the same factors up to rounding: their
     applications agree with the oracle, and with each other to rounding.  Subdomains of unequal
-    block counts (jittered cuts) cover pairs that end on an odd last column."""
+    block counts (jittered cuts) cover groups cut short by a subdomain's last column."""
     say("factor schedules", precision)
     n = (16, 14, 12)
     cuts = (jittered_cuts(16, 3, 0.2, 7), jittered_cuts(14, 2, 0.2, 8), jittered_cuts(12, 2, 0.2, 9))
@@ -400,17 +400,21 @@ def test_factor_schedules(gpu_lib, ctx, precision):
     vd = dev(v)
     ref = c.oB(v)
     out = {}
-    for sched in ("one_stream", "columns", "pairs"):
-        P = gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, schedule=sched)
+    for sched, width in (("one_stream", 0), ("lookahead", 1), ("lookahead", 2), ("lookahead", 3),
+                         ("lookahead", 4)):
+        P = gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, schedule=sched,
+                            width=width)
         z = dev(np.zeros(c.E))
         P.apply(vd, z)
         P.check()
-        out[sched] = host(z)
-        err = np.linalg.norm(out[sched] - ref) / np.linalg.norm(ref)
-        say("  ", sched, "rel err vs oracle", err)
+        out[(sched, width)] = host(z)
+        err = np.linalg.norm(out[(sched, width)] - ref) / np.linalg.norm(ref)
+        say("  ", sched, width, "rel err vs oracle", err)
         assert err <= (1e-10 if precision == "c128" else 1e-4)
-    for sched in ("columns", "pairs"):
-        d = np.linalg.norm(out[sched] - out["one_stream"]) / np.linalg.norm(out["one_stream"])
-        assert d <= (1e-12 if precision == "c128" else 1e-5)
-    with pytest.raises(gpu_lib.MxError):
-        gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, schedule=7)
+    base = out[("one_stream", 0)]
+    for key, z in out.items():
+        d = np.linalg.norm(z - base) / np.linalg.norm(base)
+        assert d <= (1e-12 if precision == "c128" else 1e-5), key
+    for bad in (dict(schedule=7), dict(schedule="lookahead", width=5)):
+        with pytest.raises(gpu_lib.MxError):
+            gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, **bad)
