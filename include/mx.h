@@ -138,7 +138,7 @@ typedef struct {
   int32_t factor_schedule; /* MX_FACTOR_*: order of the blocked factorisation's launches; every */
                            /* schedule computes the same LDL^T up to rounding (0 = automatic)   */
   int32_t factor_width;    /* look-ahead: block columns applied per pass of the trailing update */
-                           /* (1 .. 4; 0 = 4)                                                  */
+                           /* (1 .. 4; 0 = 4 for MX_C128, 3 for MX_C64)                        */
 } mx_precond_opts;
 
 /* factor_schedule values.  ONE_STREAM: diagonal tile, panel and trailing update of one block

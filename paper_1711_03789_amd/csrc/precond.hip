@@ -215,7 +215,10 @@ constexpr int kUpdCB = 8 / kUpdWaves;  // 16-column blocks per wave
 // tiles (A[q] = L_IK, B[q] = L_JK) and the pivots d[q] = D_K in LDS; 4 16-wide k slabs per source.
 // The slab loop is unrolled, so every index into these arrays is a constant.
 constexpr int kMaxWidth = 4;
-constexpr int kDefaultWidth = 4;  // block columns per look-ahead trailing update unless asked
+// block columns per look-ahead trailing update unless asked (measured best at 64^3: 4 for
+// complex128, 3 for complex64, whose cheaper matrix-core products leave less to hide the main
+// stream's longer critical path behind)
+constexpr int kDefaultWidthC128 = 4, kDefaultWidthC64 = 3;
 template <typename T>
 struct UpdSources {
   const cx<T> *A[kMaxWidth], *B[kMaxWidth], *d[kMaxWidth];
@@ -1068,7 +1071,8 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   if (opts->factor_width < 0 || opts->factor_width > kMaxWidth)
     fail(MX_EINVAL, "factor_width must be 0 .. 4");
   P->schedule = opts->factor_schedule;
-  P->width = opts->factor_width > 0 ? opts->factor_width : kDefaultWidth;
+  P->width = opts->factor_width > 0 ? opts->factor_width
+                                    : P->prec == MX_C128 ? kDefaultWidthC128 : kDefaultWidthC64;
   P->sub_begin = s0;
   P->nsub = s1 - s0;
   const int N = P->nsub;
