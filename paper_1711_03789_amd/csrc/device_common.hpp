@@ -155,7 +155,7 @@ __device__ __forceinline__ int acc_row<double>(int r0, int rb, int r) {
 }
 __device__ __forceinline__ int acc_col(int c0, int cb) { return c0 + cb * 16 + (threadIdx.x & 15); }
 
-// ---- bounded waits on agent-scope flags ----------------------------------------------------------
+// ---- agent-scope flags, publication and bounded waits ----------------------------------------------------------
 __device__ __forceinline__ int load_flag(const int *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -163,11 +163,11 @@ __device__ __forceinline__ void store_flag(int *p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Cross-workgroup publication of small results (one 64-entry block) without cache-wide fences:
-// the producer writes with device-coherent atomic stores, waits until its stores are complete and
-// only then stores the flag; the consumer reads the flag and then the data with device-coherent
-// atomic loads, which cannot hit a stale line in a non-coherent cache.  Whole-cache writeback /
-// invalidate fences at agent scope would cost more than the data moved (measured: they halve the
-// streaming bandwidth of the sweeps).
+// the producer writes with device-coherent atomic stores; the consumer reads with device-coherent
+// atomic loads, which cannot hit a stale line in a non-coherent cache, and knows a value is
+// published when it no longer holds the sentinel (below).  Whole-cache writeback / invalidate
+// fences at agent scope would cost more than the data moved (measured: they halve the streaming
+// bandwidth of the sweeps).
 template <typename T>
 __device__ __forceinline__ void pub_store(cx<T> *p, cx<T> v) {
   __hip_atomic_store(&p->re, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -178,16 +178,13 @@ __device__ __forceinline__ cx<T> pub_load(const cx<T> *p) {
   return {__hip_atomic_load(&p->re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
           __hip_atomic_load(&p->im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
 }
-// Wait until every memory operation issued by this wave has completed (vmcnt = 0; expcnt and
-// lgkmcnt left unconstrained).
-__device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
 // Sentinel marking a not-yet-written result value: a NaN bit pattern that no computed value has
-// (a NaN result means a failed factorisation, which is reported anyway).  A result vector is
-// filled with it before each sweep; a consumer of the block it depends on last polls the values
-// themselves instead of a flag, which saves the producer's store acknowledgement and one round
-// trip on the critical path.  Each half of a complex value is written by one 4- or 8-byte store,
-// so a value is complete when neither half is the sentinel.
+// (it is a signalling NaN, and arithmetic only ever produces quiet ones).  A result vector is
+// filled with it before each sweep, and a consumer polls the values it needs until none is the
+// sentinel: the data is its own completion flag, so the producer neither waits for its stores to
+// be acknowledged nor stores a flag after them, and no ordering between a flag and the data has to
+// hold.  Each half of a complex value is written by one 4- or 8-byte store, so a value is complete
+// when neither half is the sentinel.
 __device__ __forceinline__ bool is_sentinel(double v) {
   return __double_as_longlong(v) == (long long)0x7FF75EA700000001ull;
 }
@@ -205,29 +202,27 @@ __device__ __forceinline__ cx<float> sentinel<float>() {
   return {s, s};
 }
 
-// Spins until *flag == want; returns false (and raises *abort) after kSpinLimit polls or when
-// another workgroup has raised *abort.
-__device__ inline bool wait_flag(const int *flag, int want, int *abort) {
-  if (load_flag(flag) == want) return true;
-  for (long it = 0; it < kSpinLimit; ++it) {
-    __builtin_amdgcn_s_sleep(1);
-    if (load_flag(flag) == want) return true;
-    if ((it & 63) == 0 && load_flag(abort)) return false;
-  }
-  store_flag(abort, 1);
-  return false;
-}
-
 // Loads this wave's values at p, waiting (bounded) until no lane sees the sentinel in either half;
 // returns false (and raises *abort) after kSpinLimit polls or when another workgroup has raised it.
+// While waiting only lane 0 polls (its own value), so a waiting wave costs one 16-byte load per
+// poll instead of a whole block: a block is written by one store instruction of one wave, so the
+// rest of it lands right after lane 0's value.
 template <typename T>
 __device__ inline bool wait_values(const cx<T> *p, cx<T> &v, int *abort) {
   v = pub_load(p);
   if (__all(!is_sentinel(v.re) && !is_sentinel(v.im))) return true;
+  const bool lead = (threadIdx.x & 63) == 0;
   for (long it = 0; it < kSpinLimit; ++it) {
     __builtin_amdgcn_s_sleep(1);
-    v = pub_load(p);
-    if (__all(!is_sentinel(v.re) && !is_sentinel(v.im))) return true;
+    int seen = 0;
+    if (lead) {
+      const cx<T> u = pub_load(p);
+      seen = !is_sentinel(u.re) && !is_sentinel(u.im);
+    }
+    if (__builtin_amdgcn_readfirstlane(seen)) {
+      v = pub_load(p);
+      if (__all(!is_sentinel(v.re) && !is_sentinel(v.im))) return true;
+    }
     if ((it & 63) == 0 && load_flag(abort)) return false;
   }
   store_flag(abort, 1);

@@ -175,7 +175,7 @@ struct mx_precond {
   int64_t pack_entries = 0;
   mx::DevBuf d_r, d_y, d_z;                 // local vectors (factor precision)
   mx::DevBuf d_glob, d_src, d_sum_ptr, d_sum_idx;
-  mx::DevBuf d_flags, d_ctrl, d_sched_sub, d_sched_blk;
+  mx::DevBuf d_ctrl, d_sched_sub, d_sched_blk;
   mx::DevBuf d_panel_pref, d_update_pref, d_intra_pref, d_next_pref, d_rest_pref;
   int n_items = 0, trsv_grid = 0;
   mx_precond_info info{};

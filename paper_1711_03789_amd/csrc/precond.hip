@@ -428,8 +428,7 @@ __global__ void k_restrict(int64_t n, const int32_t *__restrict__ glob,
                            cx<T> *__restrict__ y, cx<T> *__restrict__ z, int *ctrl) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p == 0) {
-    ctrl[0] += 1;  // epoch of this application
-    ctrl[1] = 0;   // ticket counters of the forward and backward sweeps
+    ctrl[1] = 0;  // ticket counters of the forward and backward sweeps
     ctrl[4] = 0;
   }
   if (p < n) {
@@ -487,27 +486,6 @@ __device__ __forceinline__ cx<T> butterfly8(cx<T> acc[8]) {
   return acc[0];
 }
 
-// Wave-level scan of completion flags.  Starting at J and moving by `step` (+1 or -1) towards
-// (exclusive) Jlimit, finds how many consecutive block rows have published `epoch`: one flag per
-// lane, then a ballot.  When none is ready yet, lane 0 waits (bounded) on flags[J].  Returns the
-// first not-yet-checked row (!= J), or INT_MIN after an expired wait or an abort.
-__device__ inline int ready_run(const int *flags, int J, int Jlimit, int step, int epoch, int *abort) {
-  const int lane = threadIdx.x & 63;
-  while (true) {
-    const int cnt = min(64, (Jlimit - J) * step);
-    const bool ok = lane < cnt && load_flag(&flags[J + step * lane]) == epoch;
-    const uint64_t m = __ballot(ok);
-    const uint64_t valid = cnt == 64 ? ~0ull : ((1ull << cnt) - 1);
-    const uint64_t bad = ~m & valid;
-    const int first_bad = bad ? __ffsll((long long)bad) - 1 : cnt;
-    if (first_bad > 0) return __builtin_amdgcn_readfirstlane(J + step * first_bad);
-    int okw = 1;
-    if (lane == 0) okw = wait_flag(&flags[J], epoch, abort) ? 1 : 0;
-    // readfirstlane (not a shuffle) keeps the result, and the caller's loop bounds, scalar
-    if (!__builtin_amdgcn_readfirstlane(okw)) return INT_MIN;
-  }
-}
-
 constexpr int kSweepWaves = 8;              // 512-thread workgroups, 8 tile rows per wave
 constexpr int kSweepThreads = 64 * kSweepWaves;
 constexpr int kRows = kTile / kSweepWaves;  // = 8
@@ -523,16 +501,15 @@ struct SweepMinWaves {
 // (subdomain, block row) are handed out by an atomic ticket in an order in which every item
 // comes after all items it depends on (a subdomain's rows ascending for the forward sweep,
 // descending for the backward one), so a workgroup only ever waits for tickets already taken by
-// running workgroups.  Completion is published per block row with an epoch-tagged flag; all waits
-// are bounded.
+// running workgroups.  A block row is complete when its results no longer hold the sentinel the
+// result vectors are filled with before the sweep; all waits are bounded.
 //   forward  (FWD): y_I = inv(L_II) (r_I - sum_{J<I} L_IJ y_J)
 //   backward      : z_J = inv(L_JJ)^T (y_J / D_J - sum_{I>J} L_IJ^T z_I)
 // Tiles are read row by row with the lanes along a tile row (coalesced) in both directions, up to
 // four tiles per wave in flight.  The two tiles needed right after the last dependency (the
 // neighbour tile and the diagonal tile) are staged in LDS when the item starts, so the dependency
-// chain itself carries no tile loads.  Results of a block are written by wave 0 only, which
-// performs the agent-scope release and stores the flag; readers take an agent-scope acquire after
-// seeing a flag.
+// chain itself carries no tile loads.  Results of a block are written by wave 0 only, with
+// device-coherent stores; readers load them with device-coherent loads and check them.
 // Streaming helpers over the trimmed tiles.  A wave owns 8 consecutive rows of a tile; a row
 // missing from a tile contributes zero and is not read.
 // The factor is read once per sweep: nontemporal loads keep it from displacing reusable lines
@@ -558,20 +535,36 @@ __device__ __forceinline__ void wave_rows(const cx<T> *__restrict__ pack, TileMe
   }
 }
 
+// A batch of NT tiles per wave in flight.  The block results it multiplies are validated by their
+// values: a result still holding the sentinel is not published yet, and the wave waits (bounded)
+// for it.  Returns false after an expired wait or an abort.
+template <typename T>
+__device__ __forceinline__ bool published(cx<T> v) {
+  return !is_sentinel(v.re) && !is_sentinel(v.im);
+}
+
 template <typename T, int NT>
-__device__ __forceinline__ void stream_fwd(const cx<T> *__restrict__ pack, const TileMeta *rm,
-                                           int J, int row0, const cx<T> *yp, cx<T> acc[kRows]) {
+__device__ __forceinline__ bool stream_fwd(const cx<T> *__restrict__ pack, const TileMeta *rm, int J,
+                                           int row0, const cx<T> *yp, cx<T> acc[kRows], int *abort) {
   // tiles (B, J..J+NT-1) of this wave's rows; rm[J] = meta of tile (B, J); yp = y of block J
   cx<T> a[NT][kRows], y[NT];
+  bool ready = true;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     y[t] = pub_load(yp + t * kTile);
+    ready = ready && published(y[t]);
     wave_rows(pack, rm[J + t], row0, a[t]);
+  }
+  if (!__all(ready)) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (!__all(published(y[t])) && !wait_values(yp + t * kTile, y[t], abort)) return false;
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int r = 0; r < kRows; ++r) cfma(acc[r], a[t][r], y[t]);
+  return true;
 }
 
 template <typename T>
@@ -580,28 +573,38 @@ __device__ __forceinline__ cx<T> bcast(cx<T> v, int src) {
 }
 
 template <typename T, int NT>
-__device__ __forceinline__ void stream_bwd(const cx<T> *__restrict__ pack, const TileMeta *cm,
+__device__ __forceinline__ bool stream_bwd(const cx<T> *__restrict__ pack, const TileMeta *cm,
                                            int64_t vb, int I, int row0, const cx<T> *zvec,
-                                           cx<T> &acc) {
-  // tiles (I, B), (I-1, B), ...; cm[I] = meta of tile (I, B)
+                                           cx<T> &acc, int *abort) {
+  // tiles (I, B), (I-1, B), ...; cm[I] = meta of tile (I, B); the wave needs z of its 8 rows
   const int lane = threadIdx.x & 63;
   cx<T> a[NT][kRows], z[NT];
+  bool ready = true;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     z[t] = pub_load(zvec + vb + (int64_t)(I - t) * kTile + row0 + (lane & (kRows - 1)));
+    ready = ready && published(z[t]);
     wave_rows(pack, cm[I - t], row0, a[t]);
+  }
+  if (!__all(ready)) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (!__all(published(z[t])) &&
+          !wait_values(zvec + vb + (int64_t)(I - t) * kTile + row0 + (lane & (kRows - 1)), z[t], abort))
+        return false;
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int r = 0; r < kRows; ++r) cfma(acc, a[t][r], bcast(z[t], r));
+  return true;
 }
 
 template <typename T, bool FWD>
 __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_sweep(
     SubView v, const cx<T> *__restrict__ pack, const int32_t *__restrict__ sched_sub,
     const int32_t *__restrict__ sched_blk, int n_items, const cx<T> *__restrict__ rvec, cx<T> *yvec,
-    cx<T> *zvec, int *flags, int *ctrl) {
+    cx<T> *zvec, int *ctrl) {
   __shared__ int s_item;
   __shared__ int s_dead;
   __shared__ cx<T> sL[kTile][kTile];  // neighbour tile of the last dependency
@@ -614,7 +617,6 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
   const int row0 = w * kRows;  // this wave's first row inside a block
   // tiles per wave in flight (eight for complex float measured slower than four)
   constexpr int kBatch = 4;
-  const int epoch = ctrl[0];
   int *abort = &ctrl[2];
   int *ticket = &ctrl[FWD ? 1 : 4];
   while (true) {
@@ -630,9 +632,8 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
     const int l = sched_sub[item], B = sched_blk[item];
     const int bb = v.brow_base[l];
     const int64_t vb = v.vec_base[l];
-    int *fl = flags + bb;
-    // Every wave streams its own 8 rows and checks the readiness of the blocks it needs by
-    // itself (one ballot per 64 flags), so waves only meet at the final reductions.
+    // Every wave streams its own 8 rows and checks the block results it multiplies by itself, so
+    // waves only meet at the final reductions.
     bool dead = false;
     if (FWD) {
       const int f = v.bfirst[bb + B];
@@ -653,17 +654,10 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       for (int r = 0; r < kRows; ++r) acc[r] = {0, 0};
       const cx<T> rB = rvec[vb + (int64_t)B * kTile + lane];
       int J = f;
-      while (J < B - 1) {
-        const int Jend = ready_run(fl, J, B - 1, 1, epoch, abort);
-        if (Jend == INT_MIN) {
-          dead = true;
-          break;
-        }
-        for (; J + kBatch - 1 < Jend; J += kBatch)
-          stream_fwd<T, kBatch>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc);
-        for (; J < Jend; ++J)
-          stream_fwd<T, 1>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc);
-      }
+      for (; !dead && J + kBatch - 1 < B - 1; J += kBatch)
+        dead = !stream_fwd<T, kBatch>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc, abort);
+      for (; !dead && J < B - 1; ++J)
+        dead = !stream_fwd<T, 1>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc, abort);
       if (has_prev && !dead) {
         // the last dependency is read directly (sentinel polling), not through its flag
         cx<T> y0;
@@ -688,8 +682,6 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       __syncthreads();
       if (w == 0 && !s_dead) {
         pub_store(yvec + vb + (int64_t)B * kTile + lane, cadd(tm, s_out[lane]));
-        stores_complete();
-        if (lane == 0) store_flag(&fl[B], epoch);
       }
     } else {
       const int last = v.blast[bb + B];
@@ -712,15 +704,9 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       cx<T> acc = {0, 0};
       // rows far below B finish first: consume I = last, last-1, ..., B+2 as they become ready
       int I = last;
-      while (I > B + 1) {
-        const int Iend = ready_run(fl, I, B + 1, -1, epoch, abort);
-        if (Iend == INT_MIN) {
-          dead = true;
-          break;
-        }
-        for (; I - (kBatch - 1) > Iend; I -= kBatch) stream_bwd<T, kBatch>(pack, cm, vb, I, row0, zvec, acc);
-        for (; I > Iend; --I) stream_bwd<T, 1>(pack, cm, vb, I, row0, zvec, acc);
-      }
+      for (; !dead && I - (kBatch - 1) > B + 1; I -= kBatch)
+        dead = !stream_bwd<T, kBatch>(pack, cm, vb, I, row0, zvec, acc, abort);
+      for (; !dead && I > B + 1; --I) dead = !stream_bwd<T, 1>(pack, cm, vb, I, row0, zvec, acc, abort);
       if (has_next && !dead) {
         cx<T> zv;  // the last dependency, read directly (sentinel polling)
         if (!wait_values(zvec + vb + (int64_t)(B + 1) * kTile + row0 + (lane & (kRows - 1)), zv, abort)) {
@@ -752,8 +738,6 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
 #pragma unroll
         for (int q = 1; q < kSweepWaves; ++q) t = cadd(t, s_red[q][lane]);
         pub_store(zvec + vb + (int64_t)B * kTile + lane, cadd(s_vec[lane], t));
-        stores_complete();
-        if (lane == 0) store_flag(&fl[B], epoch);
       }
     }
   }
@@ -915,7 +899,6 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
   k_restrict<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
       n, P->d_glob.as<int32_t>(), (const cx<double> *)vin, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
       P->d_z.as<cx<T>>(), P->d_ctrl.as<int>());
-  int *flags = P->d_flags.as<int>();
   if (P->timing) {
     if (P->n_timed == P->ev_start.size()) {
       hipEvent_t a, b, c;
@@ -931,12 +914,12 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
   const int half = P->n_items / 2;
   k_sweep<T, true><<<P->trsv_grid, kSweepThreads, 0, st>>>(
       v, P->pack.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(), half,
-      P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), flags, P->d_ctrl.as<int>());
+      P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), P->d_ctrl.as<int>());
   if (P->timing) MX_HIP(hipEventRecord(P->ev_mid[P->n_timed], st));
   k_sweep<T, false><<<P->trsv_grid, kSweepThreads, 0, st>>>(
       v, P->pack.as<cx<T>>(), P->d_sched_sub.as<int32_t>() + half,
       P->d_sched_blk.as<int32_t>() + half, half, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
-      P->d_z.as<cx<T>>(), flags + P->blocks_total, P->d_ctrl.as<int>());
+      P->d_z.as<cx<T>>(), P->d_ctrl.as<int>());
   if (P->timing) MX_HIP(hipEventRecord(P->ev_stop[P->n_timed++], st));
   const int64_t E = P->E;
   if (P->kind == MX_AS)
@@ -1409,9 +1392,7 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   P->d_r.alloc(vec * esz);
   P->d_y.alloc(vec * esz);
   P->d_z.alloc(vec * esz);
-  P->d_flags.alloc(2 * blocks * sizeof(int));
   P->d_ctrl.alloc(64);
-  MX_HIP(hipMemsetAsync(P->d_flags.p, 0, 2 * blocks * sizeof(int), st));
   MX_HIP(hipMemsetAsync(P->d_ctrl.p, 0, 64, st));
   MX_HIP(hipMemsetAsync(P->d_y.p, 0, vec * esz, st));
   MX_HIP(hipMemsetAsync(P->d_z.p, 0, vec * esz, st));
