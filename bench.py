@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # command (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0: what the counters read for a 1 GiB
 # device copy), averaged over the launches; summaries in profiles/.  Valid for the sweep kernel
 # as it is now; None where not measured.
-SWEEP_TRAFFIC = {("scale", "c128"): 58.86e9, ("apply", "c128"): 65.82e9}
+SWEEP_TRAFFIC = {("scale", "c128"): 58.85e9, ("apply", "c128"): 65.81e9}
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
@@ -266,7 +266,7 @@ def run_serving(args):
     """Continuous-batching server: seeded Poisson arrivals of unit-cube requests (k ~ U[4,16],
     xi in {k, k^2}, n = ceil(k^1.5)+4 cubes per side, p = clamp(ceil(n/17),2,4) subdomains per
     side, Gaussian sources), mixed-precision ORAS FGMRES(50) rtol 1e-6, admission by exact HBM
-    footprint.  Unless --rate is given, the arrival rate is 0.8 x the saturated throughput of a
+    footprint.  Unless --rate is given, the arrival rate is 0.7 x the saturated throughput of a
     closed-loop calibration run (all calibration requests submitted at once).  Reports
     throughput and p50/p99 latency (arrival to result)."""
     import numpy as np
@@ -284,7 +284,7 @@ def run_serving(args):
             srv.wait(t, 600.0)
             srv.release(t)
         sat = len(creqs) / (time.perf_counter() - c0)
-        rate = 0.8 * sat
+        rate = 0.7 * sat
         calib = {"requests": len(creqs), "saturated_solves_per_s": sat, "rate": rate}
     reqs = serving_requests(args.requests, rate, args.seed)
     t0 = time.perf_counter()
@@ -334,7 +334,7 @@ def main():
     ap.add_argument("--reps", type=int, default=10, help="applications timed (batching)")
     ap.add_argument("--requests", type=int, default=120, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0,
-                    help="serving: arrivals per second (0 = 0.8 x calibrated saturated throughput)")
+                    help="serving: arrivals per second (0 = 0.7 x calibrated saturated throughput)")
     ap.add_argument("--calib-requests", type=int, default=24, help="serving: calibration requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: requests in flight")
     ap.add_argument("--seed", type=int, default=0)
