@@ -780,9 +780,10 @@ static double now_s() {
 }
 
 // Right-looking blocked LDL^T over the subdomains [l0, l1) at once (their tiles are in `pool`,
-// starting with tile v.tile_shift), one block step K after the other.  Two streams overlap step
-// K's bulk trailing update (aux stream) with the chain that gates step K+1 on the main stream:
-// update of block column K+1, then diagonal tile K+1, then panel K+1.
+// starting with tile v.tile_shift), block column after block column.  Either on one stream, or
+// with look-ahead on two: the main stream carries the chain that gates the next block columns
+// (their updates, diagonal tiles and panels) while the aux stream applies the bulk of each
+// trailing update, from groups of P->width block columns at a time.
 template <typename T>
 static void factor_group(mx_precond *P, hipStream_t st, int l0, int l1, SubView v, cx<T> *pool) {
   const int N = P->nsub;
