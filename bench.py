@@ -378,15 +378,16 @@ def main():
 
     refs = {}
 
-    # The host half of the next instance's setup (assembly, local problems, RCM, tile layout)
-    # runs on a second host thread while the device factors and solves the current one; every
-    # device step stays on this thread, in order.  At most two instances are alive at once.
+    # The host half of the next instance's setup (assembly and its upload, local problems, RCM,
+    # tile layout) runs on a second host thread while the device factors and solves the current
+    # one; every kernel stays on this thread, in order.  At most two instances are alive at once.
     ctx_host = mx.Context(0)
 
     def prepare(mesh, part, kind, e):
         xi = w.k ** e
         t0 = time.perf_counter()
         A = mx.Matrix(None, mesh, w.k, xi)
+        A.upload(ctx_host)  # its own stream: overlaps the device work of the current instance
         t1 = time.perf_counter()
         P = mx.Precond(ctx_host, A, mesh, part, kind, precision=args.precision, plan_only=True)
         t2 = time.perf_counter()
@@ -405,7 +406,6 @@ def main():
                 A, P, xi, t_asm, t_pre = fut.result()
                 if idx + 1 < len(inst):
                     fut = ex.submit(prepare, mesh, part, inst[idx + 1][0], inst[idx + 1][1])
-                A.upload(ctx)
                 P.materialize(ctx)
                 t2 = time.perf_counter()
                 if record:

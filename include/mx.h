@@ -94,8 +94,10 @@ void mx_mesh_destroy(mx_mesh *m);
 /* ctx may be NULL: the matrix is then host-only until mx_matrix_upload. */
 int mx_matrix_assemble(mx_ctx *ctx, const mx_mesh *m, double k, double xi, int bc,
                        mx_matrix **out);
-/* Device copy of a host-only matrix (assembled with ctx = NULL).  Errors: MX_EINVAL (already on
- * a device), MX_ENOMEM, MX_EDEVICE. */
+/* Device copy of a host-only matrix (assembled with ctx = NULL).  The copies run on a private
+ * stream that does not wait for other streams, and the call returns when they are done, so
+ * another host thread may upload the next matrix while the device works.  Errors: MX_EINVAL
+ * (already on a device), MX_ENOMEM, MX_EDEVICE. */
 int mx_matrix_upload(mx_ctx *ctx, mx_matrix *A);
 int mx_matrix_sizes(const mx_matrix *A, int64_t *n, int64_t *nnz);
 /* Host copies: rowptr[n+1], col[nnz], val[2*nnz] (complex128).  Any may be NULL. */

@@ -252,15 +252,48 @@ size_t gmres_device_bytes(int64_t n, int restart, bool flexible) {
          (size_t)(restart + 1) * restart * 16 + 64 * (size_t)(restart + 1) + 8192;
 }
 
+__global__ void k_narrow(int64_t n, const double *__restrict__ in, float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+// Outside an allocation scope the copies run on a stream of their own that does not synchronise
+// with other streams, so a host thread can upload the next matrix while the device works on
+// something else; the buffers are then allocated unscoped, since they outlive that stream.
+// Inside a scope (a setup on a caller's stream) allocations and copies use the scope's stream.
+// Either way the call returns when the copy is complete.  The complex64 copy of the values is made
+// on the device.
 void matrix_upload(mx_matrix *A) {
-  A->rowptr.upload(A->h.rowptr);
-  A->col.upload(A->h.col);
-  A->val.upload(A->h.val);
-  raw_vector<float> v32(A->h.val.size());
-  parallel_for((int64_t)v32.size(), [&](int64_t a, int64_t b) {
-    for (int64_t i = a; i < b; ++i) v32[i] = (float)A->h.val[i];
-  });
-  A->val32.upload(v32);
+  const bool scoped = t_alloc_scoped != 0;
+  const hipStream_t prev = t_alloc_stream;
+  hipStream_t own = nullptr;
+  if (!scoped) {
+    MX_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    t_alloc_stream = own;
+  }
+  auto restore = [&]() {
+    t_alloc_stream = prev;
+    if (own) {
+      (void)hipStreamSynchronize(own);
+      (void)hipStreamDestroy(own);
+      own = nullptr;
+    }
+  };
+  try {
+    const hipStream_t s = t_alloc_stream;
+    A->rowptr.upload(A->h.rowptr);
+    A->col.upload(A->h.col);
+    A->val.upload(A->h.val);
+    const int64_t nv = (int64_t)A->h.val.size();
+    A->val32.alloc((size_t)nv * sizeof(float));
+    if (nv > 0) k_narrow<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(nv, A->val.as<double>(), A->val32.as<float>());
+    MX_HIP(hipGetLastError());
+    MX_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    restore();
+    throw;
+  }
+  restore();
 }
 
 void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
