@@ -197,6 +197,14 @@ int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx
 int mx_precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
                     const mx_precond_opts *opts, mx_precond **out, uint64_t *device_bytes);
 int mx_precond_materialize(mx_ctx *ctx, mx_precond *P, void *stream);
+/* Optional, between plan and materialize: copies everything the device half reads from the
+ * host (tile layout, schedules, gather maps, the local matrices' entries) to the device and
+ * returns when done.  The copies run on a private stream that does not wait for other streams,
+ * so another host thread can stage the next preconditioner while the device works;
+ * mx_precond_materialize then only zeroes, scatters, factors and trims.  The staged entries are
+ * freed by mx_precond_materialize.  Errors: MX_EINVAL (materialised or staged already, or
+ * planned for another device), MX_ENOMEM, MX_EDEVICE. */
+int mx_precond_stage(mx_ctx *ctx, mx_precond *P);
 /* z = sum_l R_l^T D_l (A^l)^-1 R_l v (D_l = I for AS); v_dev, z_dev complex128[E], distinct.
  * Enqueued on `stream`; device-side failures surface at the next synchronising call.
  * apply_bytes = factors read twice (forward and backward sweep) + local vectors + gathers. */

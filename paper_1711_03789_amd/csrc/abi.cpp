@@ -280,6 +280,17 @@ int mx_precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_
   });
 }
 
+int mx_precond_stage(mx_ctx *ctx, mx_precond *P) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && P, "NULL argument");
+    MX_REQUIRE(P->plan, "preconditioner is already materialised");
+    MX_REQUIRE(!P->staged, "preconditioner is already staged");
+    MX_REQUIRE(ctx->device == P->device, "preconditioner was planned for another device");
+    bind_device(ctx->device);
+    mx::precond_stage(P, *P->plan);
+  });
+}
+
 int mx_precond_materialize(mx_ctx *ctx, mx_precond *P, void *stream) {
   MX_GUARD({
     MX_REQUIRE(ctx && P, "NULL argument");

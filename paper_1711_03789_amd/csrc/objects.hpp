@@ -171,6 +171,8 @@ struct mx_precond {
   mx::DevBuf d_sub_nb, d_sub_brow_base, d_sub_tile_base, d_sub_vec_base;
   mx::DevBuf d_brow_off, d_bfirst, d_blast;
   mx::DevBuf pool;                          // 64x64 tiles (factorisation only)
+  bool staged = false;                      // mx_precond_stage copied the metadata and entries
+  mx::DevBuf d_off_all, d_val_all;          // staged scatter of the local matrices' entries
   mx::DevBuf pack, d_rmeta, d_cmeta, d_cptr;  // trimmed tiles of the factor (sweeps)
   int64_t pack_entries = 0;
   mx::DevBuf d_r, d_y, d_z;                 // local vectors (factor precision)
@@ -196,6 +198,7 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_p
                    const mx_precond_opts *opts, mx_precond *P, hipStream_t st);
 void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
                   const mx_precond_opts *opts, mx_precond *P, PrecondPlan &plan);
+void precond_stage(mx_precond *P, PrecondPlan &plan);
 void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st);
 size_t matrix_device_bytes(const mx_matrix *A);
 size_t gmres_device_bytes(int64_t n, int restart, bool flexible);

@@ -1354,42 +1354,70 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
                       24 * off.size() + (1 << 20);
 }
 
-void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
-  const double t1 = now_s();
-  const int N = P->nsub;
-  const int64_t blocks = P->blocks_total, vec = P->vec_total, tiles = P->tiles_total;
-  std::vector<int64_t> &brow_off = plan.brow_off;
-  std::vector<int32_t> &bfirst = plan.bfirst, &blast = plan.blast;
-  std::vector<int32_t> &glob = plan.glob;
-  std::vector<int64_t> &src = plan.src, &sum_ptr = plan.sum_ptr, &sum_idx = plan.sum_idx;
-  std::vector<int32_t> &sched_sub = plan.sched_sub, &sched_blk = plan.sched_blk;
-  AllocScope scope(st);
-  // device buffers
-  const size_t esz = P->prec == MX_C128 ? 16 : 8;
+// Everything the device half reads from the plan except the local matrices' entries.
+static void upload_metadata(mx_precond *P, PrecondPlan &plan) {
   P->d_sub_nb.upload(P->sub_nb);
   P->d_sub_brow_base.upload(P->sub_brow_base);
   P->d_sub_tile_base.upload(P->sub_tile_base);
   P->d_sub_vec_base.upload(P->sub_vec_base);
-  P->d_brow_off.upload(brow_off);
-  P->d_bfirst.upload(bfirst);
-  P->d_blast.upload(blast);
-  P->d_glob.upload(glob);
+  P->d_brow_off.upload(plan.brow_off);
+  P->d_bfirst.upload(plan.bfirst);
+  P->d_blast.upload(plan.blast);
+  P->d_glob.upload(plan.glob);
   if (P->kind == MX_AS) {
-    P->d_sum_ptr.upload(sum_ptr);
-    P->d_sum_idx.upload(sum_idx);
+    P->d_sum_ptr.upload(plan.sum_ptr);
+    P->d_sum_idx.upload(plan.sum_idx);
   } else {
-    P->d_src.upload(src);
+    P->d_src.upload(plan.src);
   }
   P->d_panel_pref.upload(P->panel_pref);
   P->d_update_pref.upload(P->update_pref);
   P->d_intra_pref.upload(P->intra_pref);
   P->d_next_pref.upload(P->next_pref);
   P->d_rest_pref.upload(P->rest_pref);
-  P->d_sched_sub.upload(sched_sub);
-  P->d_sched_blk.upload(sched_blk);
+  P->d_sched_sub.upload(plan.sched_sub);
+  P->d_sched_blk.upload(plan.sched_blk);
   P->d_rmeta.upload(plan.rmeta);
   P->d_cmeta.upload(plan.cmeta);
   P->d_cptr.upload(plan.cptr);
+}
+
+// Optional middle step: the host-to-device copies of the device half, on a private stream that
+// does not wait for other streams (so another host thread can run it while the device works).
+// Buffers are allocated unscoped: they outlive that stream.
+void precond_stage(mx_precond *P, PrecondPlan &plan) {
+  hipStream_t own;
+  MX_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+  const hipStream_t prev = t_alloc_stream;
+  const int prev_scoped = t_alloc_scoped;
+  t_alloc_stream = own;
+  t_alloc_scoped = 0;
+  auto restore = [&]() {
+    t_alloc_stream = prev;
+    t_alloc_scoped = prev_scoped;
+    (void)hipStreamSynchronize(own);
+    (void)hipStreamDestroy(own);
+  };
+  try {
+    upload_metadata(P, plan);
+    P->d_off_all.upload(plan.off);
+    P->d_val_all.upload(plan.val);
+  } catch (...) {
+    restore();
+    throw;
+  }
+  restore();
+  P->staged = true;
+}
+
+void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
+  const double t1 = now_s();
+  const int N = P->nsub;
+  const int64_t blocks = P->blocks_total, vec = P->vec_total, tiles = P->tiles_total;
+  AllocScope scope(st);
+  // device buffers
+  const size_t esz = P->prec == MX_C128 ? 16 : 8;
+  if (!P->staged) upload_metadata(P, plan);
   P->d_r.alloc(vec * esz);
   P->d_y.alloc(vec * esz);
   P->d_z.alloc(vec * esz);
@@ -1445,18 +1473,26 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
     {
       const int64_t e0 = plan.scat[l0], ne = plan.scat[l1] - e0;
       DevBuf d_off, d_val;
-      d_off.alloc((size_t)ne * 8);
-      d_val.alloc((size_t)ne * 16);
+      const int64_t *off = P->staged ? P->d_off_all.as<int64_t>() + e0 : nullptr;
+      const cx<double> *val = P->staged ? P->d_val_all.as<cx<double>>() + e0 : nullptr;
+      if (!P->staged) {
+        d_off.alloc((size_t)ne * 8);
+        d_val.alloc((size_t)ne * 16);
+        if (ne > 0) {
+          MX_HIP(hipMemcpyAsync(d_off.p, plan.off.data() + e0, (size_t)ne * 8, hipMemcpyHostToDevice, st));
+          MX_HIP(hipMemcpyAsync(d_val.p, plan.val.data() + 2 * e0, (size_t)ne * 16, hipMemcpyHostToDevice, st));
+        }
+        off = d_off.as<int64_t>();
+        val = d_val.as<cx<double>>();
+      }
       if (ne > 0) {
-        MX_HIP(hipMemcpyAsync(d_off.p, plan.off.data() + e0, (size_t)ne * 8, hipMemcpyHostToDevice, st));
-        MX_HIP(hipMemcpyAsync(d_val.p, plan.val.data() + 2 * e0, (size_t)ne * 16, hipMemcpyHostToDevice, st));
         const int64_t shift = T0 * kTileElems;
         if (P->prec == MX_C128)
-          k_scatter<double><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(
-              ne, d_off.as<int64_t>(), d_val.as<cx<double>>(), shift, P->pool.as<cx<double>>());
+          k_scatter<double><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(ne, off, val, shift,
+                                                                          P->pool.as<cx<double>>());
         else
-          k_scatter<float><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(
-              ne, d_off.as<int64_t>(), d_val.as<cx<double>>(), shift, P->pool.as<cx<float>>());
+          k_scatter<float><<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(ne, off, val, shift,
+                                                                         P->pool.as<cx<float>>());
       }
       MX_HIP(hipGetLastError());
       MX_HIP(hipStreamSynchronize(st));
@@ -1486,6 +1522,8 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   precond_check(P, st);
   P->pool.release();
   MX_HIP(hipStreamSynchronize(st));
+  P->d_off_all.release();
+  P->d_val_all.release();
   // host staging no longer needed
   std::vector<int64_t>().swap(plan.off);
   std::vector<double>().swap(plan.val);

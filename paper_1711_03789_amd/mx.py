@@ -27,7 +27,7 @@ SYMBOLS = [
     "mx_mesh_sizes", "mx_mesh_export", "mx_mesh_destroy", "mx_matrix_assemble", "mx_matrix_sizes",
     "mx_matrix_export", "mx_matrix_destroy", "mx_spmv", "mx_rhs_gaussian", "mx_partition_box",
     "mx_partition_sizes", "mx_partition_export", "mx_partition_destroy", "mx_precond_setup",
-    "mx_precond_apply", "mx_precond_get_info", "mx_precond_export_perm", "mx_precond_export_diag",
+    "mx_precond_apply", "mx_precond_get_info", "mx_precond_stage", "mx_precond_export_perm", "mx_precond_export_diag",
     "mx_precond_check", "mx_precond_destroy", "mx_gmres", "mx_selftest", "mx_local_problem",
     "mx_precond_sweep_timing", "mx_precond_autotune", "mx_server_create", "mx_server_submit",
     "mx_server_wait", "mx_server_solution", "mx_server_release", "mx_server_stats",
@@ -140,6 +140,7 @@ def load(path=LIB_PATH):
         "mx_precond_plan": (C.c_int, [P, P, P, P, C.POINTER(PrecondOpts), C.POINTER(P),
                                       C.POINTER(C.c_uint64)]),
         "mx_precond_materialize": (C.c_int, [P, P, P]),
+        "mx_precond_stage": (C.c_int, [P, P]),
         "mx_matrix_upload": (C.c_int, [P, P]),
         "mx_precond_apply": (C.c_int, [P, P, P, P, P]),
         "mx_precond_get_info": (C.c_int, [P, C.POINTER(PrecondInfo)]),
@@ -341,6 +342,10 @@ class Precond:
         else:
             _check(_lib.mx_precond_setup(ctx.h, A.h, mesh.h, part.h, C.byref(o), C.byref(h)))
         self.h, self.ctx = h, ctx
+
+    def stage(self, ctx):
+        """Host-to-device copies of the setup's device half (any host thread; optional)."""
+        _check(_lib.mx_precond_stage(ctx.h, self.h))
 
     def materialize(self, ctx, stream=None):
         _check(_lib.mx_precond_materialize(ctx.h, self.h, _stream(stream)))

@@ -335,6 +335,56 @@ def test_plan_then_materialize(gpu_lib, ctx):
     assert s1["iters"] == s2["iters"] and np.array_equal(host(x1), host(x2))
 
 
+def test_plan_stage_materialize_threads(gpu_lib, ctx):
+    """The staged setup (matrix upload and host-to-device copies of the plan made on a second
+    host thread with its own context, while this thread keeps the device busy with another
+    preconditioner) gives the same preconditioner, bit for bit; staging twice, or after
+    materialising, is refused."""
+    import threading
+    say("plan + stage + materialize on two host threads")
+    n, parts = (9, 8, 7), (2, 2, 2)
+    lm = gpu_lib.Mesh(*n)
+    lp = gpu_lib.Partition(lm, *parts, 2)
+    A_dev = gpu_lib.Matrix(ctx, lm, 4.0, 16.0)
+    ref = gpu_lib.Precond(ctx, A_dev, lm, lp, "oras")
+    ctx2 = gpu_lib.Context(0)
+    out = {}
+
+    def prepare():
+        try:
+            A = gpu_lib.Matrix(None, lm, 4.0, 16.0)
+            A.upload(ctx2)
+            P = gpu_lib.Precond(ctx2, A, lm, lp, "oras", plan_only=True)
+            P.stage(ctx2)
+            out["A"], out["P"] = A, P
+        except Exception as e:  # reported below, on this thread
+            out["err"] = e
+
+    v = random_rhs(lm.n_edge, 23)
+    vd, z1, z2 = dev(v), dev(np.zeros(lm.n_edge)), dev(np.zeros(lm.n_edge))
+    th = threading.Thread(target=prepare)
+    th.start()
+    for _ in range(20):  # device work on this thread meanwhile
+        ref.apply(vd, z1)
+    th.join()
+    assert "err" not in out, out.get("err")
+    P = out["P"]
+    with pytest.raises(gpu_lib.MxError):
+        P.stage(ctx2)
+    P.materialize(ctx)
+    with pytest.raises(gpu_lib.MxError):
+        P.stage(ctx)
+    P.apply(vd, z2)
+    ref.check()
+    P.check()
+    assert np.array_equal(host(z1), host(z2))
+    b = dev(random_rhs(lm.n_edge, 24))
+    x1, x2 = dev(np.zeros(lm.n_edge)), dev(np.zeros(lm.n_edge))
+    s1 = gpu_lib.gmres(ctx, A_dev, ref, b, x1, restart=30, rtol=1e-8)
+    s2 = gpu_lib.gmres(ctx, out["A"], P, b, x2, restart=30, rtol=1e-8)
+    assert s1["iters"] == s2["iters"] and np.array_equal(host(x1), host(x2))
+
+
 @pytest.mark.parametrize("n,parts", [((1, 1, 1), (1, 1, 1)), ((2, 1, 1), (2, 1, 1)), ((3, 2, 1), (3, 2, 1))])
 def test_tiny_meshes(gpu_lib, ctx, n, parts):
     """Subdomains far smaller than one 64-row tile (a single ragged block each), including the
