@@ -600,6 +600,97 @@ __device__ __forceinline__ bool stream_bwd(const cx<T> *__restrict__ pack, const
   return true;
 }
 
+// complex64 streaming with 16-byte lanes: lane (h, c) = (lane / 32, lane % 32) loads entries 2c
+// and 2c+1 of one tile row, so one load instruction covers two rows (1 KiB, like complex128)
+// instead of one (512 bytes).  Instruction i of a wave reads rows row0 + 2i + h.
+typedef float f4 __attribute__((ext_vector_type(4)));  // (re, im) of entries 2c and 2c+1
+
+__device__ __forceinline__ f4 load_stream4(const cx<float> *p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p));
+}
+
+__device__ __forceinline__ void wave_rows_wide(const cx<float> *__restrict__ pack, TileMeta m, int row0,
+                                               f4 a[kRows / 2]) {
+  const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
+  const uint32_t mb = (uint32_t)(m.mask >> row0) & 0xFFu;
+  const int k0 = rank_below(m.mask, row0);
+  const cx<float> *tp = pack + m.base + 2 * c;
+#pragma unroll
+  for (int i = 0; i < kRows / 2; ++i) {
+    const int r = 2 * i + h;
+    const int k = k0 + __popc(mb & ((1u << r) - 1u));
+    a[i] = (mb >> r) & 1u ? load_stream4(tp + (int64_t)k * kTile) : f4{0.f, 0.f, 0.f, 0.f};
+  }
+}
+
+// acc[i] += row (row0 + 2i + h) of tiles (B, J..J+NT-1), restricted to entries 2c, 2c+1, times y;
+// yb = y of block J.
+template <int NT>
+__device__ __forceinline__ bool stream_fwd_wide(const cx<float> *__restrict__ pack, const TileMeta *rm, int J,
+                                                int row0, const cx<float> *yb, cx<float> acc[kRows / 2],
+                                                int *abort) {
+  const int c = threadIdx.x & 31;
+  f4 a[NT][kRows / 2];
+  cx<float> y0[NT], y1[NT];
+  bool ready = true;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    y0[t] = pub_load(yb + t * kTile + 2 * c);
+    y1[t] = pub_load(yb + t * kTile + 2 * c + 1);
+    ready = ready && published(y0[t]) && published(y1[t]);
+    wave_rows_wide(pack, rm[J + t], row0, a[t]);
+  }
+  if (!__all(ready)) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (!__all(published(y0[t])) && !wait_values(yb + t * kTile + 2 * c, y0[t], abort)) return false;
+      if (!__all(published(y1[t])) && !wait_values(yb + t * kTile + 2 * c + 1, y1[t], abort)) return false;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < kRows / 2; ++i) {
+      cfma(acc[i], cx<float>{a[t][i].x, a[t][i].y}, y0[t]);
+      cfma(acc[i], cx<float>{a[t][i].z, a[t][i].w}, y1[t]);
+    }
+  return true;
+}
+
+// acc0/acc1 (entries 2c, 2c+1 of block B) += sum over this wave's rows r of tiles (I-t, B) of
+// L[r][.] z_I[r]; the wave's 8 values of z_I are loaded once and broadcast.
+template <int NT>
+__device__ __forceinline__ bool stream_bwd_wide(const cx<float> *__restrict__ pack, const TileMeta *cm,
+                                                int64_t vb, int I, int row0, const cx<float> *zvec,
+                                                cx<float> &acc0, cx<float> &acc1, int *abort) {
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  f4 a[NT][kRows / 2];
+  cx<float> z[NT];
+  bool ready = true;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    z[t] = pub_load(zvec + vb + (int64_t)(I - t) * kTile + row0 + (lane & (kRows - 1)));
+    ready = ready && published(z[t]);
+    wave_rows_wide(pack, cm[I - t], row0, a[t]);
+  }
+  if (!__all(ready)) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (!__all(published(z[t])) &&
+          !wait_values(zvec + vb + (int64_t)(I - t) * kTile + row0 + (lane & (kRows - 1)), z[t], abort))
+        return false;
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < kRows / 2; ++i) {
+      const cx<float> zr = bcast(z[t], 2 * i + h);
+      cfma(acc0, cx<float>{a[t][i].x, a[t][i].y}, zr);
+      cfma(acc1, cx<float>{a[t][i].z, a[t][i].w}, zr);
+    }
+  return true;
+}
+
 template <typename T, bool FWD>
 __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_sweep(
     SubView v, const cx<T> *__restrict__ pack, const int32_t *__restrict__ sched_sub,
@@ -654,10 +745,27 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       for (int r = 0; r < kRows; ++r) acc[r] = {0, 0};
       const cx<T> rB = rvec[vb + (int64_t)B * kTile + lane];
       int J = f;
-      for (; !dead && J + kBatch - 1 < B - 1; J += kBatch)
-        dead = !stream_fwd<T, kBatch>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc, abort);
-      for (; !dead && J < B - 1; ++J)
-        dead = !stream_fwd<T, 1>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc, abort);
+      if constexpr (sizeof(T) == 4) {
+        cx<float> accw[kRows / 2];
+#pragma unroll
+        for (int i = 0; i < kRows / 2; ++i) accw[i] = {0, 0};
+        for (; !dead && J + kBatch - 1 < B - 1; J += kBatch)
+          dead = !stream_fwd_wide<kBatch>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile, accw, abort);
+        for (; !dead && J < B - 1; ++J)
+          dead = !stream_fwd_wide<1>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile, accw, abort);
+        // fold into the one-entry-per-lane layout: row row0 + 2i + h lives in half h
+        const bool upper = lane >= 32;
+#pragma unroll
+        for (int i = 0; i < kRows / 2; ++i) {
+          acc[2 * i] = upper ? acc[2 * i] : cadd(acc[2 * i], accw[i]);
+          acc[2 * i + 1] = upper ? cadd(acc[2 * i + 1], accw[i]) : acc[2 * i + 1];
+        }
+      } else {
+        for (; !dead && J + kBatch - 1 < B - 1; J += kBatch)
+          dead = !stream_fwd<T, kBatch>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc, abort);
+        for (; !dead && J < B - 1; ++J)
+          dead = !stream_fwd<T, 1>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc, abort);
+      }
       if (has_prev && !dead) {
         // the last dependency is read directly (sentinel polling), not through its flag
         cx<T> y0;
@@ -704,9 +812,21 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
       cx<T> acc = {0, 0};
       // rows far below B finish first: consume I = last, last-1, ..., B+2 as they become ready
       int I = last;
-      for (; !dead && I - (kBatch - 1) > B + 1; I -= kBatch)
-        dead = !stream_bwd<T, kBatch>(pack, cm, vb, I, row0, zvec, acc, abort);
-      for (; !dead && I > B + 1; --I) dead = !stream_bwd<T, 1>(pack, cm, vb, I, row0, zvec, acc, abort);
+      if constexpr (sizeof(T) == 4) {
+        cx<float> a0 = {0, 0}, a1 = {0, 0};
+        for (; !dead && I - (kBatch - 1) > B + 1; I -= kBatch)
+          dead = !stream_bwd_wide<kBatch>(pack, cm, vb, I, row0, zvec, a0, a1, abort);
+        for (; !dead && I > B + 1; --I) dead = !stream_bwd_wide<1>(pack, cm, vb, I, row0, zvec, a0, a1, abort);
+        // both halves hold partial sums for entries 2c, 2c+1: add them, then move entry j to lane j
+        a0 = cadd(a0, shfl_xor_c(a0, 32));
+        a1 = cadd(a1, shfl_xor_c(a1, 32));
+        const cx<float> e0 = bcast(a0, lane >> 1), e1 = bcast(a1, lane >> 1);
+        acc = cadd(acc, (lane & 1) ? e1 : e0);
+      } else {
+        for (; !dead && I - (kBatch - 1) > B + 1; I -= kBatch)
+          dead = !stream_bwd<T, kBatch>(pack, cm, vb, I, row0, zvec, acc, abort);
+        for (; !dead && I > B + 1; --I) dead = !stream_bwd<T, 1>(pack, cm, vb, I, row0, zvec, acc, abort);
+      }
       if (has_next && !dead) {
         cx<T> zv;  // the last dependency, read directly (sentinel polling)
         if (!wait_values(zvec + vb + (int64_t)(B + 1) * kTile + row0 + (lane & (kRows - 1)), zv, abort)) {
