@@ -1,5 +1,5 @@
 // Device-side helpers shared by the gfx950 kernels: complex arithmetic, matrix-core tile
-// products, wavefront reductions and bounded flag waits.
+// products, wavefront reductions, publication of block results and bounded waits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -155,7 +155,7 @@ __device__ __forceinline__ int acc_row<double>(int r0, int rb, int r) {
 }
 __device__ __forceinline__ int acc_col(int c0, int cb) { return c0 + cb * 16 + (threadIdx.x & 15); }
 
-// ---- agent-scope flags, publication and bounded waits ----------------------------------------------------------
+// ---- agent-scope flags, publication and bounded waits ---------------------------------------------
 __device__ __forceinline__ int load_flag(const int *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -767,7 +767,7 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
           dead = !stream_fwd<T, 1>(pack, rm, J, row0, yvec + vb + (int64_t)J * kTile + lane, acc, abort);
       }
       if (has_prev && !dead) {
-        // the last dependency is read directly (sentinel polling), not through its flag
+        // the last dependency: its tile is staged in LDS already
         cx<T> y0;
         if (!wait_values(yvec + vb + (int64_t)(B - 1) * kTile + lane, y0, abort)) {
           dead = true;
