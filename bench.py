@@ -266,7 +266,7 @@ def run_serving(args):
     """Continuous-batching server: seeded Poisson arrivals of unit-cube requests (k ~ U[4,16],
     xi in {k, k^2}, n = ceil(k^1.5)+4 cubes per side, p = clamp(ceil(n/17),2,4) subdomains per
     side, Gaussian sources), mixed-precision ORAS FGMRES(50) rtol 1e-6, admission by exact HBM
-    footprint.  Unless --rate is given, the arrival rate is 0.7 x the saturated throughput of a
+    footprint.  Unless --rate is given, the arrival rate is 0.6 x the saturated throughput of a
     closed-loop calibration run (all calibration requests submitted at once).  Reports
     throughput and p50/p99 latency (arrival to result)."""
     import numpy as np
@@ -284,7 +284,7 @@ def run_serving(args):
             srv.wait(t, 600.0)
             srv.release(t)
         sat = len(creqs) / (time.perf_counter() - c0)
-        rate = 0.7 * sat
+        rate = 0.6 * sat
         calib = {"requests": len(creqs), "saturated_solves_per_s": sat, "rate": rate}
     reqs = serving_requests(args.requests, rate, args.seed)
     t0 = time.perf_counter()
@@ -294,11 +294,15 @@ def run_serving(args):
         if wait > 0:
             time.sleep(wait)
         tickets.append((r, srv.submit(r["n"], r["p"], r["k"], r["xi"], r["center"], r["pol"], 0.1)))
+        if len(tickets) % 100 == 0:
+            print("submitted %d/%d" % (len(tickets), len(reqs)), file=sys.stderr, flush=True)
     res = []
     for r, t in tickets:
         out = srv.wait(t, 600.0)
         res.append(out)
         srv.release(t)
+        if len(res) % 100 == 0:  # progress for long runs (stderr; stdout carries one JSON line)
+            print("served %d/%d" % (len(res), len(tickets)), file=sys.stderr, flush=True)
     t1 = time.perf_counter()
     st = srv.stats()
     srv.close()
@@ -334,7 +338,7 @@ def main():
     ap.add_argument("--reps", type=int, default=10, help="applications timed (batching)")
     ap.add_argument("--requests", type=int, default=120, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0,
-                    help="serving: arrivals per second (0 = 0.7 x calibrated saturated throughput)")
+                    help="serving: arrivals per second (0 = 0.6 x calibrated saturated throughput)")
     ap.add_argument("--calib-requests", type=int, default=24, help="serving: calibration requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: requests in flight")
     ap.add_argument("--seed", type=int, default=0)
