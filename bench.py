@@ -266,9 +266,10 @@ def run_serving(args):
     """Continuous-batching server: seeded Poisson arrivals of unit-cube requests (k ~ U[4,16],
     xi in {k, k^2}, n = ceil(k^1.5)+4 cubes per side, p = clamp(ceil(n/17),2,4) subdomains per
     side, Gaussian sources), mixed-precision ORAS FGMRES(50) rtol 1e-6, admission by exact HBM
-    footprint.  Unless --rate is given, the arrival rate is 0.6 x the saturated throughput of a
-    closed-loop calibration run (all calibration requests submitted at once).  Reports
-    throughput and p50/p99 latency (arrival to result)."""
+    footprint.  Arrivals at a fixed rate (--rate, default 1.5/s; with --rate 0, 0.6 x the
+    throughput of a closed-loop calibration run, all calibration requests submitted at once).
+    Reports throughput and p50/p99 latency (arrival to result), and any request that failed or
+    did not converge."""
     import numpy as np
 
     from mx_inputs import serving_requests
@@ -308,6 +309,11 @@ def run_serving(args):
     srv.close()
     lat = np.array([x["t_total"] for x in res])
     ok = all(x["status"] == 0 and x["converged"] for x in res)
+    failed = [{"request": i, "n": r["n"], "p": r["p"], "k": r["k"], "xi": r["xi"],
+               "status": x["status"], "converged": x["converged"], "iters": x["iters"],
+               "relres": x["relres_true"], "error": x.get("error", "")}
+              for i, ((r, _), x) in enumerate(zip(tickets, res))
+              if x["status"] != 0 or not x["converged"]]
     return {
         "metric": "p50/p99 solve latency", "value": float(np.percentile(lat, 50)), "unit": "s",
         "n_gpus": 1, "steps": len(res), "warmup": 0, "ms_per_step": (t1 - t0) / len(res) * 1e3,
@@ -322,6 +328,7 @@ def run_serving(args):
         "mean_queue_s": float(np.mean([x["t_queue"] for x in res])),
         "calibration": calib,
         "server": st,
+        "failed": failed[:20],
     }
 
 
@@ -337,8 +344,9 @@ def main():
                     help="c64: complex64 factors and SpMV values inside FP64 flexible GMRES")
     ap.add_argument("--reps", type=int, default=10, help="applications timed (batching)")
     ap.add_argument("--requests", type=int, default=120, help="serving: number of requests")
-    ap.add_argument("--rate", type=float, default=0.0,
-                    help="serving: arrivals per second (0 = 0.6 x calibrated saturated throughput)")
+    ap.add_argument("--rate", type=float, default=1.5,
+                    help="serving: arrivals per second (0 = 0.6 x a closed-loop calibration's "
+                         "throughput)")
     ap.add_argument("--calib-requests", type=int, default=24, help="serving: calibration requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: requests in flight")
     ap.add_argument("--seed", type=int, default=0)

@@ -199,6 +199,11 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_p
 void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
                   const mx_precond_opts *opts, mx_precond *P, PrecondPlan &plan);
 void precond_stage(mx_precond *P, PrecondPlan &plan);
+// device bytes of the full factor tiles and staged entries of all subdomains at once (the
+// tile-pool cap that makes the factorisation run in one group)
+size_t precond_one_group_bytes(const mx_precond *P, const PrecondPlan &plan);
+// frees every device buffer of P (host state kept: P can be materialised again from its plan)
+void precond_release_device(mx_precond *P);
 void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st);
 size_t matrix_device_bytes(const mx_matrix *A);
 size_t gmres_device_bytes(int64_t n, int restart, bool flexible);

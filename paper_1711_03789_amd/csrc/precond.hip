@@ -1502,6 +1502,22 @@ static void upload_metadata(mx_precond *P, PrecondPlan &plan) {
   P->d_cptr.upload(plan.cptr);
 }
 
+size_t precond_one_group_bytes(const mx_precond *P, const PrecondPlan &plan) {
+  const size_t esz = P->prec == MX_C128 ? 16 : 8;
+  return (size_t)P->tiles_total * kTileElems * esz + (size_t)(plan.scat.back() - plan.scat.front()) * 24;
+}
+
+void precond_release_device(mx_precond *P) {
+  for (DevBuf *b : {&P->d_sub_nb, &P->d_sub_brow_base, &P->d_sub_tile_base, &P->d_sub_vec_base,
+                    &P->d_brow_off, &P->d_bfirst, &P->d_blast, &P->pool, &P->d_off_all, &P->d_val_all,
+                    &P->pack, &P->d_rmeta, &P->d_cmeta, &P->d_cptr, &P->d_r, &P->d_y, &P->d_z,
+                    &P->d_glob, &P->d_src, &P->d_sum_ptr, &P->d_sum_idx, &P->d_ctrl, &P->d_sched_sub,
+                    &P->d_sched_blk, &P->d_panel_pref, &P->d_update_pref, &P->d_intra_pref,
+                    &P->d_next_pref, &P->d_rest_pref})
+    b->release();
+  P->staged = false;
+}
+
 // Optional middle step: the host-to-device copies of the device half, on a private stream that
 // does not wait for other streams (so another host thread can run it while the device works).
 // Buffers are allocated unscoped: they outlive that stream.

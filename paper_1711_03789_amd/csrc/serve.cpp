@@ -51,9 +51,12 @@ struct Server {
   uint64_t next_id = 1;
   bool stop = false;
   int admitted = 0, max_admitted = 0;
+  uint64_t finished = 0;  // device phases ended (successfully or not)
   std::vector<std::thread> workers;
 
   void run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R);
+  void device_phase(mx_ctx *ctx, hipStream_t st, SrvRequest *R, mx_matrix *A, mx_precond *P,
+                    PrecondPlan &plan, const std::vector<double> &f, int64_t E);
   void worker();
 };
 
@@ -83,57 +86,100 @@ void Server::run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
   R->res.footprint_bytes = need;
   R->t_host_done = wall();
   if (need > budget) fail(MX_EHBM, "request footprint exceeds the server's HBM budget");
-  // ---- admission by footprint ----
-  {
-    std::unique_lock<std::mutex> lk(mu);
-    cv_mem.wait(lk, [&] { return used + need <= budget; });
-    used += need;
-    peak = std::max(peak, used);
-    ++admitted;
-    max_admitted = std::max(max_admitted, admitted);
-    R->t_admit = wall();
-  }
-  struct Release {
-    Server *s;
-    uint64_t n;
-    ~Release() {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->used -= n;
-      --s->admitted;
-      s->cv_mem.notify_all();
+  // The factorisation gets the request's own footprint as its tile-pool cap (one group), instead
+  // of sizing itself from what the device has free at that moment, which other requests share.
+  P->pool_limit = (int64_t)precond_one_group_bytes(P.get(), plan);
+  // Admission by footprint, then the device phase.  The footprints are exact, but freed memory
+  // held by the block cache and by the stream-ordered pools of other slots is not in the
+  // budget: a device allocation can still fail.  Then the reservation is returned, this slot's
+  // stream drained, the caches emptied, and the request waits for another one to finish before
+  // it tries again (at most kMemRetries times; alone on the device it gives up).
+  constexpr int kMemRetries = 8;
+  for (int attempt = 0;; ++attempt) {
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_mem.wait(lk, [&] { return used + need <= budget; });
+      used += need;
+      peak = std::max(peak, used);
+      ++admitted;
+      max_admitted = std::max(max_admitted, admitted);
+      if (attempt == 0) R->t_admit = wall();
     }
-  } rel{this, need};
-  // ---- device phase, all on this slot's stream ----
-  {
-    AllocScope scope(st);
-    matrix_upload(A.get());
-    precond_materialize(P.get(), plan, st);
-    DevBuf b, x;
-    b.alloc(16 * (size_t)E);
-    x.alloc(16 * (size_t)E);
-    MX_HIP(hipMemcpyAsync(b.p, f.data(), 16 * (size_t)E, hipMemcpyHostToDevice, st));
-    MX_HIP(hipMemsetAsync(x.p, 0, 16 * (size_t)E, st));
-    mx_gmres_opts go{};
-    go.restart = opts.restart;
-    go.max_iters = opts.max_iters;
-    go.flexible = opts.flexible;
-    go.spmv_c64 = opts.spmv_c64;
-    go.rtol = opts.rtol;
-    mx_gmres_stats gs{};
-    gmres_run(ctx, A.get(), P.get(), b.p, x.p, &go, &gs, nullptr, st);
-    R->x.resize(2 * E);
-    MX_HIP(hipMemcpyAsync(R->x.data(), x.p, 16 * (size_t)E, hipMemcpyDeviceToHost, st));
-    MX_HIP(hipStreamSynchronize(st));
-    R->res.iters = gs.iters;
-    R->res.converged = gs.converged;
-    R->res.relres_true = gs.relres_true;
-    P.reset();
-    A.reset();
+    struct Release {
+      Server *s;
+      uint64_t n;
+      ~Release() {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->used -= n;
+        --s->admitted;
+        ++s->finished;
+        s->cv_mem.notify_all();
+      }
+    };
+    int others = 0;
+    uint64_t seen = 0;
+    try {
+      Release rel{this, need};
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        others = admitted - 1;
+        seen = finished;
+      }
+      device_phase(ctx, st, R, A.get(), P.get(), plan, f, E);
+      return;
+    } catch (const Error &e) {
+      if (e.code != MX_ENOMEM || attempt >= kMemRetries || others == 0) throw;
+    }
+    (void)hipStreamSynchronize(st);
+    precond_release_device(P.get());
+    A->rowptr.release();
+    A->col.release();
+    A->val.release();
+    A->val32.release();
     ctx->krylov.buf.release();
-    b.release();
-    x.release();
-    MX_HIP(hipStreamSynchronize(st));
+    big_trim(device);
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+    std::unique_lock<std::mutex> lk(mu);
+    // `finished` counts this attempt too: wait for one more (another request) or an idle device
+    cv_mem.wait_for(lk, std::chrono::seconds(10), [&] { return finished > seen + 1 || admitted == 0; });
   }
+}
+
+void Server::device_phase(mx_ctx *ctx, hipStream_t st, SrvRequest *R, mx_matrix *A, mx_precond *P,
+                          PrecondPlan &plan, const std::vector<double> &f, int64_t E) {
+  AllocScope scope(st);
+  matrix_upload(A);
+  precond_materialize(P, plan, st);
+  DevBuf b, x;
+  b.alloc(16 * (size_t)E);
+  x.alloc(16 * (size_t)E);
+  MX_HIP(hipMemcpyAsync(b.p, f.data(), 16 * (size_t)E, hipMemcpyHostToDevice, st));
+  MX_HIP(hipMemsetAsync(x.p, 0, 16 * (size_t)E, st));
+  mx_gmres_opts go{};
+  go.restart = opts.restart;
+  go.max_iters = opts.max_iters;
+  go.flexible = opts.flexible;
+  go.spmv_c64 = opts.spmv_c64;
+  go.rtol = opts.rtol;
+  mx_gmres_stats gs{};
+  gmres_run(ctx, A, P, b.p, x.p, &go, &gs, nullptr, st);
+  R->x.resize(2 * E);
+  MX_HIP(hipMemcpyAsync(R->x.data(), x.p, 16 * (size_t)E, hipMemcpyDeviceToHost, st));
+  MX_HIP(hipStreamSynchronize(st));
+  R->res.iters = gs.iters;
+  R->res.converged = gs.converged;
+  R->res.relres_true = gs.relres_true;
+  // device memory of the request goes back before its reservation does
+  precond_release_device(P);
+  A->rowptr.release();
+  A->col.release();
+  A->val.release();
+  A->val32.release();
+  ctx->krylov.buf.release();
+  b.release();
+  x.release();
+  MX_HIP(hipStreamSynchronize(st));
 }
 
 void Server::worker() {
