@@ -190,7 +190,8 @@ int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx
 /* The two halves of mx_precond_setup, so that the host half of one preconditioner can run on
  * another host thread while the device works on an earlier one.  mx_precond_plan does all host
  * work (local matrices, orderings, tile layout, schedules; no device work, A needs no device
- * copy) and returns the exact peak device bytes that materialising it will allocate;
+ * copy; ctx may be NULL, and the device is then bound by stage or materialize) and returns the
+ * exact peak device bytes that materialising it will allocate;
  * mx_precond_materialize uploads and factors on `stream` (NULL = null stream) and returns when
  * done.  A planned, not yet materialised preconditioner may only be materialised or destroyed.
  * Errors: as mx_precond_setup. */

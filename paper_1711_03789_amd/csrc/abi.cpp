@@ -270,8 +270,8 @@ int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx
 int mx_precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
                     const mx_precond_opts *opts, mx_precond **out, uint64_t *device_bytes) {
   MX_GUARD({
-    MX_REQUIRE(ctx && A && m && p && opts && out, "NULL argument");
-    bind_device(ctx->device);
+    MX_REQUIRE(A && m && p && opts && out, "NULL argument");
+    if (ctx) bind_device(ctx->device);
     auto P = std::make_unique<mx_precond>();
     P->plan = std::make_unique<mx::PrecondPlan>();
     mx::precond_plan(ctx, A, m, p, opts, P.get(), *P->plan);
@@ -285,8 +285,10 @@ int mx_precond_stage(mx_ctx *ctx, mx_precond *P) {
     MX_REQUIRE(ctx && P, "NULL argument");
     MX_REQUIRE(P->plan, "preconditioner is already materialised");
     MX_REQUIRE(!P->staged, "preconditioner is already staged");
-    MX_REQUIRE(ctx->device == P->device, "preconditioner was planned for another device");
+    MX_REQUIRE(P->device < 0 || ctx->device == P->device, "preconditioner was planned for another device");
     bind_device(ctx->device);
+    P->device = ctx->device;
+    mx::set_sweep_grid(P, ctx->cus);
     mx::precond_stage(P, *P->plan);
   });
 }
@@ -295,8 +297,10 @@ int mx_precond_materialize(mx_ctx *ctx, mx_precond *P, void *stream) {
   MX_GUARD({
     MX_REQUIRE(ctx && P, "NULL argument");
     MX_REQUIRE(P->plan, "preconditioner is already materialised");
-    MX_REQUIRE(ctx->device == P->device, "preconditioner was planned for another device");
+    MX_REQUIRE(P->device < 0 || ctx->device == P->device, "preconditioner was planned for another device");
     bind_device(ctx->device);
+    P->device = ctx->device;
+    mx::set_sweep_grid(P, ctx->cus);
     mx::precond_materialize(P, *P->plan, (hipStream_t)stream);
     P->plan.reset();
   });

@@ -179,7 +179,7 @@ struct mx_precond {
   mx::DevBuf d_glob, d_src, d_sum_ptr, d_sum_idx;
   mx::DevBuf d_ctrl, d_sched_sub, d_sched_blk;
   mx::DevBuf d_panel_pref, d_update_pref, d_intra_pref, d_next_pref, d_rest_pref;
-  int n_items = 0, trsv_grid = 0;
+  int n_items = 0, trsv_grid = 0, sweep_grid = 0;
   mx_precond_info info{};
   // optional per-launch timing of the sweep kernel
   bool timing = false;
@@ -199,6 +199,8 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_p
 void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
                   const mx_precond_opts *opts, mx_precond *P, PrecondPlan &plan);
 void precond_stage(mx_precond *P, PrecondPlan &plan);
+// persistent sweep grid from the requested sweep_grid (0: one workgroup per compute unit)
+void set_sweep_grid(mx_precond *P, int cus);
 // device bytes of the full factor tiles and staged entries of all subdomains at once (the
 // tile-pool cap that makes the factorisation run in one group)
 size_t precond_one_group_bytes(const mx_precond *P, const PrecondPlan &plan);

@@ -1153,6 +1153,11 @@ void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_
   precond_materialize(P, plan, st);
 }
 
+void set_sweep_grid(mx_precond *P, int cus) {
+  const int grid = P->sweep_grid > 0 ? P->sweep_grid : cus;
+  P->trsv_grid = std::max(1, std::min(P->n_items / 2, grid));
+}
+
 void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_partition *ph,
                   const mx_precond_opts *opts, mx_precond *P, PrecondPlan &plan) {
   const Mesh &m = mh->m;
@@ -1164,7 +1169,7 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   P->kind = opts->kind;
   P->prec = opts->precision;
   P->E = m.ne;
-  P->device = ctx->device;
+  P->device = ctx ? ctx->device : -1;
   int s0 = opts->sub_begin, s1 = opts->sub_end;
   if (s0 == 0 && s1 == 0) s1 = part.nsub;
   if (s0 < 0 || s1 > part.nsub || s0 >= s1) fail(MX_EINVAL, "subdomain share out of range");
@@ -1450,19 +1455,11 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
       sched_blk.push_back(it.b);
     }
   P->n_items = (int)sched_sub.size();
-  {
-    // persistent sweeps: as many workgroups as can be resident at once
-    int per_cu = 1;
-    if (P->prec == MX_C128)
-      MX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<double, true>, kSweepThreads, 0));
-    else
-      MX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<float, true>, kSweepThreads, 0));
-    // one workgroup per CU: a second co-resident workgroup streaming tiles delays the
-    // dependency chain of the first one more than it adds bandwidth (measured)
-    (void)per_cu;
-    int grid = opts->sweep_grid > 0 ? opts->sweep_grid : ctx->cus;
-    P->trsv_grid = std::max(1, std::min(P->n_items / 2, grid));
-  }
+  // persistent sweeps: one workgroup per CU (a second co-resident workgroup streaming tiles delays
+  // the dependency chain of the first one more than it adds bandwidth, measured); without a
+  // context the grid is chosen when the preconditioner is materialised
+  P->sweep_grid = opts->sweep_grid;
+  if (ctx) set_sweep_grid(P, ctx->cus);
   const double t1 = now_s();
   P->info.t_host_setup = t1 - t0;
   const size_t esz = P->prec == MX_C128 ? 16 : 8;

@@ -191,8 +191,14 @@ def _ptr(a):
 def _stream(stream):
     if stream is None:
         import torch
+        if not torch.cuda.is_available():
+            return None  # the library reports the missing device itself
         return torch.cuda.current_stream().cuda_stream
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def _h(obj):
+    return obj.h if obj is not None else None
 
 
 class Context:
@@ -336,7 +342,7 @@ class Precond:
         self.device_bytes = None
         if plan_only:
             nb = C.c_uint64()
-            _check(_lib.mx_precond_plan(ctx.h, A.h, mesh.h, part.h, C.byref(o), C.byref(h),
+            _check(_lib.mx_precond_plan(_h(ctx), A.h, mesh.h, part.h, C.byref(o), C.byref(h),
                                         C.byref(nb)))
             self.device_bytes = nb.value
         else:
@@ -362,7 +368,7 @@ class Precond:
         return inf.as_dict()
 
     def apply(self, v, z, stream=None):
-        _check(_lib.mx_precond_apply(self.ctx.h, self.h, _ptr(v), _ptr(z), _stream(stream)))
+        _check(_lib.mx_precond_apply(_h(self.ctx), self.h, _ptr(v), _ptr(z), _stream(stream)))
 
     def check(self):
         _check(_lib.mx_precond_check(self.h))
@@ -370,7 +376,7 @@ class Precond:
     def autotune(self, stream=None):
         """Picks the fastest sweep grid; returns (grid, ms per application)."""
         g, ms = C.c_int32(), C.c_double()
-        _check(_lib.mx_precond_autotune(self.ctx.h, self.h, _stream(stream), C.byref(g), C.byref(ms)))
+        _check(_lib.mx_precond_autotune(_h(self.ctx), self.h, _stream(stream), C.byref(g), C.byref(ms)))
         return g.value, ms.value
 
     def sweep_timing(self, enable):

@@ -150,3 +150,26 @@ def test_errors_are_reported():
         mx.Partition(m, 2, 2, 2, 1, cx=[0, 3, 2])
     with pytest.raises(mx.MxError):
         mx.Partition(m, 5, 1, 1, 1)
+
+
+def test_plan_needs_no_device():
+    """The host half of the setup runs without a context (and so without a GPU): it returns the
+    device footprint, is deterministic, and a planned preconditioner refuses to be used before it
+    is materialised; bad schedule options are refused at planning time."""
+    m = mx.Mesh(9, 8, 7)
+    p = mx.Partition(m, 2, 2, 2, 2)
+    A = mx.Matrix(None, m, 4.0, 16.0)
+    sizes = set()
+    for kind in ("oras", "as"):
+        for prec in ("c128", "c64"):
+            P1 = mx.Precond(None, A, m, p, kind, precision=prec, plan_only=True)
+            P2 = mx.Precond(None, A, m, p, kind, precision=prec, plan_only=True)
+            assert P1.device_bytes > 0 and P1.device_bytes == P2.device_bytes
+            sizes.add(P1.device_bytes)
+            with pytest.raises(mx.MxError):
+                P1.apply(None, None)
+    assert len(sizes) == 4  # kinds and precisions differ in footprint
+    for bad in (dict(schedule=7), dict(schedule="lookahead", width=5)):
+        with pytest.raises(mx.MxError) as ei:
+            mx.Precond(None, A, m, p, "oras", plan_only=True, **bad)
+        assert ei.value.code == mx.MX_EINVAL
