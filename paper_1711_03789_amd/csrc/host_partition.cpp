@@ -124,7 +124,14 @@ struct LEntry {
 };
 
 static void merge_row(std::vector<LEntry> &ent) {
-  std::stable_sort(ent.begin(), ent.end(), [](const LEntry &a, const LEntry &b) { return a.col < b.col; });
+  // stable insertion sort by column: rows hold a few dozen entries, and equal columns keep their
+  // order, so the sums below are taken in push order (as a stable sort would)
+  for (size_t i = 1; i < ent.size(); ++i) {
+    const LEntry x = ent[i];
+    size_t j = i;
+    for (; j > 0 && ent[j - 1].col > x.col; --j) ent[j] = ent[j - 1];
+    ent[j] = x;
+  }
   size_t w = 0;
   for (size_t r = 0; r < ent.size(); ++r) {
     if (w > 0 && ent[w - 1].col == ent[r].col) {
