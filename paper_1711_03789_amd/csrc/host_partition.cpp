@@ -197,30 +197,28 @@ void local_impedance(const Mesh &m, const KuhnElements &ke, double k, double xi,
   const int64_t n = (int64_t)set.size();
   for (int64_t i = 0; i < n; ++i) g2l[set[i]] = (int32_t)i;
   for (int32_t t : tets) tet_stamp[t] = stamp;
-  // faces of the subdomain's tetrahedra that appear once: the boundary of the subdomain
-  struct FaceRec {
-    std::array<int32_t, 3> v;
-  };
-  std::vector<FaceRec> faces;
-  faces.reserve(4 * tets.size());
+  // faces of the subdomain's tetrahedra that appear once: the boundary of the subdomain.  The
+  // other tetrahedron on a face (if any) is the one besides t that contains the face's first edge
+  // and its third vertex; the face is on the boundary unless that tetrahedron is in the
+  // subdomain.  Sorted by vertex triple.
+  std::vector<std::array<int32_t, 3>> bfaces;
   for (int32_t t : tets) {
     const int32_t *tv = &m.tet_vert[4 * (int64_t)t];
     for (int f = 0; f < 4; ++f) {
       std::array<int32_t, 3> v = {tv[kLocalFace[f][0]], tv[kLocalFace[f][1]], tv[kLocalFace[f][2]]};
       std::sort(v.begin(), v.end());
-      faces.push_back({v});
+      const int32_t e = m.edge_id(v[0], v[1]);
+      bool inside = false;
+      for (int64_t q = m.et_ptr[e]; q < m.et_ptr[e + 1] && !inside; ++q) {
+        const int32_t u = m.et_tet[q];
+        if (u == t || tet_stamp[u] != stamp) continue;
+        const int32_t *uv = &m.tet_vert[4 * (int64_t)u];
+        inside = uv[0] == v[2] || uv[1] == v[2] || uv[2] == v[2] || uv[3] == v[2];
+      }
+      if (!inside && !(bc == MX_BC_PEC && on_box_boundary(m, v.data()))) bfaces.push_back(v);
     }
   }
-  std::sort(faces.begin(), faces.end(), [](const FaceRec &a, const FaceRec &b) { return a.v < b.v; });
-  std::vector<std::array<int32_t, 3>> bfaces;
-  for (size_t i = 0; i < faces.size();) {
-    size_t j = i + 1;
-    while (j < faces.size() && faces[j].v == faces[i].v) ++j;
-    if (j - i == 1) {
-      if (!(bc == MX_BC_PEC && on_box_boundary(m, faces[i].v.data()))) bfaces.push_back(faces[i].v);
-    }
-    i = j;
-  }
+  std::sort(bfaces.begin(), bfaces.end());
   // local row -> boundary faces incidence
   const double cb = -(xi >= 0 ? 1.0 : -1.0) * k;
   std::vector<std::array<int32_t, 3>> fedge(bfaces.size());
