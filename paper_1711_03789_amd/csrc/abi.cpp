@@ -237,8 +237,7 @@ int mx_local_problem(const mx_mesh *m, const mx_matrix *A, const mx_partition *p
       mx::KuhnElements ke;
       mx::kuhn_elements(M.lx / M.nx, M.ly / M.ny, M.lz / M.nz, ke);
       std::vector<int32_t> tstamp(M.nt, -1);
-      mx::local_impedance(M, ke, A->k, opts->xi_prec, A->bc, p->p.tets[l], sets[l], a, g2l,
-                          tstamp, l);
+      mx::local_impedance(M, ke, A->k, opts->xi_prec, A->bc, p->p.tets[l], sets[l], a, g2l, tstamp);
     } else {
       mx::local_minor(M, A->h, A->bc, sets[l], a, g2l);
     }

@@ -192,11 +192,26 @@ static bool on_box_boundary(const Mesh &m, const int32_t v[3]) {
 
 void local_impedance(const Mesh &m, const KuhnElements &ke, double k, double xi, int bc,
                      const std::vector<int32_t> &tets, const std::vector<int32_t> &set,
-                     LocalCSR &out, std::vector<int32_t> &g2l, std::vector<int32_t> &tet_stamp,
-                     int32_t stamp) {
+                     LocalCSR &out, std::vector<int32_t> &g2l, std::vector<int32_t> &tet_pos) {
   const int64_t n = (int64_t)set.size();
+  const int32_t nt = (int32_t)tets.size();
   for (int64_t i = 0; i < n; ++i) g2l[set[i]] = (int32_t)i;
-  for (int32_t t : tets) tet_stamp[t] = stamp;
+  // tet_pos[t] = position of t in `tets`; an entry left by an earlier subdomain fails the check
+  for (int32_t j = 0; j < nt; ++j) tet_pos[tets[j]] = j;
+  auto local_tet = [&](int32_t t) {
+    const int32_t j = tet_pos[t];
+    return j >= 0 && j < nt && tets[j] == t ? j : -1;
+  };
+  // per tetrahedron of the subdomain: local ids and signs of its 6 edges
+  std::vector<std::array<int32_t, 6>> tle(nt);
+  std::vector<std::array<double, 6>> tsg(nt);
+  for (int32_t j = 0; j < nt; ++j) {
+    const int64_t t = tets[j];
+    for (int b = 0; b < 6; ++b) {
+      tle[j][b] = g2l[m.tet_edge[6 * t + b]];
+      tsg[j][b] = m.tet_sign[6 * t + b];
+    }
+  }
   // faces of the subdomain's tetrahedra that appear once: the boundary of the subdomain.  The
   // other tetrahedron on a face (if any) is the one besides t that contains the face's first edge
   // and its third vertex; the face is on the boundary unless that tetrahedron is in the
@@ -211,7 +226,7 @@ void local_impedance(const Mesh &m, const KuhnElements &ke, double k, double xi,
       bool inside = false;
       for (int64_t q = m.et_ptr[e]; q < m.et_ptr[e + 1] && !inside; ++q) {
         const int32_t u = m.et_tet[q];
-        if (u == t || tet_stamp[u] != stamp) continue;
+        if (u == t || local_tet(u) < 0) continue;
         const int32_t *uv = &m.tet_vert[4 * (int64_t)u];
         inside = uv[0] == v[2] || uv[1] == v[2] || uv[2] == v[2] || uv[3] == v[2];
       }
@@ -254,14 +269,14 @@ void local_impedance(const Mesh &m, const KuhnElements &ke, double k, double xi,
     int32_t g = set[i];
     ent.clear();
     for (int64_t q = m.et_ptr[g]; q < m.et_ptr[g + 1]; ++q) {
-      int32_t t = m.et_tet[q];
-      if (tet_stamp[t] != stamp) continue;
-      int a = m.et_loc[q], pp = t % 6;
-      double sa = m.tet_sign[6 * (int64_t)t + a];
+      const int32_t t = m.et_tet[q];
+      const int32_t j = local_tet(t);
+      if (j < 0) continue;
+      const int a = m.et_loc[q], pp = t % 6;
+      const double sa = tsg[j][a];
       for (int b = 0; b < 6; ++b) {
-        double s = sa * m.tet_sign[6 * (int64_t)t + b];
-        ent.push_back({g2l[m.tet_edge[6 * (int64_t)t + b]], s * (ke.K[pp][a][b] + sre * ke.M[pp][a][b]),
-                       s * sim * ke.M[pp][a][b]});
+        const double s = sa * tsg[j][b];
+        ent.push_back({tle[j][b], s * (ke.K[pp][a][b] + sre * ke.M[pp][a][b]), s * sim * ke.M[pp][a][b]});
       }
     }
     for (int64_t q = rf_ptr[i]; q < rf_ptr[i + 1]; ++q) {

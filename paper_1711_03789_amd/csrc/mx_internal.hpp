@@ -167,10 +167,11 @@ struct LocalCSR {  // a local matrix in local (sorted global id) numbering
 void local_minor(const Mesh &m, const HostCSR &A, int bc, const std::vector<int32_t> &set,
                  LocalCSR &out, std::vector<int32_t> &g2l_scratch);
 // ORAS local impedance problem on the tetrahedra `tets` (local DOFs `set`).
+// Scratch: g2l_scratch[E] all -1 on entry and exit; tet_pos[T] any contents (caller-owned, -1
+// initially), reusable across calls.
 void local_impedance(const Mesh &m, const KuhnElements &ke, double k, double xi, int bc,
                      const std::vector<int32_t> &tets, const std::vector<int32_t> &set,
-                     LocalCSR &out, std::vector<int32_t> &g2l_scratch,
-                     std::vector<int32_t> &tet_stamp, int32_t stamp);
+                     LocalCSR &out, std::vector<int32_t> &g2l_scratch, std::vector<int32_t> &tet_pos);
 // Reverse Cuthill-McKee of the pattern of `a` (perm[new] = old).
 void rcm_order(const LocalCSR &a, std::vector<int32_t> &perm);
 

@@ -1199,8 +1199,7 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
     if (opts->kind == MX_ORAS) tstamp.assign(m.nt, -1);
     for (int64_t l; (l = next()) >= 0;) {
       if (opts->kind == MX_ORAS)
-        local_impedance(m, ke, A->k, opts->xi_prec, A->bc, part.tets[s0 + l], sets[l], loc[l], g2l,
-                        tstamp, (int32_t)l);
+        local_impedance(m, ke, A->k, opts->xi_prec, A->bc, part.tets[s0 + l], sets[l], loc[l], g2l, tstamp);
       else
         local_minor(m, A->h, A->bc, sets[l], loc[l], g2l);
       build_skyline(loc[l], P->sky[l]);
