@@ -87,55 +87,64 @@ __global__ void k_combine(int64_t n, const cx<double> *__restrict__ V, int64_t l
 }
 
 // Block sum of 4 complex values over 256 threads; result valid in thread 0.
-__device__ inline void block_sum4(cx<double> v[4], cx<double> (*red)[4]) {
+template <int C>
+__device__ inline void block_sum(cx<double> v[C], cx<double> (*red)[C]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int c = 0; c < 4; ++c)
+  for (int c = 0; c < C; ++c)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v[c] = cadd(v[c], shfl_xor_c(v[c], o));
   __syncthreads();
   if (lane == 0)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) red[w][c] = v[c];
+    for (int c = 0; c < C; ++c) red[w][c] = v[c];
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) v[c] = cadd(cadd(red[0][c], red[1][c]), cadd(red[2][c], red[3][c]));
+    for (int c = 0; c < C; ++c) v[c] = cadd(cadd(red[0][c], red[1][c]), cadd(red[2][c], red[3][c]));
 }
 
 // partial[q * G + b] = sum_{i in block b} conj(V_q[i]) w[i], q < nv (mode 0), or
-// partial[b] = sum |w_i|^2 (mode 1, nv ignored).  Block b covers a fixed row range.
+// partial[b] = sum |w_i|^2 (mode 1, nv ignored).  Block b covers a fixed row range; eight basis
+// vectors per pass over it, so w is read once per eight.
+constexpr int kDotVecs = 8;
+// blocks of the partial dot products: rows split into at most 1024 ranges of at least 1024
+static inline int dot_blocks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 1023) / 1024));
+}
 __global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const cx<double> *__restrict__ V,
                                                      int64_t ldv, int nv,
                                                      const cx<double> *__restrict__ w,
                                                      cx<double> *__restrict__ partial, int mode) {
-  __shared__ cx<double> red[4][4];
+  __shared__ cx<double> red[4][kDotVecs];
   const int G = gridDim.x, b = blockIdx.x;
   const int64_t chunk = (n + G - 1) / G;
   const int64_t i0 = b * chunk, i1 = std::min(n, i0 + chunk);
   if (mode == 1) {
-    cx<double> v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    cx<double> v[1] = {{0, 0}};
     for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) v[0].re += w[i].re * w[i].re + w[i].im * w[i].im;
-    block_sum4(v, red);
+    block_sum<1>(v, reinterpret_cast<cx<double>(*)[1]>(red));
     if (threadIdx.x == 0) partial[b] = v[0];
     return;
   }
-  for (int q0 = 0; q0 < nv; q0 += 4) {
-    cx<double> v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  for (int q0 = 0; q0 < nv; q0 += kDotVecs) {
+    cx<double> v[kDotVecs];
+#pragma unroll
+    for (int c = 0; c < kDotVecs; ++c) v[c] = {0, 0};
     for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
       const cx<double> wi = w[i];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < kDotVecs; ++c)
         if (q0 + c < nv) {
           const cx<double> a = V[(q0 + c) * ldv + i];
           v[c].re += a.re * wi.re + a.im * wi.im;
           v[c].im += a.re * wi.im - a.im * wi.re;
         }
     }
-    block_sum4(v, red);
+    block_sum<kDotVecs>(v, red);
     if (threadIdx.x == 0)
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < kDotVecs; ++c)
         if (q0 + c < nv) partial[(q0 + c) * G + b] = v[c];
   }
 }
@@ -259,7 +268,7 @@ size_t matrix_device_bytes(const mx_matrix *A) {
 
 size_t gmres_device_bytes(int64_t n, int restart, bool flexible) {
   const size_t vb = ((size_t)n * 16 + 255) & ~(size_t)255;
-  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 1023) / 1024));
+  const int G = dot_blocks(n);
   return vb * (restart + 1 + (flexible ? restart : 0) + 4) + (size_t)G * (restart + 1) * 16 +
          (size_t)(restart + 1) * restart * 16 + 64 * (size_t)(restart + 1) + 8192;
 }
@@ -315,7 +324,7 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
   const int m = o->restart;
   if (m < 1 || o->max_iters < 0 || o->fixed_iters < 0 || !(o->rtol >= 0)) fail(MX_EINVAL, "bad GMRES options");
   const bool flex = o->flexible != 0, c64 = o->spmv_c64 != 0;
-  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 1023) / 1024));
+  const int G = dot_blocks(n);
   // workspace layout (bytes, 256-aligned)
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t vb = al((size_t)n * 16);
