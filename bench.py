@@ -350,6 +350,9 @@ def main():
     ap.add_argument("--calib-requests", type=int, default=24, help="serving: calibration requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: requests in flight")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--overlap-factor", type=int, default=0, choices=[0, 1],
+                    help="1: the next instance's factorisation also runs on the second host "
+                         "thread (its own non-blocking stream), overlapping the current GMRES")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world > 1:
@@ -394,6 +397,7 @@ def main():
     # tile layout) runs on a second host thread while the device factors and solves the current
     # one; every kernel stays on this thread, in order.  At most two instances are alive at once.
     ctx_host = mx.Context(0)
+    fstream = torch.cuda.Stream() if args.overlap_factor else None  # default priority
 
     def prepare(mesh, part, kind, e):
         xi = w.k ** e
@@ -403,6 +407,8 @@ def main():
         t1 = time.perf_counter()
         P = mx.Precond(ctx_host, A, mesh, part, kind, precision=args.precision, plan_only=True)
         P.stage(ctx_host)  # host-to-device copies, also overlapping the current instance
+        if fstream is not None:
+            P.materialize(ctx_host, fstream)  # returns once its factor tiles are complete
         t2 = time.perf_counter()
         return A, P, xi, t1 - t0, t2 - t1
 
@@ -419,7 +425,8 @@ def main():
                 A, P, xi, t_asm, t_pre = fut.result()
                 if idx + 1 < len(inst):
                     fut = ex.submit(prepare, mesh, part, inst[idx + 1][0], inst[idx + 1][1])
-                P.materialize(ctx)
+                if fstream is None:
+                    P.materialize(ctx)
                 t2 = time.perf_counter()
                 if record:
                     P.sweep_timing(True)
@@ -504,7 +511,10 @@ def main():
             "factor": t_factor / args.steps,
             "gmres": t_gmres / args.steps,
             "note": "assemble and precond_host of the next instance run on a second host thread "
-                    "while the device factors and solves the current one"},
+                    "while the device factors and solves the current one" +
+                    ("; the next instance's factorisation too, on its own stream (factor times "
+                     "then include contention with the current GMRES)" if fstream is not None
+                     else "")},
         "solves": [{k: r[k] for k in ("kind", "xi", "iters", "converged", "relres", "t_gmres",
                                       "t_factor")} for r in recs[0][1]],
         "all_converged": converged,
