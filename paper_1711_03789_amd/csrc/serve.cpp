@@ -57,6 +57,7 @@ struct Server {
   void run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R);
   void device_phase(mx_ctx *ctx, hipStream_t st, SrvRequest *R, mx_matrix *A, mx_precond *P,
                     PrecondPlan &plan, const std::vector<double> &f, int64_t E);
+  void release_request(mx_ctx *ctx, hipStream_t st, mx_matrix *A, mx_precond *P);
   void worker();
 };
 
@@ -91,9 +92,10 @@ void Server::run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
   P->pool_limit = (int64_t)precond_one_group_bytes(P.get(), plan);
   // Admission by footprint, then the device phase.  The footprints are exact, but freed memory
   // held by the block cache and by the stream-ordered pools of other slots is not in the
-  // budget: a device allocation can still fail.  Then the reservation is returned, this slot's
-  // stream drained, the caches emptied, and the request waits for another one to finish before
-  // it tries again (at most kMemRetries times; alone on the device it gives up).
+  // budget: a device allocation can still fail.  Then this slot's stream is drained, its device
+  // memory freed and the caches emptied before the reservation is returned, and the request waits
+  // for another one to finish before it tries again (at most kMemRetries times; alone on the
+  // device it gives up).
   constexpr int kMemRetries = 8;
   for (int attempt = 0;; ++attempt) {
     {
@@ -118,28 +120,29 @@ void Server::run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
     };
     int others = 0;
     uint64_t seen = 0;
-    try {
+    {
+      // declared first, destroyed last: a failed attempt's device memory goes back (below)
+      // before its reservation does, as on success
       Release rel{this, need};
       {
         std::lock_guard<std::mutex> lk(mu);
         others = admitted - 1;
         seen = finished;
       }
-      device_phase(ctx, st, R, A.get(), P.get(), plan, f, E);
-      return;
-    } catch (const Error &e) {
-      if (e.code != MX_ENOMEM || attempt >= kMemRetries || others == 0) throw;
+      try {
+        device_phase(ctx, st, R, A.get(), P.get(), plan, f, E);
+        return;
+      } catch (const Error &e) {
+        release_request(ctx, st, A.get(), P.get());
+        if (e.code != MX_ENOMEM || attempt >= kMemRetries || others == 0) throw;
+      } catch (...) {
+        release_request(ctx, st, A.get(), P.get());
+        throw;
+      }
+      big_trim(device);
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
     }
-    (void)hipStreamSynchronize(st);
-    precond_release_device(P.get());
-    A->rowptr.release();
-    A->col.release();
-    A->val.release();
-    A->val32.release();
-    ctx->krylov.buf.release();
-    big_trim(device);
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
     std::unique_lock<std::mutex> lk(mu);
     // `finished` counts this attempt too: wait for one more (another request) or an idle device
     cv_mem.wait_for(lk, std::chrono::seconds(10), [&] { return finished > seen + 1 || admitted == 0; });
@@ -171,15 +174,23 @@ void Server::device_phase(mx_ctx *ctx, hipStream_t st, SrvRequest *R, mx_matrix 
   R->res.converged = gs.converged;
   R->res.relres_true = gs.relres_true;
   // device memory of the request goes back before its reservation does
+  b.release();
+  x.release();
+  release_request(ctx, st, A, P);
+}
+
+// Frees every device buffer a request holds.  The frees are stream-ordered on the slot's stream,
+// so the stream is drained before (work that reads the buffers) and after (the frees themselves).
+// Errors are ignored: this also runs while an error propagates.
+void Server::release_request(mx_ctx *ctx, hipStream_t st, mx_matrix *A, mx_precond *P) {
+  (void)hipStreamSynchronize(st);
   precond_release_device(P);
   A->rowptr.release();
   A->col.release();
   A->val.release();
   A->val32.release();
   ctx->krylov.buf.release();
-  b.release();
-  x.release();
-  MX_HIP(hipStreamSynchronize(st));
+  (void)hipStreamSynchronize(st);
 }
 
 void Server::worker() {
