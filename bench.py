@@ -378,6 +378,10 @@ def main():
     w, cfg = workload_desc(args.workload)
     inst = instances(args.workload)
     mixed = args.precision == "c64"
+    if mixed:
+        cfg["workload"] = cfg["workload"].replace(
+            "GMRES(", "FGMRES(").replace("complex128", "complex64 factors and SpMV values, FP64 "
+                                                      "Krylov vectors")
     ctx = mx.Context(0)
     n = w.n
     # inputs resident in HBM before the timed region
