@@ -37,6 +37,8 @@ def instances(name):
         return [(kind, e, s) for kind in ("oras", "as") for s, e in enumerate((1.0, 1.5, 2.0))]
     if name == "scale-oras":
         return [("oras", e, s) for s, e in enumerate((1.0, 1.5, 2.0))]
+    if name == "scale-xi0":  # here the exponent gives xi_prec; the problem has xi_prob = 0
+        return [("oras", 1.0, 0), ("as", 1.0, 1)]
     if name == "small":
         return [("oras", 2.0, 0)]
     if name == "small-mixed":
@@ -46,6 +48,13 @@ def instances(name):
 
 def workload_desc(name):
     from mx_inputs import config_scale, config_small
+    if name == "scale-xi0":
+        w = config_scale()
+        return w, {"workload": "unit cube 64^3 cubes x 6 tets (1,872,064 complex DOFs), k=16, "
+                               "xi_prob = 0 (no absorption) preconditioned with xi_prec = k, "
+                               "4x4x4 subdomains, 2-layer overlap, ORAS and AS, GMRES(100) rtol "
+                               "1e-6, complex128, seeded random complex Gaussian J",
+                   "instances": len(instances(name))}
     if name.startswith("scale"):
         w = config_scale()
         return w, {"workload": "unit cube 64^3 cubes x 6 tets (1,872,064 complex DOFs), k=16, "
@@ -403,13 +412,18 @@ def main():
     ctx_host = mx.Context(0)
     fstream = torch.cuda.Stream() if args.overlap_factor else None  # default priority
 
+    xi0 = args.workload == "scale-xi0"
+
     def prepare(mesh, part, kind, e):
-        xi = w.k ** e
+        xi = w.k ** e  # the preconditioner's absorption; also the problem's unless xi0
         t0 = time.perf_counter()
-        A = mx.Matrix(None, mesh, w.k, xi)
+        A = mx.Matrix(None, mesh, w.k, 0.0 if xi0 else xi)
+        A_prec = mx.Matrix(None, mesh, w.k, xi) if xi0 else A  # host only
         A.upload(ctx_host)  # its own stream: overlaps the device work of the current instance
         t1 = time.perf_counter()
-        P = mx.Precond(ctx_host, A, mesh, part, kind, precision=args.precision, plan_only=True)
+        P = mx.Precond(ctx_host, A_prec, mesh, part, kind, xi_prec=xi, precision=args.precision,
+                       plan_only=True)
+        del A_prec
         P.stage(ctx_host)  # host-to-device copies, also overlapping the current instance
         if fstream is not None:
             P.materialize(ctx_host, fstream)  # returns once its factor tiles are complete
@@ -440,7 +454,8 @@ def main():
                 if record and mixed and "x_mixed" not in refs:
                     refs["x_mixed"] = (kind, e, seed, x.clone())
                 t3 = time.perf_counter()
-                r = {"kind": kind, "xi": xi, "iters": st["iters"], "converged": st["converged"],
+                r = {"kind": kind, "xi": 0.0 if xi0 else xi, "xi_prec": xi,
+                     "iters": st["iters"], "converged": st["converged"],
                      "relres": st["relres_true"], "t_assemble": t_asm, "t_precond_plan": t_pre,
                      "t_gmres": t3 - t2}
                 inf = P.info()
@@ -519,8 +534,8 @@ def main():
                     ("; the next instance's factorisation too, on its own stream (factor times "
                      "then include contention with the current GMRES)" if fstream is not None
                      else "")},
-        "solves": [{k: r[k] for k in ("kind", "xi", "iters", "converged", "relres", "t_gmres",
-                                      "t_factor")} for r in recs[0][1]],
+        "solves": [{k: r[k] for k in ("kind", "xi", "xi_prec", "iters", "converged", "relres",
+                                      "t_gmres", "t_factor")} for r in recs[0][1]],
         "all_converged": converged,
     }
     if mixed and "x_mixed" in refs:
@@ -528,8 +543,9 @@ def main():
         kind, e, seed, xm = refs["x_mixed"]
         mesh = mx.Mesh(*n, *w.lengths)
         part = mx.Partition(mesh, *w.parts, w.layers)
-        A = mx.Matrix(ctx, mesh, w.k, w.k ** e)
-        P = mx.Precond(ctx, A, mesh, part, kind, precision="c128")
+        A = mx.Matrix(ctx, mesh, w.k, 0.0 if xi0 else w.k ** e)
+        A_prec = mx.Matrix(None, mesh, w.k, w.k ** e) if xi0 else A
+        P = mx.Precond(ctx, A_prec, mesh, part, kind, xi_prec=w.k ** e, precision="c128")
         x.zero_()
         st = mx.gmres(ctx, A, P, rhs[seed], x, restart=w.restart, rtol=w.rtol,
                       max_iters=args.max_iters)

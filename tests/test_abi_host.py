@@ -46,7 +46,7 @@ def _csr(rp, col, val, n):
 
 
 @pytest.mark.parametrize("bc", [mx.MX_BC_IMPEDANCE, mx.MX_BC_PEC])
-@pytest.mark.parametrize("k,xi", [(4.0, 16.0), (3.0, -2.0)])
+@pytest.mark.parametrize("k,xi", [(4.0, 16.0), (3.0, -2.0), (4.0, 0.0)])
 def test_matrix_matches_oracle(bc, k, xi):
     n = (4, 3, 5)
     om = OMesh(*n, 1.0, 0.8, 1.1)

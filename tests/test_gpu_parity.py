@@ -168,6 +168,42 @@ def test_gmres_config_small(gpu_lib, ctx, kind):
     assert err <= 1e-8
 
 
+@pytest.mark.parametrize("kind", ["oras", "as"])
+def test_gmres_absorption_only_in_preconditioner(gpu_lib, ctx, kind):
+    """The problem without absorption (xi_prob = 0) preconditioned by the Schwarz method built
+    with xi_prec = k (Sec. 1.2, eq. key_intro; Appendix B): the preconditioner is set up from the
+    matrix assembled at xi_prec, GMRES multiplies by the matrix at xi_prob.  8^3, k = 4, 2x2x2
+    subdomains, 2 layers, Gaussian source, GMRES(50): iterations within one of the oracle's, and
+    the solution at the oracle's iteration count to 1e-8."""
+    w = config_small(kind)
+    k, xp = w.k, w.k
+    say("gmres xi_prob 0, xi_prec k", kind)
+    om = OMesh(*w.n, *w.lengths)
+    oA0, oAp = fem.assemble(om, k, 0.0), fem.assemble(om, k, xp)
+    op = dd.Partition(om, *w.parts, w.layers)
+    oB = dd.Schwarz(op, oAp, OKIND[kind], k, xp)
+    lm = gpu_lib.Mesh(*w.n, *w.lengths)
+    lA0 = gpu_lib.Matrix(ctx, lm, k, 0.0)
+    lAp = gpu_lib.Matrix(None, lm, k, xp)  # host only: the local problems are built from it
+    lp = gpu_lib.Partition(lm, *w.parts, w.layers)
+    lP = gpu_lib.Precond(ctx, lAp, lm, lp, kind, xi_prec=xp)
+    f = fem.load_vector(om, fem.gaussian_source(w.center, w.pol, w.sigma))
+    ores = gmres.gmres(oA0, f, oB, restart=w.restart, rtol=w.rtol)
+    ores_same = gmres.gmres(oAp, f, oB, restart=w.restart, rtol=w.rtol)
+    E = om.n_edge
+    bd, xd = dev(f), dev(np.zeros(E))
+    st = gpu_lib.gmres(ctx, lA0, lP, bd, xd, restart=w.restart, rtol=w.rtol)
+    say("  iters gpu", st["iters"], "oracle", ores.iters, "(xi_prob = xi_prec:", ores_same.iters,
+        ") relres", st["relres_true"])
+    assert ores.converged and st["converged"] and st["relres_true"] <= w.rtol
+    assert abs(st["iters"] - ores.iters) <= 1
+    xd2 = dev(np.zeros(E))
+    st2 = gpu_lib.gmres(ctx, lA0, lP, bd, xd2, restart=w.restart, fixed_iters=ores.iters)
+    err = np.linalg.norm(host(xd2) - ores.x) / np.linalg.norm(ores.x)
+    say("  fixed-iteration solution rel err", err)
+    assert st2["iters"] == ores.iters and err <= 1e-8
+
+
 def test_gmres_restart_and_flexible(gpu_lib, ctx):
     """Small restart length (several cycles), flexible variant, nonzero initial guess."""
     say("gmres restart")

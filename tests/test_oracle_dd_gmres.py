@@ -109,6 +109,32 @@ def test_single_subdomain_is_exact(kind):
     assert np.linalg.norm(A @ res.x - f) < 1e-10 * np.linalg.norm(f)
 
 
+@pytest.mark.parametrize("kind", [dd.AS, dd.ORAS])
+def test_absorption_only_in_the_preconditioner(kind):
+    """A_0 (no absorption) preconditioned by the Schwarz method built at xi_prec (Sec. 1.2,
+    eq. key_intro).  A_0 - A_prec = i xi_prec M exactly (the impedance term keeps sign +1 at
+    xi = 0).  With one subdomain B^-1 = A_prec^-1, so the preconditioned operator is
+    I + i xi_prec M A_prec^-1: GMRES takes more than one iteration (one when xi_prec = xi_prob)
+    and converges to the solution of A_0 x = f."""
+    m = Mesh(4, 3, 3)
+    k, xp = 4.0, 4.0
+    A0 = fem.assemble(m, k, 0.0)
+    Ap = fem.assemble(m, k, xp)
+    _, M, _ = fem.assemble_parts(m)
+    assert abs(A0 - Ap - 1j * xp * M).max() <= 1e-14 * abs(A0).max()
+    part = dd.Partition(m, 1, 1, 1, 2)
+    B = dd.Schwarz(part, Ap, kind, k, xp)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(m.n_edge) + 1j * rng.standard_normal(m.n_edge)
+    zp = spla.spsolve(Ap.tocsc(), v)
+    assert np.linalg.norm(B(v) - zp) <= 1e-12 * np.linalg.norm(zp)
+    f = rng.standard_normal(m.n_edge) + 0j
+    res = gmres.gmres(A0, f, B, restart=m.n_edge, rtol=1e-12)
+    assert res.converged and 1 < res.iters < m.n_edge
+    x = spla.spsolve(A0.tocsc(), f)
+    assert np.linalg.norm(res.x - x) <= 1e-9 * np.linalg.norm(x)
+
+
 def test_full_overlap_limits():
     """Every Omega_l = Omega: RAS and ORAS equal A^-1, AS equals N A^-1."""
     m = Mesh(4, 4, 2)
