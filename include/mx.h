@@ -131,6 +131,9 @@ void mx_partition_destroy(mx_partition *p);
 typedef struct {
   int kind;        /* MX_AS | MX_RAS | MX_ORAS                                                */
   double xi_prec;  /* absorption of the local problems (ORAS local assembly; AS/RAS use A's)  */
+                   /* A problem at another xi (xi_prob != xi_prec, e.g. 0) is preconditioned  */
+                   /* by setting up from a matrix assembled at xi_prec and passing the       */
+                   /* problem's matrix to mx_gmres (Sec. 1.2, eq. key_intro)                 */
   int precision;   /* MX_C128 | MX_C64 (local factors and local solves)                       */
   int sweep_grid;  /* workgroups of the persistent sweep kernels; 0 = one per compute unit      */
   int sub_begin;   /* resident share: build only subdomains [sub_begin, sub_end) (both 0 = all); */
