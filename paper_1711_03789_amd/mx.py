@@ -188,6 +188,24 @@ def _ptr(a):
     return a.data_ptr()
 
 
+def _dvec(t, n, what):
+    """Device pointer of `t`, which must be a contiguous torch tensor on the GPU holding n
+    complex128 values (16 n bytes; any dtype of that byte size).  The kernels index such vectors
+    up to n without knowing their allocation, so a wrong size is refused here (MX_EINVAL).  None
+    passes through; the library reports it."""
+    if t is None:
+        return None
+    if not getattr(t, "is_cuda", False):
+        raise MxError(MX_EINVAL, "%s: expected a torch tensor on the GPU" % what)
+    if not t.is_contiguous():
+        raise MxError(MX_EINVAL, "%s: tensor must be contiguous" % what)
+    nb = t.numel() * t.element_size()
+    if nb != 16 * n:
+        raise MxError(MX_EINVAL, "%s: %d bytes, expected complex128[%d] (%d bytes)"
+                      % (what, nb, n, 16 * n))
+    return t.data_ptr()
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -279,7 +297,8 @@ class Matrix:
         return rp, col, val
 
     def spmv(self, ctx, x, y, stream=None):
-        _check(_lib.mx_spmv(ctx.h, self.h, _ptr(x), _ptr(y), _stream(stream)))
+        _check(_lib.mx_spmv(ctx.h, self.h, _dvec(x, self.n, "x"), _dvec(y, self.n, "y"),
+                            _stream(stream)))
 
 
 class Partition:
@@ -347,7 +366,7 @@ class Precond:
             self.device_bytes = nb.value
         else:
             _check(_lib.mx_precond_setup(ctx.h, A.h, mesh.h, part.h, C.byref(o), C.byref(h)))
-        self.h, self.ctx = h, ctx
+        self.h, self.ctx, self.n = h, ctx, A.n
 
     def stage(self, ctx):
         """Host-to-device copies of the setup's device half (any host thread; optional)."""
@@ -368,7 +387,8 @@ class Precond:
         return inf.as_dict()
 
     def apply(self, v, z, stream=None):
-        _check(_lib.mx_precond_apply(_h(self.ctx), self.h, _ptr(v), _ptr(z), _stream(stream)))
+        _check(_lib.mx_precond_apply(_h(self.ctx), self.h, _dvec(v, self.n, "v"),
+                                     _dvec(z, self.n, "z"), _stream(stream)))
 
     def check(self):
         _check(_lib.mx_precond_check(self.h))
@@ -404,7 +424,8 @@ def gmres(ctx, A, Pc, b, x, restart=50, rtol=1e-6, max_iters=1000, flexible=Fals
     o = GmresOpts(restart, max_iters, int(flexible), fixed_iters, int(spmv_c64), rtol)
     st = GmresStats()
     hist = np.zeros(max(max_iters, fixed_iters) + 2, np.float64) if history else None
-    _check(_lib.mx_gmres(ctx.h, A.h, Pc.h if Pc is not None else None, _ptr(b), _ptr(x),
+    _check(_lib.mx_gmres(ctx.h, A.h, Pc.h if Pc is not None else None, _dvec(b, A.n, "b"),
+                         _dvec(x, A.n, "x"),
                          C.byref(o), C.byref(st), _ptr(hist), _stream(stream)))
     out = st.as_dict()
     if history:

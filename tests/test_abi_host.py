@@ -173,3 +173,39 @@ def test_plan_needs_no_device():
         with pytest.raises(mx.MxError) as ei:
             mx.Precond(None, A, m, p, "oras", plan_only=True, **bad)
         assert ei.value.code == mx.MX_EINVAL
+
+
+def test_device_vectors_are_checked():
+    """Device vectors are handed to kernels that index them up to the problem size, so the
+    binding refuses anything but a contiguous GPU tensor of exactly complex128[n] bytes (a CPU
+    tensor, a strided view, a short or long buffer) with MX_EINVAL; None reaches the library,
+    which reports it."""
+    import torch
+
+    class GpuTensorStandIn:  # the attributes the check reads (there is no GPU here)
+        is_cuda = True
+
+        def __init__(self, numel, esize, contiguous=True):
+            self._n, self._e, self._c = numel, esize, contiguous
+
+        def is_contiguous(self):
+            return self._c
+
+        def numel(self):
+            return self._n
+
+        def element_size(self):
+            return self._e
+
+        def data_ptr(self):
+            return 4096
+
+    assert mx._dvec(None, 5, "v") is None
+    assert mx._dvec(GpuTensorStandIn(5, 16), 5, "v") == 4096
+    assert mx._dvec(GpuTensorStandIn(10, 8), 5, "v") == 4096  # any dtype of the right byte size
+    bad = [GpuTensorStandIn(4, 16), GpuTensorStandIn(6, 16), GpuTensorStandIn(5, 8),
+           GpuTensorStandIn(5, 16, contiguous=False), torch.zeros(5, dtype=torch.complex128)]
+    for t in bad:
+        with pytest.raises(mx.MxError) as ei:
+            mx._dvec(t, 5, "v")
+        assert ei.value.code == mx.MX_EINVAL
