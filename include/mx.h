@@ -215,10 +215,12 @@ int mx_precond_stage(mx_ctx *ctx, mx_precond *P);
 int mx_precond_apply(mx_ctx *ctx, mx_precond *P, const void *v_dev, void *z_dev, void *stream);
 int mx_precond_get_info(const mx_precond *P, mx_precond_info *info);
 /* For subdomain l: perm[n_l] (new -> old local index, RCM) and first[n_l] (envelope start of
- * each permuted row).  Either may be NULL. */
-int mx_precond_export_perm(const mx_precond *P, int l, int32_t *perm, int32_t *first);
-/* Host copy of the factored diagonal D of subdomain l (complex128[n_l], permuted order). */
-int mx_precond_export_diag(const mx_precond *P, int l, double *d);
+ * each permuted row).  Either may be NULL.  n is the caller's buffer length and must equal n_l
+ * (MX_EINVAL otherwise; nothing is written).  Available once planned. */
+int mx_precond_export_perm(const mx_precond *P, int l, int64_t n, int32_t *perm, int32_t *first);
+/* Host copy of the factored diagonal D of subdomain l (complex128[n_l], permuted order); n as
+ * for mx_precond_export_perm.  Needs a materialised preconditioner. */
+int mx_precond_export_diag(const mx_precond *P, int l, int64_t n, double *d);
 /* Per-launch timing of the two block-sweep kernels (forward and backward; together the dominant
  * work of an application) with HIP events recorded on the launch stream around each launch.
  * enable = 1 clears earlier records and starts recording; enable = 0 stops, waits for the

@@ -322,23 +322,25 @@ int mx_precond_get_info(const mx_precond *P, mx_precond_info *info) {
   });
 }
 
-int mx_precond_export_perm(const mx_precond *P, int l, int32_t *perm, int32_t *first) {
+int mx_precond_export_perm(const mx_precond *P, int l, int64_t n, int32_t *perm, int32_t *first) {
   MX_GUARD({
     MX_REQUIRE(P, "NULL argument");
     MX_REQUIRE(l >= 0 && l < P->nsub, "subdomain out of range");
     const auto &s = P->sky[l];
+    MX_REQUIRE(n == (int64_t)s.perm.size(), "n differs from the subdomain's DOF count");
     if (perm) std::memcpy(perm, s.perm.data(), s.perm.size() * 4);
     if (first) std::memcpy(first, s.first.data(), s.first.size() * 4);
   });
 }
 
-int mx_precond_export_diag(const mx_precond *P, int l, double *d) {
+int mx_precond_export_diag(const mx_precond *P, int l, int64_t n, double *d) {
   MX_GUARD({
     MX_REQUIRE(P && d, "NULL argument");
     MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
     MX_REQUIRE(l >= 0 && l < P->nsub, "subdomain out of range");
-    bind_device(P->device);
     const auto &s = P->sky[l];
+    MX_REQUIRE(n == (int64_t)s.perm.size(), "n differs from the subdomain's DOF count");
+    bind_device(P->device);
     mx::precond_export_diag(P, l, d);
   });
 }

@@ -144,8 +144,8 @@ def load(path=LIB_PATH):
         "mx_matrix_upload": (C.c_int, [P, P]),
         "mx_precond_apply": (C.c_int, [P, P, P, P, P]),
         "mx_precond_get_info": (C.c_int, [P, C.POINTER(PrecondInfo)]),
-        "mx_precond_export_perm": (C.c_int, [P, C.c_int, P, P]),
-        "mx_precond_export_diag": (C.c_int, [P, C.c_int, P]),
+        "mx_precond_export_perm": (C.c_int, [P, C.c_int, C.c_int64, P, P]),
+        "mx_precond_export_diag": (C.c_int, [P, C.c_int, C.c_int64, P]),
         "mx_precond_check": (C.c_int, [P]),
         "mx_precond_autotune": (C.c_int, [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "mx_server_create": (C.c_int, [C.c_int, C.POINTER(ServerOpts), C.POINTER(P)]),
@@ -410,12 +410,12 @@ class Precond:
     def perm(self, l, n_local):
         perm = np.zeros(n_local, np.int32)
         first = np.zeros(n_local, np.int32)
-        _check(_lib.mx_precond_export_perm(self.h, l, _ptr(perm), _ptr(first)))
+        _check(_lib.mx_precond_export_perm(self.h, l, n_local, _ptr(perm), _ptr(first)))
         return perm, first
 
     def diag(self, l, n_local):
         d = np.zeros(n_local, np.complex128)
-        _check(_lib.mx_precond_export_diag(self.h, l, _ptr(d)))
+        _check(_lib.mx_precond_export_diag(self.h, l, n_local, _ptr(d)))
         return d
 
 

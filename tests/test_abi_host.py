@@ -209,3 +209,26 @@ def test_device_vectors_are_checked():
         with pytest.raises(mx.MxError) as ei:
             mx._dvec(t, 5, "v")
         assert ei.value.code == mx.MX_EINVAL
+
+
+def test_export_sizes_are_checked():
+    """A planned preconditioner exports each subdomain's reverse Cuthill-McKee order, equal to
+    the host view of the same local problem; a buffer length other than the subdomain's DOF
+    count is refused with MX_EINVAL before anything is written."""
+    m = mx.Mesh(6, 5, 4)
+    p = mx.Partition(m, 2, 2, 1, 2)
+    A = mx.Matrix(None, m, 4.0, 16.0)
+    for kind in ("oras", "as"):
+        P = mx.Precond(None, A, m, p, kind, plan_only=True)
+        for l in range(4):
+            ref = mx.local_problem(m, A, p, l, kind)
+            n = len(ref["perm"])
+            perm, first = P.perm(l, n)
+            assert np.array_equal(perm, ref["perm"]) and np.array_equal(first, ref["first"])
+            for bad in (n - 1, n + 1):
+                with pytest.raises(mx.MxError) as ei:
+                    P.perm(l, bad)
+                assert ei.value.code == mx.MX_EINVAL
+            with pytest.raises(mx.MxError) as ei:
+                P.diag(l, n)  # needs the factors on a device
+            assert ei.value.code == mx.MX_EINVAL
