@@ -251,3 +251,78 @@ def test_paper_ordering_ras_beats_as():
         assert res.converged and res.relres_true <= 1e-6
         its[kind] = res.iters
     assert its[dd.RAS] < its[dd.AS] and its[dd.ORAS] <= its[dd.RAS]
+
+
+def _box_problem_on_own_mesh(m, cuts, box, k, xi, bc):
+    """The local problem of box `box` of the cut planes, built independently of dd: a mesh of
+    the box alone, its Galerkin matrix with the impedance term of eq:imp on its own boundary
+    triangles (PEC variant: impedance only on the triangles inside the global box, identity rows
+    on edges lying in a face of the global box), and the map of its edges to global edge ids
+    through integer vertex coordinates.  Returns (global edge id, orientation sign) per box edge,
+    the box matrix, and its impedance face mass over the interface triangles alone."""
+    o = [int(cuts[a][box[a]]) for a in range(3)]
+    nb = [int(cuts[a][box[a] + 1]) - o[a] for a in range(3)]
+    h = [m.L[a] / m.n[a] for a in range(3)]
+    sub = Mesh(*nb, *[nb[a] * h[a] for a in range(3)])
+    ijk = np.rint(sub.xyz / np.array(h)).astype(np.int64) + np.array(o)
+    nx, ny, _ = m.n
+    gid = ijk[:, 0] + (nx + 1) * (ijk[:, 1] + (ny + 1) * ijk[:, 2])
+    a, b = gid[sub.edge_vert[:, 0]], gid[sub.edge_vert[:, 1]]
+    sign = np.where(a < b, 1.0, -1.0)
+    eid = m.edge_index(np.minimum(a, b), np.maximum(a, b))
+
+    def on_global_face(verts):  # all vertices on one boundary plane of the global box
+        c = ijk[verts]  # (F, nv, 3)
+        hit = np.zeros(verts.shape[0], dtype=bool)
+        for ax in range(3):
+            for plane in (0, m.n[ax]):
+                hit |= np.all(c[:, :, ax] == plane, axis=1)
+        return hit
+
+    glob_face = on_global_face(sub.bface_vert)
+    interface = sub.bface_vert[~glob_face]
+    K, M, _ = fem.assemble_parts(sub, bfaces=np.zeros((0, 3), np.int64))
+    _, _, Mb_if = fem.assemble_parts(sub, bfaces=interface)
+    if bc == fem.BC_IMPEDANCE:
+        As = fem.assemble(sub, k, xi, fem.BC_IMPEDANCE)  # eq:imp on every face of the box
+    else:
+        As = (K - (k * k + 1j * xi) * M - 1j * fem.impedance_sign(xi) * k * Mb_if).tocsr()
+        pec = on_global_face(sub.edge_vert)
+        keep = sp.diags((~pec).astype(np.float64))
+        As = (keep @ As @ keep + sp.diags(pec.astype(np.float64))).tocsr()
+    return eid, sign, As, Mb_if
+
+
+@pytest.mark.parametrize("bc,box", [(fem.BC_IMPEDANCE, (1, 1, 1)), (fem.BC_IMPEDANCE, (0, 0, 0)),
+                                    (fem.BC_IMPEDANCE, (2, 1, 0)), (fem.BC_PEC, (0, 0, 0)),
+                                    (fem.BC_PEC, (1, 2, 1))])
+def test_oras_local_matrix_is_the_box_impedance_problem(bc, box):
+    """ImpRAS (Sec. 6.3): the local problem of Omega_l carries the impedance condition of eq:imp
+    (coefficient k) on the faces of dOmega_l inside Omega, and the global condition on the faces
+    of dOmega.  With no overlap layers a subdomain is a box of cubes, and its local matrix must
+    then equal the Galerkin matrix of that box assembled on a mesh of its own, with the
+    impedance term on the box's own boundary triangles (interior box: every face an interface;
+    corner and edge boxes: interface and global faces mixed; PEC: global faces stay PEC).  The
+    two are matched through vertex coordinates and (lo, hi) edge keys.  A coefficient other than
+    k on the interface faces (0.7k, 1.5k, 2k) changes the matrix by far more than the bar."""
+    m = Mesh(7, 8, 6)
+    cuts = ([0, 2, 5, 7], [0, 3, 5, 8], [0, 2, 4, 6])
+    k, xi = 3.0, 5.0
+    A = fem.assemble(m, k, xi, bc)
+    part = dd.Partition(m, 3, 3, 3, 0, *cuts)
+    l = box[0] + 3 * (box[1] + 3 * box[2])
+    Al = dd.local_matrix(part, A, dd.ORAS, k, xi, l, bc).tocsr()
+    eid, sign, As, Mb_if = _box_problem_on_own_mesh(m, cuts, box, k, xi, bc)
+    idx = part.oras_sets[l]
+    assert len(idx) == len(eid)  # the ORAS DOFs are exactly the edges of the box
+    pos = np.searchsorted(idx, eid)
+    assert np.array_equal(idx[pos], eid)
+    S = sp.csr_matrix((sign, (pos, np.arange(len(eid)))), shape=(len(idx), len(eid)))
+    mapped = (S @ As @ S.T).tocsr()
+    scale = abs(Al).max()
+    assert abs(Al - mapped).max() <= 1e-12 * scale
+    # sensitivity: the interface term is resolved far above the bar
+    Mif = (S @ Mb_if @ S.T).tocsr()
+    assert Mif.nnz > 0
+    for factor in (0.7, 1.5, 2.0):
+        assert abs((factor - 1.0) * k * Mif).max() > 1e6 * 1e-12 * scale
