@@ -197,6 +197,8 @@ int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx
  * exact peak device bytes that materialising it will allocate;
  * mx_precond_materialize uploads and factors on `stream` (NULL = null stream) and returns when
  * done.  A planned, not yet materialised preconditioner may only be materialised or destroyed.
+ * Device buffers of P are allocated on `stream` and released on it by mx_precond_destroy, so a
+ * stream passed here must outlive P (the null stream always does).
  * Errors: as mx_precond_setup. */
 int mx_precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
                     const mx_precond_opts *opts, mx_precond **out, uint64_t *device_bytes);
@@ -234,7 +236,11 @@ int mx_precond_sweep_timing(mx_precond *P, int enable, int64_t *launches, double
  * Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_ESTALL. */
 int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_grid,
                         double *best_ms);
-/* Checks the device error word of P (set by a failed pivot or an expired wait). */
+/* Checks the device error word of P (set by a failed pivot or an expired wait).  Once such an
+ * error has been reported (by this call, mx_gmres or mx_precond_autotune), P is unusable: its
+ * device flags stay set, and every later mx_precond_apply, mx_precond_autotune, mx_gmres and
+ * mx_precond_check with P returns the same code without enqueuing work.  Applications enqueued
+ * before the report write NaN into z.  Destroy P and set it up again. */
 int mx_precond_check(mx_precond *P);
 void mx_precond_destroy(mx_precond *P);
 
@@ -318,6 +324,14 @@ void mx_server_destroy(mx_server *s);
  * both precisions and compares with a plain device loop; *err64, *err32 receive the max
  * relative errors.  Synchronous. */
 int mx_selftest(mx_ctx *ctx, double *err64, double *err32);
+/* Host-only check of the error path of the library's host thread pool (which runs the per-
+ * subdomain host work of setups and plans): n_items items run on up to 16 threads, twice (a
+ * work-queue pass and a range-split pass); item fail_item (none if outside [0, n_items)) throws
+ * the library's internal error (fail_code = MX_EINVAL) or an allocation failure (MX_ENOMEM).
+ * Returns that code, as any entry point would, after every thread has been joined, with
+ * *items_run = items completed before the failure stopped the pass; MX_OK when nothing failed
+ * and every item ran exactly once per pass. */
+int mx_selftest_host(int64_t n_items, int64_t fail_item, int fail_code, int64_t *items_run);
 
 #ifdef __cplusplus
 }

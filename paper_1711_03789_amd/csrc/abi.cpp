@@ -1,10 +1,13 @@
 // extern "C" entry points of libmx: argument checks, error capture, handle lifetimes.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "objects.hpp"
 
@@ -310,6 +313,7 @@ int mx_precond_apply(mx_ctx *ctx, mx_precond *P, const void *v_dev, void *z_dev,
     MX_REQUIRE(ctx && P && v_dev && z_dev, "NULL argument");
     MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
     MX_REQUIRE(v_dev != z_dev, "v and z must be distinct");
+    mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::precond_apply(P, v_dev, z_dev, (hipStream_t)stream);
   });
@@ -360,6 +364,7 @@ int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_
   MX_GUARD({
     MX_REQUIRE(ctx && P, "NULL argument");
     MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
+    mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::precond_autotune(ctx, P, (hipStream_t)stream, best_grid, best_ms);
   });
@@ -385,6 +390,7 @@ int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, 
     MX_REQUIRE(A->rowptr.p, "matrix has no device copy");
     MX_REQUIRE(!P || P->E == A->h.n, "preconditioner and matrix sizes differ");
     MX_REQUIRE(!P || !P->plan, "preconditioner is planned but not materialised");
+    if (P) mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream);
   });
@@ -395,6 +401,39 @@ int mx_selftest(mx_ctx *ctx, double *err64, double *err32) {
     MX_REQUIRE(ctx && err64 && err32, "NULL argument");
     bind_device(ctx->device);
     mx::selftest_run(err64, err32);
+  });
+}
+
+int mx_selftest_host(int64_t n_items, int64_t fail_item, int fail_code, int64_t *items_run) {
+  MX_GUARD({
+    MX_REQUIRE(n_items >= 0 && items_run, "bad arguments");
+    MX_REQUIRE(fail_code == MX_EINVAL || fail_code == MX_ENOMEM, "fail_code must be MX_EINVAL or MX_ENOMEM");
+    std::vector<std::atomic<int>> seen(n_items);
+    for (auto &x : seen) x.store(0);
+    std::atomic<int64_t> ran(0);
+    auto item = [&](int64_t i) {
+      if (i == fail_item) {
+        if (fail_code == MX_ENOMEM) throw std::bad_alloc();
+        mx::fail(MX_EINVAL, "planted failure of item " + std::to_string(i));
+      }
+      seen[i].fetch_add(1);
+      ran.fetch_add(1);
+    };
+    *items_run = 0;
+    try {
+      mx::parallel_items(n_items, [&](auto next) {
+        for (int64_t i; (i = next()) >= 0;) item(i);
+      });
+      mx::parallel_for(n_items, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) item(i);
+      }, 1);
+    } catch (...) {
+      *items_run = ran.load();
+      throw;
+    }
+    *items_run = ran.load();
+    for (auto &x : seen)
+      if (x.load() != 2) mx::fail(MX_EINVAL, "host thread pool: an item did not run exactly once per pass");
   });
 }
 

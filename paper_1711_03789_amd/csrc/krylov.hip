@@ -381,8 +381,10 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
   auto read_status = [&](int slot) -> const GmresStatus & {
     MX_HIP(hipEventSynchronize(ev.e[slot]));
     const GmresStatus &s = hst[slot];
-    if (s.pivot) fail(MX_EPIVOT, "zero or non-finite pivot in a local factorisation");
-    if (s.abort) fail(MX_ESTALL, "a device-side wait in the block sweeps expired");
+    if (P && (s.pivot || s.abort)) {
+      P->failed = s.pivot ? MX_EPIVOT : MX_ESTALL;
+      precond_refuse_failed(P);
+    }
     return s;
   };
   auto residual = [&]() {  // r = b - A x, beta -> status

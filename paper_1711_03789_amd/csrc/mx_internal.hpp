@@ -10,6 +10,8 @@
 #include <atomic>
 #include <thread>
 #include <algorithm>
+#include <exception>
+#include <mutex>
 
 #include "../../include/mx.h"
 
@@ -23,6 +25,28 @@ struct Error {
 void set_error(int code, const std::string &msg);
 [[noreturn]] void fail(int code, const std::string &msg);
 
+// Exceptions thrown on worker threads: the first one is kept, every thread is joined, then it is
+// rethrown on the calling thread (an exception escaping a std::thread, or a joinable thread
+// destroyed during unwinding, would terminate the process).
+struct FirstError {
+  std::mutex mu;
+  std::exception_ptr e;
+  std::atomic<bool> failed{false};
+  template <class G>
+  void run(G &&g) {
+    try {
+      g();
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!e) e = std::current_exception();
+      failed.store(true);
+    }
+  }
+  void rethrow() {
+    if (e) std::rethrow_exception(e);
+  }
+};
+
 // Runs f(begin, end) over [0, n) split across up to 16 host threads.
 template <class F>
 void parallel_for(int64_t n, F &&f, int64_t grain = 4096) {
@@ -31,31 +55,45 @@ void parallel_for(int64_t n, F &&f, int64_t grain = 4096) {
     f((int64_t)0, n);
     return;
   }
+  FirstError err;
   std::vector<std::thread> th;
-  int64_t chunk = (n + nt - 1) / nt;
-  for (unsigned t = 0; t < nt; ++t) {
-    int64_t a = (int64_t)t * chunk, b = std::min(n, a + chunk);
-    if (a >= b) break;
-    th.emplace_back([&f, a, b] { f(a, b); });
-  }
+  const int64_t chunk = (n + nt - 1) / nt;
+  err.run([&] {
+    for (unsigned t = 1; t < nt; ++t) {
+      const int64_t a = (int64_t)t * chunk, b = std::min(n, a + chunk);
+      if (a >= b) break;
+      th.emplace_back([&f, &err, a, b] { err.run([&] { f(a, b); }); });
+    }
+  });
+  err.run([&] { f((int64_t)0, std::min(n, chunk)); });
   for (auto &x : th) x.join();
+  err.rethrow();
 }
 
 // Items of very different cost (subdomains): f(next) runs once on each of up to 16 threads, so
 // it can set up per-thread scratch; next() hands out the unclaimed items in order, then -1.
+// After a failure on any thread the remaining items are not handed out.
 template <class F>
 void parallel_items(int64_t n, F &&f) {
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   nt = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nt, n));
   std::atomic<int64_t> counter(0);
+  FirstError err;
   auto next = [&counter, n]() -> int64_t {
     const int64_t i = counter.fetch_add(1);
     return i < n ? i : -1;
   };
+  auto body = [&] {
+    err.run([&] { f(next); });
+    if (err.failed.load()) counter.store(n);
+  };
   std::vector<std::thread> th;
-  for (unsigned t = 1; t < nt; ++t) th.emplace_back([&] { f(next); });
-  f(next);
+  err.run([&] {
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(body);
+  });
+  body();
   for (auto &x : th) x.join();
+  err.rethrow();
 }
 
 // ---- structured Kuhn mesh ------------------------------------------------------------------------

@@ -114,7 +114,7 @@ struct Workspace {  // grow-only scratch owned by a context
 struct mx_ctx {
   int device = 0;
   int cus = 256;
-  mx::Workspace krylov, tmp;
+  mx::Workspace krylov;
   double *pinned = nullptr;  // small host-visible status area
 };
 
@@ -180,6 +180,9 @@ struct mx_precond {
   mx::DevBuf d_ctrl, d_sched_sub, d_sched_blk;
   mx::DevBuf d_panel_pref, d_update_pref, d_intra_pref, d_next_pref, d_rest_pref;
   int n_items = 0, trsv_grid = 0, sweep_grid = 0;
+  // MX_ESTALL or MX_EPIVOT once a device error word has been reported; the preconditioner is
+  // then refused by every later application (its device flags stay set)
+  int failed = 0;
   mx_precond_info info{};
   // optional per-launch timing of the sweep kernel
   bool timing = false;
@@ -211,6 +214,8 @@ size_t matrix_device_bytes(const mx_matrix *A);
 size_t gmres_device_bytes(int64_t n, int restart, bool flexible);
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st);
 int precond_check(mx_precond *P, hipStream_t st = nullptr);
+// throws the recorded device error of P, if any (see mx_precond::failed)
+void precond_refuse_failed(const mx_precond *P);
 void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_grid, double *best_ms);
 void precond_export_diag(const mx_precond *P, int l, double *d);
 void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd, double *ms_bwd);

@@ -1141,9 +1141,16 @@ int precond_check(mx_precond *P, hipStream_t st) {
   int h[4];
   MX_HIP(hipMemcpyAsync(h, P->d_ctrl.p, sizeof(h), hipMemcpyDeviceToHost, st));
   MX_HIP(hipStreamSynchronize(st));
-  if (h[3]) fail(MX_EPIVOT, "zero or non-finite pivot in a local factorisation");
-  if (h[2]) fail(MX_ESTALL, "a device-side wait in the block sweeps expired");
+  if (h[3]) P->failed = MX_EPIVOT;
+  else if (h[2]) P->failed = MX_ESTALL;
+  precond_refuse_failed(P);
   return MX_OK;
+}
+
+void precond_refuse_failed(const mx_precond *P) {
+  if (P->failed == MX_EPIVOT) fail(MX_EPIVOT, "zero or non-finite pivot in a local factorisation");
+  if (P->failed == MX_ESTALL)
+    fail(MX_ESTALL, "a device-side wait in the block sweeps expired; the preconditioner is unusable");
 }
 
 void precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_partition *ph,

@@ -194,12 +194,12 @@ void Server::release_request(mx_ctx *ctx, hipStream_t st, mx_matrix *A, mx_preco
 }
 
 void Server::worker() {
-  hipSetDevice(device);
   hipStream_t st = nullptr;
   mx_ctx ctx;
   ctx.device = device;
   ctx.cus = cus;
-  bool ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+  bool ok = hipSetDevice(device) == hipSuccess &&
+            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
             hipHostMalloc((void **)&ctx.pinned, 4096, hipHostMallocDefault) == hipSuccess;
   while (true) {
     uint64_t id;
@@ -226,6 +226,9 @@ void Server::worker() {
       } catch (const std::bad_alloc &) {
         code = MX_ENOMEM;
         msg = "host allocation failed";
+      } catch (const std::exception &e) {
+        code = MX_EINVAL;
+        msg = e.what();
       }
     }
     {
@@ -281,12 +284,28 @@ int mx_server_create(int device, const mx_server_opts *opts, mx_server **out) {
     }
     MX_HIP(hipMemGetInfo(&free_b, &total_b));
     S->s.budget = opts->hbm_budget ? opts->hbm_budget : (uint64_t)(0.85 * (double)free_b);
-    for (int i = 0; i < opts->slots; ++i) S->s.workers.emplace_back([p = &S->s] { p->worker(); });
+    try {
+      for (int i = 0; i < opts->slots; ++i) S->s.workers.emplace_back([p = &S->s] { p->worker(); });
+    } catch (...) {  // the workers already started are stopped and joined before S goes away
+      {
+        std::lock_guard<std::mutex> lk(S->s.mu);
+        S->s.stop = true;
+      }
+      S->s.cv_queue.notify_all();
+      for (auto &t : S->s.workers) t.join();
+      throw;
+    }
     *out = S.release();
     return MX_OK;
   } catch (const Error &e) {
     mx::set_error(e.code, e.msg);
     return e.code;
+  } catch (const std::bad_alloc &) {
+    mx::set_error(MX_ENOMEM, "host allocation failed");
+    return MX_ENOMEM;
+  } catch (const std::exception &e) {
+    mx::set_error(MX_EINVAL, e.what());
+    return MX_EINVAL;
   }
 }
 
@@ -309,6 +328,12 @@ int mx_server_submit(mx_server *S, const mx_request *req, uint64_t *ticket) {
   } catch (const Error &e) {
     mx::set_error(e.code, e.msg);
     return e.code;
+  } catch (const std::bad_alloc &) {
+    mx::set_error(MX_ENOMEM, "host allocation failed");
+    return MX_ENOMEM;
+  } catch (const std::exception &e) {
+    mx::set_error(MX_EINVAL, e.what());
+    return MX_EINVAL;
   }
 }
 
@@ -329,6 +354,12 @@ int mx_server_wait(mx_server *S, uint64_t ticket, double timeout_s, mx_result *r
   } catch (const Error &e) {
     mx::set_error(e.code, e.msg);
     return e.code;
+  } catch (const std::bad_alloc &) {
+    mx::set_error(MX_ENOMEM, "host allocation failed");
+    return MX_ENOMEM;
+  } catch (const std::exception &e) {
+    mx::set_error(MX_EINVAL, e.what());
+    return MX_EINVAL;
   }
 }
 
@@ -347,6 +378,12 @@ int mx_server_solution(mx_server *S, uint64_t ticket, double *x_host, int64_t n)
   } catch (const Error &e) {
     mx::set_error(e.code, e.msg);
     return e.code;
+  } catch (const std::bad_alloc &) {
+    mx::set_error(MX_ENOMEM, "host allocation failed");
+    return MX_ENOMEM;
+  } catch (const std::exception &e) {
+    mx::set_error(MX_EINVAL, e.what());
+    return MX_EINVAL;
   }
 }
 
@@ -362,6 +399,12 @@ int mx_server_release(mx_server *S, uint64_t ticket) {
   } catch (const Error &e) {
     mx::set_error(e.code, e.msg);
     return e.code;
+  } catch (const std::bad_alloc &) {
+    mx::set_error(MX_ENOMEM, "host allocation failed");
+    return MX_ENOMEM;
+  } catch (const std::exception &e) {
+    mx::set_error(MX_EINVAL, e.what());
+    return MX_EINVAL;
   }
 }
 
@@ -376,6 +419,12 @@ int mx_server_stats(mx_server *S, uint64_t *budget, uint64_t *peak_used, int *ma
   } catch (const Error &e) {
     mx::set_error(e.code, e.msg);
     return e.code;
+  } catch (const std::bad_alloc &) {
+    mx::set_error(MX_ENOMEM, "host allocation failed");
+    return MX_ENOMEM;
+  } catch (const std::exception &e) {
+    mx::set_error(MX_EINVAL, e.what());
+    return MX_EINVAL;
   }
 }
 

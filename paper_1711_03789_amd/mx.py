@@ -32,6 +32,7 @@ SYMBOLS = [
     "mx_precond_sweep_timing", "mx_precond_autotune", "mx_server_create", "mx_server_submit",
     "mx_server_wait", "mx_server_solution", "mx_server_release", "mx_server_stats",
     "mx_server_destroy", "mx_matrix_upload", "mx_precond_plan", "mx_precond_materialize",
+    "mx_selftest_host",
 ]
 
 
@@ -161,6 +162,7 @@ def load(path=LIB_PATH):
         "mx_precond_destroy": (None, [P]),
         "mx_gmres": (C.c_int, [P, P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresStats), P, P]),
         "mx_selftest": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "mx_selftest_host": (C.c_int, [C.c_int64, C.c_int64, C.c_int, C.POINTER(C.c_int64)]),
         "mx_local_problem": (C.c_int, [P, P, P, C.POINTER(PrecondOpts), C.c_int,
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64), P, P, P, P, P]),
     }
@@ -327,6 +329,14 @@ class Partition:
         _check(_lib.mx_partition_export(self.h, kind, _ptr(off), _ptr(l2g), _ptr(owner), _ptr(nt)))
         return {"offsets": off, "loc2glob": l2g, "owner": owner, "n_tet": nt,
                 "sets": [l2g[off[i]:off[i + 1]] for i in range(n.value)]}
+
+
+def selftest_host(n_items, fail_item=-1, fail_code=MX_EINVAL):
+    """Host thread-pool error path (no device): returns (status, items run before a failure)."""
+    load()
+    ran = C.c_int64()
+    rc = _lib.mx_selftest_host(n_items, fail_item, fail_code, C.byref(ran))
+    return rc, ran.value
 
 
 def local_problem(mesh, A, part, l, kind="oras", xi_prec=None):

@@ -232,3 +232,84 @@ def test_export_sizes_are_checked():
             with pytest.raises(mx.MxError) as ei:
                 P.diag(l, n)  # needs the factors on a device
             assert ei.value.code == mx.MX_EINVAL
+
+
+def test_concurrent_host_threads():
+    """Host halves of the library on several host threads at once (ctypes releases the GIL, so
+    the calls overlap): each thread builds its own mesh, host matrix, partition and preconditioner
+    plan, while all of them also plan from one shared mesh and partition, and every handle is
+    destroyed on a thread other than the one that made it. Results equal a single-threaded run
+    bit for bit."""
+    import threading
+
+    shared_m = mx.Mesh(7, 6, 5)
+    shared_p = mx.Partition(shared_m, 2, 2, 1, 2)
+    shared_A = mx.Matrix(None, shared_m, 3.0, 9.0)
+
+    def work(seed):
+        n = (5 + seed % 3, 4 + seed % 2, 6)
+        m = mx.Mesh(*n)
+        p = mx.Partition(m, 2, 1, 2, 1 + seed % 2)
+        A = mx.Matrix(None, m, 2.0 + seed, (2.0 + seed) ** 2)
+        out = {"own": (m, p, A)}
+        for kind in ("oras", "as"):
+            P = mx.Precond(None, A, m, p, kind, plan_only=True)
+            Ps = mx.Precond(None, shared_A, shared_m, shared_p, kind, plan_only=True)
+            ref = mx.local_problem(shared_m, shared_A, shared_p, 1, kind)
+            perm, _ = Ps.perm(1, len(ref["perm"]))
+            out[kind] = (P, Ps, P.device_bytes, Ps.device_bytes, perm, ref["perm"])
+        return out
+
+    serial = [work(s) for s in range(6)]
+    results = [None] * 6
+    errors = []
+
+    def run(i):
+        try:
+            results[i] = work(i)
+        except Exception as e:  # reported on the main thread
+            errors.append(e)
+
+    for _ in range(2):
+        th = [threading.Thread(target=run, args=(i,)) for i in range(6)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        assert not errors, errors
+        for a, b in zip(serial, results):
+            for kind in ("oras", "as"):
+                assert a[kind][2] == b[kind][2] and a[kind][3] == b[kind][3]
+                assert np.array_equal(a[kind][4], b[kind][4])
+                assert np.array_equal(b[kind][4], b[kind][5])
+        # destroy the handles made on the worker threads from other threads, concurrently
+        doomed = results[:]
+        results = [None] * 6
+
+        def drop(i):
+            doomed[i] = None
+
+        th = [threading.Thread(target=drop, args=((i + 1) % 6,)) for i in range(6)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+
+
+def test_host_thread_pool_errors():
+    """An error raised on one of the library's host worker threads (the per-subdomain host work of
+    plans and setups) comes back as the entry point's status code on the calling thread, after
+    every worker has been joined, instead of terminating the process; with no failure every item
+    runs exactly once per pass."""
+    for n in (0, 1, 7, 100, 5000):
+        rc, ran = mx.selftest_host(n)
+        assert rc == mx.MX_OK and ran == 2 * n
+    for code in (mx.MX_EINVAL, mx.MX_ENOMEM):
+        for n, at in ((1, 0), (64, 0), (64, 63), (5000, 2500)):
+            rc, ran = mx.selftest_host(n, at, code)
+            assert rc == code
+            assert 0 <= ran < n  # the failing item never completes; the pass stops
+            if code == mx.MX_EINVAL:
+                assert "planted failure of item %d" % at in mx._lib.mx_last_error().decode()
+    rc, _ = mx.selftest_host(10, -1, 123)
+    assert rc == mx.MX_EINVAL
