@@ -69,10 +69,12 @@ def config_scale(kind=ORAS, xi_exp=2.0, seed=0):
 
 
 def config_medium(kind=ORAS, xi_exp=2.0, seed=0, n=32, parts=4):
-    """Intermediate unit-cube problem used by parity tests at several tiles per subdomain."""
+    """Unit cube 32^3 cubes x 6 tets (238,688 DOFs), k = 8, xi = k^xi_exp, 4x4x4 subdomains
+    (every class of box: corner, edge, face, interior), 2 layers, GMRES(100), seeded complex
+    Gaussian per-DOF load: the 64^3 benchmark problem at half the resolution and wavenumber."""
     k = 8.0
-    return Workload("unit-cube %d^3, k=8" % n, (n, n, n), (1, 1, 1), k, k ** xi_exp,
-                    (parts, parts, parts), 2, kind, 50, rhs="random", seed=seed)
+    return Workload("unit-cube %d^3, k=8, xi=k^%g" % (n, xi_exp), (n, n, n), (1, 1, 1), k,
+                    k ** xi_exp, (parts, parts, parts), 2, kind, 100, rhs="random", seed=seed)
 
 
 def config_batching(seed=0):

@@ -19,6 +19,8 @@ with absorption", Math. Comp. 2019 / arXiv:1711.03789):
 * rcm.py       reverse Cuthill-McKee ordering of a local matrix graph (not in the paper: the
                paper's local solves are sparse direct; the ordering is only compared
                integer-for-integer with the library's own)
+* pool.py      the same Schwarz preconditioner with its local factorisations and solves on a
+               pool of host processes, one subdomain per task (bitwise equal to dd.Schwarz)
 * gmres.py     restarted right-preconditioned (F)GMRES with classical Gram-Schmidt twice and
                complex Givens rotations (Sec. 5.2 minimal-residual definition, Sec. 6.1
                stopping rule)

@@ -18,12 +18,13 @@ Test infrastructure only (see oracle/__init__.py).
   tetrahedra containing e, D^l_ee = [owner(e) = l]; sum_l R^T D R = I holds exactly.
 * Preconditioners: AS = sum_l R^T (A^l)^-1 R (eq:defAS without the coarse term, Sec. 6.2),
   RAS = sum_l R^T D^l (A^l)^-1 R (one-level RAS, Sec. 6.3), ORAS = RAS with impedance local
-  matrices.  Local solves are exact sparse LU (SuperLU), independent of any ordering the
-  library uses.
+  matrices.  Local solves are exact sparse LU (SuperLU, factor_local), independent of the
+  ordering and factorisation the library uses.
 """
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
+from threadpoolctl import threadpool_limits
 
 from . import fem
 
@@ -136,6 +137,19 @@ def local_matrix(part, A, kind, k, xi, l, bc=fem.BC_IMPEDANCE):
     return Al[idx][:, idx].tocsc()
 
 
+def factor_local(Al):
+    """Exact sparse LU of a local matrix (SuperLU).  Fill-reducing minimum-degree order on the
+    pattern of A^l + (A^l)^T, applied symmetrically, with diagonal pivots: A^l is complex
+    symmetric, and every principal submatrix of it is nonsingular for xi != 0 by the coercivity
+    estimate of Sec. 2.3 (eq:coercivity), applied to the local problems as in Sec. 3.3, so no
+    row interchange is needed; a vanishing pivot raises instead of returning a wrong factor.
+    The order only changes rounding.  BLAS runs on one thread (here and in the local solves), so
+    the rounding does not depend on the host's core count."""
+    with threadpool_limits(1):
+        return spla.splu(Al, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                         options=dict(SymmetricMode=True))
+
+
 def local_matrices(part, A, kind, k, xi, bc=fem.BC_IMPEDANCE):
     """A^l for every subdomain: minors of A (AS, RAS) or impedance local problems (ORAS)."""
     return [local_matrix(part, A, kind, k, xi, l, bc) for l in range(part.N)]
@@ -148,17 +162,18 @@ class Schwarz:
         self.part, self.kind = part, kind
         self.sets = part.local_set(kind)
         self.local = local if local is not None else local_matrices(part, A, kind, k, xi, bc)
-        self.lu = [spla.splu(Al) for Al in self.local]
+        self.lu = [factor_local(Al) for Al in self.local]
         self.D = [part.pou(l, kind) if kind in (RAS, ORAS) else None for l in range(part.N)]
         self.n = A.shape[0]
 
     def local_solve(self, l, r):
-        return self.lu[l].solve(r)
+        with threadpool_limits(1):
+            return self.lu[l].solve(r)
 
     def apply(self, v):
         z = np.zeros(self.n, dtype=np.complex128)
         for l, idx in enumerate(self.sets):
-            x = self.lu[l].solve(v[idx])
+            x = self.local_solve(l, v[idx])
             if self.D[l] is not None:
                 x = self.D[l] * x
             np.add.at(z, idx, x)

@@ -313,3 +313,28 @@ def test_host_thread_pool_errors():
                 assert "planted failure of item %d" % at in mx._lib.mx_last_error().decode()
     rc, _ = mx.selftest_host(10, -1, 123)
     assert rc == mx.MX_EINVAL
+
+
+def test_medium_partition_and_orders_bit_exact():
+    """The 32^3 problem with 4x4x4 subdomains and 2 layers: local DOF sets of both kinds and the
+    owners of every subdomain, and the reverse Cuthill-McKee order and envelope of a corner, an
+    edge, a face and an interior subdomain, equal the oracle's integer for integer."""
+    from mx_inputs import config_medium
+    w = config_medium()
+    om, lm = OMesh(*w.n), mx.Mesh(*w.n)
+    op = dd.Partition(om, *w.parts, w.layers)
+    lp = mx.Partition(lm, *w.parts, w.layers)
+    for kind, sets in (("oras", op.oras_sets), ("as", op.as_sets)):
+        ex = lp.export(kind)
+        assert len(ex["sets"]) == 64
+        for l in range(64):
+            assert np.array_equal(ex["sets"][l], sets[l]), (kind, l)
+        assert np.array_equal(ex["owner"], op.owner)
+    A = mx.Matrix(None, lm, w.k, w.xi)
+    for l in (0, 1, 5, 21):  # corner, edge, face, interior box
+        for kind in ("oras", "as"):
+            lp_ = mx.local_problem(lm, A, lp, l, kind)
+            g = rcm.pattern_graph(dd.local_pattern(op, l, {"oras": dd.ORAS, "as": dd.AS}[kind]))
+            perm = rcm.rcm(*g)
+            assert np.array_equal(lp_["perm"], perm), (kind, l)
+            assert np.array_equal(lp_["first"], rcm.envelope(*g, perm)), (kind, l)

@@ -1,26 +1,34 @@
 """Full-size checks on the 64^3 benchmark problem (1,872,064 DOFs, 4x4x4 subdomains, 2 layers,
-k = 16, xi = k^2), with the launch configuration the benchmark times: all 64 subdomains factored
-together and applied with one sweep launch per direction, one sweep workgroup per CU.
+k = 16), with the launch configuration the benchmark times: all 64 subdomains factored together
+and applied with one sweep launch per direction, one sweep workgroup per CU.
 
 The oracle cannot solve the whole problem in test time, so the checks are:
-* sampled outputs: the ORAS application restricted to the DOFs owned by subdomain 0 equals the
-  oracle's local solve there (Boolean partition of unity: z_e = x_l[e] for owner(e) = l). The
-  bar is 1e-10 relative.
-* the same for AS, through a one-subdomain resident share, whose output is R_l^T x_l.
+* integer work at full size: the local DOF sets of both kinds and the owners of all 64
+  subdomains, and the reverse Cuthill-McKee order of an interior subdomain, bit-exact;
+* sampled outputs at xi = k and xi = k^2 (the ends of the benchmark's range): the ORAS
+  application restricted to the DOFs owned by a corner (0), an interior (42, the largest local
+  problem) and the last subdomain (63, the highest tile and vector offsets) equals the oracle's
+  local solve there (Boolean partition of unity: z_e = x_l[e] for owner(e) = l); the AS local
+  solves of the same subdomains, through one-subdomain resident shares (output R_l^T x_l), equal
+  the oracle's.  Bar: 1e-10 relative.  The oracle's local problems are factored in parallel on
+  host worker processes;
 * a property at full size: GMRES's reported convergence holds for the oracle's matrix, i.e. the
   true relative residual computed with the oracle's A is <= rtol."""
 import sys
+import time
 
 import numpy as np
 import pytest
 
 from mx_inputs import random_rhs
-from oracle import dd, fem
+from oracle import dd, fem, pool, rcm
 from oracle.mesh import Mesh as OMesh
 
 pytestmark = pytest.mark.gpu
 
-N, P_, L, K, XI = 64, 4, 2, 16.0, 256.0
+N, P_, L, K = 64, 4, 2, 16.0
+XIS = (K, K * K)
+SAMPLED = (0, 42, 63)
 
 
 def say(*a):
@@ -30,17 +38,18 @@ def say(*a):
 
 @pytest.fixture(scope="module")
 def big(gpu_lib):
-    import time
     t0 = time.time()
     ctx = gpu_lib.Context(0)
     lm = gpu_lib.Mesh(N, N, N)
     lp = gpu_lib.Partition(lm, P_, P_, P_, L)
-    lA = gpu_lib.Matrix(ctx, lm, K, XI)
     say("library objects", time.time() - t0)
     om = OMesh(N, N, N)
     op = dd.Partition(om, P_, P_, P_, L)
     say("oracle mesh + partition", time.time() - t0)
-    return {"ctx": ctx, "lm": lm, "lp": lp, "lA": lA, "om": om, "op": op, "E": om.n_edge}
+    Kg, Mg, Bg = fem.assemble_parts(om)
+    say("oracle K, M, M_b", time.time() - t0)
+    return {"ctx": ctx, "lm": lm, "lp": lp, "om": om, "op": op, "E": om.n_edge,
+            "oA": lambda xi: fem.combine(Kg, Mg, Bg, K, xi, fem.BC_IMPEDANCE)}
 
 
 def _dev(x):
@@ -54,29 +63,6 @@ def _host(t):
     return t.cpu().numpy()
 
 
-def _local_solve(Al, r):
-    import scipy.sparse.linalg as spla
-    return spla.splu(Al).solve(r)
-
-
-@pytest.mark.timeout(900)
-def test_oras_fullsize_sampled_subdomain(gpu_lib, big):
-    mx, b = gpu_lib, big
-    say("full-size ORAS application, sampled subdomain 0")
-    P = mx.Precond(b["ctx"], b["lA"], b["lm"], b["lp"], "oras")
-    v = random_rhs(b["E"], 5)
-    z = _host_apply(P, v)
-    l = 0
-    idx = b["op"].oras_sets[l]
-    Al = dd.local_matrix(b["op"], None, dd.ORAS, K, XI, l)
-    say("  local n", Al.shape[0])
-    x = _local_solve(Al, v[idx])
-    own = b["op"].pou(l, dd.ORAS) > 0
-    err = np.max(np.abs(z[idx[own]] - x[own])) / np.max(np.abs(x[own]))
-    say("  max rel err on owned DOFs", err, "owned", int(own.sum()))
-    assert err <= 1e-10
-
-
 def _host_apply(P, v):
     vd = _dev(v)
     zd = _dev(np.zeros_like(v))
@@ -85,37 +71,82 @@ def _host_apply(P, v):
     return _host(zd)
 
 
-@pytest.mark.timeout(900)
-def test_as_fullsize_share_subdomain(gpu_lib, big):
-    """AS local solve of subdomain 0 at full size: its resident share returns R_0^T x_0."""
-    mx, b = gpu_lib, big
-    say("full-size AS local solve of subdomain 0 (share)")
-    oA = fem.assemble(b["om"], K, XI)
-    P = mx.Precond(b["ctx"], b["lA"], b["lm"], b["lp"], "as", share=(0, 1))
-    v = random_rhs(b["E"], 6)
-    z = _host_apply(P, v)
-    idx = b["op"].as_sets[0]
-    x = _local_solve(dd.local_matrix(b["op"], oA, dd.AS, K, XI, 0), v[idx])
-    err = np.max(np.abs(z[idx] - x)) / np.max(np.abs(x))
-    say("  max rel err", err)
-    assert err <= 1e-10
-    rest = np.ones(b["E"], bool)
-    rest[idx] = False
-    assert not np.any(z[rest])
-    b["oA"] = oA
+@pytest.mark.timeout(600)
+def test_fullsize_partition_and_order_bit_exact(gpu_lib, big):
+    say("full-size partition sets, owners, RCM order of subdomain 42")
+    op, lp = big["op"], big["lp"]
+    for kind, sets in (("oras", op.oras_sets), ("as", op.as_sets)):
+        ex = lp.export(kind)
+        assert len(ex["sets"]) == 64
+        for l in range(64):
+            assert np.array_equal(ex["sets"][l], sets[l]), (kind, l)
+        assert np.array_equal(ex["owner"], op.owner)
+    A = gpu_lib.Matrix(None, big["lm"], K, K)
+    for kind, okind in (("oras", dd.ORAS), ("as", dd.AS)):
+        g = rcm.pattern_graph(dd.local_pattern(op, 42, okind))
+        perm = rcm.rcm(*g)
+        lp_ = gpu_lib.local_problem(big["lm"], A, lp, 42, kind)
+        say("  ", kind, "n", len(perm))
+        assert np.array_equal(lp_["perm"], perm)
+        assert np.array_equal(lp_["first"], rcm.envelope(*g, perm))
+
+
+@pytest.mark.timeout(1200)
+def test_fullsize_sampled_local_solves(gpu_lib, big):
+    mx, b, op = gpu_lib, big, big["op"]
+    E = b["E"]
+    v = random_rhs(E, 5)
+    tasks, keys, gpu = [], [], {}
+    for xi in XIS:
+        say("xi", xi)
+        lA = mx.Matrix(b["ctx"], b["lm"], K, xi)
+        P = mx.Precond(b["ctx"], lA, b["lm"], b["lp"], "oras")
+        gpu[("oras", xi)] = _host_apply(P, v)
+        del P
+        for l in SAMPLED:
+            S = mx.Precond(b["ctx"], lA, b["lm"], b["lp"], "as", share=(l, l + 1))
+            gpu[("as", xi, l)] = _host_apply(S, v)
+            del S
+        oA = b["oA"](xi)
+        for l in SAMPLED:
+            tasks.append((dd.local_matrix(op, None, dd.ORAS, K, xi, l), v[op.oras_sets[l]]))
+            keys.append(("oras", xi, l))
+            tasks.append((dd.local_matrix(op, oA, dd.AS, K, xi, l), v[op.as_sets[l]]))
+            keys.append(("as", xi, l))
+        del oA
+    t0 = time.time()
+    res = pool.solve_many(tasks)
+    say("oracle: %d local solves in %.1f s (longest factorisation %.1f s)"
+        % (len(tasks), time.time() - t0, max(t for _, t in res)))
+    for key, (x, _) in zip(keys, res):
+        kind, xi, l = key
+        if kind == "oras":
+            idx = op.oras_sets[l]
+            own = op.pou(l, dd.ORAS) > 0
+            z = gpu[("oras", xi)]
+            err = np.max(np.abs(z[idx[own]] - x[own])) / np.max(np.abs(x[own]))
+            say("  ORAS xi %g l %d owned %d: max rel err %.2e" % (xi, l, int(own.sum()), err))
+        else:
+            idx = op.as_sets[l]
+            z = gpu[("as", xi, l)]
+            err = np.max(np.abs(z[idx] - x)) / np.max(np.abs(x))
+            rest = np.ones(E, bool)
+            rest[idx] = False
+            assert not np.any(z[rest])
+            say("  AS xi %g l %d n %d: max rel err %.2e" % (xi, l, len(idx), err))
+        assert err <= 1e-10, key
 
 
 @pytest.mark.timeout(900)
 def test_gmres_fullsize_true_residual(gpu_lib, big):
     mx, b = gpu_lib, big
     say("full-size ORAS GMRES(100), true residual with the oracle's matrix")
-    oA = b.get("oA")
-    if oA is None:
-        oA = fem.assemble(b["om"], K, XI)
-    P = mx.Precond(b["ctx"], b["lA"], b["lm"], b["lp"], "oras")
+    oA = b["oA"](K * K)
+    lA = mx.Matrix(b["ctx"], b["lm"], K, K * K)
+    P = mx.Precond(b["ctx"], lA, b["lm"], b["lp"], "oras")
     f = random_rhs(b["E"], 2)
     x = _dev(np.zeros(b["E"]))
-    st = mx.gmres(b["ctx"], b["lA"], P, _dev(f), x, restart=100, rtol=1e-6)
+    st = mx.gmres(b["ctx"], lA, P, _dev(f), x, restart=100, rtol=1e-6)
     xs = _host(x)
     rel = np.linalg.norm(f - oA @ xs) / np.linalg.norm(f)
     say("  iterations", st["iters"], "reported", st["relres_true"], "oracle residual", rel)

@@ -7,6 +7,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from mx_inputs import jittered_cuts, random_rhs
 from oracle import dd, fem, gmres, rcm
 from oracle.mesh import Mesh
 
@@ -326,3 +327,44 @@ def test_oras_local_matrix_is_the_box_impedance_problem(bc, box):
     assert Mif.nnz > 0
     for factor in (0.7, 1.5, 2.0):
         assert abs((factor - 1.0) * k * Mif).max() > 1e6 * 1e-12 * scale
+
+
+@pytest.mark.parametrize("kind,bc,cuts", [("oras", fem.BC_IMPEDANCE, False), ("as", fem.BC_IMPEDANCE, True),
+                                          ("ras", fem.BC_PEC, True), ("oras", fem.BC_PEC, False)])
+def test_pooled_schwarz_equals_serial(kind, bc, cuts):
+    """The worker-pool form of the oracle's Schwarz preconditioner (local problems factored and
+    solved in separate processes, summed in subdomain order here) returns exactly what the
+    one-process form returns."""
+    from oracle import pool
+    n, parts, k, xi = (8, 7, 6), (3, 2, 2), 4.0, 7.0
+    c = (jittered_cuts(8, 3, 0.2, 1), jittered_cuts(7, 2, 0.2, 2), None) if cuts else (None, None, None)
+    m = Mesh(*n)
+    A = fem.assemble(m, k, xi, bc)
+    P = dd.Partition(m, *parts, 2, *c)
+    K = {"as": dd.AS, "ras": dd.RAS, "oras": dd.ORAS}[kind]
+    ref = dd.Schwarz(P, A, K, k, xi, bc)
+    v = random_rhs(m.n_edge, 3)
+    with pool.PooledSchwarz(P, A, K, k, xi, bc, workers=3) as B:
+        assert len(B.procs) == 3 and len(B.t_lu) == P.N
+        for _ in range(2):
+            assert np.array_equal(B(v), ref(v))
+
+
+def test_local_factor_is_exact():
+    """The oracle's local factorisation (symmetric minimum-degree order, diagonal pivots) solves
+    the local problems to rounding: against a dense solve on small subdomains of every kind, and
+    against SuperLU with partial pivoting in its default column order."""
+    m = Mesh(6, 5, 4)
+    for bc in (fem.BC_IMPEDANCE, fem.BC_PEC):
+        A = fem.assemble(m, 3.0, 9.0, bc)
+        P = dd.Partition(m, 2, 2, 1, 1)
+        for K in (dd.AS, dd.ORAS):
+            for l in range(P.N):
+                Al = dd.local_matrix(P, A, K, 3.0, 9.0, l, bc)
+                r = random_rhs(Al.shape[0], l)
+                x = dd.factor_local(Al).solve(r)
+                xd = np.linalg.solve(Al.toarray(), r)
+                xp = spla.splu(Al).solve(r)
+                assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
+                assert np.linalg.norm(x - xp) <= 1e-12 * np.linalg.norm(xp)
+                assert np.linalg.norm(Al @ x - r) <= 1e-12 * np.linalg.norm(r)
