@@ -31,6 +31,21 @@ FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
 
+def factor_line(env_flops, tile_flops, seconds, precision):
+    """The factorisation against its matrix-core roofline.  achieved_env: envelope LDL^T flops
+    (8 sum_i w_i^2 / 2) per second; achieved_executed: the flops of the tiles the blocked
+    factorisation runs, per second; mfma_util = achieved_executed / peak, the fraction of the
+    matrix cores' peak rate the factorisation sustains over its whole duration (diagonal tiles,
+    launches and stream hand-offs included).  A rocprofv3 counter run of the same workload
+    (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512) counts the same executed flops; its summary gives the
+    per-kernel matrix-core busy fraction."""
+    peak = FP64_PEAK_TFS if precision == "c128" else FP32_PEAK_TFS
+    ex = tile_flops / seconds / 1e12 if seconds > 0 else 0.0
+    return {"bound": "mfma", "achieved_env": env_flops / seconds / 1e12 if seconds > 0 else 0.0,
+            "achieved_executed": ex, "peak": peak, "unit": "TFLOP/s", "mfma_util": ex / peak,
+            "executed_tflop": tile_flops / 1e12, "seconds_total": seconds}
+
+
 def instances(name):
     """(kind, xi exponent, rhs seed) of one batch."""
     if name == "scale":
@@ -517,10 +532,8 @@ def main():
                      max(sum(r["env_bytes"] for r in all_r), 1),
                      "backward": {"achieved": achieved_bwd, "frac": achieved_bwd / HBM_PEAK_GBS,
                                   "avg_launch_ms": bwd_ms / max(launches, 1)}},
-        "factor": {"bound": "mfma", "achieved_env": sum(r["env_flops"] for r in all_r) / t_factor / 1e12,
-                   "achieved_executed": sum(r["tile_flops"] for r in all_r) / t_factor / 1e12,
-                   "peak": FP64_PEAK_TFS if args.precision == "c128" else FP32_PEAK_TFS,
-                   "unit": "TFLOP/s", "seconds_total": t_factor},
+        "factor": factor_line(sum(r["env_flops"] for r in all_r), sum(r["tile_flops"] for r in all_r),
+                              t_factor, args.precision),
         "solve_phase_solves_per_s": n_solves / t_gmres if converged and t_gmres > 0 else 0.0,
         "phase_seconds_per_step": {
             "mesh_partition": sum(t for t, _ in recs) / args.steps,
