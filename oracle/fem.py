@@ -146,6 +146,25 @@ def assemble(mesh, k, xi, bc=BC_IMPEDANCE):
     return combine(K, M, Mb, k, xi, bc, pec)
 
 
+def weight_matrix(mesh, k, bc=BC_IMPEDANCE):
+    """D_k of eq:ip: the Gram matrix of the wavenumber-weighted inner product of eq:weight,
+    (v, w)_{curl,k} = (curl v, curl w) + k^2 (v, w), in the Whitney basis, i.e. D = K + k^2 M
+    (real symmetric positive definite; the boundary term of the impedance form is not part of
+    it).  With the PEC condition the constrained boundary edges get identity rows and columns,
+    as in the Galerkin matrix, so D stays positive definite on the full DOF vector and the
+    constrained DOFs do not enter the norm of the free ones."""
+    K, M, _ = assemble_parts(mesh, bfaces=np.zeros((0, 3), dtype=np.int64))
+    D = (K + (k * k) * M).tocsr()
+    if bc == BC_PEC:
+        pec = mesh.boundary_edge_mask()
+        if pec.any():
+            keep = sp.diags((~pec).astype(np.float64))
+            D = (keep @ D @ keep + sp.diags(pec.astype(np.float64))).tocsr()
+    D.sum_duplicates()
+    D.sort_indices()
+    return D
+
+
 def sparsity_pattern(mesh, tets=None):
     """Structural pattern: edge pairs sharing a tetrahedron (of the given subset)."""
     E = mesh.n_edge

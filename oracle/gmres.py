@@ -17,6 +17,15 @@ orthogonalisation or the least-squares update; this oracle uses:
 * the solve ends when the true relative residual ||b - A x|| / ||b - A x0|| <= rtol, or when
   max_iters iterations have been taken;
 * fixed_iters > 0 runs exactly that many iterations (restarting every m) ignoring rtol.
+
+Weighted GMRES (Sec. 5.2 with a Hermitian positive definite D): the iterate minimises
+||b - A x||_D = sqrt((b - A x)^H D (b - A x)) over the same Krylov space.  The Arnoldi process
+orthonormalises in <v, w>_D = w^H D v (weighted Arnoldi): h_i = <w, v_i>_D = v_i^H (D w), again
+classical Gram-Schmidt twice (D w recomputed before each pass), h_{j+1,j} = ||w||_D.  The basis
+is then D-orthonormal, so ||beta e_1 - H y||_2 = ||r||_D and the Givens least squares is
+unchanged.  Every residual norm of the method (beta, the cycle test, the true-residual test) is
+the D-norm: rtol bounds ||b - A x||_D / ||b - A x0||_D.  D = None is the standard method above
+(the same operations, not D = I).
 """
 import numpy as np
 
@@ -41,13 +50,25 @@ class Result:
 
 
 def gmres(A, b, M=None, x0=None, restart=50, rtol=1e-6, max_iters=1000, flexible=False,
-          fixed_iters=0):
-    """A: object with @ (matrix), M: callable preconditioner (None = identity)."""
+          fixed_iters=0, D=None):
+    """A: object with @ (matrix), M: callable preconditioner (None = identity), D: Hermitian
+    positive definite weight with @ (None = Euclidean inner product)."""
     n = b.shape[0]
     Mf = (lambda v: v) if M is None else M
+    if D is None:
+        norm = np.linalg.norm
+
+        def dots(Vj, w):  # v_i^H w
+            return Vj.conj() @ w
+    else:
+        def norm(w):  # ||w||_D
+            return np.sqrt(np.real(np.vdot(w, D @ w)))
+
+        def dots(Vj, w):  # <w, v_i>_D = v_i^H D w
+            return Vj.conj() @ (D @ w)
     x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
     r = b - A @ x
-    beta0 = np.linalg.norm(r)
+    beta0 = norm(r)
     history = [1.0]
     total = 0
     cycles = 0
@@ -56,7 +77,7 @@ def gmres(A, b, M=None, x0=None, restart=50, rtol=1e-6, max_iters=1000, flexible
         return Result(x, 0, 0, True, 0.0, 0.0, history)
     est = 1.0
     while True:
-        beta = np.linalg.norm(r)
+        beta = norm(r)
         if fixed_iters == 0 and beta <= rtol * beta0:
             return Result(x, total, cycles, True, beta / beta0, est, history)
         if total >= limit:
@@ -77,12 +98,12 @@ def gmres(A, b, M=None, x0=None, restart=50, rtol=1e-6, max_iters=1000, flexible
             if flexible:
                 Z[j] = z
             w = A @ z
-            h = V[: j + 1].conj() @ w
+            h = dots(V[: j + 1], w)
             w = w - V[: j + 1].T @ h
-            h2 = V[: j + 1].conj() @ w
+            h2 = dots(V[: j + 1], w)
             w = w - V[: j + 1].T @ h2
             h = h + h2
-            hn = np.linalg.norm(w)
+            hn = norm(w)
             H[: j + 1, j] = h
             H[j + 1, j] = hn
             if hn > 0:

@@ -368,3 +368,57 @@ def test_local_factor_is_exact():
                 assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
                 assert np.linalg.norm(x - xp) <= 1e-12 * np.linalg.norm(xp)
                 assert np.linalg.norm(Al @ x - r) <= 1e-12 * np.linalg.norm(r)
+
+
+@pytest.mark.parametrize("flexible", [False, True])
+def test_weighted_gmres_minimal_residual_brute_force(flexible):
+    """Weighted GMRES (Sec. 5.2): x_m minimises ||b - A x||_D over x0 + M^-1 K_m(A M^-1, r0) for a
+    Hermitian positive definite D, checked for every m against an explicit Krylov basis and a
+    dense least-squares solve in the Cholesky-transformed norm ||L^H r||_2 (D = L L^H); the
+    residual estimates are the D-norms of the residuals.  The Euclidean minimiser differs."""
+    rng = np.random.default_rng(16)
+    n = 24
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 6 * np.eye(n)
+    Minv = np.linalg.inv(A + 0.5 * rng.standard_normal((n, n)))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    D = G @ G.conj().T + 0.5 * np.eye(n)
+    L = np.linalg.cholesky(D)
+    C = A @ Minv
+    dn = lambda r: np.linalg.norm(L.conj().T @ r)
+    for msteps in range(1, 9):
+        res = gmres.gmres(A, b, lambda v: Minv @ v, restart=30, fixed_iters=msteps,
+                          flexible=flexible, D=D)
+        Kb = np.stack([np.linalg.matrix_power(C, j) @ b for j in range(msteps)], axis=1)
+        Q, _ = np.linalg.qr(Kb)
+        c, *_ = np.linalg.lstsq(L.conj().T @ (C @ Q), L.conj().T @ b, rcond=None)
+        x_ref = Minv @ (Q @ c)
+        assert np.linalg.norm(res.x - x_ref) < 1e-9 * np.linalg.norm(x_ref)
+        assert res.iters == msteps
+        assert abs(res.history[-1] - dn(b - A @ x_ref) / dn(b)) < 1e-9
+        if msteps >= 3:
+            c2, *_ = np.linalg.lstsq(C @ Q, b, rcond=None)
+            assert np.linalg.norm(Minv @ (Q @ c2) - x_ref) > 1e-6 * np.linalg.norm(x_ref)
+
+
+def test_weighted_gmres_identity_weight_and_restarts():
+    """With D = I the weighted method reproduces the standard iterates (to rounding); with the
+    finite-element weight D_k on a preconditioned Maxwell problem it converges in the D_k-norm,
+    across restarts, with the true D-norm residual below rtol."""
+    m = Mesh(6, 6, 6)
+    k, xi = 4.0, 16.0
+    A = fem.assemble(m, k, xi)
+    P = dd.Partition(m, 2, 2, 2, 2)
+    B = dd.Schwarz(P, A, dd.ORAS, k, xi)
+    f = random_rhs(m.n_edge, 9)
+    std = gmres.gmres(A, f, B, restart=3, rtol=1e-8)
+    ide = gmres.gmres(A, f, B, restart=3, rtol=1e-8, D=sp.identity(m.n_edge, format="csr"))
+    assert ide.iters == std.iters and ide.cycles == std.cycles
+    assert np.linalg.norm(ide.x - std.x) <= 1e-12 * np.linalg.norm(std.x)
+    Dk = fem.weight_matrix(m, k)
+    wgt = gmres.gmres(A, f, B, restart=3, rtol=1e-8, D=Dk)
+    dn = lambda r: np.sqrt(np.real(np.vdot(r, Dk @ r)))
+    assert wgt.converged and wgt.cycles > 1
+    assert dn(f - A @ wgt.x) <= 1e-8 * dn(f)
+    assert abs(wgt.relres_true - dn(f - A @ wgt.x) / dn(f)) <= 1e-12
+    assert abs(wgt.iters - std.iters) <= max(2, std.iters // 5)  # Sec. 6.2: little difference

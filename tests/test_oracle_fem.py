@@ -322,3 +322,54 @@ def test_manufactured_first_order():
         errs.append(_l2_error(m, u, Efun))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > 0.85) and np.all(rates < 1.3), (errs, rates)
+
+
+@pytest.mark.parametrize("lengths", [(1.0, 1.0, 1.0), (0.7, 1.3, 1.1)])
+@pytest.mark.parametrize("k", [0.0, 3.0, 11.0])
+def test_weight_matrix_is_the_gram_matrix(lengths, k):
+    """D_k (eq:ip) is the Gram matrix of (v, w)_{curl,k} = (curl v, curl w) + k^2 (v, w)
+    (eq:weight): for fields E = a + b x x, which the lowest-order Whitney space holds exactly,
+    V^H D V with V the edge interpolant equals int |curl E|^2 + k^2 int |E|^2 (curl E = 2 b),
+    computed here by a tensor Gauss rule exact for the quadratic integrand.  Also for the
+    bilinear form between two such fields."""
+    m = Mesh(4, 3, 5, *lengths)
+    D = fem.weight_matrix(m, k)
+    rng = np.random.default_rng(int(10 * k) + int(10 * lengths[0]))
+    s, w = np.polynomial.legendre.leggauss(2)
+    pts, wts = [], []
+    for (si, wi), (sj, wj), (sk, wk) in itertools.product(zip(s, w), repeat=3):
+        pts.append([(si + 1) / 2 * lengths[0], (sj + 1) / 2 * lengths[1], (sk + 1) / 2 * lengths[2]])
+        wts.append(wi * wj * wk / 8 * lengths[0] * lengths[1] * lengths[2])
+    pts, wts = np.array(pts), np.array(wts)
+    vol = lengths[0] * lengths[1] * lengths[2]
+    fields = []
+    for _ in range(2):
+        a = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        b = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        fields.append((a, b))
+    V = [fem.interpolate(m, lambda x, a=a, b=b: a[None, :] + np.cross(b[None, :], x)) for a, b in fields]
+    for (a1, b1), V1 in zip(fields, V):
+        for (a2, b2), V2 in zip(fields, V):
+            E1 = a1[None, :] + np.cross(b1[None, :], pts)
+            E2 = a2[None, :] + np.cross(b2[None, :], pts)
+            exact = 4.0 * np.vdot(b2, b1) * vol + k * k * np.sum(wts * np.sum(E1 * np.conj(E2), axis=1))
+            got = np.vdot(V2, D @ V1)
+            assert abs(got - exact) <= 1e-12 * max(1.0, abs(exact))
+    # real symmetric positive definite; k only enters through k^2 M
+    assert abs(D - D.T).max() <= 1e-14 * abs(D).max()
+    K, M, _ = fem.assemble_parts(m)
+    assert abs(D - (K + k * k * M)).max() <= 1e-14 * abs(D).max()
+
+
+def test_weight_matrix_pec_rows():
+    """With PEC, the constrained boundary edges get identity rows and columns in D_k, and the
+    free block equals that of K + k^2 M."""
+    m = Mesh(3, 3, 3)
+    Dp = fem.weight_matrix(m, 5.0, fem.BC_PEC).toarray()
+    Di = fem.weight_matrix(m, 5.0).toarray()
+    pec = m.boundary_edge_mask()
+    free = ~pec
+    assert np.array_equal(Dp[np.ix_(pec, pec)], np.eye(pec.sum()))
+    assert not Dp[np.ix_(pec, free)].any() and not Dp[np.ix_(free, pec)].any()
+    assert np.array_equal(Dp[np.ix_(free, free)], Di[np.ix_(free, free)])
+    assert np.linalg.eigvalsh(Dp).min() > 0
