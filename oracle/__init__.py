@@ -16,6 +16,9 @@ with absorption", Math. Comp. 2019 / arXiv:1711.03789):
                sets and restriction (eq:restriction1), minors (eq:minor), Boolean partition
                of unity (eq:algebPartUnity), local impedance problems (ImpRAS, Sec. 6.3),
                AS / RAS / ORAS application (eq:defAS without the coarse term, RAS_1, ImpRAS_1)
+* coarse.py    nested coarse mesh, restriction R^0 (eq:restriction), coarse Galerkin matrix and
+               the two-level AS / RAS / ImpRAS preconditioners in additive (eq:defAS,
+               eq:RAS2), hybrid (eq:HRAS) and deflated (eq:ADEF1ras) form
 * rcm.py       reverse Cuthill-McKee ordering of a local matrix graph (not in the paper: the
                paper's local solves are sparse direct; the ordering is only compared
                integer-for-integer with the library's own)
@@ -23,7 +26,7 @@ with absorption", Math. Comp. 2019 / arXiv:1711.03789):
                pool of host processes, one subdomain per task (bitwise equal to dd.Schwarz)
 * gmres.py     restarted right-preconditioned (F)GMRES with classical Gram-Schmidt twice and
                complex Givens rotations (Sec. 5.2 minimal-residual definition, Sec. 6.1
-               stopping rule)
+               stopping rule), also in the D_k-weighted inner product (eq:ip)
 
 Precision: float64 / complex128 throughout.
 """

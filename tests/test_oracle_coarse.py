@@ -1,0 +1,119 @@
+"""The oracle's coarse space and two-level preconditioners (Sec. 3.2, Sec. 3.3, Sec. 6.3) against
+what the paper and the mathematics fix:
+* the Galerkin coarse matrix R^0 A (R^0)^T (eq:minor, l = 0) of the nested coarse space equals the
+  Galerkin matrix assembled directly on the coarse mesh (Sec. 3.3: "the Galerkin matrix for the
+  variational problem discretised in the coarse space"), impedance and PEC;
+* (R^0)^T interpolates coarse fields into the fine space exactly: fields a + b x x, which both
+  Whitney spaces hold, map to their fine interpolant;
+* a coarse mesh equal to the fine one makes R^0 the identity and the hybrid and deflated
+  two-level preconditioners the exact inverse (GMRES: one iteration);
+* the hybrid (eq:HRAS) and deflated (eq:ADEF1ras) forms act as the identity on A applied to the
+  coarse space, B A (R^0)^T y = (R^0)^T y; the additive AS form (eq:defAS) is complex symmetric;
+* context only (parity unpinned against the paper's meshes): the two-level methods take fewer
+  GMRES iterations than the one-level ones (Table tab:1 parentheses, Table tab:rasHras)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from mx_inputs import random_rhs
+from oracle import coarse, dd, fem, gmres
+from oracle.mesh import Mesh
+
+
+@pytest.mark.parametrize("n,ratio,lengths", [((8, 8, 8), 2, (1, 1, 1)), ((8, 4, 6), 2, (0.7, 1.3, 1.1)),
+                                             ((12, 6, 9), 3, (1, 1, 1)), ((4, 4, 4), 4, (1, 1, 1))])
+@pytest.mark.parametrize("bc", [fem.BC_IMPEDANCE, fem.BC_PEC])
+def test_coarse_galerkin_matrix_equals_coarse_assembly(n, ratio, lengths, bc):
+    f = Mesh(*n, *lengths)
+    c = coarse.coarse_mesh(f, ratio)
+    R = coarse.restriction(f, c, bc)
+    keep = coarse.coarse_dofs(c, bc)
+    assert R.shape == (len(keep), f.n_edge)
+    for k, xi in ((4.0, 16.0), (2.5, -3.0), (6.0, 0.0)):
+        A = fem.assemble(f, k, xi, bc)
+        A0 = (R @ A @ R.T).tocsr()
+        Ac = fem.assemble(c, k, xi, bc)[keep][:, keep]
+        assert abs(A0 - Ac).max() <= 1e-13 * abs(Ac).max()
+    if bc == fem.BC_PEC:  # interior coarse functions have zero trace: no fine boundary DOF
+        assert abs(R[:, f.boundary_edge_mask()]).max() <= 1e-14
+
+
+@pytest.mark.parametrize("ratio", [2, 3])
+def test_coarse_interpolation_of_whitney_fields(ratio):
+    f = Mesh(6, 6, 12, 1.0, 0.8, 1.2)
+    c = coarse.coarse_mesh(f, ratio)
+    R = coarse.restriction(f, c)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        a = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        b = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        E = lambda x: a[None, :] + np.cross(b[None, :], x)
+        assert np.abs(R.T @ fem.interpolate(c, E) - fem.interpolate(f, E)).max() <= 1e-13
+
+
+def test_coarse_equal_to_fine_is_exact():
+    f = Mesh(5, 4, 3)
+    c = coarse.coarse_mesh(f, 1)
+    R = coarse.restriction(f, c)
+    assert abs(R - sp.identity(f.n_edge)).max() <= 1e-14
+    k, xi = 3.0, 9.0
+    A = fem.assemble(f, k, xi)
+    P = dd.Partition(f, 2, 2, 1, 1)
+    b = random_rhs(f.n_edge, 1)
+    x = sp.linalg.spsolve(A.tocsc(), b)
+    for combine in (coarse.HYBRID, coarse.DEFLATION):
+        B = coarse.TwoLevel(dd.Schwarz(P, A, dd.ORAS, k, xi), A, R, combine)
+        assert np.linalg.norm(B(b) - x) <= 1e-10 * np.linalg.norm(x)
+        res = gmres.gmres(A, b, B, restart=20, rtol=1e-8)
+        assert res.converged and res.iters == 1
+
+
+@pytest.mark.parametrize("kind", [dd.RAS, dd.ORAS])
+def test_hybrid_and_deflation_are_exact_on_the_coarse_space(kind):
+    f = Mesh(8, 8, 8)
+    c = coarse.coarse_mesh(f, 4)
+    k, xi = 4.0, 16.0
+    A = fem.assemble(f, k, xi)
+    R = coarse.restriction(f, c)
+    B1 = dd.Schwarz(dd.Partition(f, 2, 2, 2, 2), A, kind, k, xi)
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(R.shape[0]) + 1j * rng.standard_normal(R.shape[0])
+    u = R.T @ y
+    for combine in (coarse.HYBRID, coarse.DEFLATION):
+        B = coarse.TwoLevel(B1, A, R, combine)
+        assert np.linalg.norm(B(A @ u) - u) <= 1e-10 * np.linalg.norm(u)
+    Badd = coarse.TwoLevel(B1, A, R, coarse.ADDITIVE)  # the additive form is not
+    assert np.linalg.norm(Badd(A @ u) - u) > 1e-3 * np.linalg.norm(u)
+
+
+def test_two_level_as_is_complex_symmetric():
+    f = Mesh(4, 4, 4)
+    c = coarse.coarse_mesh(f, 2)
+    k, xi = 3.0, 9.0
+    A = fem.assemble(f, k, xi)
+    B = coarse.TwoLevel(dd.Schwarz(dd.Partition(f, 2, 2, 1, 1), A, dd.AS, k, xi), A,
+                        coarse.restriction(f, c), coarse.ADDITIVE)
+    M = np.stack([B(e) for e in np.eye(f.n_edge)], axis=1)
+    assert np.abs(M - M.T).max() <= 1e-12 * np.abs(M).max()
+    assert np.abs(M - M.conj().T).max() > 1e-6 * np.abs(M).max()
+
+
+def test_paper_ordering_two_level_beats_one_level():
+    """Context, not parity (the paper's meshes, partition of unity and x0 differ): on a 16^3
+    box with 4x4x4 subdomains and a coarse mesh of 8^3 cubes, at xi = k, every two-level form
+    takes fewer GMRES iterations than its one-level base, as in Tables tab:1 and tab:rasHras."""
+    f = Mesh(16, 16, 16)
+    c = coarse.coarse_mesh(f, 2)
+    k, xi = 6.0, 6.0
+    A = fem.assemble(f, k, xi)
+    P = dd.Partition(f, 4, 4, 4, 2)
+    R = coarse.restriction(f, c)
+    b = fem.load_vector(f, fem.gaussian_source((0.5, 0.5, 0.5), (1, 0, 0), 0.1))
+    for kind, combos in ((dd.AS, (coarse.ADDITIVE,)),
+                         (dd.RAS, (coarse.ADDITIVE, coarse.HYBRID, coarse.DEFLATION)),
+                         (dd.ORAS, (coarse.ADDITIVE, coarse.HYBRID, coarse.DEFLATION))):
+        B1 = dd.Schwarz(P, A, kind, k, xi)
+        one = gmres.gmres(A, b, B1, restart=100, rtol=1e-6).iters
+        for comb in combos:
+            two = gmres.gmres(A, b, coarse.TwoLevel(B1, A, R, comb), restart=100, rtol=1e-6).iters
+            assert two < one, (kind, comb, one, two)
