@@ -268,6 +268,20 @@ typedef struct {
 int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
              const mx_gmres_opts *opts, mx_gmres_stats *stats, double *res_hist, void *stream);
 
+/* The same solve as mx_gmres for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the Krylov workspace
+ * (basis, Hessenberg matrix, rotations, reduction partials, status) lives in a fixed array of
+ * 64 MiB per GPU that the library holds from the first mx_ctx_create on that GPU until the
+ * process ends, instead of the context's workspace, and the call makes no device allocation.
+ * Workspace bytes are about 16 E (restart + 5) (+ 16 E restart when flexible); a call needing
+ * more than the array returns MX_EINVAL without enqueuing work.  The preconditioner, matrix and
+ * vectors are the caller's as for mx_gmres; results are identical to mx_gmres's.  Every call on
+ * one GPU shares that GPU's array: calls that overlap in time on the same GPU (from several
+ * host threads or on several streams) race and must not be made.  Errors: as mx_gmres. */
+int mx_gmres_noalloc(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev,
+                     void *x_dev, const mx_gmres_opts *opts, mx_gmres_stats *stats,
+                     double *res_hist, void *stream);
+
 /* ---- solve server: continuous batching of independent solves -------------------------------- */
 /* Requests are unit-cube problems solved by the path above (Sec. 6.1 workloads).  `slots` worker
  * threads, each with its own HIP stream, pull requests in submission order; a slot first does the

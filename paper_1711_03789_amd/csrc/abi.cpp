@@ -63,6 +63,7 @@ int mx_ctx_create(int device, mx_ctx **out) {
     auto c = std::make_unique<mx_ctx>();
     c->device = device;
     c->cus = prop.multiProcessorCount;
+    mx::noalloc_scratch_init(device);
     MX_HIP(hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault));
     *out = c.release();
   });
@@ -393,6 +394,20 @@ int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, 
     if (P) mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream);
+  });
+}
+
+int mx_gmres_noalloc(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
+                     const mx_gmres_opts *opts, mx_gmres_stats *stats, double *res_hist, void *stream) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && A && b_dev && x_dev && opts && stats, "NULL argument");
+    MX_REQUIRE(b_dev != x_dev, "b and x must be distinct");
+    MX_REQUIRE(A->rowptr.p, "matrix has no device copy");
+    MX_REQUIRE(!P || P->E == A->h.n, "preconditioner and matrix sizes differ");
+    MX_REQUIRE(!P || !P->plan, "preconditioner is planned but not materialised");
+    if (P) mx::precond_refuse_failed(P);
+    bind_device(ctx->device);
+    mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream, true);
   });
 }
 

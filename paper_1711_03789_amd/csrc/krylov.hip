@@ -8,7 +8,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <random>
+#include <string>
 
 #include "device_common.hpp"
 #include "objects.hpp"
@@ -317,8 +319,41 @@ void matrix_upload(mx_matrix *A) {
   restore();
 }
 
+// ---- fixed device scratch for GMRES without allocation -------------------------------------------
+// One array per device, held by the code object until the process ends.  In host code `scratch`
+// only stands for the symbol; its device address (one per GPU) comes from hipGetSymbolAddress,
+// taken once per device when a context is created there, and only that address is handed to
+// kernels and copies.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+void noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(MX_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  int cur = 0;
+  MX_HIP(hipGetDevice(&cur));
+  if (cur != device) fail(MX_EDEVICE, "scratch set-up needs its device current");
+  void *ptr = nullptr;
+  MX_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) fail(MX_EDEVICE, "no device address for the GMRES scratch array");
+  g_scratch_ptr[device] = ptr;
+}
+
+static void *noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  void *p = (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+  if (!p) fail(MX_EDEVICE, "GMRES scratch not set up on this device (create a context first)");
+  return p;
+}
+
 void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
-               const mx_gmres_opts *o, mx_gmres_stats *stats, double *hist, hipStream_t st) {
+               const mx_gmres_opts *o, mx_gmres_stats *stats, double *hist, hipStream_t st,
+               bool noalloc) {
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t n = A->h.n;
   const int m = o->restart;
@@ -345,7 +380,17 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
   const size_t oY = off; off += al((size_t)(m + 1) * 16);
   const size_t oN = off; off += 256;
   const size_t oST = off; off += 256;
-  char *ws = (char *)ctx->krylov.get(off);
+  char *ws = nullptr;
+  if (noalloc) {
+    if (off > kNoAllocScratchBytes)
+      fail(MX_EINVAL, "GMRES without allocation needs " + std::to_string(off) +
+                          " bytes of workspace; its fixed scratch holds " +
+                          std::to_string(kNoAllocScratchBytes) +
+                          " (fewer unknowns or a shorter restart, or use mx_gmres)");
+    ws = (char *)noalloc_scratch(ctx->device);
+  } else {
+    ws = (char *)ctx->krylov.get(off);
+  }
   cx<double> *V = (cx<double> *)(ws + oV), *Z = flex ? (cx<double> *)(ws + oZ) : nullptr;
   cx<double> *w = (cx<double> *)(ws + oW), *r = (cx<double> *)(ws + oR);
   cx<double> *tmp = (cx<double> *)(ws + oT), *u = (cx<double> *)(ws + oU);

@@ -221,7 +221,14 @@ void precond_export_diag(const mx_precond *P, int l, double *d);
 void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd, double *ms_bwd);
 void spmv_run(const mx_matrix *A, const void *x, void *y, bool c64, hipStream_t st);
 void matrix_upload(mx_matrix *A);
+// noalloc: the Krylov workspace is the fixed per-device scratch array (at most
+// kNoAllocScratchBytes; larger requests fail with MX_EINVAL) instead of the context's workspace
 void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
-               const mx_gmres_opts *o, mx_gmres_stats *stats, double *hist, hipStream_t st);
+               const mx_gmres_opts *o, mx_gmres_stats *stats, double *hist, hipStream_t st,
+               bool noalloc = false);
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+// takes the device address of the GMRES scratch array on `device` (must be current); idempotent
+void noalloc_scratch_init(int device);
 void selftest_run(double *e64, double *e32);
 }  // namespace mx

@@ -32,7 +32,7 @@ SYMBOLS = [
     "mx_precond_sweep_timing", "mx_precond_autotune", "mx_server_create", "mx_server_submit",
     "mx_server_wait", "mx_server_solution", "mx_server_release", "mx_server_stats",
     "mx_server_destroy", "mx_matrix_upload", "mx_precond_plan", "mx_precond_materialize",
-    "mx_selftest_host",
+    "mx_selftest_host", "mx_gmres_noalloc",
 ]
 
 
@@ -161,6 +161,8 @@ def load(path=LIB_PATH):
                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "mx_precond_destroy": (None, [P]),
         "mx_gmres": (C.c_int, [P, P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresStats), P, P]),
+        "mx_gmres_noalloc": (C.c_int, [P, P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresStats), P,
+                                       P]),
         "mx_selftest": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "mx_selftest_host": (C.c_int, [C.c_int64, C.c_int64, C.c_int, C.POINTER(C.c_int64)]),
         "mx_local_problem": (C.c_int, [P, P, P, C.POINTER(PrecondOpts), C.c_int,
@@ -430,11 +432,13 @@ class Precond:
 
 
 def gmres(ctx, A, Pc, b, x, restart=50, rtol=1e-6, max_iters=1000, flexible=False,
-          fixed_iters=0, spmv_c64=False, history=False, stream=None):
+          fixed_iters=0, spmv_c64=False, history=False, stream=None, noalloc=False):
+    """noalloc=True calls mx_gmres_noalloc (fixed per-GPU workspace, no device allocation)."""
     o = GmresOpts(restart, max_iters, int(flexible), fixed_iters, int(spmv_c64), rtol)
     st = GmresStats()
     hist = np.zeros(max(max_iters, fixed_iters) + 2, np.float64) if history else None
-    _check(_lib.mx_gmres(ctx.h, A.h, Pc.h if Pc is not None else None, _dvec(b, A.n, "b"),
+    fn = _lib.mx_gmres_noalloc if noalloc else _lib.mx_gmres
+    _check(fn(ctx.h, A.h, Pc.h if Pc is not None else None, _dvec(b, A.n, "b"),
                          _dvec(x, A.n, "x"),
                          C.byref(o), C.byref(st), _ptr(hist), _stream(stream)))
     out = st.as_dict()
