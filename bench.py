@@ -374,6 +374,10 @@ def main():
     ap.add_argument("--calib-requests", type=int, default=24, help="serving: calibration requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: requests in flight")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--coarse", type=int, default=0,
+                    help="two-level: coarse mesh with this many times fewer cubes per axis (0: one-level)")
+    ap.add_argument("--combine", default="hybrid", choices=["additive", "hybrid", "deflation"],
+                    help="two-level form (eq:defAS / eq:RAS2, eq:HRAS, eq:ADEF1ras)")
     ap.add_argument("--overlap-factor", type=int, default=0, choices=[0, 1],
                     help="1: the next instance's factorisation also runs on the second host "
                          "thread (its own non-blocking stream), overlapping the current GMRES")
@@ -406,6 +410,11 @@ def main():
         cfg["workload"] = cfg["workload"].replace(
             "GMRES(", "FGMRES(").replace("complex128", "complex64 factors and SpMV values, FP64 "
                                                       "Krylov vectors")
+    if args.coarse:
+        if args.workload == "scale-xi0" or args.overlap_factor:
+            raise SystemExit("--coarse is not combined with scale-xi0 or --overlap-factor")
+        cfg["workload"] += ("; two-level (%s) with a nested coarse mesh of %s cubes"
+                            % (args.combine, "x".join(str(v // args.coarse) for v in w.n)))
     ctx = mx.Context(0)
     n = w.n
     # inputs resident in HBM before the timed region
@@ -460,6 +469,11 @@ def main():
                     fut = ex.submit(prepare, mesh, part, inst[idx + 1][0], inst[idx + 1][1])
                 if fstream is None:
                     P.materialize(ctx)
+                t_coarse = 0.0
+                if args.coarse:
+                    tc = time.perf_counter()
+                    P.add_coarse(ctx, A, mesh, args.coarse, args.combine)
+                    t_coarse = time.perf_counter() - tc
                 t2 = time.perf_counter()
                 if record:
                     P.sweep_timing(True)
@@ -472,7 +486,7 @@ def main():
                 r = {"kind": kind, "xi": 0.0 if xi0 else xi, "xi_prec": xi,
                      "iters": st["iters"], "converged": st["converged"],
                      "relres": st["relres_true"], "t_assemble": t_asm, "t_precond_plan": t_pre,
-                     "t_gmres": t3 - t2}
+                     "t_gmres": t3 - t2, "t_coarse": t_coarse}
                 inf = P.info()
                 r.update({"t_precond_host": inf["t_host_setup"], "t_upload": inf["t_upload"],
                           "t_factor": inf["t_factor"], "env_flops": inf["env_flops"],

@@ -94,6 +94,12 @@ void mx_mesh_destroy(mx_mesh *m);
 /* ctx may be NULL: the matrix is then host-only until mx_matrix_upload. */
 int mx_matrix_assemble(mx_ctx *ctx, const mx_mesh *m, double k, double xi, int bc,
                        mx_matrix **out);
+/* D_k of eq:ip: the Gram matrix of the wavenumber-weighted inner product of eq:weight,
+ * (v, w)_{curl,k} = (curl v, curl w) + k^2 (v, w), in the edge basis: D = K + k^2 M (real
+ * symmetric positive definite, stored like a Galerkin matrix with zero imaginary parts; no
+ * boundary term; PEC: identity rows and columns on boundary edges).  For mx_gmres_weighted.
+ * ctx may be NULL (host-only until mx_matrix_upload).  Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE. */
+int mx_weight_assemble(mx_ctx *ctx, const mx_mesh *m, double k, int bc, mx_matrix **out);
 /* Device copy of a host-only matrix (assembled with ctx = NULL).  The copies run on a private
  * stream that does not wait for other streams, and the call returns when they are done, so
  * another host thread may upload the next matrix while the device works.  Errors: MX_EINVAL
@@ -236,6 +242,41 @@ int mx_precond_sweep_timing(mx_precond *P, int enable, int64_t *launches, double
  * Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_ESTALL. */
 int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_grid,
                         double *best_ms);
+/* ---- two-level preconditioners (Sec. 3.2, Sec. 3.3, Sec. 6.3) ------------------------------ */
+#define MX_COARSE_ADDITIVE 0   /* B = B1 + G: AS_2 (eq:defAS), RAS_2 (eq:RAS2), ImpRAS_2            */
+#define MX_COARSE_HYBRID 1     /* B = (I - G A) B1 (I - A G) + G: HRAS, ImpHRAS (eq:HRAS)           */
+#define MX_COARSE_DEFLATION 2  /* B = B1 (I - A G) + G: ADEF1-RAS, ADEF1-ImpRAS (eq:ADEF1ras)       */
+/* Adds a coarse level to the materialised one-level preconditioner P (B1: AS, RAS or ORAS =
+ * ImpRAS), which was built from A on mesh m (all subdomains, not a resident share).  Coarse
+ * mesh: the box of m with `ratio` times fewer cubes on every axis (ratio must divide each
+ * count; the two meshes are then nested).  Coarse basis: the Whitney functions of the coarse
+ * edges (PEC: those with zero tangential trace).  R^0 (eq:restriction): (R^0)_pj = fine DOF j of
+ * coarse basis function p (line integral along fine edge j); A^0 = R^0 A R^0^T (eq:minor),
+ * factored on the device like a local problem; G = R^0^T (A^0)^-1 R^0.  Afterwards
+ * mx_precond_apply and mx_gmres with P apply the two-level form `combine` (MX_COARSE_*).  A is
+ * borrowed: it must have a device copy and outlive P (the hybrid and deflated forms multiply by
+ * it), and it must be the matrix P was built from (same k and bc, xi = the xi of the local
+ * problems).  Synchronous on `stream`, which must outlive P.
+ * Errors: MX_EINVAL (ratio, matrix, a share, already two-level), MX_ENOMEM, MX_EDEVICE,
+ * MX_EPIVOT. */
+int mx_precond_add_coarse(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m,
+                          int ratio, int combine, void *stream);
+/* Host copies of the coarse level, for inspection and tests: R^0 as CSR r_rowptr[n_coarse+1],
+ * r_col[nnz_r] (fine edge ids), r_val[nnz_r] (real), and A^0 as a_rowptr[n_coarse+1],
+ * a_col[nnz_a], a_val[2*nnz_a] (complex128).  Rows are all coarse edges: with PEC the boundary
+ * edges carry no basis function, so their R^0 rows are empty and their A^0 rows are unit rows.
+ * Any pointer may be NULL (call first with the arrays NULL for the sizes).  Errors: MX_EINVAL
+ * (no coarse level). */
+int mx_precond_coarse_export(const mx_precond *P, int64_t *n_coarse, int64_t *nnz_r,
+                             int64_t *nnz_a, int64_t *r_rowptr, int32_t *r_col, double *r_val,
+                             int64_t *a_rowptr, int32_t *a_col, double *a_val);
+/* Host-only: the coarse operators mx_precond_add_coarse builds for a matrix A on mesh m (same
+ * layout as mx_precond_coarse_export), without a preconditioner or a device.  Call with the six
+ * arrays NULL to get the sizes; then *n_coarse, *nnz_r and *nnz_a must hold those sizes.
+ * Errors: MX_EINVAL. */
+int mx_coarse_operators(const mx_mesh *m, const mx_matrix *A, int ratio, int64_t *n_coarse,
+                        int64_t *nnz_r, int64_t *nnz_a, int64_t *r_rowptr, int32_t *r_col,
+                        double *r_val, int64_t *a_rowptr, int32_t *a_col, double *a_val);
 /* Checks the device error word of P (set by a failed pivot or an expired wait).  Once such an
  * error has been reported (by this call, mx_gmres or mx_precond_autotune), P is unusable: its
  * device flags stay set, and every later mx_precond_apply, mx_precond_autotune, mx_gmres and
@@ -267,6 +308,16 @@ typedef struct {
  * Synchronous.  Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_ENAN, MX_ESTALL. */
 int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
              const mx_gmres_opts *opts, mx_gmres_stats *stats, double *res_hist, void *stream);
+
+/* Weighted GMRES (Sec. 5.2, eq:ip): as mx_gmres, but the iterate minimises ||b - A x||_D over
+ * the Krylov space, with <v, w>_D = w^H D v for a Hermitian positive definite D (e.g. D_k from
+ * mx_weight_assemble).  The Arnoldi process orthonormalises in <.,.>_D (classical Gram-Schmidt
+ * twice, D w formed before each pass and for the norm: three products with D per iteration),
+ * so the Givens least squares is unchanged, and every residual norm (the estimate, rtol, the
+ * true-residual test, res_hist) is the D-norm.  D = NULL is mx_gmres.  Errors: as mx_gmres. */
+int mx_gmres_weighted(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const mx_matrix *D,
+                      const void *b_dev, void *x_dev, const mx_gmres_opts *opts,
+                      mx_gmres_stats *stats, double *res_hist, void *stream);
 
 /* The same solve as mx_gmres for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the Krylov workspace

@@ -134,6 +134,23 @@ int mx_matrix_assemble(mx_ctx *ctx, const mx_mesh *m, double k, double xi, int b
   });
 }
 
+int mx_weight_assemble(mx_ctx *ctx, const mx_mesh *m, double k, int bc, mx_matrix **out) {
+  MX_GUARD({
+    MX_REQUIRE(m && out, "NULL argument");
+    MX_REQUIRE(bc == MX_BC_PEC || bc == MX_BC_IMPEDANCE, "unknown boundary condition");
+    MX_REQUIRE(std::isfinite(k) && k >= 0, "need finite k >= 0");
+    auto D = std::make_unique<mx_matrix>();
+    D->k = k, D->xi = 0, D->bc = bc, D->weight = true;
+    mx::assemble_global(m->m, k, 0.0, bc, D->h, true);
+    if (ctx) {
+      bind_device(ctx->device);
+      D->device = ctx->device;
+      mx::matrix_upload(D.get());
+    }
+    *out = D.release();
+  });
+}
+
 int mx_matrix_upload(mx_ctx *ctx, mx_matrix *A) {
   MX_GUARD({
     MX_REQUIRE(ctx && A, "NULL argument");
@@ -397,6 +414,57 @@ int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, 
   });
 }
 
+int mx_precond_add_coarse(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m,
+                          int ratio, int combine, void *stream) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && P && A && m, "NULL argument");
+    MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
+    mx::precond_refuse_failed(P);
+    bind_device(ctx->device);
+    mx::coarse_setup(ctx, P, A, m, ratio, combine, (hipStream_t)stream);
+  });
+}
+
+int mx_coarse_operators(const mx_mesh *m, const mx_matrix *A, int ratio, int64_t *n_coarse,
+                        int64_t *nnz_r, int64_t *nnz_a, int64_t *r_rowptr, int32_t *r_col,
+                        double *r_val, int64_t *a_rowptr, int32_t *a_col, double *a_val) {
+  MX_GUARD({
+    MX_REQUIRE(m && A && n_coarse && nnz_r && nnz_a, "NULL argument");
+    MX_REQUIRE(A->h.n == m->m.ne, "matrix and mesh sizes differ");
+    MX_REQUIRE(ratio >= 1 && m->m.nx % ratio == 0 && m->m.ny % ratio == 0 && m->m.nz % ratio == 0,
+               "the coarse ratio must divide the cube count of every axis");
+    mx::Mesh cm;
+    mx::build_mesh(cm, m->m.nx / ratio, m->m.ny / ratio, m->m.nz / ratio, m->m.lx, m->m.ly, m->m.lz);
+    mx::HostCSR R0, R0T, A0;
+    mx::build_restriction(m->m, cm, ratio, A->bc, R0, R0T);
+    mx::galerkin_coarse(A->h, R0, R0T, cm, A->bc, A0);
+    const bool sizes_only = !r_rowptr && !r_col && !r_val && !a_rowptr && !a_col && !a_val;
+    if (!sizes_only) {
+      MX_REQUIRE(*n_coarse == R0.n && *nnz_r == R0.nnz() && *nnz_a == A0.nnz(),
+                 "buffer sizes differ from the coarse operators' (query them first)");
+      if (r_rowptr) std::copy(R0.rowptr.begin(), R0.rowptr.end(), r_rowptr);
+      if (r_col) std::copy(R0.col.begin(), R0.col.end(), r_col);
+      if (r_val)
+        for (int64_t q = 0; q < R0.nnz(); ++q) r_val[q] = R0.val[2 * q];
+      if (a_rowptr) std::copy(A0.rowptr.begin(), A0.rowptr.end(), a_rowptr);
+      if (a_col) std::copy(A0.col.begin(), A0.col.end(), a_col);
+      if (a_val) std::copy(A0.val.begin(), A0.val.end(), a_val);
+    }
+    *n_coarse = R0.n;
+    *nnz_r = R0.nnz();
+    *nnz_a = A0.nnz();
+  });
+}
+
+int mx_precond_coarse_export(const mx_precond *P, int64_t *n_coarse, int64_t *nnz_r, int64_t *nnz_a,
+                             int64_t *r_rowptr, int32_t *r_col, double *r_val, int64_t *a_rowptr,
+                             int32_t *a_col, double *a_val) {
+  MX_GUARD({
+    MX_REQUIRE(P, "NULL argument");
+    mx::coarse_export(P, n_coarse, nnz_r, nnz_a, r_rowptr, r_col, r_val, a_rowptr, a_col, a_val);
+  });
+}
+
 int mx_gmres_noalloc(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
                      const mx_gmres_opts *opts, mx_gmres_stats *stats, double *res_hist, void *stream) {
   MX_GUARD({
@@ -408,6 +476,22 @@ int mx_gmres_noalloc(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void 
     if (P) mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream, true);
+  });
+}
+
+int mx_gmres_weighted(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const mx_matrix *D,
+                      const void *b_dev, void *x_dev, const mx_gmres_opts *opts,
+                      mx_gmres_stats *stats, double *res_hist, void *stream) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && A && b_dev && x_dev && opts && stats, "NULL argument");
+    MX_REQUIRE(b_dev != x_dev, "b and x must be distinct");
+    MX_REQUIRE(A->rowptr.p, "matrix has no device copy");
+    MX_REQUIRE(!D || (D->rowptr.p && D->h.n == A->h.n), "weight needs a device copy of A's size");
+    MX_REQUIRE(!P || P->E == A->h.n, "preconditioner and matrix sizes differ");
+    MX_REQUIRE(!P || !P->plan, "preconditioner is planned but not materialised");
+    if (P) mx::precond_refuse_failed(P);
+    bind_device(ctx->device);
+    mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream, false, D);
   });
 }
 

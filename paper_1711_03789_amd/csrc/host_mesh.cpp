@@ -303,11 +303,13 @@ static void merge_entries(std::vector<Entry> &ent, std::vector<int32_t> &slot) {
 
 static double imp_sign(double xi) { return xi >= 0 ? 1.0 : -1.0; }
 
-// Row e of the global matrix: tetrahedra in ascending id, then boundary triangles.
+// Row e of the global matrix: tetrahedra in ascending id, then boundary triangles.  With
+// `weight`, row e of the weight D_k = K + k^2 M instead (no boundary term).
 static void global_row(const Mesh &m, const KuhnElements &ke, double k, double xi, int bc,
-                       int64_t e, std::vector<Entry> &ent, std::vector<int32_t> &slot) {
+                       bool weight, int64_t e, std::vector<Entry> &ent, std::vector<int32_t> &slot) {
   ent.clear();
-  const double sre = -k * k, sim = -xi;  // coefficient -(k^2 + i xi) of M
+  // coefficient -(k^2 + i xi) of M, or +k^2 for the weight
+  const double sre = weight ? k * k : -k * k, sim = weight ? 0.0 : -xi;
   for (int64_t q = m.et_ptr[e]; q < m.et_ptr[e + 1]; ++q) {
     int32_t t = m.et_tet[q];
     int a = m.et_loc[q];
@@ -319,7 +321,7 @@ static void global_row(const Mesh &m, const KuhnElements &ke, double k, double x
                      s * sim * ke.M[p][a][b]});
     }
   }
-  if (bc == MX_BC_IMPEDANCE) {
+  if (bc == MX_BC_IMPEDANCE && !weight) {
     double cb = -imp_sign(xi) * k;  // coefficient -i sign(xi) k of M_b (purely imaginary)
     for (int64_t q = m.eb_ptr[e]; q < m.eb_ptr[e + 1]; ++q) {
       int32_t f = m.eb_face[q];
@@ -344,7 +346,7 @@ static void global_row(const Mesh &m, const KuhnElements &ke, double k, double x
   }
 }
 
-void assemble_global(const Mesh &m, double k, double xi, int bc, HostCSR &A) {
+void assemble_global(const Mesh &m, double k, double xi, int bc, HostCSR &A, bool weight) {
   KuhnElements ke;
   kuhn_elements(m.lx / m.nx, m.ly / m.ny, m.lz / m.nz, ke);
   A.n = m.ne;
@@ -362,7 +364,7 @@ void assemble_global(const Mesh &m, double k, double xi, int bc, HostCSR &A) {
       std::vector<Entry> &out = part[t];
       out.reserve((size_t)std::max<int64_t>(0, b - a) * 17);  // about 16.3 entries per row
       for (int64_t e = a; e < b; ++e) {
-        global_row(m, ke, k, xi, bc, e, ent, slot);
+        global_row(m, ke, k, xi, bc, weight, e, ent, slot);
         A.rowptr[e + 1] = (int64_t)ent.size();
         out.insert(out.end(), ent.begin(), ent.end());
       }

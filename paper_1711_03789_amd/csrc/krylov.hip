@@ -319,6 +319,133 @@ void matrix_upload(mx_matrix *A) {
   restore();
 }
 
+// ---- two-level preconditioners (Sec. 3.2, 3.3, 6.3) -------------------------------------------------
+// The coarse problem A^0 = R^0 A R^0^T is factored and solved by the same batched LDL^T and block
+// sweeps as the local problems: it is the single subdomain of a one-level AS preconditioner on
+// the coarse mesh whose matrix is A^0 (its minor over every coarse edge is A^0 itself), so
+// G v = R^0^T (A^0)^-1 R^0 v is an SpMV, that application, and an SpMV.
+struct CoarseLevel {
+  int ratio = 0, combine = MX_COARSE_ADDITIVE;
+  mx_mesh mesh;                    // coarse box mesh
+  mx_partition part;               // one subdomain, no overlap
+  mx_matrix R0, R0T, A0;           // restriction (coarse x fine), its transpose, coarse matrix
+  std::unique_ptr<mx_precond> P0;  // factored coarse problem
+  const mx_matrix *A = nullptr;    // fine matrix the preconditioner is built for (borrowed)
+  DevBuf c, y, g, t, s, u;         // coarse vectors c, y; fine vectors g = G v, t, s, u
+};
+
+void coarse_free(CoarseLevel *c) { delete c; }
+
+// z = s - w + g
+__global__ void k_hybrid_finish(int64_t n, const cx<double> *s, const cx<double> *w,
+                                const cx<double> *g, cx<double> *z) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = cadd(csub(s[i], w[i]), g[i]);
+}
+
+static void coarse_correction(CoarseLevel &C, const void *in, cx<double> *out, hipStream_t st) {
+  spmv_run(&C.R0, in, C.c.p, false, st);                 // c = R^0 in
+  precond_apply_level1(C.P0.get(), C.c.p, C.y.p, st);   // y = (A^0)^-1 c
+  spmv_run(&C.R0T, C.y.p, out, false, st);               // out = R^0^T y
+}
+
+void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
+  if (!P->coarse) {
+    precond_apply_level1(P, vin, zout, st);
+    return;
+  }
+  CoarseLevel &C = *P->coarse;
+  const int64_t n = P->E;
+  cx<double> *z = (cx<double> *)zout, *g = C.g.as<cx<double>>();
+  const cx<double> *v = (const cx<double> *)vin;
+  coarse_correction(C, vin, g, st);  // g = G v
+  if (C.combine == MX_COARSE_ADDITIVE) {  // B1 v + G v (eq:defAS, eq:RAS2)
+    precond_apply_level1(P, vin, zout, st);
+    k_add<<<nblk(n), 256, 0, st>>>(n, z, g);
+  } else {
+    cx<double> *t = C.t.as<cx<double>>(), *u = C.u.as<cx<double>>();
+    spmv_run(C.A, g, u, false, st);
+    k_sub<<<nblk(n), 256, 0, st>>>(n, v, u, t);  // t = (I - A G) v
+    if (C.combine == MX_COARSE_DEFLATION) {     // B1 (I - A G) v + G v (eq:ADEF1ras)
+      precond_apply_level1(P, t, zout, st);
+      k_add<<<nblk(n), 256, 0, st>>>(n, z, g);
+    } else {                                    // (I - G A) B1 (I - A G) v + G v (eq:HRAS)
+      cx<double> *s = C.s.as<cx<double>>();
+      precond_apply_level1(P, t, s, st);
+      spmv_run(C.A, s, u, false, st);
+      coarse_correction(C, u, t, st);           // t = G A s
+      k_hybrid_finish<<<nblk(n), 256, 0, st>>>(n, s, t, g, z);
+    }
+  }
+  MX_HIP(hipGetLastError());
+}
+
+void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *mh, int ratio,
+                  int combine, hipStream_t st) {
+  const Mesh &m = mh->m;
+  if (P->coarse) fail(MX_EINVAL, "preconditioner already has a coarse level");
+  if (P->share) fail(MX_EINVAL, "a resident share cannot have a coarse level");
+  if (combine < MX_COARSE_ADDITIVE || combine > MX_COARSE_DEFLATION) fail(MX_EINVAL, "unknown coarse combination");
+  if (ratio < 1 || m.nx % ratio || m.ny % ratio || m.nz % ratio)
+    fail(MX_EINVAL, "the coarse ratio must divide the cube count of every axis");
+  if (A->h.n != P->E || m.ne != P->E) fail(MX_EINVAL, "matrix, mesh and preconditioner sizes differ");
+  if (A->k != P->k || A->xi != P->xi_prec || A->bc != P->bc)
+    fail(MX_EINVAL, "the matrix is not the one the preconditioner was built for (k, xi_prec, bc)");
+  if (!A->rowptr.p) fail(MX_EINVAL, "matrix has no device copy");
+  AllocScope scope(st);
+  auto C = std::make_unique<CoarseLevel>();
+  C->ratio = ratio;
+  C->combine = combine;
+  C->A = A;
+  build_mesh(C->mesh.m, m.nx / ratio, m.ny / ratio, m.nz / ratio, m.lx, m.ly, m.lz);
+  build_restriction(m, C->mesh.m, ratio, A->bc, C->R0.h, C->R0T.h);
+  galerkin_coarse(A->h, C->R0.h, C->R0T.h, C->mesh.m, A->bc, C->A0.h);
+  for (mx_matrix *X : {&C->R0, &C->R0T, &C->A0}) {
+    X->k = A->k, X->xi = A->xi, X->bc = A->bc, X->device = ctx->device;
+  }
+  matrix_upload(&C->R0);
+  matrix_upload(&C->R0T);
+  build_partition(C->mesh.m, 1, 1, 1, nullptr, nullptr, nullptr, 0, C->part.p);
+  mx_precond_opts o{};
+  o.kind = MX_AS;
+  o.xi_prec = A->xi;
+  o.precision = P->prec;
+  C->P0 = std::make_unique<mx_precond>();
+  PrecondPlan plan;
+  precond_plan(ctx, &C->A0, &C->mesh, &C->part, &o, C->P0.get(), plan);
+  set_sweep_grid(C->P0.get(), ctx->cus);
+  precond_materialize(C->P0.get(), plan, st);
+  const int64_t nc = C->mesh.m.ne, E = P->E;
+  C->c.alloc((size_t)nc * 16);
+  C->y.alloc((size_t)nc * 16);
+  C->g.alloc((size_t)E * 16);
+  if (combine != MX_COARSE_ADDITIVE) {
+    C->t.alloc((size_t)E * 16);
+    C->u.alloc((size_t)E * 16);
+    if (combine == MX_COARSE_HYBRID) C->s.alloc((size_t)E * 16);
+  }
+  MX_HIP(hipStreamSynchronize(st));
+  P->coarse = C.release();
+}
+
+void coarse_export(const mx_precond *P, int64_t *n_coarse, int64_t *nnz_r, int64_t *nnz_a,
+                   int64_t *r_rowptr, int32_t *r_col, double *r_val, int64_t *a_rowptr,
+                   int32_t *a_col, double *a_val) {
+  if (!P->coarse) fail(MX_EINVAL, "preconditioner has no coarse level");
+  const CoarseLevel &C = *P->coarse;
+  if (n_coarse) *n_coarse = C.R0.h.n;
+  if (nnz_r) *nnz_r = C.R0.h.nnz();
+  if (nnz_a) *nnz_a = C.A0.h.nnz();
+  const HostCSR &R = C.R0.h, &A0 = C.A0.h;
+  if (r_rowptr) std::copy(R.rowptr.begin(), R.rowptr.end(), r_rowptr);
+  if (r_col) std::copy(R.col.begin(), R.col.end(), r_col);
+  if (r_val)
+    for (int64_t q = 0; q < R.nnz(); ++q) r_val[q] = R.val[2 * q];
+  if (a_rowptr) std::copy(A0.rowptr.begin(), A0.rowptr.end(), a_rowptr);
+  if (a_col) std::copy(A0.col.begin(), A0.col.end(), a_col);
+  if (a_val) std::copy(A0.val.begin(), A0.val.end(), a_val);
+}
+
 // ---- fixed device scratch for GMRES without allocation -------------------------------------------
 // One array per device, held by the code object until the process ends.  In host code `scratch`
 // only stands for the symbol; its device address (one per GPU) comes from hipGetSymbolAddress,
@@ -353,7 +480,7 @@ static void *noalloc_scratch(int device) {
 
 void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
                const mx_gmres_opts *o, mx_gmres_stats *stats, double *hist, hipStream_t st,
-               bool noalloc) {
+               bool noalloc, const mx_matrix *D) {
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t n = A->h.n;
   const int m = o->restart;
@@ -406,9 +533,24 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
   const cx<double> *b = (const cx<double> *)b_dev;
   cx<double> *x = (cx<double> *)x_dev;
 
-  auto norm_of = [&](const cx<double> *vec) {
-    k_dot_partial<<<G, 256, 0, st>>>(n, nullptr, 0, 0, vec, part, 1);
+  // ||vec|| (Euclidean) or ||vec||_D = sqrt(vec^H (D vec)), with D vec formed in `scratch`
+  auto norm_of = [&](const cx<double> *vec, cx<double> *scratch) {
+    if (D) {
+      spmv_run(D, vec, scratch, false, st);
+      k_dot_partial<<<G, 256, 0, st>>>(n, vec, ldv, 1, scratch, part, 0);
+    } else {
+      k_dot_partial<<<G, 256, 0, st>>>(n, nullptr, 0, 0, vec, part, 1);
+    }
     k_reduce<<<1, 256, 0, st>>>(G, part, nullptr, nullptr, nrm, 2);
+  };
+  // partial sums of h_q = <w, v_q> = v_q^H w, or v_q^H (D w) with D w formed in `scratch`
+  auto dots = [&](int nv, const cx<double> *w, cx<double> *scratch) {
+    const cx<double> *x = w;
+    if (D) {
+      spmv_run(D, w, scratch, false, st);
+      x = scratch;
+    }
+    k_dot_partial<<<G, 256, 0, st>>>(n, V, ldv, nv, x, part, 0);
   };
   // Arnoldi steps are enqueued one ahead of the host: step j+1 is queued before the status of
   // step j is read, so the device never waits for the host between steps. The status of step j
@@ -435,7 +577,7 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
   auto residual = [&]() {  // r = b - A x, beta -> status
     spmv_run(A, x, tmp, false, st);
     k_sub<<<nblk(n), 256, 0, st>>>(n, b, tmp, r);
-    norm_of(r);
+    norm_of(r, tmp);
     k_copy_beta<<<1, 64, 0, st>>>(nrm, dst);
     hst->pivot = hst->abort = 0;
     MX_HIP(hipMemcpyAsync(hst, dst, sizeof(GmresStatus), hipMemcpyDeviceToHost, st));
@@ -476,13 +618,13 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
         apply_prec(V + (int64_t)j * ldv, z);
         spmv_run(A, z, w, c64, st);
         const int nv = j + 1;
-        k_dot_partial<<<G, 256, 0, st>>>(n, V, ldv, nv, w, part, 0);
+        dots(nv, w, u);
         k_reduce<<<nv, 256, 0, st>>>(G, part, h2, h1, nullptr, 0);
         k_update<<<nblk(n), 256, 0, st>>>(n, V, ldv, nv, h2, w);
-        k_dot_partial<<<G, 256, 0, st>>>(n, V, ldv, nv, w, part, 0);
+        dots(nv, w, u);
         k_reduce<<<nv, 256, 0, st>>>(G, part, h2, h1, nullptr, 1);
         k_update<<<nblk(n), 256, 0, st>>>(n, V, ldv, nv, h2, w);
-        norm_of(w);
+        norm_of(w, u);
         k_givens<<<1, 64, 0, st>>>(j, m + 1, h1, nrm, H, cs, sn, g, dst, pctrl);
         k_scale<<<nblk(n), 256, 0, st>>>(n, w, nrm, V + (int64_t)(j + 1) * ldv);
         MX_HIP(hipGetLastError());

@@ -175,7 +175,9 @@ struct HostCSR {
   raw_vector<double> val;  // interleaved complex, 2 * nnz
   int64_t nnz() const { return (int64_t)col.size(); }
 };
-void assemble_global(const Mesh &m, double k, double xi, int bc, HostCSR &A);
+// A = K - (k^2 + i xi) M - i sign(xi) k M_b (impedance) or with PEC identity rows; with weight,
+// the Gram matrix D_k = K + k^2 M of the k-weighted inner product instead (xi unused)
+void assemble_global(const Mesh &m, double k, double xi, int bc, HostCSR &A, bool weight = false);
 void rhs_gaussian(const Mesh &m, int bc, const double c[3], const double pol[3], double sigma,
                   double *f);
 

@@ -130,6 +130,7 @@ struct mx_matrix {
   mx::HostCSR h;
   double k = 0, xi = 0;
   int bc = MX_BC_IMPEDANCE;
+  bool weight = false;  // the Gram matrix D_k of the weighted inner product, not a Galerkin matrix
   int device = 0;
   mx::DevBuf rowptr, col, val, val32;
 };
@@ -152,8 +153,17 @@ struct PrecondPlan {
 };
 }  // namespace mx
 
+namespace mx {
+struct CoarseLevel;                 // the coarse level of a two-level preconditioner (krylov.hip)
+void coarse_free(CoarseLevel *c);
+}  // namespace mx
+
 struct mx_precond {
   int kind = MX_ORAS, prec = MX_C128, nsub = 0, device = 0, sub_begin = 0;
+  double k = 0, xi_prec = 0;       // wavenumber and absorption the local problems were built with
+  int bc = MX_BC_IMPEDANCE;
+  bool share = false;               // built for a resident share of the subdomains only
+  mx::CoarseLevel *coarse = nullptr;  // set by mx_precond_add_coarse (owned)
   std::unique_ptr<mx::PrecondPlan> plan;  // set between mx_precond_plan and mx_precond_materialize
   int64_t pool_limit = 0;                 // bytes of full tiles at a time (0: what device memory allows)
   int schedule = 0;                       // factorisation schedule (MX_FACTOR_*; 0 = automatic)
@@ -189,6 +199,7 @@ struct mx_precond {
   std::vector<hipEvent_t> ev_start, ev_mid, ev_stop;
   size_t n_timed = 0;
   ~mx_precond() {
+    if (coarse) mx::coarse_free(coarse);
     for (auto e : ev_start) (void)hipEventDestroy(e);
     for (auto e : ev_mid) (void)hipEventDestroy(e);
     for (auto e : ev_stop) (void)hipEventDestroy(e);
@@ -212,7 +223,22 @@ void precond_release_device(mx_precond *P);
 void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st);
 size_t matrix_device_bytes(const mx_matrix *A);
 size_t gmres_device_bytes(int64_t n, int restart, bool flexible);
+// z = B^-1 v: the one-level preconditioner of P, combined with its coarse level if it has one
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st);
+// the one-level part alone: restriction, block sweeps, prolongation
+void precond_apply_level1(mx_precond *P, const void *vin, void *zout, hipStream_t st);
+// coarse level (Sec. 3.2, 3.3): R^0 and A^0 = R^0 A R^0^T on the host (host_coarse.cpp)
+void build_restriction(const Mesh &fine, const Mesh &coarse, int ratio, int bc, HostCSR &R0,
+                       HostCSR &R0T);
+void galerkin_coarse(const HostCSR &A, const HostCSR &R0, const HostCSR &R0T, const Mesh &coarse,
+                     int bc, HostCSR &A0);
+// attaches a coarse level to the materialised one-level P built from A (krylov.hip)
+void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m, int ratio,
+                  int combine, hipStream_t st);
+// host copies of R^0 and A^0 (sizes when the arrays are NULL)
+void coarse_export(const mx_precond *P, int64_t *n_coarse, int64_t *nnz_r, int64_t *nnz_a,
+                   int64_t *r_rowptr, int32_t *r_col, double *r_val, int64_t *a_rowptr,
+                   int32_t *a_col, double *a_val);
 int precond_check(mx_precond *P, hipStream_t st = nullptr);
 // throws the recorded device error of P, if any (see mx_precond::failed)
 void precond_refuse_failed(const mx_precond *P);
@@ -223,9 +249,10 @@ void spmv_run(const mx_matrix *A, const void *x, void *y, bool c64, hipStream_t 
 void matrix_upload(mx_matrix *A);
 // noalloc: the Krylov workspace is the fixed per-device scratch array (at most
 // kNoAllocScratchBytes; larger requests fail with MX_EINVAL) instead of the context's workspace
+// D (nullable): weighted GMRES in <v, w>_D = w^H D v (Sec. 5.2) instead of the Euclidean one
 void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, void *x_dev,
                const mx_gmres_opts *o, mx_gmres_stats *stats, double *hist, hipStream_t st,
-               bool noalloc = false);
+               bool noalloc = false, const mx_matrix *D = nullptr);
 constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 constexpr int kMaxDevices = 64;
 // takes the device address of the GMRES scratch array on `device` (must be current); idempotent

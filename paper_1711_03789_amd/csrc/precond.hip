@@ -1053,7 +1053,7 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
   MX_HIP(hipGetLastError());
 }
 
-void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
+void precond_apply_level1(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
   if (P->prec == MX_C128) apply_t<double>(P, vin, zout, st);
   else apply_t<float>(P, vin, zout, st);
 }
@@ -1120,9 +1120,9 @@ void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_
   for (int g : cand) {
     if (g < 1) continue;
     P->trsv_grid = std::min(g, std::max(1, P->n_items / 2));
-    precond_apply(P, vin.p, zout.p, st);  // warm-up
+    precond_apply_level1(P, vin.p, zout.p, st);  // warm-up
     MX_HIP(hipEventRecord(a, st));
-    for (int r = 0; r < 3; ++r) precond_apply(P, vin.p, zout.p, st);
+    for (int r = 0; r < 3; ++r) precond_apply_level1(P, vin.p, zout.p, st);
     MX_HIP(hipEventRecord(b, st));
     MX_HIP(hipEventSynchronize(b));
     float ms = 0;
@@ -1175,6 +1175,9 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   const double t0 = now_s();
   P->kind = opts->kind;
   P->prec = opts->precision;
+  P->k = A->k;
+  P->xi_prec = opts->kind == MX_ORAS ? opts->xi_prec : A->xi;
+  P->bc = A->bc;
   P->E = m.ne;
   P->device = ctx ? ctx->device : -1;
   int s0 = opts->sub_begin, s1 = opts->sub_end;
@@ -1191,6 +1194,7 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
                                     : P->prec == MX_C128 ? kDefaultWidthC128 : kDefaultWidthC64;
   P->sub_begin = s0;
   P->nsub = s1 - s0;
+  P->share = s0 != 0 || s1 != part.nsub;
   const int N = P->nsub;
   // subdomain j of this preconditioner is subdomain s0 + j of the partition
   std::vector<std::vector<int32_t>> sets_share(part.set(opts->kind).begin() + s0,

@@ -32,7 +32,8 @@ SYMBOLS = [
     "mx_precond_sweep_timing", "mx_precond_autotune", "mx_server_create", "mx_server_submit",
     "mx_server_wait", "mx_server_solution", "mx_server_release", "mx_server_stats",
     "mx_server_destroy", "mx_matrix_upload", "mx_precond_plan", "mx_precond_materialize",
-    "mx_selftest_host", "mx_gmres_noalloc",
+    "mx_selftest_host", "mx_gmres_noalloc", "mx_precond_add_coarse", "mx_precond_coarse_export",
+    "mx_coarse_operators", "mx_weight_assemble", "mx_gmres_weighted",
 ]
 
 
@@ -44,6 +45,8 @@ class MxError(RuntimeError):
 
 # factor_schedule values of mx_precond_opts (mx.h)
 FACTOR_SCHEDULES = {"auto": 0, "one_stream": 1, "lookahead": 2}
+# combine values of mx_precond_add_coarse (mx.h)
+COARSE = {"additive": 0, "hybrid": 1, "deflation": 2}
 
 
 class PrecondOpts(C.Structure):
@@ -148,6 +151,9 @@ def load(path=LIB_PATH):
         "mx_precond_export_perm": (C.c_int, [P, C.c_int, C.c_int64, P, P]),
         "mx_precond_export_diag": (C.c_int, [P, C.c_int, C.c_int64, P]),
         "mx_precond_check": (C.c_int, [P]),
+        "mx_precond_add_coarse": (C.c_int, [P, P, P, P, C.c_int, C.c_int, P]),
+        "mx_precond_coarse_export": (C.c_int, [P] + [C.POINTER(C.c_int64)] * 3 + [P] * 6),
+        "mx_coarse_operators": (C.c_int, [P, P, C.c_int] + [C.POINTER(C.c_int64)] * 3 + [P] * 6),
         "mx_precond_autotune": (C.c_int, [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "mx_server_create": (C.c_int, [C.c_int, C.POINTER(ServerOpts), C.POINTER(P)]),
         "mx_server_submit": (C.c_int, [P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
@@ -161,6 +167,9 @@ def load(path=LIB_PATH):
                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "mx_precond_destroy": (None, [P]),
         "mx_gmres": (C.c_int, [P, P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresStats), P, P]),
+        "mx_weight_assemble": (C.c_int, [P, P, C.c_double, C.c_int, C.POINTER(P)]),
+        "mx_gmres_weighted": (C.c_int, [P, P, P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresStats),
+                                        P, P]),
         "mx_gmres_noalloc": (C.c_int, [P, P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresStats), P,
                                        P]),
         "mx_selftest": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -285,6 +294,19 @@ class Matrix:
         _check(_lib.mx_matrix_sizes(h, C.byref(n), C.byref(nnz)))
         self.n, self.nnz = n.value, nnz.value
 
+    @classmethod
+    def weight(cls, ctx, mesh, k, bc=MX_BC_IMPEDANCE):
+        """D_k = K + k^2 M, the weight of weighted GMRES (mx_weight_assemble)."""
+        load()
+        self = cls.__new__(cls)
+        h = P()
+        _check(_lib.mx_weight_assemble(ctx.h if ctx is not None else None, mesh.h, k, bc, C.byref(h)))
+        self.h, self.k, self.xi, self.bc = h, k, 0.0, bc
+        n, nnz = C.c_int64(), C.c_int64()
+        _check(_lib.mx_matrix_sizes(h, C.byref(n), C.byref(nnz)))
+        self.n, self.nnz = n.value, nnz.value
+        return self
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.mx_matrix_destroy(self.h)
@@ -339,6 +361,25 @@ def selftest_host(n_items, fail_item=-1, fail_code=MX_EINVAL):
     ran = C.c_int64()
     rc = _lib.mx_selftest_host(n_items, fail_item, fail_code, C.byref(ran))
     return rc, ran.value
+
+
+def _coarse_csr(fn, n_fine):
+    import scipy.sparse as sp
+    n, nr, na = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(fn(C.byref(n), C.byref(nr), C.byref(na), None, None, None, None, None, None))
+    rp, rc, rv = np.zeros(n.value + 1, np.int64), np.zeros(nr.value, np.int32), np.zeros(nr.value)
+    ap, ac = np.zeros(n.value + 1, np.int64), np.zeros(na.value, np.int32)
+    av = np.zeros(na.value, np.complex128)
+    _check(fn(C.byref(n), C.byref(nr), C.byref(na), _ptr(rp), _ptr(rc), _ptr(rv), _ptr(ap), _ptr(ac),
+              _ptr(av)))
+    return (sp.csr_matrix((rv, rc, rp), shape=(n.value, n_fine)),
+            sp.csr_matrix((av, ac, ap), shape=(n.value, n.value)))
+
+
+def coarse_operators(mesh, A, ratio):
+    """Host-only (R0, A0) of the coarse level for A on mesh (mx_coarse_operators)."""
+    load()
+    return _coarse_csr(lambda *a: _lib.mx_coarse_operators(mesh.h, A.h, int(ratio), *a), A.n)
 
 
 def local_problem(mesh, A, part, l, kind="oras", xi_prec=None):
@@ -405,6 +446,16 @@ class Precond:
     def check(self):
         _check(_lib.mx_precond_check(self.h))
 
+    def add_coarse(self, ctx, A, mesh, ratio, combine="additive", stream=None):
+        """Two-level form (mx_precond_add_coarse); A and mesh are the ones P was built from."""
+        _check(_lib.mx_precond_add_coarse(ctx.h, self.h, A.h, mesh.h, int(ratio),
+                                          COARSE.get(combine, combine), _stream(stream)))
+        self._coarse_A = A  # the library borrows A
+
+    def coarse_export(self):
+        """(R0, A0) as scipy CSR matrices (coarse edges x fine edges, coarse x coarse)."""
+        return _coarse_csr(lambda *a: _lib.mx_precond_coarse_export(self.h, *a), self.n)
+
     def autotune(self, stream=None):
         """Picks the fastest sweep grid; returns (grid, ms per application)."""
         g, ms = C.c_int32(), C.c_double()
@@ -432,11 +483,20 @@ class Precond:
 
 
 def gmres(ctx, A, Pc, b, x, restart=50, rtol=1e-6, max_iters=1000, flexible=False,
-          fixed_iters=0, spmv_c64=False, history=False, stream=None, noalloc=False):
-    """noalloc=True calls mx_gmres_noalloc (fixed per-GPU workspace, no device allocation)."""
+          fixed_iters=0, spmv_c64=False, history=False, stream=None, noalloc=False, weight=None):
+    """noalloc=True calls mx_gmres_noalloc (fixed per-GPU workspace, no device allocation);
+    weight=D (a Matrix.weight) calls mx_gmres_weighted (residual minimised in the D-norm)."""
     o = GmresOpts(restart, max_iters, int(flexible), fixed_iters, int(spmv_c64), rtol)
     st = GmresStats()
     hist = np.zeros(max(max_iters, fixed_iters) + 2, np.float64) if history else None
+    if weight is not None:
+        _check(_lib.mx_gmres_weighted(ctx.h, A.h, Pc.h if Pc is not None else None, weight.h,
+                                      _dvec(b, A.n, "b"), _dvec(x, A.n, "x"), C.byref(o),
+                                      C.byref(st), _ptr(hist), _stream(stream)))
+        out = st.as_dict()
+        if history:
+            out["history"] = hist[: st.iters + 1].copy()
+        return out
     fn = _lib.mx_gmres_noalloc if noalloc else _lib.mx_gmres
     _check(fn(ctx.h, A.h, Pc.h if Pc is not None else None, _dvec(b, A.n, "b"),
                          _dvec(x, A.n, "x"),

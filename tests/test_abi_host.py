@@ -338,3 +338,43 @@ def test_medium_partition_and_orders_bit_exact():
             perm = rcm.rcm(*g)
             assert np.array_equal(lp_["perm"], perm), (kind, l)
             assert np.array_equal(lp_["first"], rcm.envelope(*g, perm)), (kind, l)
+
+
+@pytest.mark.parametrize("n,ratio,bc", [((8, 8, 8), 2, mx.MX_BC_IMPEDANCE), ((8, 8, 8), 4, mx.MX_BC_PEC),
+                                        ((12, 6, 9), 3, mx.MX_BC_IMPEDANCE), ((6, 4, 8), 2, mx.MX_BC_PEC)])
+def test_coarse_operators_match_oracle(n, ratio, bc):
+    """The library's coarse restriction R^0 (closed form on the Kuhn split) and coarse Galerkin
+    matrix R^0 A R^0^T equal the oracle's (generic barycentric search) to rounding; with PEC the
+    boundary coarse edges have empty R^0 rows and unit A^0 rows."""
+    from oracle import coarse
+    lengths = (1.0, 0.9, 1.2)
+    om, lm = OMesh(*n, *lengths), mx.Mesh(*n, *lengths)
+    for k, xi in ((4.0, 16.0), (3.0, -2.0)):
+        A = mx.Matrix(None, lm, k, xi, bc)
+        R, A0 = mx.coarse_operators(lm, A, ratio)
+        oc = coarse.coarse_mesh(om, ratio)
+        oR = coarse.restriction(om, oc, bc)
+        keep = coarse.coarse_dofs(oc, bc)
+        assert R.shape == (oc.n_edge, om.n_edge)
+        assert abs(R[keep] - oR).max() <= 1e-14 * abs(oR).max()
+        oA0 = (oR @ fem.assemble(om, k, xi, bc) @ oR.T).tocsr()
+        assert abs(A0[keep][:, keep] - oA0).max() <= 1e-13 * abs(oA0).max()
+        drop = np.setdiff1d(np.arange(oc.n_edge), keep)
+        assert R[drop].count_nonzero() == 0
+        assert abs(A0[drop] - sp.identity(oc.n_edge).tocsr()[drop]).max() == 0 if len(drop) else True
+    with pytest.raises(mx.MxError):
+        mx.coarse_operators(lm, A, 5)
+
+
+@pytest.mark.parametrize("bc", [mx.MX_BC_IMPEDANCE, mx.MX_BC_PEC])
+def test_weight_matrix_matches_oracle(bc):
+    """D_k = K + k^2 M (eq:ip, eq:weight) assembled by the library equals the oracle's."""
+    n = (5, 4, 6)
+    om, lm = OMesh(*n), mx.Mesh(*n)
+    for k in (0.0, 4.0, 9.5):
+        D = mx.Matrix.weight(None, lm, k, bc)
+        rp, col, val = D.export()
+        L = sp.csr_matrix((val, col, rp), shape=(D.n, D.n))
+        O = fem.weight_matrix(om, k, bc)
+        assert not np.any(val.imag)
+        assert abs(L - O).max() <= 1e-14 * abs(O).max()
