@@ -378,6 +378,8 @@ def main():
                     help="two-level: coarse mesh with this many times fewer cubes per axis (0: one-level)")
     ap.add_argument("--combine", default="hybrid", choices=["additive", "hybrid", "deflation"],
                     help="two-level form (eq:defAS / eq:RAS2, eq:HRAS, eq:ADEF1ras)")
+    ap.add_argument("--weighted", action="store_true",
+                    help="weighted GMRES in the D_k = K + k^2 M inner product (Sec. 5.2, eq:ip)")
     ap.add_argument("--overlap-factor", type=int, default=0, choices=[0, 1],
                     help="1: the next instance's factorisation also runs on the second host "
                          "thread (its own non-blocking stream), overlapping the current GMRES")
@@ -410,6 +412,8 @@ def main():
         cfg["workload"] = cfg["workload"].replace(
             "GMRES(", "FGMRES(").replace("complex128", "complex64 factors and SpMV values, FP64 "
                                                       "Krylov vectors")
+    if args.weighted:
+        cfg["workload"] += "; weighted GMRES in the D_k = K + k^2 M inner product"
     if args.coarse:
         if args.workload == "scale-xi0" or args.overlap_factor:
             raise SystemExit("--coarse is not combined with scale-xi0 or --overlap-factor")
@@ -449,6 +453,8 @@ def main():
                        plan_only=True)
         del A_prec
         P.stage(ctx_host)  # host-to-device copies, also overlapping the current instance
+        if args.coarse:  # host half of the coarse level (R^0, A^0, plan of its factorisation)
+            P.plan_coarse(A, mesh, args.coarse, args.combine)
         if fstream is not None:
             P.materialize(ctx_host, fstream)  # returns once its factor tiles are complete
         t2 = time.perf_counter()
@@ -459,6 +465,7 @@ def main():
         t = time.perf_counter()
         mesh = mx.Mesh(*n, *w.lengths)
         part = mx.Partition(mesh, *w.parts, w.layers)
+        D = mx.Matrix.weight(ctx, mesh, w.k) if args.weighted else None
         t_topo = time.perf_counter() - t
         rec = []
         with ThreadPoolExecutor(max_workers=1) as ex:
@@ -479,7 +486,7 @@ def main():
                     P.sweep_timing(True)
                 x.zero_()
                 st = mx.gmres(ctx, A, P, rhs[seed], x, restart=w.restart, rtol=w.rtol,
-                              max_iters=args.max_iters, flexible=mixed, spmv_c64=mixed)
+                              max_iters=args.max_iters, flexible=mixed, spmv_c64=mixed, weight=D)
                 if record and mixed and "x_mixed" not in refs:
                     refs["x_mixed"] = (kind, e, seed, x.clone())
                 t3 = time.perf_counter()
@@ -562,7 +569,7 @@ def main():
                      "then include contention with the current GMRES)" if fstream is not None
                      else "")},
         "solves": [{k: r[k] for k in ("kind", "xi", "xi_prec", "iters", "converged", "relres",
-                                      "t_gmres", "t_factor")} for r in recs[0][1]],
+                                      "t_gmres", "t_factor", "t_coarse")} for r in recs[0][1]],
         "all_converged": converged,
     }
     if mixed and "x_mixed" in refs:

@@ -261,6 +261,13 @@ int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_
  * MX_EPIVOT. */
 int mx_precond_add_coarse(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m,
                           int ratio, int combine, void *stream);
+/* Optional host half of mx_precond_add_coarse (coarse mesh, R^0, A^0 and the plan of its
+ * factorisation; no device work, A needs no device copy), so that it can run on another host
+ * thread, also on a planned, not yet materialised P.  mx_precond_add_coarse with the same A, m,
+ * ratio and combine then only builds the device half; until then P is refused by
+ * mx_precond_apply and mx_gmres.  Errors: as mx_precond_add_coarse. */
+int mx_precond_plan_coarse(mx_precond *P, const mx_matrix *A, const mx_mesh *m, int ratio,
+                           int combine);
 /* Host copies of the coarse level, for inspection and tests: R^0 as CSR r_rowptr[n_coarse+1],
  * r_col[nnz_r] (fine edge ids), r_val[nnz_r] (real), and A^0 as a_rowptr[n_coarse+1],
  * a_col[nnz_a], a_val[2*nnz_a] (complex128).  Rows are all coarse edges: with PEC the boundary

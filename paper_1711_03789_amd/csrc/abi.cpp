@@ -331,6 +331,7 @@ int mx_precond_apply(mx_ctx *ctx, mx_precond *P, const void *v_dev, void *z_dev,
     MX_REQUIRE(ctx && P && v_dev && z_dev, "NULL argument");
     MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
     MX_REQUIRE(v_dev != z_dev, "v and z must be distinct");
+    MX_REQUIRE(!mx::coarse_incomplete(P), "coarse level planned but not built (mx_precond_add_coarse)");
     mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::precond_apply(P, v_dev, z_dev, (hipStream_t)stream);
@@ -408,6 +409,7 @@ int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, 
     MX_REQUIRE(A->rowptr.p, "matrix has no device copy");
     MX_REQUIRE(!P || P->E == A->h.n, "preconditioner and matrix sizes differ");
     MX_REQUIRE(!P || !P->plan, "preconditioner is planned but not materialised");
+    MX_REQUIRE(!P || !mx::coarse_incomplete(P), "coarse level planned but not built (mx_precond_add_coarse)");
     if (P) mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream);
@@ -422,6 +424,14 @@ int mx_precond_add_coarse(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const 
     mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::coarse_setup(ctx, P, A, m, ratio, combine, (hipStream_t)stream);
+  });
+}
+
+int mx_precond_plan_coarse(mx_precond *P, const mx_matrix *A, const mx_mesh *m, int ratio,
+                           int combine) {
+  MX_GUARD({
+    MX_REQUIRE(P && A && m, "NULL argument");
+    mx::coarse_plan(P, A, m, ratio, combine);
   });
 }
 
@@ -473,6 +483,7 @@ int mx_gmres_noalloc(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void 
     MX_REQUIRE(A->rowptr.p, "matrix has no device copy");
     MX_REQUIRE(!P || P->E == A->h.n, "preconditioner and matrix sizes differ");
     MX_REQUIRE(!P || !P->plan, "preconditioner is planned but not materialised");
+    MX_REQUIRE(!P || !mx::coarse_incomplete(P), "coarse level planned but not built (mx_precond_add_coarse)");
     if (P) mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream, true);
@@ -489,6 +500,7 @@ int mx_gmres_weighted(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const mx_m
     MX_REQUIRE(!D || (D->rowptr.p && D->h.n == A->h.n), "weight needs a device copy of A's size");
     MX_REQUIRE(!P || P->E == A->h.n, "preconditioner and matrix sizes differ");
     MX_REQUIRE(!P || !P->plan, "preconditioner is planned but not materialised");
+    MX_REQUIRE(!P || !mx::coarse_incomplete(P), "coarse level planned but not built (mx_precond_add_coarse)");
     if (P) mx::precond_refuse_failed(P);
     bind_device(ctx->device);
     mx::gmres_run(ctx, A, P, b_dev, x_dev, opts, stats, res_hist, (hipStream_t)stream, false, D);

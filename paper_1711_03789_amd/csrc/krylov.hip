@@ -330,6 +330,8 @@ struct CoarseLevel {
   mx_partition part;               // one subdomain, no overlap
   mx_matrix R0, R0T, A0;           // restriction (coarse x fine), its transpose, coarse matrix
   std::unique_ptr<mx_precond> P0;  // factored coarse problem
+  std::unique_ptr<PrecondPlan> plan0;  // host half of P0 until the device half is built
+  bool ready = false;              // device half built (R^0 uploaded, A^0 factored)
   const mx_matrix *A = nullptr;    // fine matrix the preconditioner is built for (borrowed)
   DevBuf c, y, g, t, s, u;         // coarse vectors c, y; fine vectors g = G v, t, s, u
 };
@@ -380,8 +382,8 @@ void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
   MX_HIP(hipGetLastError());
 }
 
-void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *mh, int ratio,
-                  int combine, hipStream_t st) {
+// Host half: coarse mesh, R^0, A^0 = R^0 A R^0^T, and the plan of the coarse factorisation.
+void coarse_plan(mx_precond *P, const mx_matrix *A, const mx_mesh *mh, int ratio, int combine) {
   const Mesh &m = mh->m;
   if (P->coarse) fail(MX_EINVAL, "preconditioner already has a coarse level");
   if (P->share) fail(MX_EINVAL, "a resident share cannot have a coarse level");
@@ -389,10 +391,8 @@ void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh 
   if (ratio < 1 || m.nx % ratio || m.ny % ratio || m.nz % ratio)
     fail(MX_EINVAL, "the coarse ratio must divide the cube count of every axis");
   if (A->h.n != P->E || m.ne != P->E) fail(MX_EINVAL, "matrix, mesh and preconditioner sizes differ");
-  if (A->k != P->k || A->xi != P->xi_prec || A->bc != P->bc)
+  if (A->weight || A->k != P->k || A->xi != P->xi_prec || A->bc != P->bc)
     fail(MX_EINVAL, "the matrix is not the one the preconditioner was built for (k, xi_prec, bc)");
-  if (!A->rowptr.p) fail(MX_EINVAL, "matrix has no device copy");
-  AllocScope scope(st);
   auto C = std::make_unique<CoarseLevel>();
   C->ratio = ratio;
   C->combine = combine;
@@ -400,33 +400,68 @@ void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh 
   build_mesh(C->mesh.m, m.nx / ratio, m.ny / ratio, m.nz / ratio, m.lx, m.ly, m.lz);
   build_restriction(m, C->mesh.m, ratio, A->bc, C->R0.h, C->R0T.h);
   galerkin_coarse(A->h, C->R0.h, C->R0T.h, C->mesh.m, A->bc, C->A0.h);
-  for (mx_matrix *X : {&C->R0, &C->R0T, &C->A0}) {
-    X->k = A->k, X->xi = A->xi, X->bc = A->bc, X->device = ctx->device;
-  }
-  matrix_upload(&C->R0);
-  matrix_upload(&C->R0T);
+  for (mx_matrix *X : {&C->R0, &C->R0T, &C->A0}) X->k = A->k, X->xi = A->xi, X->bc = A->bc;
   build_partition(C->mesh.m, 1, 1, 1, nullptr, nullptr, nullptr, 0, C->part.p);
   mx_precond_opts o{};
   o.kind = MX_AS;
   o.xi_prec = A->xi;
   o.precision = P->prec;
   C->P0 = std::make_unique<mx_precond>();
-  PrecondPlan plan;
-  precond_plan(ctx, &C->A0, &C->mesh, &C->part, &o, C->P0.get(), plan);
-  set_sweep_grid(C->P0.get(), ctx->cus);
-  precond_materialize(C->P0.get(), plan, st);
-  const int64_t nc = C->mesh.m.ne, E = P->E;
-  C->c.alloc((size_t)nc * 16);
-  C->y.alloc((size_t)nc * 16);
-  C->g.alloc((size_t)E * 16);
-  if (combine != MX_COARSE_ADDITIVE) {
-    C->t.alloc((size_t)E * 16);
-    C->u.alloc((size_t)E * 16);
-    if (combine == MX_COARSE_HYBRID) C->s.alloc((size_t)E * 16);
-  }
-  MX_HIP(hipStreamSynchronize(st));
+  C->plan0 = std::make_unique<PrecondPlan>();
+  precond_plan(nullptr, &C->A0, &C->mesh, &C->part, &o, C->P0.get(), *C->plan0);
   P->coarse = C.release();
 }
+
+// Device half: uploads of R^0 and its transpose, factorisation of A^0, work vectors.
+void coarse_materialize(mx_ctx *ctx, mx_precond *P, hipStream_t st) {
+  if (!P->coarse) fail(MX_EINVAL, "preconditioner has no coarse level");
+  CoarseLevel &C = *P->coarse;
+  if (C.ready) fail(MX_EINVAL, "coarse level already built");
+  if (!C.A->rowptr.p) fail(MX_EINVAL, "matrix has no device copy");
+  AllocScope scope(st);
+  for (mx_matrix *X : {&C.R0, &C.R0T, &C.A0}) X->device = ctx->device;
+  matrix_upload(&C.R0);
+  matrix_upload(&C.R0T);
+  C.P0->device = ctx->device;
+  set_sweep_grid(C.P0.get(), ctx->cus);
+  precond_materialize(C.P0.get(), *C.plan0, st);
+  C.plan0.reset();
+  const int64_t nc = C.mesh.m.ne, E = P->E;
+  C.c.alloc((size_t)nc * 16);
+  C.y.alloc((size_t)nc * 16);
+  C.g.alloc((size_t)E * 16);
+  if (C.combine != MX_COARSE_ADDITIVE) {
+    C.t.alloc((size_t)E * 16);
+    C.u.alloc((size_t)E * 16);
+    if (C.combine == MX_COARSE_HYBRID) C.s.alloc((size_t)E * 16);
+  }
+  MX_HIP(hipStreamSynchronize(st));
+  C.ready = true;
+}
+
+void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *mh, int ratio,
+                  int combine, hipStream_t st) {
+  if (P->coarse) {  // planned earlier: the arguments must be the same
+    const CoarseLevel &C = *P->coarse;
+    if (C.ready) fail(MX_EINVAL, "preconditioner already has a coarse level");
+    if (C.A != A || C.ratio != ratio || C.combine != combine || C.mesh.m.ne == 0 ||
+        mh->m.ne != P->E)
+      fail(MX_EINVAL, "arguments differ from those the coarse level was planned with");
+  } else {
+    coarse_plan(P, A, mh, ratio, combine);
+  }
+  try {
+    coarse_materialize(ctx, P, st);
+  } catch (...) {
+    if (!P->coarse->ready) {  // leave P one-level and usable
+      coarse_free(P->coarse);
+      P->coarse = nullptr;
+    }
+    throw;
+  }
+}
+
+bool coarse_incomplete(const mx_precond *P) { return P->coarse && !P->coarse->ready; }
 
 void coarse_export(const mx_precond *P, int64_t *n_coarse, int64_t *nnz_r, int64_t *nnz_a,
                    int64_t *r_rowptr, int32_t *r_col, double *r_val, int64_t *a_rowptr,

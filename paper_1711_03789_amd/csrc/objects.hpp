@@ -232,7 +232,11 @@ void build_restriction(const Mesh &fine, const Mesh &coarse, int ratio, int bc, 
                        HostCSR &R0T);
 void galerkin_coarse(const HostCSR &A, const HostCSR &R0, const HostCSR &R0T, const Mesh &coarse,
                      int bc, HostCSR &A0);
-// attaches a coarse level to the materialised one-level P built from A (krylov.hip)
+// host half of a coarse level (R^0, A^0, plan of its factorisation), attached to P but not usable
+// until coarse_setup builds its device half (krylov.hip)
+void coarse_plan(mx_precond *P, const mx_matrix *A, const mx_mesh *m, int ratio, int combine);
+bool coarse_incomplete(const mx_precond *P);
+// attaches a coarse level to the materialised one-level P built from A, or completes a planned one
 void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m, int ratio,
                   int combine, hipStream_t st);
 // host copies of R^0 and A^0 (sizes when the arrays are NULL)

@@ -33,7 +33,7 @@ SYMBOLS = [
     "mx_server_wait", "mx_server_solution", "mx_server_release", "mx_server_stats",
     "mx_server_destroy", "mx_matrix_upload", "mx_precond_plan", "mx_precond_materialize",
     "mx_selftest_host", "mx_gmres_noalloc", "mx_precond_add_coarse", "mx_precond_coarse_export",
-    "mx_coarse_operators", "mx_weight_assemble", "mx_gmres_weighted",
+    "mx_coarse_operators", "mx_weight_assemble", "mx_gmres_weighted", "mx_precond_plan_coarse",
 ]
 
 
@@ -152,6 +152,7 @@ def load(path=LIB_PATH):
         "mx_precond_export_diag": (C.c_int, [P, C.c_int, C.c_int64, P]),
         "mx_precond_check": (C.c_int, [P]),
         "mx_precond_add_coarse": (C.c_int, [P, P, P, P, C.c_int, C.c_int, P]),
+        "mx_precond_plan_coarse": (C.c_int, [P, P, P, C.c_int, C.c_int]),
         "mx_precond_coarse_export": (C.c_int, [P] + [C.POINTER(C.c_int64)] * 3 + [P] * 6),
         "mx_coarse_operators": (C.c_int, [P, P, C.c_int] + [C.POINTER(C.c_int64)] * 3 + [P] * 6),
         "mx_precond_autotune": (C.c_int, [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
@@ -451,6 +452,12 @@ class Precond:
         _check(_lib.mx_precond_add_coarse(ctx.h, self.h, A.h, mesh.h, int(ratio),
                                           COARSE.get(combine, combine), _stream(stream)))
         self._coarse_A = A  # the library borrows A
+
+    def plan_coarse(self, A, mesh, ratio, combine="additive"):
+        """Host half of add_coarse (mx_precond_plan_coarse); any host thread."""
+        _check(_lib.mx_precond_plan_coarse(self.h, A.h, mesh.h, int(ratio),
+                                           COARSE.get(combine, combine)))
+        self._coarse_A = A
 
     def coarse_export(self):
         """(R0, A0) as scipy CSR matrices (coarse edges x fine edges, coarse x coarse)."""

@@ -132,3 +132,44 @@ def test_two_level_refusals(gpu_lib, ctx):
     P.add_coarse(ctx, lA, lm, 2, "hybrid")
     with pytest.raises(mx.MxError):
         P.add_coarse(ctx, lA, lm, 3, "hybrid")
+
+
+def test_two_level_planned_on_another_thread(gpu_lib, ctx):
+    """The host half of the coarse level (mx_precond_plan_coarse), made on a planned one-level
+    preconditioner on a second host thread, then completed by mx_precond_add_coarse, gives the
+    same two-level preconditioner bit for bit as the one-call path; before completion the
+    preconditioner is refused."""
+    import threading
+    mx = gpu_lib
+    n, parts = (12, 12, 12), (3, 3, 3)
+    lm = mx.Mesh(*n)
+    lp = mx.Partition(lm, *parts, 2)
+    A = mx.Matrix(ctx, lm, 5.0, 5.0)
+    ref = mx.Precond(ctx, A, lm, lp, "oras")
+    ref.add_coarse(ctx, A, lm, 3, "deflation")
+    out = {}
+
+    def prepare():
+        try:
+            P = mx.Precond(None, A, lm, lp, "oras", plan_only=True)
+            P.plan_coarse(A, lm, 3, "deflation")
+            out["P"] = P
+        except Exception as e:
+            out["err"] = e
+
+    th = threading.Thread(target=prepare)
+    th.start()
+    th.join()
+    assert "err" not in out, out.get("err")
+    P = out["P"]
+    P.materialize(ctx)
+    v = random_rhs(lm.n_edge, 41)
+    vd, z1, z2 = dev(v), dev(np.zeros(lm.n_edge)), dev(np.zeros(lm.n_edge))
+    with pytest.raises(mx.MxError):
+        P.apply(vd, z2)
+    with pytest.raises(mx.MxError):
+        P.add_coarse(ctx, A, lm, 3, "hybrid")  # differs from the plan
+    P.add_coarse(ctx, A, lm, 3, "deflation")
+    ref.apply(vd, z1)
+    P.apply(vd, z2)
+    assert np.array_equal(host(z1), host(z2))
