@@ -49,12 +49,13 @@ def _solve_one(task):
     t = time.perf_counter()
     lu = dd.factor_local(Al)
     t_lu = time.perf_counter() - t
-    return lu.solve(r), t_lu
+    x = lu.solve(r)
+    return x, t_lu, time.perf_counter() - t - t_lu
 
 
 def solve_many(tasks, workers=None):
-    """[(A^l, r), ...] -> [((A^l)^-1 r, seconds of the factorisation), ...], each pair on a
-    worker process (the same exact local solve as dd.Schwarz.local_solve)."""
+    """[(A^l, r), ...] -> [((A^l)^-1 r, seconds of the factorisation, seconds of the solve), ...],
+    each pair on a worker process (the same exact local solve as dd.Schwarz.local_solve)."""
     nw = max(1, min(len(tasks), workers or default_workers()))
     with mp.get_context("spawn").Pool(nw) as p:
         return p.map(_solve_one, tasks, chunksize=1)

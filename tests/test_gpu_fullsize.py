@@ -117,8 +117,8 @@ def test_fullsize_sampled_local_solves(gpu_lib, big):
     t0 = time.time()
     res = pool.solve_many(tasks)
     say("oracle: %d local solves in %.1f s (longest factorisation %.1f s)"
-        % (len(tasks), time.time() - t0, max(t for _, t in res)))
-    for key, (x, _) in zip(keys, res):
+        % (len(tasks), time.time() - t0, max(r[1] for r in res)))
+    for key, (x, _, _) in zip(keys, res):
         kind, xi, l = key
         if kind == "oras":
             idx = op.oras_sets[l]
