@@ -399,6 +399,9 @@ def main():
                     help="two-level: coarse mesh with this many times fewer cubes per axis (0: one-level)")
     ap.add_argument("--combine", default="hybrid", choices=["additive", "hybrid", "deflation"],
                     help="two-level form (eq:defAS / eq:RAS2, eq:HRAS, eq:ADEF1ras)")
+    ap.add_argument("--tune", action="store_true",
+                    help="before timing, pick the factorisation launch shape (mx_precond_tune_factor) "
+                         "and the sweep grid (mx_precond_autotune) on the first instance")
     ap.add_argument("--weighted", action="store_true",
                     help="weighted GMRES in the D_k = K + k^2 M inner product (Sec. 5.2, eq:ip)")
     ap.add_argument("--overlap-factor", type=int, default=0, choices=[0, 1],
@@ -454,6 +457,18 @@ def main():
     torch.cuda.synchronize()
 
     refs = {}
+    tuned = {"schedule": "auto", "width": 0, "sweep_grid": 0}
+    if args.tune:  # untimed: a property of the mesh, partition and precision, reused by every solve
+        kind0, e0, _ = inst[0]
+        m0 = mx.Mesh(*n, *w.lengths)
+        p0 = mx.Partition(m0, *w.parts, w.layers)
+        A0 = mx.Matrix(ctx, m0, w.k, w.k ** e0)
+        sch, wid, best, each = mx.tune_factor(ctx, A0, m0, p0, kind0, precision=args.precision)
+        P0 = mx.Precond(ctx, A0, m0, p0, kind0, precision=args.precision, schedule=sch, width=wid)
+        grid, ms = P0.autotune()
+        del P0, A0, p0, m0
+        tuned = {"schedule": sch, "width": wid, "sweep_grid": grid, "factor_ms_each": each,
+                 "candidates": "one stream; look-ahead widths 1, 2, 3, 4", "apply_ms": ms}
 
     # The host half of the next instance's setup (assembly and its upload, local problems, RCM,
     # tile layout) runs on a second host thread while the device factors and solves the current
@@ -471,7 +486,8 @@ def main():
         A.upload(ctx_host)  # its own stream: overlaps the device work of the current instance
         t1 = time.perf_counter()
         P = mx.Precond(ctx_host, A_prec, mesh, part, kind, xi_prec=xi, precision=args.precision,
-                       plan_only=True)
+                       plan_only=True, schedule=tuned["schedule"], width=tuned["width"],
+                       sweep_grid=tuned["sweep_grid"])
         del A_prec
         P.stage(ctx_host)  # host-to-device copies, also overlapping the current instance
         if args.coarse:  # host half of the coarse level (R^0, A^0, plan of its factorisation)
@@ -595,6 +611,8 @@ def main():
                                       "t_gmres", "t_factor", "t_coarse")} for r in recs[0][1]],
         "all_converged": converged,
     }
+    if args.tune:
+        out["tuned"] = tuned
     if mixed and "x_mixed" in refs:
         # accuracy of the mixed path against the complex128 path on the first instance
         kind, e, seed, xm = refs["x_mixed"]

@@ -284,6 +284,16 @@ int mx_precond_coarse_export(const mx_precond *P, int64_t *n_coarse, int64_t *nn
 int mx_coarse_operators(const mx_mesh *m, const mx_matrix *A, int ratio, int64_t *n_coarse,
                         int64_t *nnz_r, int64_t *nnz_a, int64_t *r_rowptr, int32_t *r_col,
                         double *r_val, int64_t *a_rowptr, int32_t *a_col, double *a_val);
+/* Factorisation tuner: sets up the preconditioner that mx_precond_setup would build from these
+ * arguments once for each factorisation launch shape -- one stream, and look-ahead with 1, 2, 3
+ * and 4 block columns per trailing-update pass (factor_width) -- times each factorisation, frees
+ * it, and returns the fastest (best_schedule, best_width for mx_precond_opts; best_ms) and all
+ * five times in ms_each[5] (either may be NULL).  opts->factor_schedule and factor_width are
+ * ignored.  Every candidate computes the same factors up to rounding.  Costs five setups.
+ * Errors: as mx_precond_setup. */
+int mx_precond_tune_factor(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
+                           const mx_precond_opts *opts, void *stream, int32_t *best_schedule,
+                           int32_t *best_width, double *best_ms, double *ms_each);
 /* Checks the device error word of P (set by a failed pivot or an expired wait).  Once such an
  * error has been reported (by this call, mx_gmres or mx_precond_autotune), P is unusable: its
  * device flags stay set, and every later mx_precond_apply, mx_precond_autotune, mx_gmres and

@@ -389,6 +389,17 @@ int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_
   });
 }
 
+int mx_precond_tune_factor(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
+                           const mx_precond_opts *opts, void *stream, int32_t *best_schedule,
+                           int32_t *best_width, double *best_ms, double *ms_each) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && A && m && p && opts, "NULL argument");
+    bind_device(ctx->device);
+    mx::precond_tune_factor(ctx, A, m, p, opts, (hipStream_t)stream, best_schedule, best_width,
+                            best_ms, ms_each);
+  });
+}
+
 int mx_precond_check(mx_precond *P) {
   MX_GUARD({
     MX_REQUIRE(P, "NULL argument");

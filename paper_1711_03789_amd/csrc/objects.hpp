@@ -247,6 +247,9 @@ int precond_check(mx_precond *P, hipStream_t st = nullptr);
 // throws the recorded device error of P, if any (see mx_precond::failed)
 void precond_refuse_failed(const mx_precond *P);
 void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_grid, double *best_ms);
+void precond_tune_factor(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_partition *ph,
+                         const mx_precond_opts *opts, hipStream_t st, int32_t *best_schedule,
+                         int32_t *best_width, double *best_ms, double *ms_each);
 void precond_export_diag(const mx_precond *P, int l, double *d);
 void precond_timing(mx_precond *P, int enable, int64_t *launches, double *ms_fwd, double *ms_bwd);
 void spmv_run(const mx_matrix *A, const void *x, void *y, bool c64, hipStream_t st);

@@ -1137,6 +1137,41 @@ void precond_autotune(mx_ctx *ctx, mx_precond *P, hipStream_t st, int32_t *best_
   if (best_ms) *best_ms = best_t;
 }
 
+// Factorisation tuner: sets up the preconditioner described by opts once per candidate
+// schedule (one stream; look-ahead with 1 .. 4 block columns per trailing-update pass) and keeps
+// the one whose factorisation took least time.  Every candidate computes the same factors up to
+// rounding; only the launch shapes differ.
+void precond_tune_factor(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_partition *ph,
+                         const mx_precond_opts *opts, hipStream_t st, int32_t *best_schedule,
+                         int32_t *best_width, double *best_ms, double *ms_each) {
+  struct Cand {
+    int sched, width;
+  };
+  const Cand cand[5] = {{MX_FACTOR_ONE_STREAM, 1}, {MX_FACTOR_LOOKAHEAD, 1}, {MX_FACTOR_LOOKAHEAD, 2},
+                        {MX_FACTOR_LOOKAHEAD, 3}, {MX_FACTOR_LOOKAHEAD, 4}};
+  double best = 1e300;
+  int bs = cand[0].sched, bw = cand[0].width;
+  for (int c = 0; c < 5; ++c) {
+    mx_precond_opts o = *opts;
+    o.factor_schedule = cand[c].sched;
+    o.factor_width = cand[c].width;
+    double ms;
+    {
+      mx_precond T;
+      PrecondPlan plan;
+      precond_plan(ctx, A, mh, ph, &o, &T, plan);
+      set_sweep_grid(&T, ctx->cus);
+      precond_materialize(&T, plan, st);
+      ms = T.info.t_factor * 1e3;
+    }  // its device memory goes back to the block cache before the next candidate
+    if (ms_each) ms_each[c] = ms;
+    if (ms < best) best = ms, bs = cand[c].sched, bw = cand[c].width;
+  }
+  if (best_schedule) *best_schedule = bs;
+  if (best_width) *best_width = bw;
+  if (best_ms) *best_ms = best;
+}
+
 int precond_check(mx_precond *P, hipStream_t st) {
   int h[4];
   MX_HIP(hipMemcpyAsync(h, P->d_ctrl.p, sizeof(h), hipMemcpyDeviceToHost, st));

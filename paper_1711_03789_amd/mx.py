@@ -34,6 +34,7 @@ SYMBOLS = [
     "mx_server_destroy", "mx_matrix_upload", "mx_precond_plan", "mx_precond_materialize",
     "mx_selftest_host", "mx_gmres_noalloc", "mx_precond_add_coarse", "mx_precond_coarse_export",
     "mx_coarse_operators", "mx_weight_assemble", "mx_gmres_weighted", "mx_precond_plan_coarse",
+    "mx_precond_tune_factor",
 ]
 
 
@@ -153,6 +154,8 @@ def load(path=LIB_PATH):
         "mx_precond_check": (C.c_int, [P]),
         "mx_precond_add_coarse": (C.c_int, [P, P, P, P, C.c_int, C.c_int, P]),
         "mx_precond_plan_coarse": (C.c_int, [P, P, P, C.c_int, C.c_int]),
+        "mx_precond_tune_factor": (C.c_int, [P, P, P, P, C.POINTER(PrecondOpts), P, C.POINTER(C.c_int32),
+                                             C.POINTER(C.c_int32), C.POINTER(C.c_double), P]),
         "mx_precond_coarse_export": (C.c_int, [P] + [C.POINTER(C.c_int64)] * 3 + [P] * 6),
         "mx_coarse_operators": (C.c_int, [P, P, C.c_int] + [C.POINTER(C.c_int64)] * 3 + [P] * 6),
         "mx_precond_autotune": (C.c_int, [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
@@ -487,6 +490,18 @@ class Precond:
         d = np.zeros(n_local, np.complex128)
         _check(_lib.mx_precond_export_diag(self.h, l, n_local, _ptr(d)))
         return d
+
+
+def tune_factor(ctx, A, mesh, part, kind="oras", xi_prec=None, precision="c128", stream=None):
+    """Factorisation tuner (mx_precond_tune_factor): returns (schedule, width, best ms, ms of the
+    five candidates: one stream, look-ahead with widths 1..4)."""
+    o = PrecondOpts(KINDS.get(kind, kind), A.xi if xi_prec is None else xi_prec,
+                    PRECISIONS.get(precision, precision), 0, 0, 0, 0, 0, 0)
+    bs, bw, ms = C.c_int32(), C.c_int32(), C.c_double()
+    each = np.zeros(5)
+    _check(_lib.mx_precond_tune_factor(ctx.h, A.h, mesh.h, part.h, C.byref(o), _stream(stream),
+                                       C.byref(bs), C.byref(bw), C.byref(ms), _ptr(each)))
+    return bs.value, bw.value, ms.value, each.tolist()
 
 
 def gmres(ctx, A, Pc, b, x, restart=50, rtol=1e-6, max_iters=1000, flexible=False,

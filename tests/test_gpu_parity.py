@@ -504,3 +504,27 @@ def test_factor_schedules(gpu_lib, ctx, precision):
     for bad in (dict(schedule=7), dict(schedule="lookahead", width=5)):
         with pytest.raises(gpu_lib.MxError):
             gpu_lib.Precond(ctx, c.lA, c.lm, c.lp, "oras", precision=precision, **bad)
+
+
+def test_factor_tuner(gpu_lib, ctx):
+    """The factorisation tuner times the five launch shapes and returns one of them; the
+    preconditioner built with its choice applies like the default one (same factors up to
+    rounding)."""
+    say("factor tuner")
+    n, parts = (16, 14, 12), (3, 2, 2)
+    cuts = (jittered_cuts(16, 3, 0.2, 7), jittered_cuts(14, 2, 0.2, 8), jittered_cuts(12, 2, 0.2, 9))
+    lm = gpu_lib.Mesh(*n)
+    lp = gpu_lib.Partition(lm, *parts, 2, *cuts)
+    A = gpu_lib.Matrix(ctx, lm, 5.0, 5.0)
+    sch, wid, best, each = gpu_lib.tune_factor(ctx, A, lm, lp, "oras")
+    say("  choice", sch, wid, best, each)
+    assert (sch, wid) in [(1, 1), (2, 1), (2, 2), (2, 3), (2, 4)]
+    assert len(each) == 5 and min(each) > 0 and best == min(each)
+    P1 = gpu_lib.Precond(ctx, A, lm, lp, "oras")
+    P2 = gpu_lib.Precond(ctx, A, lm, lp, "oras", schedule=sch, width=wid)
+    v = random_rhs(lm.n_edge, 51)
+    vd, z1, z2 = dev(v), dev(np.zeros(lm.n_edge)), dev(np.zeros(lm.n_edge))
+    P1.apply(vd, z1)
+    P2.apply(vd, z2)
+    a, b = host(z1), host(z2)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
