@@ -356,15 +356,22 @@ int mx_gmres_noalloc(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void 
  * request's host work (mesh, assembly, partition, local problems, orderings), which fixes its exact
  * device footprint, then waits until the footprint fits in what is left of `hbm_budget`, runs the
  * device work (upload, factorisation, GMRES) on its stream concurrently with the other admitted
- * requests and returns its memory.  Results do not depend on what else is running (deterministic
- * kernels).  A server is driven from any number of host threads. */
+ * requests and returns its memory.  With batch_applies, the preconditioner applications of the
+ * requests that are in their GMRES phase are batched: a batcher thread collects one application
+ * from each of them (or whatever arrived within batch_window_us) and runs their restrictions,
+ * one forward and one backward block-sweep launch over all their subdomains, and their
+ * prolongations, on its own stream; each request's stream waits for that batch.  Results do not
+ * depend on what else is running (deterministic kernels; a batched application computes exactly
+ * what a single one does).  A server is driven from any number of host threads. */
 typedef struct {
   uint64_t hbm_budget;  /* device bytes the server may hold; 0 = 85% of the free memory          */
-  int slots;            /* requests in flight (worker threads / streams)                           */
+  int slots;            /* requests in flight (worker threads / streams), at most 16               */
   int kind, precision;  /* preconditioner (MX_AS/MX_RAS/MX_ORAS) and factor precision             */
   int layers;           /* overlap sweeps                                                          */
   int restart, max_iters, flexible, spmv_c64;
   double rtol;
+  int batch_applies;    /* 1: batch the applications of co-resident requests; 0: each on its own  */
+  int batch_window_us;  /* longest wait for the other requests' applications (0 = 200 us)          */
 } mx_server_opts;
 
 typedef struct {
@@ -398,6 +405,9 @@ int mx_server_solution(mx_server *s, uint64_t ticket, double *x_host, int64_t n)
 int mx_server_release(mx_server *s, uint64_t ticket);
 /* Budget, peak reserved bytes and the largest number of simultaneously admitted requests. */
 int mx_server_stats(mx_server *s, uint64_t *budget, uint64_t *peak_used, int *max_admitted);
+/* Batched applications so far: launches of the batcher and the applications they carried
+ * (equal when nothing was batched; both 0 without batch_applies).  Errors: MX_EINVAL. */
+int mx_server_batch_stats(mx_server *s, uint64_t *batches, uint64_t *applications);
 /* Finishes every submitted request, then stops the workers. */
 void mx_server_destroy(mx_server *s);
 

@@ -163,6 +163,10 @@ struct mx_precond {
   double k = 0, xi_prec = 0;       // wavenumber and absorption the local problems were built with
   int bc = MX_BC_IMPEDANCE;
   bool share = false;               // built for a resident share of the subdomains only
+  // when set, one-level applications go to this function instead of being launched here (a
+  // server batching the applications of several requests)
+  void (*apply_hook)(void *arg, mx_precond *P, const void *vin, void *zout, hipStream_t st) = nullptr;
+  void *apply_hook_arg = nullptr;
   mx::CoarseLevel *coarse = nullptr;  // set by mx_precond_add_coarse (owned)
   std::unique_ptr<mx::PrecondPlan> plan;  // set between mx_precond_plan and mx_precond_materialize
   int64_t pool_limit = 0;                 // bytes of full tiles at a time (0: what device memory allows)
@@ -227,6 +231,13 @@ size_t gmres_device_bytes(int64_t n, int restart, bool flexible);
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st);
 // the one-level part alone: restriction, block sweeps, prolongation
 void precond_apply_level1(mx_precond *P, const void *vin, void *zout, hipStream_t st);
+// batched one-level applications (precond.hip): bytes of one sweep job, writing P's job into a
+// device array of jobs, and one launch per sweep direction over up to 16 preconditioners
+size_t batch_job_bytes();
+void batch_job_write(mx_precond *P, void *jobs, int slot);
+constexpr int kMaxBatchJobs = 16;
+void batch_apply(int njobs, const int *slots, mx_precond *const *Ps, const void *const *vin,
+                 void *const *zout, const void *jobs_dev, int *bctrl, int grid_cap, hipStream_t st);
 // coarse level (Sec. 3.2, 3.3): R^0 and A^0 = R^0 A R^0^T on the host (host_coarse.cpp)
 void build_restriction(const Mesh &fine, const Mesh &coarse, int ratio, int bc, HostCSR &R0,
                        HostCSR &R0T);

@@ -691,11 +691,32 @@ __device__ __forceinline__ bool stream_bwd_wide(const cx<float> *__restrict__ pa
   return true;
 }
 
-template <typename T, bool FWD>
+// One sweep of several preconditioners in one launch (serving several requests at once): each
+// preconditioner's items keep their own order, and the jobs follow one another in the ticket
+// order, so an item still comes after every item it depends on.  A job is a preconditioner's
+// view of its factors, ticket orders and local vectors; batch launches find an item's job from
+// the prefix of item counts (slot[j] = the job's entry in the device array of jobs).
+template <typename T>
+struct SweepJob {
+  SubView v;
+  const cx<T> *pack;
+  const int32_t *sub_f, *blk_f, *sub_b, *blk_b;  // forward and backward ticket orders
+  int n_half;                                      // items per direction
+  cx<T> *r, *y, *z;
+  int *ctrl;                                       // the preconditioner's control block
+};
+constexpr int kMaxBatch = 16;
+struct BatchIndex {
+  int njobs;
+  int slot[kMaxBatch];
+  int prefix[kMaxBatch + 1];
+};
+
+template <typename T, bool FWD, bool BATCH>
 __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_sweep(
-    SubView v, const cx<T> *__restrict__ pack, const int32_t *__restrict__ sched_sub,
-    const int32_t *__restrict__ sched_blk, int n_items, const cx<T> *__restrict__ rvec, cx<T> *yvec,
-    cx<T> *zvec, int *ctrl) {
+    SubView v0, const cx<T> *__restrict__ pack0, const int32_t *__restrict__ sched_sub0,
+    const int32_t *__restrict__ sched_blk0, int n_items, const cx<T> *__restrict__ rvec0,
+    cx<T> *yvec0, cx<T> *zvec0, int *ctrl, const SweepJob<T> *__restrict__ jobs, BatchIndex bidx) {
   __shared__ int s_item;
   __shared__ int s_dead;
   __shared__ cx<T> sL[kTile][kTile];  // neighbour tile of the last dependency
@@ -720,7 +741,26 @@ __global__ __launch_bounds__(kSweepThreads, SweepMinWaves<T>::value) void k_swee
     const int item = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (item >= n_items) break;
-    const int l = sched_sub[item], B = sched_blk[item];
+    SubView v = v0;
+    const cx<T> *__restrict__ pack = pack0;
+    const int32_t *sched_sub = sched_sub0, *sched_blk = sched_blk0;
+    const cx<T> *__restrict__ rvec = rvec0;
+    cx<T> *yvec = yvec0, *zvec = zvec0;
+    int li = item;
+    if constexpr (BATCH) {  // the job holding this item (uniform across the workgroup)
+      int j = 0;
+      while (j + 1 < bidx.njobs && bidx.prefix[j + 1] <= item) ++j;
+      const SweepJob<T> &jb = jobs[bidx.slot[j]];
+      v = jb.v;
+      pack = jb.pack;
+      sched_sub = FWD ? jb.sub_f : jb.sub_b;
+      sched_blk = FWD ? jb.blk_f : jb.blk_b;
+      rvec = jb.r;
+      yvec = jb.y;
+      zvec = jb.z;
+      li = item - bidx.prefix[j];
+    }
+    const int l = sched_sub[li], B = sched_blk[li];
     const int bb = v.brow_base[l];
     const int64_t vb = v.vec_base[l];
     // Every wave streams its own 8 rows and checks the block results it multiplies by itself, so
@@ -1033,14 +1073,15 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
     MX_HIP(hipEventRecord(P->ev_start[P->n_timed], st));
   }
   const int half = P->n_items / 2;
-  k_sweep<T, true><<<P->trsv_grid, kSweepThreads, 0, st>>>(
+  k_sweep<T, true, false><<<P->trsv_grid, kSweepThreads, 0, st>>>(
       v, P->pack.as<cx<T>>(), P->d_sched_sub.as<int32_t>(), P->d_sched_blk.as<int32_t>(), half,
-      P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), P->d_ctrl.as<int>());
+      P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), P->d_ctrl.as<int>(), nullptr,
+      BatchIndex{});
   if (P->timing) MX_HIP(hipEventRecord(P->ev_mid[P->n_timed], st));
-  k_sweep<T, false><<<P->trsv_grid, kSweepThreads, 0, st>>>(
+  k_sweep<T, false, false><<<P->trsv_grid, kSweepThreads, 0, st>>>(
       v, P->pack.as<cx<T>>(), P->d_sched_sub.as<int32_t>() + half,
       P->d_sched_blk.as<int32_t>() + half, half, P->d_r.as<cx<T>>(), P->d_y.as<cx<T>>(),
-      P->d_z.as<cx<T>>(), P->d_ctrl.as<int>());
+      P->d_z.as<cx<T>>(), P->d_ctrl.as<int>(), nullptr, BatchIndex{});
   if (P->timing) MX_HIP(hipEventRecord(P->ev_stop[P->n_timed++], st));
   const int64_t E = P->E;
   if (P->kind == MX_AS)
@@ -1053,7 +1094,111 @@ static void apply_t(mx_precond *P, const void *vin, void *zout, hipStream_t st) 
   MX_HIP(hipGetLastError());
 }
 
+// ---- batched applications of several preconditioners (serving) ------------------------------------
+template <typename T>
+static SweepJob<T> job_of(mx_precond *P) {
+  SweepJob<T> j{};
+  j.v = view_of(P);
+  j.pack = P->pack.as<cx<T>>();
+  const int half = P->n_items / 2;
+  j.sub_f = P->d_sched_sub.as<int32_t>();
+  j.blk_f = P->d_sched_blk.as<int32_t>();
+  j.sub_b = j.sub_f + half;
+  j.blk_b = j.blk_f + half;
+  j.n_half = half;
+  j.r = P->d_r.as<cx<T>>();
+  j.y = P->d_y.as<cx<T>>();
+  j.z = P->d_z.as<cx<T>>();
+  j.ctrl = P->d_ctrl.as<int>();
+  return j;
+}
+
+static_assert(sizeof(SweepJob<double>) == sizeof(SweepJob<float>), "one job layout for both precisions");
+size_t batch_job_bytes() { return sizeof(SweepJob<double>); }
+
+void batch_job_write(mx_precond *P, void *jobs, int slot) {
+  if (P->plan) fail(MX_EINVAL, "preconditioner is planned but not materialised");
+  const size_t b = batch_job_bytes();
+  if (P->prec == MX_C128) {
+    SweepJob<double> j = job_of<double>(P);
+    MX_HIP(hipMemcpy((char *)jobs + (size_t)slot * b, &j, sizeof(j), hipMemcpyHostToDevice));
+  } else {
+    SweepJob<float> j = job_of<float>(P);
+    MX_HIP(hipMemcpy((char *)jobs + (size_t)slot * b, &j, sizeof(j), hipMemcpyHostToDevice));
+  }
+}
+
+// ticket counters and abort word of a batch launch to zero
+__global__ void k_batch_reset(int *ctrl) {
+  if (threadIdx.x < 8) ctrl[threadIdx.x] = 0;
+}
+// an expired wait in a batch is reported by every preconditioner of the batch
+template <typename T>
+__global__ void k_batch_finish(const int *ctrl, const SweepJob<T> *jobs, BatchIndex bi) {
+  const int j = threadIdx.x;
+  if (j < bi.njobs && ctrl[2]) jobs[bi.slot[j]].ctrl[2] = 1;
+}
+
+template <typename T>
+static void batch_apply_t(int njobs, const int *slots, mx_precond *const *Ps, const void *const *vin,
+                          void *const *zout, const void *jobs_dev, int *bctrl, int grid_cap,
+                          hipStream_t st) {
+  BatchIndex bi{};
+  bi.njobs = njobs;
+  bi.prefix[0] = 0;
+  for (int j = 0; j < njobs; ++j) {
+    bi.slot[j] = slots[j];
+    bi.prefix[j + 1] = bi.prefix[j] + Ps[j]->n_items / 2;
+  }
+  const int total = bi.prefix[njobs];
+  const SweepJob<T> *jobs = (const SweepJob<T> *)jobs_dev;
+  for (int j = 0; j < njobs; ++j) {
+    mx_precond *P = Ps[j];
+    const int64_t n = P->vec_total;
+    k_restrict<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+        n, P->d_glob.as<int32_t>(), (const cx<double> *)vin[j], P->d_r.as<cx<T>>(),
+        P->d_y.as<cx<T>>(), P->d_z.as<cx<T>>(), P->d_ctrl.as<int>());
+  }
+  k_batch_reset<<<1, 64, 0, st>>>(bctrl);
+  const int grid = std::max(1, std::min(total, grid_cap));
+  k_sweep<T, true, true><<<grid, kSweepThreads, 0, st>>>(SubView{}, nullptr, nullptr, nullptr, total, nullptr,
+                                                         nullptr, nullptr, bctrl, jobs, bi);
+  k_sweep<T, false, true><<<grid, kSweepThreads, 0, st>>>(SubView{}, nullptr, nullptr, nullptr, total, nullptr,
+                                                          nullptr, nullptr, bctrl, jobs, bi);
+  k_batch_finish<T><<<1, 64, 0, st>>>(bctrl, jobs, bi);
+  for (int j = 0; j < njobs; ++j) {
+    mx_precond *P = Ps[j];
+    const int64_t E = P->E;
+    if (P->kind == MX_AS)
+      k_prolong_sum<T><<<(unsigned)((E + 255) / 256), 256, 0, st>>>(
+          E, P->d_sum_ptr.as<int64_t>(), P->d_sum_idx.as<int64_t>(), P->d_z.as<cx<T>>(),
+          (cx<double> *)zout[j]);
+    else
+      k_prolong_owner<T><<<(unsigned)((E + 255) / 256), 256, 0, st>>>(
+          E, P->d_src.as<int64_t>(), P->d_z.as<cx<T>>(), (cx<double> *)zout[j]);
+  }
+  MX_HIP(hipGetLastError());
+}
+
+// z_j = B_j^-1 v_j for up to kMaxBatch one-level preconditioners of one precision: their
+// restrictions, one forward and one backward sweep launch over all of them, their prolongations.
+// Their sweep jobs must have been written to jobs_dev[slots[j]] (batch_job_write); bctrl is a
+// control block of 8 ints owned by the caller.  Each result equals that of precond_apply_level1.
+void batch_apply(int njobs, const int *slots, mx_precond *const *Ps, const void *const *vin,
+                 void *const *zout, const void *jobs_dev, int *bctrl, int grid_cap, hipStream_t st) {
+  if (njobs < 1 || njobs > kMaxBatch) fail(MX_EINVAL, "batch of 1 .. 16 applications");
+  const int prec = Ps[0]->prec;
+  for (int j = 0; j < njobs; ++j)
+    if (Ps[j]->prec != prec || Ps[j]->coarse) fail(MX_EINVAL, "batched applications need one-level preconditioners of one precision");
+  if (prec == MX_C128) batch_apply_t<double>(njobs, slots, Ps, vin, zout, jobs_dev, bctrl, grid_cap, st);
+  else batch_apply_t<float>(njobs, slots, Ps, vin, zout, jobs_dev, bctrl, grid_cap, st);
+}
+
 void precond_apply_level1(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
+  if (P->apply_hook) {  // applications routed elsewhere (a server's batcher)
+    P->apply_hook(P->apply_hook_arg, P, vin, zout, st);
+    return;
+  }
   if (P->prec == MX_C128) apply_t<double>(P, vin, zout, st);
   else apply_t<float>(P, vin, zout, st);
 }

@@ -39,6 +39,145 @@ struct SrvRequest {
   std::vector<double> x;  // interleaved complex128 solution
 };
 
+// Batches the preconditioner applications of the requests in their GMRES phase.  A request's
+// GMRES calls apply() (through the preconditioner's apply hook) from its slot thread: the
+// application joins the pending batch, and the call returns once the batch has been launched on
+// the batcher's stream, after making the request's stream wait for it.  The batcher launches
+// when every request in its GMRES phase has an application pending, or when the window since
+// the first pending one has passed.  At most one application per request is pending (apply
+// blocks until launched), so a batch holds at most one per slot.
+struct Batcher {
+  struct Job {
+    mx_precond *P = nullptr;
+    const void *v = nullptr;
+    void *z = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+    bool pending = false, launched = false;
+  };
+  int device = 0, cus = 256, window_us = 200;
+  std::mutex mu;
+  std::condition_variable cv_submit, cv_launched;
+  std::vector<Job> jobs;  // one per slot
+  int active = 0;         // slots whose request is in its GMRES phase
+  int npending = 0;
+  bool stop = false;
+  std::thread th;
+  hipStream_t st = nullptr;
+  DevBuf jobs_dev, ctrl;
+  uint64_t batches = 0, applications = 0;
+
+  void start(int dev, int ncus, int slots, int window) {
+    device = dev, cus = ncus, window_us = window > 0 ? window : 200;
+    MX_HIP(hipSetDevice(device));
+    MX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    jobs.resize(slots);
+    for (auto &j : jobs) {
+      MX_HIP(hipEventCreateWithFlags(&j.ready, hipEventDisableTiming));
+      MX_HIP(hipEventCreateWithFlags(&j.done, hipEventDisableTiming));
+    }
+    jobs_dev.alloc(batch_job_bytes() * slots);
+    ctrl.alloc(64);
+    th = std::thread([this] { run(); });
+  }
+  void finish() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv_submit.notify_all();
+    if (th.joinable()) th.join();
+    if (st) (void)hipStreamSynchronize(st);
+    jobs_dev.release();
+    ctrl.release();
+    for (auto &j : jobs) {
+      if (j.ready) (void)hipEventDestroy(j.ready);
+      if (j.done) (void)hipEventDestroy(j.done);
+    }
+    if (st) (void)hipStreamDestroy(st);
+    st = nullptr;
+  }
+  // a slot's request enters (P materialised) or leaves its GMRES phase
+  void enter(int slot, mx_precond *P) {
+    batch_job_write(P, jobs_dev.p, slot);
+    std::lock_guard<std::mutex> lk(mu);
+    jobs[slot].P = P;
+    ++active;
+  }
+  void leave(int slot) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      jobs[slot].P = nullptr;
+      --active;
+    }
+    cv_submit.notify_all();  // the others may now be complete
+  }
+  void apply(int slot, const void *v, void *z, hipStream_t rst) {
+    Job &j = jobs[slot];
+    MX_HIP(hipEventRecord(j.ready, rst));
+    std::unique_lock<std::mutex> lk(mu);
+    j.v = v, j.z = z, j.pending = true, j.launched = false;
+    ++npending;
+    cv_submit.notify_all();
+    cv_launched.wait(lk, [&] { return j.launched || stop; });
+    if (!j.launched) fail(MX_EDEVICE, "server stopped with an application pending");
+    lk.unlock();
+    MX_HIP(hipStreamWaitEvent(rst, j.done, 0));
+  }
+  void run() {
+    (void)hipSetDevice(device);
+    std::vector<int> slots;
+    std::vector<mx_precond *> Ps;
+    std::vector<const void *> vin;
+    std::vector<void *> zout;
+    while (true) {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_submit.wait(lk, [&] { return stop || npending > 0; });
+      if (stop) break;
+      cv_submit.wait_for(lk, std::chrono::microseconds(window_us),
+                         [&] { return stop || npending >= active; });
+      if (stop) break;
+      slots.clear(), Ps.clear(), vin.clear(), zout.clear();
+      for (int s = 0; s < (int)jobs.size(); ++s)
+        if (jobs[s].pending) {
+          slots.push_back(s), Ps.push_back(jobs[s].P), vin.push_back(jobs[s].v), zout.push_back(jobs[s].z);
+          jobs[s].pending = false;
+        }
+      npending = 0;
+      lk.unlock();
+      std::string err;
+      try {
+        for (int s : slots) MX_HIP(hipStreamWaitEvent(st, jobs[s].ready, 0));
+        batch_apply((int)slots.size(), slots.data(), Ps.data(), vin.data(), zout.data(), jobs_dev.p,
+                    ctrl.as<int>(), cus, st);
+        for (int s : slots) MX_HIP(hipEventRecord(jobs[s].done, st));
+      } catch (const Error &e) {
+        err = e.msg;
+      }
+      lk.lock();
+      ++batches;
+      applications += slots.size();
+      for (int s : slots) jobs[s].launched = err.empty();
+      if (!err.empty()) stop = true;  // a launch failure ends batching: pending callers fail
+      lk.unlock();
+      cv_launched.notify_all();
+    }
+    cv_launched.notify_all();
+  }
+};
+
+static void batch_hook(void *arg, mx_precond *P, const void *v, void *z, hipStream_t st);
+
+struct SlotHook {  // what the apply hook of a slot's preconditioner needs
+  Batcher *b;
+  int slot;
+};
+
+static void batch_hook(void *arg, mx_precond *P, const void *v, void *z, hipStream_t st) {
+  (void)P;
+  SlotHook *h = (SlotHook *)arg;
+  h->b->apply(h->slot, v, z, st);
+}
+
 struct Server {
   mx_server_opts opts{};
   int device = 0;
@@ -53,15 +192,17 @@ struct Server {
   int admitted = 0, max_admitted = 0;
   uint64_t finished = 0;  // device phases ended (successfully or not)
   std::vector<std::thread> workers;
+  Batcher batcher;         // used when opts.batch_applies
+  std::vector<SlotHook> hooks;
 
-  void run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R);
-  void device_phase(mx_ctx *ctx, hipStream_t st, SrvRequest *R, mx_matrix *A, mx_precond *P,
+  void run_request(int slot, mx_ctx *ctx, hipStream_t st, SrvRequest *R);
+  void device_phase(int slot, mx_ctx *ctx, hipStream_t st, SrvRequest *R, mx_matrix *A, mx_precond *P,
                     PrecondPlan &plan, const std::vector<double> &f, int64_t E);
   void release_request(mx_ctx *ctx, hipStream_t st, mx_matrix *A, mx_precond *P);
-  void worker();
+  void worker(int slot);
 };
 
-void Server::run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
+void Server::run_request(int slot, mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
   const mx_request &q = R->req;
   // ---- host phase (no device memory) ----
   auto mesh = std::make_unique<mx_mesh>();
@@ -130,7 +271,7 @@ void Server::run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
         seen = finished;
       }
       try {
-        device_phase(ctx, st, R, A.get(), P.get(), plan, f, E);
+        device_phase(slot, ctx, st, R, A.get(), P.get(), plan, f, E);
         return;
       } catch (const Error &e) {
         release_request(ctx, st, A.get(), P.get());
@@ -149,8 +290,8 @@ void Server::run_request(mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
   }
 }
 
-void Server::device_phase(mx_ctx *ctx, hipStream_t st, SrvRequest *R, mx_matrix *A, mx_precond *P,
-                          PrecondPlan &plan, const std::vector<double> &f, int64_t E) {
+void Server::device_phase(int slot, mx_ctx *ctx, hipStream_t st, SrvRequest *R, mx_matrix *A,
+                          mx_precond *P, PrecondPlan &plan, const std::vector<double> &f, int64_t E) {
   AllocScope scope(st);
   matrix_upload(A);
   precond_materialize(P, plan, st);
@@ -166,7 +307,26 @@ void Server::device_phase(mx_ctx *ctx, hipStream_t st, SrvRequest *R, mx_matrix 
   go.spmv_c64 = opts.spmv_c64;
   go.rtol = opts.rtol;
   mx_gmres_stats gs{};
-  gmres_run(ctx, A, P, b.p, x.p, &go, &gs, nullptr, st);
+  if (opts.batch_applies) {  // the GMRES phase: applications go through the batcher
+    struct Phase {
+      Server *s;
+      int slot;
+      mx_precond *P;
+      Phase(Server *s_, int sl, mx_precond *P_) : s(s_), slot(sl), P(P_) {
+        s->batcher.enter(slot, P);
+        P->apply_hook = batch_hook;
+        P->apply_hook_arg = &s->hooks[slot];
+      }
+      ~Phase() {
+        P->apply_hook = nullptr;
+        P->apply_hook_arg = nullptr;
+        s->batcher.leave(slot);
+      }
+    } phase(this, slot, P);
+    gmres_run(ctx, A, P, b.p, x.p, &go, &gs, nullptr, st);
+  } else {
+    gmres_run(ctx, A, P, b.p, x.p, &go, &gs, nullptr, st);
+  }
   R->x.resize(2 * E);
   MX_HIP(hipMemcpyAsync(R->x.data(), x.p, 16 * (size_t)E, hipMemcpyDeviceToHost, st));
   MX_HIP(hipStreamSynchronize(st));
@@ -193,7 +353,7 @@ void Server::release_request(mx_ctx *ctx, hipStream_t st, mx_matrix *A, mx_preco
   (void)hipStreamSynchronize(st);
 }
 
-void Server::worker() {
+void Server::worker(int slot) {
   hipStream_t st = nullptr;
   mx_ctx ctx;
   ctx.device = device;
@@ -219,7 +379,7 @@ void Server::worker() {
       msg = "server slot could not create its stream";
     } else {
       try {
-        run_request(&ctx, st, R);
+        run_request(slot, &ctx, st, R);
       } catch (const Error &e) {
         code = e.code;
         msg = e.msg;
@@ -284,8 +444,15 @@ int mx_server_create(int device, const mx_server_opts *opts, mx_server **out) {
     }
     MX_HIP(hipMemGetInfo(&free_b, &total_b));
     S->s.budget = opts->hbm_budget ? opts->hbm_budget : (uint64_t)(0.85 * (double)free_b);
+    if (opts->slots > mx::kMaxBatchJobs) mx::fail(MX_EINVAL, "at most 16 slots");
+    if (opts->batch_applies) {
+      S->s.hooks.resize(opts->slots);
+      for (int i = 0; i < opts->slots; ++i) S->s.hooks[i] = {&S->s.batcher, i};
+      S->s.batcher.start(device, S->s.cus, opts->slots, opts->batch_window_us);
+    }
     try {
-      for (int i = 0; i < opts->slots; ++i) S->s.workers.emplace_back([p = &S->s] { p->worker(); });
+      for (int i = 0; i < opts->slots; ++i)
+        S->s.workers.emplace_back([p = &S->s, i] { p->worker(i); });
     } catch (...) {  // the workers already started are stopped and joined before S goes away
       {
         std::lock_guard<std::mutex> lk(S->s.mu);
@@ -293,6 +460,7 @@ int mx_server_create(int device, const mx_server_opts *opts, mx_server **out) {
       }
       S->s.cv_queue.notify_all();
       for (auto &t : S->s.workers) t.join();
+      S->s.batcher.finish();
       throw;
     }
     *out = S.release();
@@ -428,6 +596,19 @@ int mx_server_stats(mx_server *S, uint64_t *budget, uint64_t *peak_used, int *ma
   }
 }
 
+int mx_server_batch_stats(mx_server *S, uint64_t *batches, uint64_t *applications) {
+  try {
+    if (!S) mx::fail(MX_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->s.batcher.mu);
+    if (batches) *batches = S->s.batcher.batches;
+    if (applications) *applications = S->s.batcher.applications;
+    return MX_OK;
+  } catch (const Error &e) {
+    mx::set_error(e.code, e.msg);
+    return e.code;
+  }
+}
+
 void mx_server_destroy(mx_server *S) {
   if (!S) return;
   {
@@ -436,6 +617,7 @@ void mx_server_destroy(mx_server *S) {
   }
   S->s.cv_queue.notify_all();
   for (auto &t : S->s.workers) t.join();
+  S->s.batcher.finish();
   delete S;
 }
 

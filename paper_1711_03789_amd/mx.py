@@ -34,7 +34,7 @@ SYMBOLS = [
     "mx_server_destroy", "mx_matrix_upload", "mx_precond_plan", "mx_precond_materialize",
     "mx_selftest_host", "mx_gmres_noalloc", "mx_precond_add_coarse", "mx_precond_coarse_export",
     "mx_coarse_operators", "mx_weight_assemble", "mx_gmres_weighted", "mx_precond_plan_coarse",
-    "mx_precond_tune_factor",
+    "mx_precond_tune_factor", "mx_server_batch_stats",
 ]
 
 
@@ -87,7 +87,7 @@ class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("slots", C.c_int), ("kind", C.c_int),
                 ("precision", C.c_int), ("layers", C.c_int), ("restart", C.c_int),
                 ("max_iters", C.c_int), ("flexible", C.c_int), ("spmv_c64", C.c_int),
-                ("rtol", C.c_double)]
+                ("rtol", C.c_double), ("batch_applies", C.c_int), ("batch_window_us", C.c_int)]
 
 
 class Request(C.Structure):
@@ -167,6 +167,7 @@ def load(path=LIB_PATH):
         "mx_server_stats": (C.c_int, [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                       C.POINTER(C.c_int)]),
         "mx_server_destroy": (None, [P]),
+        "mx_server_batch_stats": (C.c_int, [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
         "mx_precond_sweep_timing": (C.c_int, [P, C.c_int, C.POINTER(C.c_int64),
                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "mx_precond_destroy": (None, [P]),
@@ -533,10 +534,12 @@ class Server:
     """Continuous-batching solve server (include/mx.h, mx_server_*)."""
 
     def __init__(self, device=0, slots=4, hbm_budget=0, kind="oras", precision="c64", layers=2,
-                 restart=50, max_iters=1000, flexible=True, spmv_c64=False, rtol=1e-6):
+                 restart=50, max_iters=1000, flexible=True, spmv_c64=False, rtol=1e-6,
+                 batch_applies=True, batch_window_us=0):
         load()
         o = ServerOpts(hbm_budget, slots, KINDS.get(kind, kind), PRECISIONS.get(precision, precision),
-                       layers, restart, max_iters, int(flexible), int(spmv_c64), rtol)
+                       layers, restart, max_iters, int(flexible), int(spmv_c64), rtol,
+                       int(batch_applies), batch_window_us)
         h = P()
         _check(_lib.mx_server_create(device, C.byref(o), C.byref(h)))
         self.h = h
@@ -567,7 +570,10 @@ class Server:
     def stats(self):
         b, pk, ma = C.c_uint64(), C.c_uint64(), C.c_int()
         _check(_lib.mx_server_stats(self.h, C.byref(b), C.byref(pk), C.byref(ma)))
-        return {"budget": b.value, "peak_used": pk.value, "max_admitted": ma.value}
+        nb, na = C.c_uint64(), C.c_uint64()
+        _check(_lib.mx_server_batch_stats(self.h, C.byref(nb), C.byref(na)))
+        return {"budget": b.value, "peak_used": pk.value, "max_admitted": ma.value,
+                "batches": nb.value, "batched_applications": na.value}
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -1,5 +1,7 @@
-"""Solve server (continuous batching): results are the same alone and in the mix, requests that
-can never fit the HBM budget are refused, and a served solution matches the FP64 oracle."""
+"""Solve server (continuous batching): results are the same alone and in the mix, with the
+preconditioner applications of co-resident requests batched into shared sweep launches or each
+on its own stream; requests that can never fit the HBM budget are refused, and a served solution
+matches the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -15,6 +17,45 @@ def say(*a):
     print(*a, flush=True)
 
 
+OTHERS = [dict(n=14, p=2, k=7.0, xi=7.0), dict(n=9, p=3, k=4.0, xi=16.0),
+          dict(n=16, p=2, k=8.0, xi=64.0), dict(n=12, p=2, k=6.0, xi=6.0)]
+
+
+def _mix(srv):
+    tickets = [srv.submit(**o) for o in OTHERS[:2]]
+    tm = srv.submit(**REQ)
+    tickets += [srv.submit(**o) for o in OTHERS[2:]]
+    rm = srv.wait(tm, 300.0)
+    sols = []
+    for tk in tickets:
+        ro = srv.wait(tk, 300.0)
+        assert ro["status"] == 0 and ro["converged"], ro
+        sols.append(srv.solution(tk, ro["n_dof"]))
+    return rm, srv.solution(tm, rm["n_dof"]), sols
+
+
+def test_batched_and_unbatched_applications_agree(gpu_lib):
+    """The same mix of requests served with batched preconditioner applications (one sweep
+    launch per direction over the co-resident requests) and with one launch per request on its
+    own stream: every solution bitwise equal; the batcher did batch."""
+    say("serve batched vs per stream")
+    res = {}
+    for batched in (True, False):
+        srv = gpu_lib.Server(slots=4, precision="c64", restart=50, batch_applies=batched)
+        res[batched] = _mix(srv)
+        st = srv.stats()
+        say("  batched" if batched else "  per stream", st)
+        if batched:
+            assert st["batched_applications"] > st["batches"] > 0
+        else:
+            assert st["batches"] == 0
+        srv.close()
+    (ra, xa, sa), (rb, xb, sb) = res[True], res[False]
+    assert ra["iters"] == rb["iters"] and np.array_equal(xa, xb)
+    for u, w in zip(sa, sb):
+        assert np.array_equal(u, w)
+
+
 def test_alone_vs_in_the_mix(gpu_lib):
     say("serve alone")
     srv = gpu_lib.Server(slots=3, precision="c64", restart=50)
@@ -24,16 +65,7 @@ def test_alone_vs_in_the_mix(gpu_lib):
     x_alone = srv.solution(t, r["n_dof"])
     say("  alone", r)
     # the same request among others of different sizes, k and xi, all in flight together
-    others = [dict(n=14, p=2, k=7.0, xi=7.0), dict(n=9, p=3, k=4.0, xi=16.0),
-              dict(n=16, p=2, k=8.0, xi=64.0), dict(n=12, p=2, k=6.0, xi=6.0)]
-    tickets = [srv.submit(**o) for o in others[:2]]
-    tm = srv.submit(**REQ)
-    tickets += [srv.submit(**o) for o in others[2:]]
-    rm = srv.wait(tm, 300.0)
-    for tk in tickets:
-        ro = srv.wait(tk, 300.0)
-        assert ro["status"] == 0 and ro["converged"], ro
-    x_mix = srv.solution(tm, rm["n_dof"])
+    rm, x_mix, _ = _mix(srv)
     st = srv.stats()
     say("  mix", rm, st)
     assert rm["iters"] == r["iters"]
