@@ -319,7 +319,8 @@ def run_serving(args):
 
     from mx_inputs import serving_requests
     from paper_1711_03789_amd import mx
-    srv = mx.Server(slots=args.slots, precision="c64", restart=50, flexible=True, rtol=1e-6)
+    srv = mx.Server(slots=args.slots, precision="c64", restart=50, flexible=True, rtol=1e-6,
+                    batch_applies=not args.no_batch, batch_window_us=args.batch_window)
     calib = None
     rate = args.rate
     if rate <= 0:
@@ -366,7 +367,10 @@ def run_serving(args):
         "dtype": "complex64 factors + FP64 FGMRES", "data": "synthetic",
         "config": {"workload": "serving: %d requests, Poisson arrivals at %.2f/s, unit cube, "
                                "k~U[4,16], xi in {k,k^2}, n=ceil(k^1.5)+4, p=clamp(ceil(n/17),2,4), "
-                               "ORAS FGMRES(50) rtol 1e-6, %d slots" % (len(res), rate, args.slots)},
+                               "ORAS FGMRES(50) rtol 1e-6, %d slots, %s" % (
+                                   len(res), rate, args.slots,
+                                   "preconditioner applications of co-resident requests batched"
+                                   if not args.no_batch else "applications on each request's stream")},
         "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
         "throughput_solves_per_s": len(res) / (t1 - t0), "all_converged": ok,
         "mean_iters": float(np.mean([x["iters"] for x in res])),
@@ -394,6 +398,11 @@ def main():
                          "throughput)")
     ap.add_argument("--calib-requests", type=int, default=24, help="serving: calibration requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: requests in flight")
+    ap.add_argument("--batch-window", type=int, default=0,
+                    help="serving: microseconds the batcher waits for co-resident requests' "
+                         "applications (0: the library's default)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="serving: each request's applications on its own stream (no batching)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--coarse", type=int, default=0,
                     help="two-level: coarse mesh with this many times fewer cubes per axis (0: one-level)")

@@ -360,7 +360,8 @@ int mx_gmres_noalloc(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void 
  * requests that are in their GMRES phase are batched: a batcher thread collects one application
  * from each of them (or whatever arrived within batch_window_us) and runs their restrictions,
  * one forward and one backward block-sweep launch over all their subdomains, and their
- * prolongations, on its own stream; each request's stream waits for that batch.  Results do not
+ * prolongations, on its own stream; each request's stream waits for that batch.  A lone
+ * application runs on its request's own stream.  Results do not
  * depend on what else is running (deterministic kernels; a batched application computes exactly
  * what a single one does).  A server is driven from any number of host threads. */
 typedef struct {
@@ -371,7 +372,7 @@ typedef struct {
   int restart, max_iters, flexible, spmv_c64;
   double rtol;
   int batch_applies;    /* 1: batch the applications of co-resident requests; 0: each on its own  */
-  int batch_window_us;  /* longest wait for the other requests' applications (0 = 200 us)          */
+  int batch_window_us;  /* longest wait for the other requests' applications (0 = 50 us)           */
 } mx_server_opts;
 
 typedef struct {

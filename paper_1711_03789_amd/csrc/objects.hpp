@@ -229,8 +229,10 @@ size_t matrix_device_bytes(const mx_matrix *A);
 size_t gmres_device_bytes(int64_t n, int restart, bool flexible);
 // z = B^-1 v: the one-level preconditioner of P, combined with its coarse level if it has one
 void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st);
-// the one-level part alone: restriction, block sweeps, prolongation
+// the one-level part alone: restriction, block sweeps, prolongation (through P's apply hook if
+// it has one; precond_apply_direct launches them here in any case)
 void precond_apply_level1(mx_precond *P, const void *vin, void *zout, hipStream_t st);
+void precond_apply_direct(mx_precond *P, const void *vin, void *zout, hipStream_t st);
 // batched one-level applications (precond.hip): bytes of one sweep job, writing P's job into a
 // device array of jobs, and one launch per sweep direction over up to 16 preconditioners
 size_t batch_job_bytes();

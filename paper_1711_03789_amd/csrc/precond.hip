@@ -1199,6 +1199,10 @@ void precond_apply_level1(mx_precond *P, const void *vin, void *zout, hipStream_
     P->apply_hook(P->apply_hook_arg, P, vin, zout, st);
     return;
   }
+  precond_apply_direct(P, vin, zout, st);
+}
+
+void precond_apply_direct(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
   if (P->prec == MX_C128) apply_t<double>(P, vin, zout, st);
   else apply_t<float>(P, vin, zout, st);
 }

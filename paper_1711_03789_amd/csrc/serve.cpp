@@ -44,15 +44,17 @@ struct SrvRequest {
 // application joins the pending batch, and the call returns once the batch has been launched on
 // the batcher's stream, after making the request's stream wait for it.  The batcher launches
 // when every request in its GMRES phase has an application pending, or when the window since
-// the first pending one has passed.  At most one application per request is pending (apply
-// blocks until launched), so a batch holds at most one per slot.
+// the first pending one has passed.  A batch of one is handed back and launched on the
+// request's own stream, so lone applications keep running concurrently on the requests'
+// streams.  At most one application per request is pending (apply blocks until launched), so a
+// batch holds at most one per slot.
 struct Batcher {
   struct Job {
     mx_precond *P = nullptr;
     const void *v = nullptr;
     void *z = nullptr;
     hipEvent_t ready = nullptr, done = nullptr;
-    bool pending = false, launched = false;
+    bool pending = false, launched = false, alone = false;
   };
   int device = 0, cus = 256, window_us = 200;
   std::mutex mu;
@@ -67,7 +69,7 @@ struct Batcher {
   uint64_t batches = 0, applications = 0;
 
   void start(int dev, int ncus, int slots, int window) {
-    device = dev, cus = ncus, window_us = window > 0 ? window : 200;
+    device = dev, cus = ncus, window_us = window > 0 ? window : 50;
     MX_HIP(hipSetDevice(device));
     MX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     jobs.resize(slots);
@@ -115,13 +117,15 @@ struct Batcher {
     Job &j = jobs[slot];
     MX_HIP(hipEventRecord(j.ready, rst));
     std::unique_lock<std::mutex> lk(mu);
-    j.v = v, j.z = z, j.pending = true, j.launched = false;
+    j.v = v, j.z = z, j.pending = true, j.launched = false, j.alone = false;
     ++npending;
     cv_submit.notify_all();
     cv_launched.wait(lk, [&] { return j.launched || stop; });
     if (!j.launched) fail(MX_EDEVICE, "server stopped with an application pending");
+    const bool alone = j.alone;
     lk.unlock();
-    MX_HIP(hipStreamWaitEvent(rst, j.done, 0));
+    if (alone) precond_apply_direct(j.P, v, z, rst);
+    else MX_HIP(hipStreamWaitEvent(rst, j.done, 0));
   }
   void run() {
     (void)hipSetDevice(device);
@@ -143,6 +147,13 @@ struct Batcher {
           jobs[s].pending = false;
         }
       npending = 0;
+      if (slots.size() == 1) {  // nothing to merge with: launched on the request's stream
+        jobs[slots[0]].alone = true;
+        jobs[slots[0]].launched = true;
+        lk.unlock();
+        cv_launched.notify_all();
+        continue;
+      }
       lk.unlock();
       std::string err;
       try {
