@@ -411,6 +411,11 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="before timing, pick the factorisation launch shape (mx_precond_tune_factor) "
                          "and the sweep grid (mx_precond_autotune) on the first instance")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each Arnoldi step from a captured HIP graph (the sweeps are then "
+                         "not timed one by one, so no roofline figure)")
+    ap.add_argument("--rhs", type=int, default=1,
+                    help="right-hand sides solved per preconditioner setup (factors resident)")
     ap.add_argument("--weighted", action="store_true",
                     help="weighted GMRES in the D_k = K + k^2 M inner product (Sec. 5.2, eq:ip)")
     ap.add_argument("--overlap-factor", type=int, default=0, choices=[0, 1],
@@ -447,6 +452,10 @@ def main():
                                                       "Krylov vectors")
     if args.weighted:
         cfg["workload"] += "; weighted GMRES in the D_k = K + k^2 M inner product"
+    if args.rhs > 1:
+        cfg["workload"] += "; %d right-hand sides per preconditioner setup" % args.rhs
+    if args.graph:
+        cfg["workload"] += "; Arnoldi steps replayed from HIP graphs"
     if args.coarse:
         if args.workload == "scale-xi0" or args.overlap_factor:
             raise SystemExit("--coarse is not combined with scale-xi0 or --overlap-factor")
@@ -459,6 +468,9 @@ def main():
     E = mesh0.n_edge
     del mesh0
     rhs = {s: torch.from_numpy(random_rhs(E, s)).cuda() for _, _, s in inst}
+    # further right-hand sides of each instance when several are solved per setup
+    rhs_more = {s: [torch.from_numpy(random_rhs(E, 1000 + 100 * s + q)).cuda()
+                    for q in range(1, args.rhs)] for _, _, s in inst}
     if args.workload == "small":
         m0 = mx.Mesh(*n, *w.lengths)
         rhs[0] = torch.from_numpy(m0.rhs_gaussian(w.center, w.pol, w.sigma)).cuda()
@@ -528,15 +540,23 @@ def main():
                     P.add_coarse(ctx, A, mesh, args.coarse, args.combine)
                     t_coarse = time.perf_counter() - tc
                 t2 = time.perf_counter()
-                if record:
+                timed = record and not args.graph
+                if timed:
                     P.sweep_timing(True)
-                x.zero_()
-                st = mx.gmres(ctx, A, P, rhs[seed], x, restart=w.restart, rtol=w.rtol,
-                              max_iters=args.max_iters, flexible=mixed, spmv_c64=mixed, weight=D)
-                if record and mixed and "x_mixed" not in refs:
-                    refs["x_mixed"] = (kind, e, seed, x.clone())
-                if record and args.workload == "small":
-                    refs.setdefault("x_small", []).append(x.clone())
+                for q, bq in enumerate([rhs[seed]] + rhs_more[seed]):
+                    x.zero_()
+                    st = mx.gmres(ctx, A, P, bq, x, restart=w.restart, rtol=w.rtol,
+                                  max_iters=args.max_iters, flexible=mixed, spmv_c64=mixed, weight=D,
+                                  graph=args.graph)
+                    if q == 0:
+                        st0 = st
+                        if record and mixed and "x_mixed" not in refs:
+                            refs["x_mixed"] = (kind, e, seed, x.clone())
+                        if record and args.workload == "small":
+                            refs.setdefault("x_small", []).append(x.clone())
+                    elif not st["converged"]:
+                        st0 = st
+                st = st0
                 t3 = time.perf_counter()
                 r = {"kind": kind, "xi": 0.0 if xi0 else xi, "xi_prec": xi,
                      "iters": st["iters"], "converged": st["converged"],
@@ -549,8 +569,10 @@ def main():
                           "apply_bytes": inf["apply_bytes"], "factor_bytes": inf["factor_bytes"],
                           "pack_bytes": inf["pack_bytes"], "env_bytes": inf["env_entries"] *
                           (16 if args.precision == "c128" else 8)})
-                if record:
+                if timed:
                     r["sweep_launches"], r["fwd_ms"], r["bwd_ms"] = P.sweep_timing(False)
+                else:
+                    r["sweep_launches"], r["fwd_ms"], r["bwd_ms"] = 0, 0.0, 0.0
                 rec.append(r)
                 del P, A
         return t_topo, rec
@@ -564,7 +586,7 @@ def main():
         recs.append(step(True))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    n_solves = args.steps * len(inst)
+    n_solves = args.steps * len(inst) * args.rhs
     all_r = [r for _, rr in recs for r in rr]
     converged = all(r["converged"] for r in all_r)
     launches = sum(r["sweep_launches"] for r in all_r)

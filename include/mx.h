@@ -310,6 +310,12 @@ typedef struct {
   int fixed_iters;  /* > 0: run exactly this many iterations, ignoring rtol                   */
   int spmv_c64;     /* 1: Arnoldi products with the complex64 copy of A (FP64 accumulate)     */
   double rtol;      /* stop when ||b - A x|| <= rtol ||b - A x0||                             */
+  int graph;        /* 1: each Arnoldi step (preconditioner application, products with A, the */
+                    /* Gram-Schmidt passes, the Givens update, the status copy) is captured    */
+                    /* once into a HIP graph and replayed, in later cycles and in later solves */
+                    /* on the same context with the same matrix, preconditioner and restart;   */
+                    /* results are bitwise those of the launched steps.  Ignored while the     */
+                    /* preconditioner's sweeps are timed or its applications are batched.      */
 } mx_gmres_opts;
 
 typedef struct {

@@ -20,6 +20,10 @@ void set_error(int code, const std::string &msg) {
   g_last_error = msg;
 }
 [[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+uint64_t next_object_id() {
+  static std::atomic<uint64_t> counter{1};
+  return counter.fetch_add(1);
+}
 }  // namespace mx
 
 using mx::Error;

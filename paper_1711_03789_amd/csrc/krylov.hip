@@ -565,6 +565,23 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
   GmresStatus *hst = (GmresStatus *)ctx->pinned;
   const int64_t ldv = (int64_t)(vb / 16);
   const int *pctrl = P ? P->d_ctrl.as<int>() : nullptr;
+  // graph replay of the Arnoldi steps: not while the preconditioner's applications are routed
+  // elsewhere or its sweeps are timed on the host side
+  // (graph instantiation may allocate, so the no-allocation entry point never captures)
+  const bool use_graph = o->graph != 0 && !noalloc && !(P && (P->apply_hook || P->timing));
+  if (use_graph) {
+    GraphCache &gc = ctx->graphs;
+    const uint64_t pid = P ? P->id : 0, did = D ? D->id : 0;
+    const void *pc = P ? (const void *)P->coarse : nullptr;  // a coarse level added later
+    if (gc.a_id != A->id || gc.p_id != pid || gc.d_id != did || gc.ws != (const void *)ws ||
+        gc.coarse != pc || gc.n != n || gc.m != m || gc.flex != flex || gc.c64 != c64 ||
+        (int)gc.steps.size() != m) {
+      gc.clear();
+      gc.a_id = A->id, gc.p_id = pid, gc.d_id = did, gc.ws = ws, gc.coarse = pc, gc.n = n, gc.m = m;
+      gc.flex = flex, gc.c64 = c64;
+      gc.steps.assign(m, nullptr);
+    }
+  }
   const cx<double> *b = (const cx<double> *)b_dev;
   cx<double> *x = (cx<double> *)x_dev;
 
@@ -648,7 +665,7 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
       k_scale<<<nblk(n), 256, 0, st>>>(n, r, nrm, V);
       k_init_g<<<1, 64, 0, st>>>(m, nrm, g, dst);
       int jend = 0;
-      auto arnoldi_step = [&](int j) {
+      auto step_body = [&](int j) {
         cx<double> *z = flex ? Z + (int64_t)j * ldv : tmp;
         apply_prec(V + (int64_t)j * ldv, z);
         spmv_run(A, z, w, c64, st);
@@ -664,6 +681,39 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
         k_scale<<<nblk(n), 256, 0, st>>>(n, w, nrm, V + (int64_t)(j + 1) * ldv);
         MX_HIP(hipGetLastError());
         MX_HIP(hipMemcpyAsync(hst + (j & 1), dst, sizeof(GmresStatus), hipMemcpyDeviceToHost, st));
+      };
+      // With graphs, step j is captured the first time it runs for this key and replayed after.
+      auto arnoldi_step = [&](int j) {
+        if (use_graph) {
+          hipGraphExec_t &ex = ctx->graphs.steps[j];
+          if (!ex) {  // captured on the context's own stream, launched on st
+            if (!ctx->capture) MX_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+            const hipStream_t run_st = st;
+            st = ctx->capture;
+            hipGraph_t gr = nullptr;
+            MX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+              step_body(j);
+            } catch (...) {
+              (void)hipStreamEndCapture(st, &gr);
+              if (gr) (void)hipGraphDestroy(gr);
+              st = run_st;
+              throw;
+            }
+            const hipError_t ec = hipStreamEndCapture(st, &gr);
+            st = run_st;
+            if (ec != hipSuccess) fail(MX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+            const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (e != hipSuccess) {
+              ex = nullptr;
+              fail(MX_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(e));
+            }
+          }
+          MX_HIP(hipGraphLaunch(ex, st));
+        } else {
+          step_body(j);
+        }
         MX_HIP(hipEventRecord(ev.e[j & 1], st));
       };
       const int total0 = total;

@@ -111,11 +111,39 @@ struct Workspace {  // grow-only scratch owned by a context
 
 }  // namespace mx
 
+namespace mx {
+// process-wide counter: every matrix and preconditioner gets a distinct id at creation, so a
+// cached graph keyed by ids never matches an object created later at the same address
+uint64_t next_object_id();
+
+// Arnoldi steps captured as HIP graphs (one per position j in the cycle), valid for one key
+struct GraphCache {
+  uint64_t a_id = 0, p_id = 0, d_id = 0;
+  const void *ws = nullptr, *coarse = nullptr;
+  int64_t n = 0;
+  int m = 0;
+  bool flex = false, c64 = false;
+  std::vector<hipGraphExec_t> steps;
+  void clear() {
+    for (auto &e : steps)
+      if (e) (void)hipGraphExecDestroy(e);
+    steps.clear();
+  }
+  ~GraphCache() { clear(); }
+};
+}  // namespace mx
+
 struct mx_ctx {
   int device = 0;
   int cus = 256;
   mx::Workspace krylov;
   double *pinned = nullptr;  // small host-visible status area
+  mx::GraphCache graphs;
+  hipStream_t capture = nullptr;  // stream the graphs are captured on (the null stream cannot be)
+  ~mx_ctx() {
+    graphs.clear();
+    if (capture) (void)hipStreamDestroy(capture);
+  }
 };
 
 struct mx_mesh {
@@ -127,6 +155,7 @@ struct mx_partition {
 };
 
 struct mx_matrix {
+  uint64_t id = mx::next_object_id();
   mx::HostCSR h;
   double k = 0, xi = 0;
   int bc = MX_BC_IMPEDANCE;
@@ -159,6 +188,7 @@ void coarse_free(CoarseLevel *c);
 }  // namespace mx
 
 struct mx_precond {
+  uint64_t id = mx::next_object_id();
   int kind = MX_ORAS, prec = MX_C128, nsub = 0, device = 0, sub_begin = 0;
   double k = 0, xi_prec = 0;       // wavenumber and absorption the local problems were built with
   int bc = MX_BC_IMPEDANCE;

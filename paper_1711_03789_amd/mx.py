@@ -72,7 +72,8 @@ class PrecondInfo(C.Structure):
 
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("flexible", C.c_int),
-                ("fixed_iters", C.c_int), ("spmv_c64", C.c_int), ("rtol", C.c_double)]
+                ("fixed_iters", C.c_int), ("spmv_c64", C.c_int), ("rtol", C.c_double),
+                ("graph", C.c_int)]
 
 
 class GmresStats(C.Structure):
@@ -506,10 +507,11 @@ def tune_factor(ctx, A, mesh, part, kind="oras", xi_prec=None, precision="c128",
 
 
 def gmres(ctx, A, Pc, b, x, restart=50, rtol=1e-6, max_iters=1000, flexible=False,
-          fixed_iters=0, spmv_c64=False, history=False, stream=None, noalloc=False, weight=None):
+          fixed_iters=0, spmv_c64=False, history=False, stream=None, noalloc=False, weight=None,
+          graph=False):
     """noalloc=True calls mx_gmres_noalloc (fixed per-GPU workspace, no device allocation);
     weight=D (a Matrix.weight) calls mx_gmres_weighted (residual minimised in the D-norm)."""
-    o = GmresOpts(restart, max_iters, int(flexible), fixed_iters, int(spmv_c64), rtol)
+    o = GmresOpts(restart, max_iters, int(flexible), fixed_iters, int(spmv_c64), rtol, int(graph))
     st = GmresStats()
     hist = np.zeros(max(max_iters, fixed_iters) + 2, np.float64) if history else None
     if weight is not None:
