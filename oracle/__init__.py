@@ -12,6 +12,8 @@ with absorption", Math. Comp. 2019 / arXiv:1711.03789):
 * mesh.py      structured box mesh, Kuhn 6-tetrahedra split, edge numbering (Sec. 2.2)
 * fem.py       Whitney element matrices, Galerkin matrix A_xi and load f (Sec. 2.2,
                eq:Helmholtzvf_intro, impedance condition eq:imp)
+* order2.py    second-order Nedelec elements (first family) in a hierarchical basis: exact element
+               integrals, assembly, order-2 local DOF sets, owners and local problems
 * dd.py        non-overlapping boxes, overlap by tetrahedron layers (Sec. 6.1), local DOF
                sets and restriction (eq:restriction1), minors (eq:minor), Boolean partition
                of unity (eq:algebPartUnity), local impedance problems (ImpRAS, Sec. 6.3),
