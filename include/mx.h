@@ -100,6 +100,37 @@ int mx_matrix_assemble(mx_ctx *ctx, const mx_mesh *m, double k, double xi, int b
  * boundary term; PEC: identity rows and columns on boundary edges).  For mx_gmres_weighted.
  * ctx may be NULL (host-only until mx_matrix_upload).  Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE. */
 int mx_weight_assemble(mx_ctx *ctx, const mx_mesh *m, double k, int bc, mx_matrix **out);
+/* The same operator on the Nedelec space of order `order` (Sec. 2.2: order m; the paper's
+ * second-order runs are Tables tab:theoryDeltamin and tab:6bis).  order 1 is mx_matrix_assemble.
+ * order 2: the hierarchical basis of the first-family space, 20 functions per tetrahedron, with
+ * l the barycentric coordinates and vertices taken in ascending global id: per edge i -> j the
+ * Whitney function l_i grad l_j - l_j grad l_i and grad(l_i l_j); per face i < j < k the two
+ * functions l_k w_ij and l_j w_ik.  DOF numbering: the E Whitney functions (the edge numbering,
+ * so the lowest-order space is the leading block), then the E edge gradients, then two per face
+ * (faces sorted by their ascending vertex triples; mx_mesh_order2_export).  Element integrals
+ * are exact (polynomial moments of barycentric coordinates).  PEC: identity rows and columns on
+ * every DOF of a boundary edge or face.  The matrix keeps its order: preconditioners built from
+ * it use the order-2 local spaces.  ctx may be NULL.  Errors: MX_EINVAL (order not 1 or 2, more
+ * than 2^31-1 DOFs), MX_ENOMEM, MX_EDEVICE. */
+int mx_matrix_assemble_order(mx_ctx *ctx, const mx_mesh *m, int order, double k, double xi, int bc,
+                             mx_matrix **out);
+/* Order-2 sizes: faces F (interior and boundary) and DOFs N = 2E + 2F.  The order-2 topology is
+ * built on the mesh's first order-2 call (thread safe) and kept with the mesh. */
+int mx_mesh_order2_sizes(const mx_mesh *m, int64_t *n_face, int64_t *n_dof);
+/* face_vert[3F] (ascending triples, sorted), tet_face[4T] (face ids of the local faces (1,2,3),
+ * (0,2,3), (0,1,3), (0,1,2) of each tetrahedron), dof_boundary[N] (1: the DOF's edge or face
+ * lies on the box boundary).  Any pointer may be NULL. */
+int mx_mesh_order2_export(const mx_mesh *m, int32_t *face_vert, int32_t *tet_face,
+                          uint8_t *dof_boundary);
+/* Order-2 local DOF sets (eq:restriction1 for the order-2 space) and the Boolean owner of every
+ * DOF (eq:algebPartUnity).  MX_AS / MX_RAS: the Whitney and gradient DOFs of the lowest-order
+ * AS set's edges and the two DOFs of every face whose tetrahedra all lie in the subdomain;
+ * MX_ORAS: every DOF of the subdomain's tetrahedra; sorted ascending.  owner = least
+ * non-overlapping part holding a tetrahedron of the DOF's edge or face.  offsets[n_sub+1]
+ * (required), loc2glob[offsets[n_sub]], owner[N] (either may be NULL; call with loc2glob NULL
+ * for the sizes).  Errors: MX_EINVAL. */
+int mx_partition_order2_export(const mx_mesh *m, const mx_partition *p, int kind, int64_t *offsets,
+                               int32_t *loc2glob, int32_t *owner);
 /* Device copy of a host-only matrix (assembled with ctx = NULL).  The copies run on a private
  * stream that does not wait for other streams, and the call returns when they are done, so
  * another host thread may upload the next matrix while the device works.  Errors: MX_EINVAL
@@ -164,7 +195,8 @@ enum { MX_FACTOR_AUTO = 0, MX_FACTOR_ONE_STREAM = 1, MX_FACTOR_LOOKAHEAD = 2 };
  * col[nnz], val[2*nnz], and its reverse Cuthill-McKee order perm[n] (new -> old; key (degree,
  * index), George-Liu pseudo-peripheral start per component, neighbours by increasing key) with
  * the envelope start first[n] of each permuted row.  Call once with rowptr == NULL to get *n and
- * *nnz, then with buffers of those sizes (any array may be NULL).  Errors: MX_EINVAL. */
+ * *nnz, then with buffers of those sizes (any array may be NULL).  An order-2 matrix gives the
+ * order-2 local problem on the sets of mx_partition_order2_export.  Errors: MX_EINVAL. */
 int mx_local_problem(const mx_mesh *m, const mx_matrix *A, const mx_partition *p,
                      const mx_precond_opts *opts, int l, int64_t *n, int64_t *nnz, int64_t *rowptr,
                      int32_t *col, double *val, int32_t *perm, int32_t *first);

@@ -356,3 +356,17 @@ def schwarz(p2, A, kind, k, xi, bc=fem.BC_IMPEDANCE):
     """One-level AS / RAS / ORAS of the order-2 space (dd.Schwarz with these local problems)."""
     loc = [local_matrix(p2, A, kind, k, xi, l, bc) for l in range(p2.N)]
     return dd.Schwarz(p2, A, kind, k, xi, bc, local=loc)
+
+
+def coarse_restriction(space, coarse_mesh, bc=fem.BC_IMPEDANCE):
+    """R^0 of eq:restriction for the order-2 fine space, with the coarse space of lowest-order
+    Whitney functions on the nested coarse mesh (reading: the paper does not say which coarse
+    element order goes with order-2 fine elements; the lowest order keeps the coarse problem the
+    one of the lowest-order runs).  A coarse Whitney function is, on every fine tetrahedron, a
+    field a + b x x, i.e. a member of the fine lowest-order space, which in the hierarchical basis
+    is spanned by the Whitney functions alone: its order-2 coefficients are its lowest-order
+    ones (oracle/coarse.py) followed by zeros for the gradient and face functions."""
+    from . import coarse as _coarse
+    R1 = _coarse.restriction(space.mesh, coarse_mesh, bc)
+    zero = sp.csr_matrix((R1.shape[0], space.n - space.E))
+    return sp.hstack([R1, zero]).tocsr()

@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
-SOURCES = ["host_mesh.cpp", "host_partition.cpp", "host_coarse.cpp", "abi.cpp", "serve.cpp", "devcache.cpp", "precond.hip",
+SOURCES = ["host_mesh.cpp", "host_partition.cpp", "host_coarse.cpp", "host_order2.cpp", "abi.cpp", "serve.cpp", "devcache.cpp", "precond.hip",
            "krylov.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -138,6 +138,66 @@ int mx_matrix_assemble(mx_ctx *ctx, const mx_mesh *m, double k, double xi, int b
   });
 }
 
+int mx_matrix_assemble_order(mx_ctx *ctx, const mx_mesh *m, int order, double k, double xi, int bc,
+                             mx_matrix **out) {
+  MX_GUARD({
+    MX_REQUIRE(m && out, "NULL argument");
+    MX_REQUIRE(order == 1 || order == 2, "order must be 1 or 2");
+    MX_REQUIRE(bc == MX_BC_PEC || bc == MX_BC_IMPEDANCE, "unknown boundary condition");
+    MX_REQUIRE(std::isfinite(k) && std::isfinite(xi) && k > 0, "need finite k > 0 and finite xi");
+    auto A = std::make_unique<mx_matrix>();
+    A->k = k, A->xi = xi, A->bc = bc, A->order = order;
+    if (order == 2) mx::assemble_order2(m->m, m->order2(), k, xi, bc, A->h);
+    else mx::assemble_global(m->m, k, xi, bc, A->h);
+    if (ctx) {
+      bind_device(ctx->device);
+      A->device = ctx->device;
+      mx::matrix_upload(A.get());
+    }
+    *out = A.release();
+  });
+}
+
+int mx_mesh_order2_sizes(const mx_mesh *m, int64_t *n_face, int64_t *n_dof) {
+  MX_GUARD({
+    MX_REQUIRE(m, "mesh is NULL");
+    const mx::Order2 &o = m->order2();
+    if (n_face) *n_face = o.F;
+    if (n_dof) *n_dof = o.N;
+  });
+}
+
+int mx_mesh_order2_export(const mx_mesh *m, int32_t *face_vert, int32_t *tet_face,
+                          uint8_t *dof_boundary) {
+  MX_GUARD({
+    MX_REQUIRE(m, "mesh is NULL");
+    const mx::Order2 &o = m->order2();
+    if (face_vert) std::memcpy(face_vert, o.face_vert.data(), o.face_vert.size() * 4);
+    if (tet_face) std::memcpy(tet_face, o.tet_face.data(), o.tet_face.size() * 4);
+    if (dof_boundary) std::memcpy(dof_boundary, o.dof_boundary.data(), o.dof_boundary.size());
+  });
+}
+
+int mx_partition_order2_export(const mx_mesh *m, const mx_partition *p, int kind, int64_t *offsets,
+                               int32_t *loc2glob, int32_t *owner) {
+  MX_GUARD({
+    MX_REQUIRE(m && p && offsets, "NULL argument");
+    MX_REQUIRE(kind >= MX_AS && kind <= MX_ORAS, "unknown kind");
+    MX_REQUIRE((int64_t)p->p.part0.size() == m->m.nt, "partition and mesh disagree");
+    std::vector<std::vector<int32_t>> sets;
+    std::vector<int32_t> own;
+    mx::order2_sets(m->m, m->order2(), p->p, kind, sets, own);
+    int64_t o = 0;
+    for (int l = 0; l < p->p.nsub; ++l) {
+      offsets[l] = o;
+      if (loc2glob) std::memcpy(loc2glob + o, sets[l].data(), sets[l].size() * 4);
+      o += (int64_t)sets[l].size();
+    }
+    offsets[p->p.nsub] = o;
+    if (owner) std::memcpy(owner, own.data(), own.size() * 4);
+  });
+}
+
 int mx_weight_assemble(mx_ctx *ctx, const mx_mesh *m, double k, int bc, mx_matrix **out) {
   MX_GUARD({
     MX_REQUIRE(m && out, "NULL argument");
@@ -253,18 +313,30 @@ int mx_local_problem(const mx_mesh *m, const mx_matrix *A, const mx_partition *p
     MX_REQUIRE(m && A && p && opts && n && nnz, "NULL argument");
     MX_REQUIRE(l >= 0 && l < p->p.nsub, "subdomain out of range");
     MX_REQUIRE(opts->kind >= MX_AS && opts->kind <= MX_ORAS, "unknown kind");
-    MX_REQUIRE(A->h.n == m->m.ne, "matrix and mesh disagree");
+    MX_REQUIRE(A->h.n == m->ndof(A->order), "matrix and mesh disagree");
+    MX_REQUIRE((int64_t)p->p.part0.size() == m->m.nt, "partition and mesh disagree");
     const auto &M = m->m;
-    const auto &sets = p->p.set(opts->kind);
     mx::LocalCSR a;
-    std::vector<int32_t> g2l(M.ne, -1);
-    if (opts->kind == MX_ORAS) {
+    std::vector<int32_t> g2l(A->h.n, -1);
+    if (A->order == 2) {
+      const mx::Order2 &o2 = m->order2();
+      std::vector<std::vector<int32_t>> sets;
+      std::vector<int32_t> own;
+      mx::order2_sets(M, o2, p->p, opts->kind, sets, own);
+      if (opts->kind == MX_ORAS) {
+        std::vector<int32_t> tstamp(M.nt, -1);
+        mx::local_impedance2(M, o2, A->k, opts->xi_prec, A->bc, p->p.tets[l], sets[l], a, g2l, tstamp);
+      } else {
+        mx::local_minor(o2.dof_boundary.data(), A->h, A->bc, sets[l], a, g2l);
+      }
+    } else if (opts->kind == MX_ORAS) {
+      const auto &sets = p->p.set(opts->kind);
       mx::KuhnElements ke;
       mx::kuhn_elements(M.lx / M.nx, M.ly / M.ny, M.lz / M.nz, ke);
       std::vector<int32_t> tstamp(M.nt, -1);
       mx::local_impedance(M, ke, A->k, opts->xi_prec, A->bc, p->p.tets[l], sets[l], a, g2l, tstamp);
     } else {
-      mx::local_minor(M, A->h, A->bc, sets[l], a, g2l);
+      mx::local_minor(M.edge_on_boundary.data(), A->h, A->bc, p->p.set(opts->kind)[l], a, g2l);
     }
     *n = a.n;
     *nnz = (int64_t)a.col.size();
@@ -455,13 +527,17 @@ int mx_coarse_operators(const mx_mesh *m, const mx_matrix *A, int ratio, int64_t
                         double *r_val, int64_t *a_rowptr, int32_t *a_col, double *a_val) {
   MX_GUARD({
     MX_REQUIRE(m && A && n_coarse && nnz_r && nnz_a, "NULL argument");
-    MX_REQUIRE(A->h.n == m->m.ne, "matrix and mesh sizes differ");
+    MX_REQUIRE(A->h.n == m->ndof(A->order), "matrix and mesh sizes differ");
     MX_REQUIRE(ratio >= 1 && m->m.nx % ratio == 0 && m->m.ny % ratio == 0 && m->m.nz % ratio == 0,
                "the coarse ratio must divide the cube count of every axis");
     mx::Mesh cm;
     mx::build_mesh(cm, m->m.nx / ratio, m->m.ny / ratio, m->m.nz / ratio, m->m.lx, m->m.ly, m->m.lz);
     mx::HostCSR R0, R0T, A0;
     mx::build_restriction(m->m, cm, ratio, A->bc, R0, R0T);
+    if (A->order == 2) {  // coarse Whitney functions have Whitney coefficients only
+      R0T.rowptr.resize(A->h.n + 1, R0T.rowptr.back());
+      R0T.n = A->h.n;
+    }
     mx::galerkin_coarse(A->h, R0, R0T, cm, A->bc, A0);
     const bool sizes_only = !r_rowptr && !r_col && !r_val && !a_rowptr && !a_col && !a_val;
     if (!sizes_only) {

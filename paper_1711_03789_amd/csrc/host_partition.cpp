@@ -153,7 +153,7 @@ static void push_row(LocalCSR &out, const std::vector<LEntry> &ent) {
   out.rowptr.push_back((int64_t)out.col.size());
 }
 
-void local_minor(const Mesh &m, const HostCSR &A, int bc, const std::vector<int32_t> &set,
+void local_minor(const uint8_t *boundary, const HostCSR &A, int bc, const std::vector<int32_t> &set,
                  LocalCSR &out, std::vector<int32_t> &g2l) {
   const int64_t n = (int64_t)set.size();
   for (int64_t i = 0; i < n; ++i) g2l[set[i]] = (int32_t)i;
@@ -165,12 +165,12 @@ void local_minor(const Mesh &m, const HostCSR &A, int bc, const std::vector<int3
   for (int64_t i = 0; i < n; ++i) {
     int32_t g = set[i];
     ent.clear();
-    bool row_pec = bc == MX_BC_PEC && m.edge_on_boundary[g];
+    bool row_pec = bc == MX_BC_PEC && boundary[g];
     for (int64_t q = A.rowptr[g]; q < A.rowptr[g + 1]; ++q) {
       int32_t c = A.col[q];
       int32_t lc = g2l[c];
       if (lc < 0) continue;
-      if (bc == MX_BC_PEC && (row_pec || m.edge_on_boundary[c]) && c != g) continue;
+      if (bc == MX_BC_PEC && (row_pec || boundary[c]) && c != g) continue;
       ent.push_back({lc, A.val[2 * q], A.val[2 * q + 1]});
     }
     push_row(out, ent);

@@ -390,7 +390,8 @@ void coarse_plan(mx_precond *P, const mx_matrix *A, const mx_mesh *mh, int ratio
   if (combine < MX_COARSE_ADDITIVE || combine > MX_COARSE_DEFLATION) fail(MX_EINVAL, "unknown coarse combination");
   if (ratio < 1 || m.nx % ratio || m.ny % ratio || m.nz % ratio)
     fail(MX_EINVAL, "the coarse ratio must divide the cube count of every axis");
-  if (A->h.n != P->E || m.ne != P->E) fail(MX_EINVAL, "matrix, mesh and preconditioner sizes differ");
+  if (A->h.n != P->E || A->order != P->order || mh->ndof(P->order) != P->E)
+    fail(MX_EINVAL, "matrix, mesh and preconditioner sizes differ");
   if (A->weight || A->k != P->k || A->xi != P->xi_prec || A->bc != P->bc)
     fail(MX_EINVAL, "the matrix is not the one the preconditioner was built for (k, xi_prec, bc)");
   auto C = std::make_unique<CoarseLevel>();
@@ -399,6 +400,13 @@ void coarse_plan(mx_precond *P, const mx_matrix *A, const mx_mesh *mh, int ratio
   C->A = A;
   build_mesh(C->mesh.m, m.nx / ratio, m.ny / ratio, m.nz / ratio, m.lx, m.ly, m.lz);
   build_restriction(m, C->mesh.m, ratio, A->bc, C->R0.h, C->R0T.h);
+  if (A->order == 2) {
+    // the coarse Whitney functions are piecewise lowest-order fields on the fine mesh, so in the
+    // hierarchical order-2 basis they have Whitney coefficients only: R^0 keeps its columns and
+    // its transpose gains empty rows for the gradient and face functions
+    C->R0T.h.rowptr.resize(P->E + 1, C->R0T.h.rowptr.back());
+    C->R0T.h.n = P->E;
+  }
   galerkin_coarse(A->h, C->R0.h, C->R0T.h, C->mesh.m, A->bc, C->A0.h);
   for (mx_matrix *X : {&C->R0, &C->R0T, &C->A0}) X->k = A->k, X->xi = A->xi, X->bc = A->bc;
   build_partition(C->mesh.m, 1, 1, 1, nullptr, nullptr, nullptr, 0, C->part.p);
@@ -445,7 +453,7 @@ void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh 
     const CoarseLevel &C = *P->coarse;
     if (C.ready) fail(MX_EINVAL, "preconditioner already has a coarse level");
     if (C.A != A || C.ratio != ratio || C.combine != combine || C.mesh.m.ne == 0 ||
-        mh->m.ne != P->E)
+        mh->ndof(P->order) != P->E)
       fail(MX_EINVAL, "arguments differ from those the coarse level was planned with");
   } else {
     coarse_plan(P, A, mh, ratio, combine);

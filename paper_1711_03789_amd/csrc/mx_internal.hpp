@@ -203,8 +203,9 @@ struct LocalCSR {  // a local matrix in local (sorted global id) numbering
   std::vector<int32_t> col;
   std::vector<double> val;  // interleaved complex
 };
-// AS/RAS minor of the global matrix (PEC-constrained rows/cols reduced to their diagonal).
-void local_minor(const Mesh &m, const HostCSR &A, int bc, const std::vector<int32_t> &set,
+// AS/RAS minor of the global matrix (PEC-constrained rows/cols reduced to their diagonal);
+// boundary[d] flags the degrees of freedom on the box boundary.
+void local_minor(const uint8_t *boundary, const HostCSR &A, int bc, const std::vector<int32_t> &set,
                  LocalCSR &out, std::vector<int32_t> &g2l_scratch);
 // ORAS local impedance problem on the tetrahedra `tets` (local DOFs `set`).
 // Scratch: g2l_scratch[E] all -1 on entry and exit; tet_pos[T] any contents (caller-owned, -1
@@ -212,6 +213,34 @@ void local_minor(const Mesh &m, const HostCSR &A, int bc, const std::vector<int3
 void local_impedance(const Mesh &m, const KuhnElements &ke, double k, double xi, int bc,
                      const std::vector<int32_t> &tets, const std::vector<int32_t> &set,
                      LocalCSR &out, std::vector<int32_t> &g2l_scratch, std::vector<int32_t> &tet_pos);
+// ---- second-order Nedelec elements -----------------------------------------------------------------
+// DOFs: E Whitney functions (edge ids), E edge gradients, then two per face (faces sorted by vertex
+// triple).  Element integrals per Kuhn type p of a cube: K, M (20 x 20, local order 6 Whitney,
+// 6 gradients, 2 per local face (1,2,3) (0,2,3) (0,1,3) (0,1,2)) and the tangential face masses B.
+struct Order2 {
+  int64_t E = 0, F = 0, N = 0;
+  std::vector<int32_t> tet_face;      // [nt][4] face ids by local face
+  std::vector<int32_t> face_vert;     // [F][3] ascending
+  std::vector<int32_t> face_tet;      // [F][2] the tetrahedra on each side (-1: box boundary)
+  std::vector<int8_t> face_lf;        // [F][2] local face index in those tetrahedra
+  std::vector<uint8_t> dof_boundary;  // [N] tangential trace lives on the box boundary
+  double K[6][20][20], M[6][20][20], B[6][4][20][20];
+};
+void build_order2(const Mesh &m, Order2 &o);
+int32_t order2_dof(const Mesh &m, const Order2 &o, int64_t t, int a);
+int32_t order2_face_of(const Order2 &o, const int32_t v[3]);  // -1 if not a face
+// A = K - (k^2 + i xi) M - i sign(xi) k M_b of the order-2 space (PEC: identity rows and columns)
+void assemble_order2(const Mesh &m, const Order2 &o, double k, double xi, int bc, HostCSR &A);
+// order-2 local DOF sets (kind AS/RAS: Whitney and gradient functions of the lowest-order AS set
+// and the faces whose tetrahedra are all in the subdomain; ORAS: every DOF of its tetrahedra),
+// and the Boolean owner (least part0 of a tetrahedron holding the DOF)
+void order2_sets(const Mesh &m, const Order2 &o, const Partition &p, int kind,
+                 std::vector<std::vector<int32_t>> &sets, std::vector<int32_t> &owner);
+// ORAS local impedance problem of the order-2 space; scratch as for local_impedance (g2l sized N)
+void local_impedance2(const Mesh &m, const Order2 &o, double k, double xi, int bc,
+                      const std::vector<int32_t> &tets, const std::vector<int32_t> &set,
+                      LocalCSR &out, std::vector<int32_t> &g2l_scratch, std::vector<int32_t> &tet_pos);
+
 // Reverse Cuthill-McKee of the pattern of `a` (perm[new] = old).
 void rcm_order(const LocalCSR &a, std::vector<int32_t> &perm);
 

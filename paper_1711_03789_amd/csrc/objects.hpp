@@ -148,6 +148,18 @@ struct mx_ctx {
 
 struct mx_mesh {
   mx::Mesh m;
+  // second-order topology and element integrals, built on first use
+  mutable std::once_flag o2_once;
+  mutable std::unique_ptr<mx::Order2> o2;
+  const mx::Order2 &order2() const {
+    std::call_once(o2_once, [this] {
+      auto p = std::make_unique<mx::Order2>();
+      mx::build_order2(m, *p);
+      o2 = std::move(p);
+    });
+    return *o2;
+  }
+  int64_t ndof(int order) const { return order == 2 ? order2().N : m.ne; }
 };
 
 struct mx_partition {
@@ -160,6 +172,7 @@ struct mx_matrix {
   double k = 0, xi = 0;
   int bc = MX_BC_IMPEDANCE;
   bool weight = false;  // the Gram matrix D_k of the weighted inner product, not a Galerkin matrix
+  int order = 1;        // Nedelec order of the space the matrix is assembled on (1 or 2)
   int device = 0;
   mx::DevBuf rowptr, col, val, val32;
 };
@@ -192,6 +205,7 @@ struct mx_precond {
   int kind = MX_ORAS, prec = MX_C128, nsub = 0, device = 0, sub_begin = 0;
   double k = 0, xi_prec = 0;       // wavenumber and absorption the local problems were built with
   int bc = MX_BC_IMPEDANCE;
+  int order = 1;                    // Nedelec order of the space
   bool share = false;               // built for a resident share of the subdomains only
   // when set, one-level applications go to this function instead of being launched here (a
   // server batching the applications of several requests)

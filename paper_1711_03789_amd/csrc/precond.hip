@@ -1353,8 +1353,11 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
                   const mx_precond_opts *opts, mx_precond *P, PrecondPlan &plan) {
   const Mesh &m = mh->m;
   const Partition &part = ph->p;
-  if (A->h.n != m.ne) fail(MX_EINVAL, "matrix and mesh disagree");
   if (opts->kind < MX_AS || opts->kind > MX_ORAS) fail(MX_EINVAL, "unknown preconditioner kind");
+  if (A->order != 1 && A->order != 2) fail(MX_EINVAL, "unknown element order");
+  const Order2 *o2 = A->order == 2 ? &mh->order2() : nullptr;
+  const int64_t ndof = o2 ? o2->N : m.ne;
+  if (A->h.n != ndof) fail(MX_EINVAL, "matrix and mesh disagree");
   if (opts->precision != MX_C128 && opts->precision != MX_C64) fail(MX_EINVAL, "unknown precision");
   const double t0 = now_s();
   P->kind = opts->kind;
@@ -1362,7 +1365,8 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   P->k = A->k;
   P->xi_prec = opts->kind == MX_ORAS ? opts->xi_prec : A->xi;
   P->bc = A->bc;
-  P->E = m.ne;
+  P->E = ndof;
+  P->order = A->order;
   P->device = ctx ? ctx->device : -1;
   int s0 = opts->sub_begin, s1 = opts->sub_end;
   if (s0 == 0 && s1 == 0) s1 = part.nsub;
@@ -1381,8 +1385,14 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   P->share = s0 != 0 || s1 != part.nsub;
   const int N = P->nsub;
   // subdomain j of this preconditioner is subdomain s0 + j of the partition
-  std::vector<std::vector<int32_t>> sets_share(part.set(opts->kind).begin() + s0,
-                                               part.set(opts->kind).begin() + s1);
+  // local DOF sets and owners: the partition's edge sets, or those of the order-2 space
+  std::vector<std::vector<int32_t>> sets2;
+  std::vector<int32_t> owner2;
+  if (o2) order2_sets(m, *o2, part, opts->kind, sets2, owner2);
+  const auto &all_sets = o2 ? sets2 : part.set(opts->kind);
+  const std::vector<int32_t> &owner = o2 ? owner2 : part.owner;
+  const uint8_t *boundary = o2 ? o2->dof_boundary.data() : m.edge_on_boundary.data();
+  std::vector<std::vector<int32_t>> sets_share(all_sets.begin() + s0, all_sets.begin() + s1);
   const auto &sets = sets_share;
   // local matrices and their orderings
   std::vector<LocalCSR> loc(N);
@@ -1390,13 +1400,15 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   KuhnElements ke;
   kuhn_elements(m.lx / m.nx, m.ly / m.ny, m.lz / m.nz, ke);
   parallel_items(N, [&](auto next) {
-    std::vector<int32_t> g2l(m.ne, -1), tstamp;
+    std::vector<int32_t> g2l(ndof, -1), tstamp;
     if (opts->kind == MX_ORAS) tstamp.assign(m.nt, -1);
     for (int64_t l; (l = next()) >= 0;) {
-      if (opts->kind == MX_ORAS)
+      if (opts->kind == MX_ORAS && o2)
+        local_impedance2(m, *o2, A->k, opts->xi_prec, A->bc, part.tets[s0 + l], sets[l], loc[l], g2l, tstamp);
+      else if (opts->kind == MX_ORAS)
         local_impedance(m, ke, A->k, opts->xi_prec, A->bc, part.tets[s0 + l], sets[l], loc[l], g2l, tstamp);
       else
-        local_minor(m, A->h, A->bc, sets[l], loc[l], g2l);
+        local_minor(boundary, A->h, A->bc, sets[l], loc[l], g2l);
       build_skyline(loc[l], P->sky[l]);
     }
   });
@@ -1545,11 +1557,11 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
   });
   std::vector<int64_t> &src = plan.src, &sum_ptr = plan.sum_ptr, &sum_idx = plan.sum_idx;
   if (opts->kind == MX_AS) {
-    sum_ptr.assign(m.ne + 1, 0);
+    sum_ptr.assign(ndof + 1, 0);
     for (int l = 0; l < N; ++l)
       for (int32_t g : sets[l]) sum_ptr[g + 1]++;
-    for (int64_t e = 0; e < m.ne; ++e) sum_ptr[e + 1] += sum_ptr[e];
-    sum_idx.resize(sum_ptr[m.ne]);
+    for (int64_t e = 0; e < ndof; ++e) sum_ptr[e + 1] += sum_ptr[e];
+    sum_idx.resize(sum_ptr[ndof]);
     std::vector<int64_t> fill(sum_ptr.begin(), sum_ptr.end() - 1);
     for (int l = 0; l < N; ++l) {
       const Skyline &s = P->sky[l];
@@ -1557,11 +1569,11 @@ void precond_plan(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *mh, const mx_p
         sum_idx[fill[sets[l][r]]++] = P->sub_vec_base[l] + s.iperm[r];
     }
   } else {
-    src.assign(m.ne, -1);
+    src.assign(ndof, -1);
     std::atomic<int> bad(0);
-    parallel_for(m.ne, [&](int64_t a0, int64_t a1) {
+    parallel_for(ndof, [&](int64_t a0, int64_t a1) {
       for (int64_t e = a0; e < a1; ++e) {
-        int o = part.owner[e] - s0;
+        int o = owner[e] - s0;
         if (o < 0 || o >= N) continue;  // owned outside the resident share
         const auto &st = sets[o];
         auto it = std::lower_bound(st.begin(), st.end(), (int32_t)e);

@@ -34,7 +34,8 @@ SYMBOLS = [
     "mx_server_destroy", "mx_matrix_upload", "mx_precond_plan", "mx_precond_materialize",
     "mx_selftest_host", "mx_gmres_noalloc", "mx_precond_add_coarse", "mx_precond_coarse_export",
     "mx_coarse_operators", "mx_weight_assemble", "mx_gmres_weighted", "mx_precond_plan_coarse",
-    "mx_precond_tune_factor", "mx_server_batch_stats",
+    "mx_precond_tune_factor", "mx_server_batch_stats", "mx_matrix_assemble_order",
+    "mx_mesh_order2_sizes", "mx_mesh_order2_export", "mx_partition_order2_export",
 ]
 
 
@@ -133,6 +134,11 @@ def load(path=LIB_PATH):
         "mx_mesh_export": (C.c_int, [P, P, P, P, P, P]),
         "mx_mesh_destroy": (None, [P]),
         "mx_matrix_assemble": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, C.POINTER(P)]),
+        "mx_matrix_assemble_order": (C.c_int, [P, P, C.c_int, C.c_double, C.c_double, C.c_int,
+                                               C.POINTER(P)]),
+        "mx_mesh_order2_sizes": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+        "mx_mesh_order2_export": (C.c_int, [P, P, P, P]),
+        "mx_partition_order2_export": (C.c_int, [P, P, C.c_int, P, P, P]),
         "mx_matrix_sizes": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
         "mx_matrix_export": (C.c_int, [P, P, P, P]),
         "mx_matrix_destroy": (None, [P]),
@@ -282,6 +288,17 @@ class Mesh:
         _check(_lib.mx_mesh_export(self.h, _ptr(tv), _ptr(ev), _ptr(te), _ptr(ts), _ptr(bf)))
         return {"tet_vert": tv, "edge_vert": ev, "tet_edge": te, "tet_edge_sign": ts, "bface_vert": bf}
 
+    def order2(self):
+        """Order-2 numbering: face vertex triples, faces of every tetrahedron, boundary DOFs."""
+        nf, nd = C.c_int64(), C.c_int64()
+        _check(_lib.mx_mesh_order2_sizes(self.h, C.byref(nf), C.byref(nd)))
+        fv = np.zeros((nf.value, 3), np.int32)
+        tf = np.zeros((self.n_tet, 4), np.int32)
+        db = np.zeros(nd.value, np.uint8)
+        _check(_lib.mx_mesh_order2_export(self.h, _ptr(fv), _ptr(tf), _ptr(db)))
+        return {"n_face": nf.value, "n_dof": nd.value, "face_vert": fv, "tet_face": tf,
+                "dof_boundary": db.astype(bool)}
+
     def rhs_gaussian(self, center, pol, sigma, bc=MX_BC_IMPEDANCE):
         f = np.zeros(self.n_edge, np.complex128)
         _check(_lib.mx_rhs_gaussian(self.h, bc, np.asarray(center, np.float64),
@@ -290,12 +307,16 @@ class Mesh:
 
 
 class Matrix:
-    def __init__(self, ctx, mesh, k, xi, bc=MX_BC_IMPEDANCE):
+    def __init__(self, ctx, mesh, k, xi, bc=MX_BC_IMPEDANCE, order=1):
         load()
         h = P()
-        _check(_lib.mx_matrix_assemble(ctx.h if ctx is not None else None, mesh.h, k, xi, bc,
-                                       C.byref(h)))
-        self.h, self.k, self.xi, self.bc = h, k, xi, bc
+        if order == 1:
+            _check(_lib.mx_matrix_assemble(ctx.h if ctx is not None else None, mesh.h, k, xi, bc,
+                                           C.byref(h)))
+        else:
+            _check(_lib.mx_matrix_assemble_order(ctx.h if ctx is not None else None, mesh.h, order,
+                                                 k, xi, bc, C.byref(h)))
+        self.h, self.k, self.xi, self.bc, self.order = h, k, xi, bc, order
         n, nnz = C.c_int64(), C.c_int64()
         _check(_lib.mx_matrix_sizes(h, C.byref(n), C.byref(nnz)))
         self.n, self.nnz = n.value, nnz.value
@@ -307,7 +328,7 @@ class Matrix:
         self = cls.__new__(cls)
         h = P()
         _check(_lib.mx_weight_assemble(ctx.h if ctx is not None else None, mesh.h, k, bc, C.byref(h)))
-        self.h, self.k, self.xi, self.bc = h, k, 0.0, bc
+        self.h, self.k, self.xi, self.bc, self.order = h, k, 0.0, bc, 1
         n, nnz = C.c_int64(), C.c_int64()
         _check(_lib.mx_matrix_sizes(h, C.byref(n), C.byref(nnz)))
         self.n, self.nnz = n.value, nnz.value
@@ -359,6 +380,20 @@ class Partition:
         _check(_lib.mx_partition_export(self.h, kind, _ptr(off), _ptr(l2g), _ptr(owner), _ptr(nt)))
         return {"offsets": off, "loc2glob": l2g, "owner": owner, "n_tet": nt,
                 "sets": [l2g[off[i]:off[i + 1]] for i in range(n.value)]}
+
+    def export_order2(self, mesh, kind):
+        """Order-2 local DOF sets and owners (mx_partition_order2_export)."""
+        kind = KINDS.get(kind, kind)
+        n, tot = C.c_int32(), C.c_int64()
+        _check(_lib.mx_partition_sizes(self.h, kind, C.byref(n), C.byref(tot)))
+        off = np.zeros(n.value + 1, np.int64)
+        _check(_lib.mx_partition_order2_export(mesh.h, self.h, kind, _ptr(off), None, None))
+        nf, nd = C.c_int64(), C.c_int64()
+        _check(_lib.mx_mesh_order2_sizes(mesh.h, C.byref(nf), C.byref(nd)))
+        l2g = np.zeros(off[-1], np.int32)
+        owner = np.zeros(nd.value, np.int32)
+        _check(_lib.mx_partition_order2_export(mesh.h, self.h, kind, _ptr(off), _ptr(l2g), _ptr(owner)))
+        return {"offsets": off, "owner": owner, "sets": [l2g[off[i]:off[i + 1]] for i in range(n.value)]}
 
 
 def selftest_host(n_items, fail_item=-1, fail_code=MX_EINVAL):

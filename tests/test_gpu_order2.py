@@ -1,0 +1,136 @@
+"""GPU parity of the second-order Nedelec path (Sec. 2.2 with order 2; the configurations of
+Tables tab:theoryDeltamin and tab:6bis) through the C ABI against the oracle (oracle/order2.py)
+on the same seeded inputs:
+* single one-level applications (AS, RAS, ORAS; impedance and PEC; complex128 to 1e-12 relative,
+  complex64 to 1e-5) and two-level ones (hybrid, deflation, additive) to 1e-10;
+* GMRES: iterations within +-1 of the oracle's, and after exactly the oracle's iteration count the
+  solution within 1e-8 relative L2, for one-level ORAS and the two order-2 settings of the paper:
+  xi_prob = xi_prec = k^2 with minimal overlap, and ImpHRAS with xi_prob = 0, xi_prec = k."""
+import sys
+
+import numpy as np
+import pytest
+
+from mx_inputs import random_rhs
+from oracle import coarse, dd, fem, gmres, order2
+from oracle.mesh import Mesh as OMesh
+
+pytestmark = pytest.mark.gpu
+
+OKIND = {"oras": dd.ORAS, "ras": dd.RAS, "as": dd.AS}
+COMB = {"additive": coarse.ADDITIVE, "hybrid": coarse.HYBRID, "deflation": coarse.DEFLATION}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, np.complex128)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    return gpu_lib.Context(0)
+
+
+class Case:
+    """The same order-2 problem in the oracle and in the library: A at xi_prob, the Schwarz
+    preconditioner built at xi_prec, optionally with a coarse level."""
+
+    def __init__(self, mx, ctx, n, parts, layers, k, xi_prob, xi_prec, kind, bc=fem.BC_IMPEDANCE,
+                 precision="c128", ratio=0, combine="hybrid"):
+        self.om = OMesh(*n)
+        self.S = order2.Space(self.om)
+        self.oA = order2.assemble(self.S, k, xi_prob, bc)
+        op = dd.Partition(self.om, *parts, layers)
+        self.p2 = order2.Partition(self.S, op)
+        Ap = self.oA if xi_prec == xi_prob else order2.assemble(self.S, k, xi_prec, bc)
+        self.oB = order2.schwarz(self.p2, Ap, OKIND[kind], k, xi_prec, bc)
+        if ratio:
+            oc = coarse.coarse_mesh(self.om, ratio)
+            self.oB = coarse.TwoLevel(self.oB, Ap, order2.coarse_restriction(self.S, oc, bc),
+                                      COMB[combine])
+        self.lm = mx.Mesh(*n)
+        self.lA = mx.Matrix(ctx, self.lm, k, xi_prob, bc, order=2)
+        self.lAp = self.lA if xi_prec == xi_prob else mx.Matrix(ctx, self.lm, k, xi_prec, bc, order=2)
+        self.lp = mx.Partition(self.lm, *parts, layers)
+        self.lP = mx.Precond(ctx, self.lAp, self.lm, self.lp, kind, xi_prec=xi_prec,
+                             precision=precision)
+        if ratio:
+            self.lP.add_coarse(ctx, self.lAp, self.lm, ratio, combine)
+        self.N = self.S.n
+        assert self.lA.n == self.N
+
+
+@pytest.mark.parametrize("kind,bc,precision", [
+    ("as", fem.BC_IMPEDANCE, "c128"), ("ras", fem.BC_IMPEDANCE, "c128"),
+    ("oras", fem.BC_IMPEDANCE, "c128"), ("oras", fem.BC_PEC, "c128"), ("ras", fem.BC_PEC, "c128"),
+    ("oras", fem.BC_IMPEDANCE, "c64")])
+def test_order2_apply(gpu_lib, ctx, kind, bc, precision):
+    say("order-2 apply", kind, bc, precision)
+    c = Case(gpu_lib, ctx, (6, 6, 6), (2, 2, 2), 1, 4.0, 16.0, 16.0, kind, bc, precision)
+    v = random_rhs(c.N, 21)
+    vd, zd = dev(v), dev(np.zeros(c.N))
+    c.lP.apply(vd, zd)
+    c.lP.check()
+    z = host(zd)
+    ref = c.oB(v)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say("  rel err", err)
+    assert err <= (1e-12 if precision == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("combine", ["additive", "hybrid", "deflation"])
+def test_order2_two_level_apply(gpu_lib, ctx, combine):
+    say("order-2 two-level apply", combine)
+    c = Case(gpu_lib, ctx, (8, 8, 8), (2, 2, 2), 1, 5.0, 0.0, 5.0, "oras", ratio=2, combine=combine)
+    v = random_rhs(c.N, 22)
+    vd, zd = dev(v), dev(np.zeros(c.N))
+    c.lP.apply(vd, zd)
+    c.lP.check()
+    z = host(zd)
+    ref = c.oB(v)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say("  rel err", err)
+    assert err <= 1e-10
+
+
+GMRES_CASES = {
+    # one-level ORAS, xi_prob = xi_prec = k
+    "oras": dict(n=(8, 8, 8), parts=(2, 2, 2), layers=1, k=5.0, xi_prob=5.0, xi_prec=5.0,
+                 kind="oras"),
+    # xi_prob = xi_prec = k^2, minimal overlap, two-level (hybrid)
+    "theory_delta_min": dict(n=(8, 8, 8), parts=(2, 2, 2), layers=1, k=4.0, xi_prob=16.0,
+                             xi_prec=16.0, kind="oras", ratio=2, combine="hybrid"),
+    # ImpHRAS: xi_prob = 0, xi_prec = k, two-level hybrid
+    "imphras_xi0": dict(n=(8, 8, 8), parts=(2, 2, 2), layers=1, k=5.0, xi_prob=0.0, xi_prec=5.0,
+                        kind="oras", ratio=2, combine="hybrid"),
+}
+
+
+@pytest.mark.parametrize("name", list(GMRES_CASES))
+def test_order2_gmres(gpu_lib, ctx, name):
+    cfg = dict(GMRES_CASES[name])
+    say("order-2 GMRES", name, cfg)
+    c = Case(gpu_lib, ctx, cfg.pop("n"), cfg.pop("parts"), cfg.pop("layers"), cfg.pop("k"),
+             cfg.pop("xi_prob"), cfg.pop("xi_prec"), cfg.pop("kind"), **cfg)
+    f = random_rhs(c.N, 23)
+    ores = gmres.gmres(c.oA, f, c.oB, restart=100, rtol=1e-6)
+    bd, xd = dev(f), dev(np.zeros(c.N))
+    st = gpu_lib.gmres(ctx, c.lA, c.lP, bd, xd, restart=100, rtol=1e-6)
+    say("  iterations gpu", st["iters"], "oracle", ores.iters)
+    assert st["converged"] and abs(st["iters"] - ores.iters) <= 1
+    xd2 = dev(np.zeros(c.N))
+    gpu_lib.gmres(ctx, c.lA, c.lP, bd, xd2, restart=100, fixed_iters=ores.iters)
+    err = np.linalg.norm(host(xd2) - ores.x) / np.linalg.norm(ores.x)
+    say("  rel L2 at the oracle's count", err)
+    assert err <= 1e-8

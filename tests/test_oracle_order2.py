@@ -190,3 +190,38 @@ def test_oras_local_matrix_is_the_box_problem_order_two(box):
     P = sp.csr_matrix((np.ones(Ss.n), (pos, np.arange(Ss.n))), shape=(len(idx), Ss.n))
     mapped = (P @ As @ P.T).tocsr()
     assert abs(Al - mapped).max() <= 1e-12 * abs(Al).max()
+
+
+@pytest.mark.parametrize("bc", [fem.BC_IMPEDANCE, fem.BC_PEC])
+def test_coarse_restriction_reproduces_coarse_whitney_fields(bc):
+    """Each row of the order-2 R^0, used as fine coefficients, is the coarse Whitney function
+    itself: evaluated on fine tetrahedra at random points it equals l_a grad l_b - l_b grad l_a
+    computed directly on the coarse tetrahedron holding the point."""
+    from oracle import coarse
+    fine = Mesh(4, 4, 4)
+    cm = coarse.coarse_mesh(fine, 2)
+    S = order2.Space(fine)
+    R = order2.coarse_restriction(S, cm, bc)
+    assert R.shape == (len(coarse.coarse_dofs(cm, bc)), S.n)
+    keep = coarse.coarse_dofs(cm, bc)
+    gc, _ = fem.tet_geometry(cm)
+    rng = np.random.default_rng(5)
+    for p in rng.choice(R.shape[0], 6, replace=False):
+        ce = keep[p]
+        a, b = cm.edge_vert[ce]
+        coef = R[p].toarray().ravel()
+        # coarse tetrahedra holding the edge, and a fine tetrahedron inside each at random
+        for T in np.nonzero((cm.tet_edge == ce).any(axis=1))[0][:3]:
+            la, lb = list(cm.tet_vert[T]).index(a), list(cm.tet_vert[T]).index(b)
+            X = cm.xyz[cm.tet_vert[T]]
+            # random point inside T, then the fine tetrahedron holding it
+            w = rng.dirichlet(np.ones(4))
+            x = w @ X
+            gf, _ = fem.tet_geometry(fine)
+            lam_all = np.einsum("tai,ti->ta", gf, x[None, :] - fine.xyz[fine.tet_vert[:, 0]])
+            lam_all[:, 0] += 1.0
+            t = int(np.argmax(lam_all.min(axis=1)))
+            lam = lam_all[t][None, :]
+            u = order2.evaluate(S, t, coef[S.tet_dof[t]], lam)[0].real
+            direct = w[la] * gc[T, lb] - w[lb] * gc[T, la]
+            assert np.allclose(u, direct, atol=1e-12 * np.abs(direct).max() + 1e-13), (p, T)
