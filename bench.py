@@ -56,11 +56,26 @@ def instances(name):
         return [("oras", 1.0, 0), ("as", 1.0, 1)]
     if name == "small":
         return [("oras", 2.0, 0)]
+    if name == "order2":  # xi_prob = xi_prec = k^2, then xi_prob = 0 with xi_prec = k
+        return [("oras", 2.0, 0), ("oras", 1.0, 1)]
     raise SystemExit("unknown workload " + name)
 
 
+def xi_prob_zero(name, idx):
+    """Whether instance idx solves the problem without absorption (xi_prob = 0)."""
+    return name == "scale-xi0" or (name == "order2" and idx == 1)
+
+
 def workload_desc(name):
-    from mx_inputs import config_scale, config_small
+    from mx_inputs import config_order2, config_scale, config_small
+    if name == "order2":
+        w = config_order2()
+        return w, {"workload": "unit cube 24^3 cubes x 6 tets, second-order Nedelec elements "
+                               "(542,736 complex DOFs), k=12, 4x4x4 subdomains, 1-layer overlap, "
+                               "ORAS two-level hybrid with the coarse mesh of 4^3 cubes: xi_prob = "
+                               "xi_prec = k^2, then ImpHRAS with xi_prob = 0, xi_prec = k; "
+                               "GMRES(100) rtol 1e-6, complex128, seeded random complex Gaussian J",
+                   "instances": len(instances(name))}
     if name == "scale-xi0":
         w = config_scale()
         return w, {"workload": "unit cube 64^3 cubes x 6 tets (1,872,064 complex DOFs), k=16, "
@@ -456,16 +471,20 @@ def main():
         cfg["workload"] += "; %d right-hand sides per preconditioner setup" % args.rhs
     if args.graph:
         cfg["workload"] += "; Arnoldi steps replayed from HIP graphs"
-    if args.coarse:
+    order = 2 if args.workload == "order2" else 1
+    if order == 2 and not args.coarse:
+        args.coarse, args.combine = 6, "hybrid"
+    elif args.coarse:
         if args.workload == "scale-xi0" or args.overlap_factor:
             raise SystemExit("--coarse is not combined with scale-xi0 or --overlap-factor")
-        cfg["workload"] += ("; two-level (%s) with a nested coarse mesh of %s cubes"
-                            % (args.combine, "x".join(str(v // args.coarse) for v in w.n)))
+        if order == 1:
+            cfg["workload"] += ("; two-level (%s) with a nested coarse mesh of %s cubes"
+                                % (args.combine, "x".join(str(v // args.coarse) for v in w.n)))
     ctx = mx.Context(0)
     n = w.n
     # inputs resident in HBM before the timed region
     mesh0 = mx.Mesh(*n, *w.lengths)
-    E = mesh0.n_edge
+    E = mesh0.n_edge if order == 1 else mesh0.order2()["n_dof"]  # DOFs of the space
     del mesh0
     rhs = {s: torch.from_numpy(random_rhs(E, s)).cuda() for _, _, s in inst}
     # further right-hand sides of each instance when several are solved per setup
@@ -483,7 +502,7 @@ def main():
         kind0, e0, _ = inst[0]
         m0 = mx.Mesh(*n, *w.lengths)
         p0 = mx.Partition(m0, *w.parts, w.layers)
-        A0 = mx.Matrix(ctx, m0, w.k, w.k ** e0)
+        A0 = mx.Matrix(ctx, m0, w.k, w.k ** e0, order=order)
         sch, wid, best, each = mx.tune_factor(ctx, A0, m0, p0, kind0, precision=args.precision)
         P0 = mx.Precond(ctx, A0, m0, p0, kind0, precision=args.precision, schedule=sch, width=wid)
         grid, ms = P0.autotune()
@@ -497,26 +516,31 @@ def main():
     ctx_host = mx.Context(0)
     fstream = torch.cuda.Stream() if args.overlap_factor else None  # default priority
 
-    xi0 = args.workload == "scale-xi0"
 
-    def prepare(mesh, part, kind, e):
-        xi = w.k ** e  # the preconditioner's absorption; also the problem's unless xi0
+    def prepare(mesh, part, kind, e, idx):
+        xi = w.k ** e  # the preconditioner's absorption; also the problem's unless xi_prob = 0
+        zero = xi_prob_zero(args.workload, idx)
         t0 = time.perf_counter()
-        A = mx.Matrix(None, mesh, w.k, 0.0 if xi0 else xi)
-        A_prec = mx.Matrix(None, mesh, w.k, xi) if xi0 else A  # host only
+        A = mx.Matrix(None, mesh, w.k, 0.0 if zero else xi, order=order)
+        A_prec = mx.Matrix(None, mesh, w.k, xi, order=order) if zero else A  # host only
         A.upload(ctx_host)  # its own stream: overlaps the device work of the current instance
         t1 = time.perf_counter()
         P = mx.Precond(ctx_host, A_prec, mesh, part, kind, xi_prec=xi, precision=args.precision,
                        plan_only=True, schedule=tuned["schedule"], width=tuned["width"],
                        sweep_grid=tuned["sweep_grid"])
-        del A_prec
         P.stage(ctx_host)  # host-to-device copies, also overlapping the current instance
-        if args.coarse:  # host half of the coarse level (R^0, A^0, plan of its factorisation)
-            P.plan_coarse(A, mesh, args.coarse, args.combine)
+        A_c = None
+        if args.coarse:  # host half of the coarse level (R^0, A^0, plan of its factorisation),
+            # built from the matrix the preconditioner is for (at xi_prec), which then stays
+            A_c = A_prec
+            if A_c is not A:
+                A_c.upload(ctx_host)
+            P.plan_coarse(A_c, mesh, args.coarse, args.combine)
+        del A_prec
         if fstream is not None:
             P.materialize(ctx_host, fstream)  # returns once its factor tiles are complete
         t2 = time.perf_counter()
-        return A, P, xi, t1 - t0, t2 - t1
+        return A, A_c, P, xi, zero, t1 - t0, t2 - t1
 
     def step(record):
         from concurrent.futures import ThreadPoolExecutor
@@ -527,17 +551,17 @@ def main():
         t_topo = time.perf_counter() - t
         rec = []
         with ThreadPoolExecutor(max_workers=1) as ex:
-            fut = ex.submit(prepare, mesh, part, inst[0][0], inst[0][1])
+            fut = ex.submit(prepare, mesh, part, inst[0][0], inst[0][1], 0)
             for idx, (kind, e, seed) in enumerate(inst):
-                A, P, xi, t_asm, t_pre = fut.result()
+                A, A_c, P, xi, zero, t_asm, t_pre = fut.result()
                 if idx + 1 < len(inst):
-                    fut = ex.submit(prepare, mesh, part, inst[idx + 1][0], inst[idx + 1][1])
+                    fut = ex.submit(prepare, mesh, part, inst[idx + 1][0], inst[idx + 1][1], idx + 1)
                 if fstream is None:
                     P.materialize(ctx)
                 t_coarse = 0.0
                 if args.coarse:
                     tc = time.perf_counter()
-                    P.add_coarse(ctx, A, mesh, args.coarse, args.combine)
+                    P.add_coarse(ctx, A_c, mesh, args.coarse, args.combine)
                     t_coarse = time.perf_counter() - tc
                 t2 = time.perf_counter()
                 timed = record and not args.graph
@@ -558,7 +582,7 @@ def main():
                         st0 = st
                 st = st0
                 t3 = time.perf_counter()
-                r = {"kind": kind, "xi": 0.0 if xi0 else xi, "xi_prec": xi,
+                r = {"kind": kind, "xi": 0.0 if zero else xi, "xi_prec": xi,
                      "iters": st["iters"], "converged": st["converged"],
                      "relres": st["relres_true"], "t_assemble": t_asm, "t_precond_plan": t_pre,
                      "t_gmres": t3 - t2, "t_coarse": t_coarse}
@@ -574,7 +598,7 @@ def main():
                 else:
                     r["sweep_launches"], r["fwd_ms"], r["bwd_ms"] = 0, 0.0, 0.0
                 rec.append(r)
-                del P, A
+                del P, A, A_c
         return t_topo, rec
 
     for _ in range(args.warmup):
@@ -649,8 +673,9 @@ def main():
         kind, e, seed, xm = refs["x_mixed"]
         mesh = mx.Mesh(*n, *w.lengths)
         part = mx.Partition(mesh, *w.parts, w.layers)
-        A = mx.Matrix(ctx, mesh, w.k, 0.0 if xi0 else w.k ** e)
-        A_prec = mx.Matrix(None, mesh, w.k, w.k ** e) if xi0 else A
+        zero = xi_prob_zero(args.workload, 0)
+        A = mx.Matrix(ctx, mesh, w.k, 0.0 if zero else w.k ** e, order=order)
+        A_prec = mx.Matrix(None, mesh, w.k, w.k ** e, order=order) if zero else A
         P = mx.Precond(ctx, A_prec, mesh, part, kind, xi_prec=w.k ** e, precision="c128")
         x.zero_()
         st = mx.gmres(ctx, A, P, rhs[seed], x, restart=w.restart, rtol=w.rtol,
@@ -659,7 +684,12 @@ def main():
                                 "rel_l2_diff": float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))}
         out["dtype"] = "complex64 factors + FP64 FGMRES"
         del P, A
-    if not args.no_cpu_baseline:
+    if order == 2:
+        out["order"] = 2
+        out["cpu_baseline"] = None
+        out["cpu_baseline_note"] = ("not taken for this secondary line: the oracle's order-2 "
+                                    "local problems are timed by the parity tests only")
+    elif not args.no_cpu_baseline:
         if args.workload == "small":
             out["cpu_baseline"], x_or = cpu_baseline_small(w)
             xo = torch.from_numpy(x_or).cuda()

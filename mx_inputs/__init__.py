@@ -77,6 +77,16 @@ def config_medium(kind=ORAS, xi_exp=2.0, seed=0, n=32, parts=4):
                     k ** xi_exp, (parts, parts, parts), 2, kind, 100, rhs="random", seed=seed)
 
 
+def config_order2(kind=ORAS, xi_exp=2.0, seed=0):
+    """Unit cube 24^3 cubes x 6 tets with second-order Nedelec elements (542,736 DOFs), k = 12
+    (about 12.6 cubes, 25 DOFs per direction, per wavelength), xi = k^xi_exp, 4x4x4 subdomains,
+    1 layer (minimal overlap), GMRES(100), seeded complex Gaussian per-DOF load; the coarse mesh
+    of 4^3 cubes (ratio 6: about two coarse cubes per wavelength)."""
+    k = 12.0
+    return Workload("unit-cube 24^3 order 2, k=12, xi=k^%g" % xi_exp, (24, 24, 24), (1, 1, 1), k,
+                    k ** xi_exp, (4, 4, 4), 1, kind, 100, rhs="random", seed=seed)
+
+
 def config_batching(seed=0):
     """Box [0,1]x[0,1]x[0,2], 96x96x192 cubes, k = xi = 24, 6x6x12 subdomains with cut planes
     jittered by +-20 % of the box width, complex64 factors."""
