@@ -5,7 +5,10 @@ on the same seeded inputs:
   complex64 to 1e-5) and two-level ones (hybrid, deflation, additive) to 1e-10;
 * GMRES: iterations within +-1 of the oracle's, and after exactly the oracle's iteration count the
   solution within 1e-8 relative L2, for one-level ORAS and the two order-2 settings of the paper:
-  xi_prob = xi_prec = k^2 with minimal overlap, and ImpHRAS with xi_prob = 0, xi_prec = k."""
+  xi_prob = xi_prec = k^2 with minimal overlap, and ImpHRAS with xi_prob = 0, xi_prec = k (8^3
+  with 2x2x2 subdomains, and 12^3 with 3x3x3, every class of box);
+* the order-2 benchmark problem (24^3) in the benchmark's launch configuration: sampled ORAS
+  local solves (corner, interior, last subdomain) against the oracle's."""
 import sys
 
 import numpy as np
@@ -119,11 +122,30 @@ GMRES_CASES = {
 
 @pytest.mark.parametrize("name", list(GMRES_CASES))
 def test_order2_gmres(gpu_lib, ctx, name):
-    cfg = dict(GMRES_CASES[name])
+    _gmres_case(gpu_lib, ctx, name, GMRES_CASES, seed=23)
+
+
+MEDIUM = {
+    # 3x3x3 subdomains (every class of box), two-level hybrid with a 4^3-cube coarse mesh
+    "medium_xi_k2": dict(n=(12, 12, 12), parts=(3, 3, 3), layers=1, k=6.0, xi_prob=36.0,
+                         xi_prec=36.0, kind="oras", ratio=3, combine="hybrid"),
+    "medium_imphras_xi0": dict(n=(12, 12, 12), parts=(3, 3, 3), layers=1, k=6.0, xi_prob=0.0,
+                               xi_prec=6.0, kind="oras", ratio=3, combine="hybrid"),
+}
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", list(MEDIUM))
+def test_order2_medium_gmres(gpu_lib, ctx, name):
+    _gmres_case(gpu_lib, ctx, name, MEDIUM)
+
+
+def _gmres_case(gpu_lib, ctx, name, table, seed=24):
+    cfg = dict(table[name])
     say("order-2 GMRES", name, cfg)
     c = Case(gpu_lib, ctx, cfg.pop("n"), cfg.pop("parts"), cfg.pop("layers"), cfg.pop("k"),
              cfg.pop("xi_prob"), cfg.pop("xi_prec"), cfg.pop("kind"), **cfg)
-    f = random_rhs(c.N, 23)
+    f = random_rhs(c.N, seed)
     ores = gmres.gmres(c.oA, f, c.oB, restart=100, rtol=1e-6)
     bd, xd = dev(f), dev(np.zeros(c.N))
     st = gpu_lib.gmres(ctx, c.lA, c.lP, bd, xd, restart=100, rtol=1e-6)
@@ -134,3 +156,44 @@ def test_order2_gmres(gpu_lib, ctx, name):
     err = np.linalg.norm(host(xd2) - ores.x) / np.linalg.norm(ores.x)
     say("  rel L2 at the oracle's count", err)
     assert err <= 1e-8
+
+
+@pytest.mark.timeout(900)
+def test_order2_benchmark_size_sampled_local_solves(gpu_lib, ctx):
+    """The order-2 benchmark problem (24^3 cubes, 542,736 DOFs, 4x4x4 subdomains, 1 layer,
+    k = 12) in the benchmark's launch configuration (all 64 subdomains factored together, one
+    sweep launch per direction): the one-level ORAS application restricted to the DOFs owned by
+    a corner (0), an interior (21) and the last subdomain (63) equals the oracle's local solve
+    there, at xi_prec = k^2 and xi_prec = k (the preconditioners of the benchmark's two
+    instances).  Bar: 1e-10 relative."""
+    from oracle import pool
+    n, k = (24, 24, 24), 12.0
+    om = OMesh(*n)
+    S = order2.Space(om)
+    op = dd.Partition(om, 4, 4, 4, 1)
+    p2 = order2.Partition(S, op)
+    lm = gpu_lib.Mesh(*n)
+    lp = gpu_lib.Partition(lm, 4, 4, 4, 1)
+    v = random_rhs(S.n, 6)
+    sampled = (0, 21, 63)
+    tasks, keys, gpu = [], [], {}
+    for xi in (k * k, k):
+        lA = gpu_lib.Matrix(ctx, lm, k, xi, order=2)
+        P = gpu_lib.Precond(ctx, lA, lm, lp, "oras", xi_prec=xi)
+        vd, zd = dev(v), dev(np.zeros(S.n))
+        P.apply(vd, zd)
+        P.check()
+        gpu[xi] = host(zd)
+        del P, lA
+        for l in sampled:
+            tasks.append((order2.local_matrix(p2, None, dd.ORAS, k, xi, l), v[p2.oras_sets[l]]))
+            keys.append((xi, l))
+    res = pool.solve_many(tasks)
+    for (xi, l), (x, _, _) in zip(keys, res):
+        idx = p2.oras_sets[l]
+        own = p2.pou(l, dd.ORAS) > 0
+        z = gpu[xi]
+        err = np.max(np.abs(z[idx[own]] - x[own])) / np.max(np.abs(x[own]))
+        say("  ORAS order 2 xi %g l %d owned %d of %d: max rel err %.2e"
+            % (xi, l, int(own.sum()), len(idx), err))
+        assert err <= 1e-10
