@@ -358,10 +358,16 @@ def run_serving(args):
         tickets.append((r, srv.submit(r["n"], r["p"], r["k"], r["xi"], r["center"], r["pol"], 0.1)))
         if len(tickets) % 100 == 0:
             print("submitted %d/%d" % (len(tickets), len(reqs)), file=sys.stderr, flush=True)
+    # a seeded sample of the small requests is solved again by the oracle after the run
+    small = [i for i, (r, _) in enumerate(tickets) if r["n"] <= 16]
+    sample = set(np.random.default_rng(args.seed + 7).permutation(small)[:4].tolist()) if small else set()
+    served = {}
     res = []
-    for r, t in tickets:
+    for i, (r, t) in enumerate(tickets):
         out = srv.wait(t, 600.0)
         res.append(out)
+        if i in sample and out["status"] == 0:
+            served[i] = srv.solution(t, out["n_dof"])
         srv.release(t)
         if len(res) % 100 == 0:  # progress for long runs (stderr; stdout carries one JSON line)
             print("served %d/%d" % (len(res), len(tickets)), file=sys.stderr, flush=True)
@@ -375,7 +381,7 @@ def run_serving(args):
                "relres": x["relres_true"], "error": x.get("error", "")}
               for i, ((r, _), x) in enumerate(zip(tickets, res))
               if x["status"] != 0 or not x["converged"]]
-    return {
+    line = {
         "metric": "p50/p99 solve latency", "value": float(np.percentile(lat, 50)), "unit": "s",
         "n_gpus": 1, "steps": len(res), "warmup": 0, "ms_per_step": (t1 - t0) / len(res) * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -394,6 +400,41 @@ def run_serving(args):
         "server": st,
         "failed": failed[:20],
     }
+    if not args.no_cpu_baseline and served:
+        line["cpu_baseline"], line["error_vs_oracle"] = cpu_baseline_serving(
+            [(tickets[i][0], served[i]) for i in sorted(served)], layers=2, restart=50)
+    return line
+
+
+def cpu_baseline_serving(sample, layers, restart):
+    """The oracle (NumPy/SciPy FP64, one thread) on a seeded sample of the served requests (at most
+    four with n <= 16 cubes per side), each solved end to end (mesh, assembly, load, partition,
+    ORAS local factorisations, GMRES(restart) to rtol 1e-6); returns the oracle's solves/s and the
+    relative L2 error of each served (mixed-precision) solution against the oracle's."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import dd, fem, gmres
+    from oracle.mesh import Mesh as OMesh
+    errs, t = [], 0.0
+    with threadpool_limits(1):
+        for r, x in sample:
+            t0 = time.perf_counter()
+            m = OMesh(r["n"], r["n"], r["n"])
+            A = fem.assemble(m, r["k"], r["xi"])
+            f = fem.load_vector(m, fem.gaussian_source(r["center"], r["pol"], 0.1))
+            part = dd.Partition(m, r["p"], r["p"], r["p"], layers)
+            B = dd.Schwarz(part, A, dd.ORAS, r["k"], r["xi"])
+            xo = gmres.gmres(A, f, B, restart=restart, rtol=1e-6).x
+            t += time.perf_counter() - t0
+            errs.append(float(np.linalg.norm(x - xo) / np.linalg.norm(xo)))
+    desc = ", ".join("n=%d p=%d k=%.2f xi=%.2f" % (r["n"], r["p"], r["k"], r["xi"]) for r, _ in sample)
+    return ({"value": len(sample) / t, "unit": "solves/s", "cores": 1, "kind": "oracle",
+             "sample": "%d served requests (%s) solved again end to end by the oracle in %.1f s"
+                       % (len(sample), desc, t)},
+            {"per_solve": errs, "per_solve_max": max(errs), "solves": len(errs),
+             "norm": "relative L2 against the FP64 oracle's solution of the same request at rtol "
+                     "1e-6", "target": 1e-5})
 
 
 def main():
