@@ -114,6 +114,11 @@ int mx_weight_assemble(mx_ctx *ctx, const mx_mesh *m, double k, int bc, mx_matri
  * than 2^31-1 DOFs), MX_ENOMEM, MX_EDEVICE. */
 int mx_matrix_assemble_order(mx_ctx *ctx, const mx_mesh *m, int order, double k, double xi, int bc,
                              mx_matrix **out);
+/* D_k = K + k^2 M of mx_weight_assemble on the Nedelec space of order `order` (1 or 2; order 2 in
+ * the basis and numbering of mx_matrix_assemble_order), for mx_gmres_weighted with a matrix of
+ * the same order.  ctx may be NULL.  Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE. */
+int mx_weight_assemble_order(mx_ctx *ctx, const mx_mesh *m, int order, double k, int bc,
+                             mx_matrix **out);
 /* Order-2 sizes: faces F (interior and boundary) and DOFs N = 2E + 2F.  The order-2 topology is
  * built on the mesh's first order-2 call (thread safe) and kept with the mesh. */
 int mx_mesh_order2_sizes(const mx_mesh *m, int64_t *n_face, int64_t *n_dof);

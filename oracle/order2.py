@@ -370,3 +370,19 @@ def coarse_restriction(space, coarse_mesh, bc=fem.BC_IMPEDANCE):
     R1 = _coarse.restriction(space.mesh, coarse_mesh, bc)
     zero = sp.csr_matrix((R1.shape[0], space.n - space.E))
     return sp.hstack([R1, zero]).tocsr()
+
+
+def weight_matrix(space, k, bc=fem.BC_IMPEDANCE):
+    """D_k = K + k^2 M (eq:ip, eq:weight) of the order-2 space, the Gram matrix of
+    (curl v, curl w) + k^2 (v, w) in the hierarchical basis; no boundary term; with PEC, identity
+    rows and columns on the boundary DOFs (as fem.weight_matrix at the lowest order)."""
+    K, M, _ = assemble_parts(space, faces=np.zeros((0, 3), dtype=np.int64))
+    D = (K + (k * k) * M).tocsr()
+    if bc == fem.BC_PEC:
+        pec = space.boundary_dof_mask()
+        if pec.any():
+            keep = sp.diags((~pec).astype(np.float64))
+            D = (keep @ D @ keep + sp.diags(pec.astype(np.float64))).tocsr()
+    D.sum_duplicates()
+    D.sort_indices()
+    return D

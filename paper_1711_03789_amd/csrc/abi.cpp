@@ -158,6 +158,26 @@ int mx_matrix_assemble_order(mx_ctx *ctx, const mx_mesh *m, int order, double k,
   });
 }
 
+int mx_weight_assemble_order(mx_ctx *ctx, const mx_mesh *m, int order, double k, int bc,
+                             mx_matrix **out) {
+  MX_GUARD({
+    MX_REQUIRE(m && out, "NULL argument");
+    MX_REQUIRE(order == 1 || order == 2, "order must be 1 or 2");
+    MX_REQUIRE(bc == MX_BC_PEC || bc == MX_BC_IMPEDANCE, "unknown boundary condition");
+    MX_REQUIRE(std::isfinite(k) && k >= 0, "need finite k >= 0");
+    auto D = std::make_unique<mx_matrix>();
+    D->k = k, D->xi = 0, D->bc = bc, D->weight = true, D->order = order;
+    if (order == 2) mx::assemble_order2(m->m, m->order2(), k, 0.0, bc, D->h, true);
+    else mx::assemble_global(m->m, k, 0.0, bc, D->h, true);
+    if (ctx) {
+      bind_device(ctx->device);
+      D->device = ctx->device;
+      mx::matrix_upload(D.get());
+    }
+    *out = D.release();
+  });
+}
+
 int mx_mesh_order2_sizes(const mx_mesh *m, int64_t *n_face, int64_t *n_dof) {
   MX_GUARD({
     MX_REQUIRE(m, "mesh is NULL");
@@ -588,7 +608,8 @@ int mx_gmres_weighted(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const mx_m
     MX_REQUIRE(ctx && A && b_dev && x_dev && opts && stats, "NULL argument");
     MX_REQUIRE(b_dev != x_dev, "b and x must be distinct");
     MX_REQUIRE(A->rowptr.p, "matrix has no device copy");
-    MX_REQUIRE(!D || (D->rowptr.p && D->h.n == A->h.n), "weight needs a device copy of A's size");
+    MX_REQUIRE(!D || (D->rowptr.p && D->h.n == A->h.n && D->order == A->order),
+               "weight needs a device copy of A's size and element order");
     MX_REQUIRE(!P || P->E == A->h.n, "preconditioner and matrix sizes differ");
     MX_REQUIRE(!P || !P->plan, "preconditioner is planned but not materialised");
     MX_REQUIRE(!P || !mx::coarse_incomplete(P), "coarse level planned but not built (mx_precond_add_coarse)");

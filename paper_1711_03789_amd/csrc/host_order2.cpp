@@ -292,14 +292,14 @@ void incidences(const Mesh &m, const Order2 &o, int64_t d, std::vector<Inc> &out
 }
 }  // namespace
 
-// Row d of K - (k^2 + i xi) M - i sign(xi) k M_b over the tetrahedra with inside(t), the
-// boundary term on the faces with term_face(f, t_other); entries merged by global column (summed
-// in a fixed order).
+// Row d of K + (sre + i sim) M + i cb M_b over the tetrahedra with inside(t), the boundary term
+// on the faces with term_face(t_other); entries merged by global column (summed in a fixed
+// order).  The Galerkin matrix has sre = -k^2, sim = -xi, cb = -sign(xi) k; the weight
+// D_k = K + k^2 M has sre = k^2, sim = 0 and no boundary term.
 template <class Inside, class TermFace>
-static void order2_row(const Mesh &m, const Order2 &o, int64_t d, double k, double xi,
+static void order2_row(const Mesh &m, const Order2 &o, int64_t d, double sre, double sim, double cb,
                        Inside inside, TermFace term_face, std::vector<Inc> &inc,
                        std::vector<CEntry> &ent) {
-  const double sre = -k * k, sim = -xi, cb = -(xi >= 0 ? 1.0 : -1.0) * k;
   ent.clear();
   incidences(m, o, d, inc);
   for (const Inc &x : inc) {
@@ -319,8 +319,12 @@ static void order2_row(const Mesh &m, const Order2 &o, int64_t d, double k, doub
   merge(ent);
 }
 
-void assemble_order2(const Mesh &m, const Order2 &o, double k, double xi, int bc, HostCSR &A) {
+void assemble_order2(const Mesh &m, const Order2 &o, double k, double xi, int bc, HostCSR &A,
+                     bool weight) {
   const int64_t N = o.N;
+  const double sre = weight ? k * k : -k * k, sim = weight ? 0.0 : -xi;
+  const double cb = -(xi >= 0 ? 1.0 : -1.0) * k;
+  const bool bterm = bc == MX_BC_IMPEDANCE && !weight;
   // rows in chunks handed out to the host threads; each chunk packs its rows contiguously
   const int64_t cs = 4096, nchunk = (N + cs - 1) / cs;
   std::vector<std::vector<CEntry>> packed(nchunk);
@@ -332,8 +336,8 @@ void assemble_order2(const Mesh &m, const Order2 &o, double k, double xi, int bc
     for (int64_t c; (c = next()) >= 0;) {
       auto &out = packed[c];
       for (int64_t d = c * cs; d < std::min(N, (c + 1) * cs); ++d) {
-        order2_row(m, o, d, k, xi, [](int32_t) { return true; },
-                   [bc](int32_t t2) { return t2 < 0 && bc == MX_BC_IMPEDANCE; }, inc, ent);
+        order2_row(m, o, d, sre, sim, cb, [](int32_t) { return true; },
+                   [bterm](int32_t t2) { return t2 < 0 && bterm; }, inc, ent);
         const size_t before = out.size();
         if (bc == MX_BC_PEC && o.dof_boundary[d]) {
           out.push_back({(int32_t)d, 1.0, 0.0});
@@ -425,7 +429,7 @@ void local_impedance2(const Mesh &m, const Order2 &o, double k, double xi, int b
   std::vector<CEntry> ent;
   for (int64_t i = 0; i < n; ++i) {
     const int32_t d = set[i];
-    order2_row(m, o, d, k, xi, inside, term_face, inc, ent);
+    order2_row(m, o, d, -k * k, -xi, -(xi >= 0 ? 1.0 : -1.0) * k, inside, term_face, inc, ent);
     const bool rp = bc == MX_BC_PEC && o.dof_boundary[d];
     for (const auto &x : ent) {  // global columns ascending, so local columns ascend too
       const int32_t lc = g2l[x.col];

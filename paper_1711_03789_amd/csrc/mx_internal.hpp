@@ -229,8 +229,10 @@ struct Order2 {
 void build_order2(const Mesh &m, Order2 &o);
 int32_t order2_dof(const Mesh &m, const Order2 &o, int64_t t, int a);
 int32_t order2_face_of(const Order2 &o, const int32_t v[3]);  // -1 if not a face
-// A = K - (k^2 + i xi) M - i sign(xi) k M_b of the order-2 space (PEC: identity rows and columns)
-void assemble_order2(const Mesh &m, const Order2 &o, double k, double xi, int bc, HostCSR &A);
+// A = K - (k^2 + i xi) M - i sign(xi) k M_b of the order-2 space (PEC: identity rows and columns);
+// with weight, the Gram matrix D_k = K + k^2 M instead (xi unused)
+void assemble_order2(const Mesh &m, const Order2 &o, double k, double xi, int bc, HostCSR &A,
+                     bool weight = false);
 // order-2 local DOF sets (kind AS/RAS: Whitney and gradient functions of the lowest-order AS set
 // and the faces whose tetrahedra are all in the subdomain; ORAS: every DOF of its tetrahedra),
 // and the Boolean owner (least part0 of a tetrahedron holding the DOF)

@@ -36,6 +36,7 @@ SYMBOLS = [
     "mx_coarse_operators", "mx_weight_assemble", "mx_gmres_weighted", "mx_precond_plan_coarse",
     "mx_precond_tune_factor", "mx_server_batch_stats", "mx_matrix_assemble_order",
     "mx_mesh_order2_sizes", "mx_mesh_order2_export", "mx_partition_order2_export",
+    "mx_weight_assemble_order",
 ]
 
 
@@ -136,6 +137,7 @@ def load(path=LIB_PATH):
         "mx_matrix_assemble": (C.c_int, [P, P, C.c_double, C.c_double, C.c_int, C.POINTER(P)]),
         "mx_matrix_assemble_order": (C.c_int, [P, P, C.c_int, C.c_double, C.c_double, C.c_int,
                                                C.POINTER(P)]),
+        "mx_weight_assemble_order": (C.c_int, [P, P, C.c_int, C.c_double, C.c_int, C.POINTER(P)]),
         "mx_mesh_order2_sizes": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
         "mx_mesh_order2_export": (C.c_int, [P, P, P, P]),
         "mx_partition_order2_export": (C.c_int, [P, P, C.c_int, P, P, P]),
@@ -322,13 +324,18 @@ class Matrix:
         self.n, self.nnz = n.value, nnz.value
 
     @classmethod
-    def weight(cls, ctx, mesh, k, bc=MX_BC_IMPEDANCE):
-        """D_k = K + k^2 M, the weight of weighted GMRES (mx_weight_assemble)."""
+    def weight(cls, ctx, mesh, k, bc=MX_BC_IMPEDANCE, order=1):
+        """D_k = K + k^2 M, the weight of weighted GMRES (mx_weight_assemble[_order])."""
         load()
         self = cls.__new__(cls)
         h = P()
-        _check(_lib.mx_weight_assemble(ctx.h if ctx is not None else None, mesh.h, k, bc, C.byref(h)))
-        self.h, self.k, self.xi, self.bc, self.order = h, k, 0.0, bc, 1
+        if order == 1:
+            _check(_lib.mx_weight_assemble(ctx.h if ctx is not None else None, mesh.h, k, bc,
+                                           C.byref(h)))
+        else:
+            _check(_lib.mx_weight_assemble_order(ctx.h if ctx is not None else None, mesh.h, order,
+                                                 k, bc, C.byref(h)))
+        self.h, self.k, self.xi, self.bc, self.order = h, k, 0.0, bc, order
         n, nnz = C.c_int64(), C.c_int64()
         _check(_lib.mx_matrix_sizes(h, C.byref(n), C.byref(nnz)))
         self.n, self.nnz = n.value, nnz.value

@@ -101,3 +101,17 @@ def test_coarse_operators_order2(bc):
     assert abs(R[keep] - oR).max() <= 1e-14 * abs(oR).max()
     oA0 = (oR @ order2.assemble(S, k, xi, bc) @ oR.T).tocsr()
     assert abs(A0[keep][:, keep] - oA0).max() <= 1e-13 * abs(oA0).max()
+
+
+@pytest.mark.parametrize("bc", [mx.MX_BC_IMPEDANCE, mx.MX_BC_PEC])
+def test_weight_matrix_order2(bc):
+    """D_k = K + k^2 M of the order-2 space equals the oracle's."""
+    n = (3, 2, 3)
+    om, lm = OMesh(*n, *LENGTHS), mx.Mesh(*n, *LENGTHS)
+    S = order2.Space(om)
+    for k in (0.0, 4.0):
+        D = mx.Matrix.weight(None, lm, k, bc, order=2)
+        L = _csr(D)
+        O = order2.weight_matrix(S, k, bc)
+        assert not np.any(L.data.imag)
+        assert abs(L - O).max() <= 1e-14 * abs(O).max()

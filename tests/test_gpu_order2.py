@@ -197,3 +197,30 @@ def test_order2_benchmark_size_sampled_local_solves(gpu_lib, ctx):
         say("  ORAS order 2 xi %g l %d owned %d of %d: max rel err %.2e"
             % (xi, l, int(own.sum()), len(idx), err))
         assert err <= 1e-10
+
+
+@pytest.mark.parametrize("bc", [fem.BC_IMPEDANCE, fem.BC_PEC])
+def test_order2_weighted_gmres(gpu_lib, ctx, bc):
+    """Weighted GMRES (Sec. 5.2, eq:ip) on the order-2 space: residual minimised in the norm of
+    D_k = K + k^2 M of that space; iterations within +-1 of the oracle's, the D-norm true residual
+    equal to the one recomputed with the oracle's matrices, and 1e-8 at the oracle's count."""
+    say("order-2 weighted GMRES", bc)
+    c = Case(gpu_lib, ctx, (6, 6, 6), (2, 2, 2), 1, 4.0, 4.0, 4.0, "oras", bc)
+    oD = order2.weight_matrix(c.S, 4.0, bc)
+    f = random_rhs(c.N, 25)
+    if bc == fem.BC_PEC:
+        f[c.S.boundary_dof_mask()] = 0
+    ores = gmres.gmres(c.oA, f, c.oB, restart=20, rtol=1e-6, D=oD)
+    lD = gpu_lib.Matrix.weight(ctx, c.lm, 4.0, bc, order=2)
+    bd, xd = dev(f), dev(np.zeros(c.N))
+    st = gpu_lib.gmres(ctx, c.lA, c.lP, bd, xd, restart=20, rtol=1e-6, weight=lD)
+    say("  iterations gpu", st["iters"], "oracle", ores.iters, "relres_D", st["relres_true"])
+    assert st["converged"] and abs(st["iters"] - ores.iters) <= 1
+    r = f - c.oA @ host(xd)
+    dn = lambda v: np.sqrt(np.real(np.vdot(v, oD @ v)))
+    assert abs(dn(r) / dn(f) - st["relres_true"]) <= 1e-10 and st["relres_true"] <= 1e-6
+    xd2 = dev(np.zeros(c.N))
+    gpu_lib.gmres(ctx, c.lA, c.lP, bd, xd2, restart=20, fixed_iters=ores.iters, weight=lD)
+    err = np.linalg.norm(host(xd2) - ores.x) / np.linalg.norm(ores.x)
+    say("  rel L2 at the oracle's count", err)
+    assert err <= 1e-8

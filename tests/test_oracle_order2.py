@@ -225,3 +225,36 @@ def test_coarse_restriction_reproduces_coarse_whitney_fields(bc):
             u = order2.evaluate(S, t, coef[S.tet_dof[t]], lam)[0].real
             direct = w[la] * gc[T, lb] - w[lb] * gc[T, la]
             assert np.allclose(u, direct, atol=1e-12 * np.abs(direct).max() + 1e-13), (p, T)
+
+
+@pytest.mark.parametrize("k", [0.0, 3.0])
+def test_weight_matrix_is_the_gram_matrix_order_two(k):
+    """D_k = K + k^2 M of the order-2 space is the Gram matrix of (curl v, curl w) + k^2 (v, w)
+    (eq:ip, eq:weight): for fields the order-2 space holds exactly -- the rotation (-y, x, 0), the
+    gradient (y, x, 0) of xy and the quadratic (y^2, -xy, 0) (whose product with x vanishes) --
+    the coefficients c of the L2 projection give c^T D c = int |curl u|^2 + k^2 int |u|^2 on the
+    unit cube: 4 + 2k^2/3, 2k^2/3 and 3 + 14k^2/45."""
+    from scipy.sparse.linalg import spsolve
+    S = order2.Space(Mesh(2, 2, 2))
+    D = order2.weight_matrix(S, k)
+    _, M, _ = order2.assemble_parts(S, faces=np.zeros((0, 3), dtype=np.int64))
+    cases = [(lambda x: np.stack([-x[:, 1], x[:, 0], 0 * x[:, 0]], 1), 4.0, 2.0 / 3.0),
+             (lambda x: np.stack([x[:, 1], x[:, 0], 0 * x[:, 0]], 1), 0.0, 2.0 / 3.0),
+             (lambda x: np.stack([x[:, 1] ** 2, -x[:, 0] * x[:, 1], 0 * x[:, 0]], 1), 3.0, 14.0 / 45.0)]
+    for F, curl2, mass2 in cases:
+        b = order2.load_vector(S, F).real
+        c = spsolve(M.tocsc(), b)
+        assert abs(c @ (M @ c) - mass2) <= 1e-12
+        assert abs(c @ (D @ c) - (curl2 + k * k * mass2)) <= 1e-11 * (1 + curl2 + k * k)
+
+
+def test_weight_matrix_pec_rows_order_two():
+    S = order2.Space(Mesh(2, 3, 2))
+    Dp = order2.weight_matrix(S, 4.0, fem.BC_PEC).toarray()
+    Di = order2.weight_matrix(S, 4.0).toarray()
+    pec = S.boundary_dof_mask()
+    free = ~pec
+    assert np.array_equal(Dp[np.ix_(pec, pec)], np.eye(pec.sum()))
+    assert not Dp[np.ix_(pec, free)].any() and not Dp[np.ix_(free, pec)].any()
+    assert np.array_equal(Dp[np.ix_(free, free)], Di[np.ix_(free, free)])
+    assert np.linalg.eigvalsh(Dp).min() > 0
