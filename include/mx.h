@@ -229,7 +229,9 @@ typedef struct {
  * impedance local problems assembled with xi_prec, impedance coefficient k on the subdomain
  * boundary), orders each by reverse Cuthill-McKee, stores it in block-skyline tiles and
  * factors all subdomains together on the device (pivot-free complex-symmetric LDL^T, which
- * exists for xi != 0 by the coercivity lemma).  Synchronous.
+ * exists for xi != 0 by the coercivity lemma).  Synchronous.  For a matrix of order 2
+ * (mx_matrix_assemble_order) the local spaces, owners and ORAS problems are those of the order-2
+ * space (mx_partition_order2_export); vectors then have the order-2 DOF count.
  * Errors: MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EPIVOT. */
 int mx_precond_setup(mx_ctx *ctx, const mx_matrix *A, const mx_mesh *m, const mx_partition *p,
                      const mx_precond_opts *opts, mx_precond **out);
