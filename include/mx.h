@@ -290,7 +290,9 @@ int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_
  * mesh: the box of m with `ratio` times fewer cubes on every axis (ratio must divide each
  * count; the two meshes are then nested).  Coarse basis: the Whitney functions of the coarse
  * edges (PEC: those with zero tangential trace).  R^0 (eq:restriction): (R^0)_pj = fine DOF j of
- * coarse basis function p (line integral along fine edge j); A^0 = R^0 A R^0^T (eq:minor),
+ * coarse basis function p (line integral along fine edge j); with an order-2 A the coarse basis
+ * stays the lowest-order one, which lies in the fine order-2 space with Whitney coefficients
+ * only, so R^0 has zero columns for the gradient and face DOFs; A^0 = R^0 A R^0^T (eq:minor),
  * factored on the device like a local problem; G = R^0^T (A^0)^-1 R^0.  Afterwards
  * mx_precond_apply and mx_gmres with P apply the two-level form `combine` (MX_COARSE_*).  A is
  * borrowed: it must have a device copy and outlive P (the hybrid and deflated forms multiply by
