@@ -531,6 +531,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="serving: each request's applications on its own stream (no batching)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--coarse-cubes", type=int, default=0,
+                    help="two-level with a coarse box mesh of C^3 cubes, nested or not (R^0 by a "
+                         "Gauss rule of --nq points per fine edge)")
+    ap.add_argument("--nq", type=int, default=12, help="quadrature points per fine edge")
     ap.add_argument("--coarse", type=int, default=0,
                     help="two-level: coarse mesh with this many times fewer cubes per axis (0: one-level)")
     ap.add_argument("--combine", default="hybrid", choices=["additive", "hybrid", "deflation"],
@@ -584,6 +588,14 @@ def main():
     if args.graph:
         cfg["workload"] += "; Arnoldi steps replayed from HIP graphs"
     order = 2 if args.workload == "order2" else 1
+    box = None
+    if args.coarse_cubes:
+        if args.coarse or order == 2 or args.overlap_factor:
+            raise SystemExit("--coarse-cubes is not combined with --coarse, --overlap-factor or "
+                             "the order-2 workload")
+        box = (args.coarse_cubes,) * 3
+        cfg["workload"] += ("; two-level (%s) with a coarse mesh of %d^3 cubes, R^0 by a %d-point "
+                            "Gauss rule per fine edge" % (args.combine, args.coarse_cubes, args.nq))
     if order == 2 and not args.coarse:
         args.coarse, args.combine = 6, "hybrid"
     elif args.coarse:
@@ -642,12 +654,12 @@ def main():
                        sweep_grid=tuned["sweep_grid"])
         P.stage(ctx_host)  # host-to-device copies, also overlapping the current instance
         A_c = None
-        if args.coarse:  # host half of the coarse level (R^0, A^0, plan of its factorisation),
-            # built from the matrix the preconditioner is for (at xi_prec), which then stays
+        if args.coarse or box:  # host half of the coarse level (R^0, A^0, plan of its
+            # factorisation), built from the matrix the preconditioner is for (at xi_prec)
             A_c = A_prec
             if A_c is not A:
                 A_c.upload(ctx_host)
-            P.plan_coarse(A_c, mesh, args.coarse, args.combine)
+            P.plan_coarse(A_c, mesh, args.coarse, args.combine, box=box, nq=args.nq)
         del A_prec
         if fstream is not None:
             P.materialize(ctx_host, fstream)  # returns once its factor tiles are complete
@@ -671,9 +683,9 @@ def main():
                 if fstream is None:
                     P.materialize(ctx)
                 t_coarse = 0.0
-                if args.coarse:
+                if args.coarse or box:
                     tc = time.perf_counter()
-                    P.add_coarse(ctx, A_c, mesh, args.coarse, args.combine)
+                    P.add_coarse(ctx, A_c, mesh, args.coarse, args.combine, box=box, nq=args.nq)
                     t_coarse = time.perf_counter() - tc
                 t2 = time.perf_counter()
                 timed = record and not args.graph

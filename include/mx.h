@@ -302,6 +302,17 @@ int mx_precond_autotune(mx_ctx *ctx, mx_precond *P, void *stream, int32_t *best_
  * MX_EPIVOT. */
 int mx_precond_add_coarse(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m,
                           int ratio, int combine, void *stream);
+/* The same with a coarse box mesh of cnx x cny x cnz cubes that need not be nested in the fine one
+ * (Sec. 6.1 uses non-nested coarse meshes of a chosen coarse size H_cs): each entry of R^0 is
+ * the line integral of the coarse Whitney function along the fine edge by an nq-point
+ * Gauss-Legendre rule (1 <= nq <= 64; the paper's runs use a fixed number of points per edge,
+ * e.g. 12).  On a nested mesh the integrand is affine along every fine edge and any nq gives the
+ * exact values up to rounding.  The coarse point of a quadrature node is located in the coarse
+ * Kuhn split (cube by floor, tetrahedron by sorting the local coordinates).  Lowest-order
+ * matrices only (an order-2 A needs the nested mesh of mx_precond_add_coarse).
+ * Errors: as mx_precond_add_coarse. */
+int mx_precond_add_coarse_box(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m,
+                              int cnx, int cny, int cnz, int nq, int combine, void *stream);
 /* Optional host half of mx_precond_add_coarse (coarse mesh, R^0, A^0 and the plan of its
  * factorisation; no device work, A needs no device copy), so that it can run on another host
  * thread, also on a planned, not yet materialised P.  mx_precond_add_coarse with the same A, m,
@@ -309,6 +320,10 @@ int mx_precond_add_coarse(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const 
  * mx_precond_apply and mx_gmres.  Errors: as mx_precond_add_coarse. */
 int mx_precond_plan_coarse(mx_precond *P, const mx_matrix *A, const mx_mesh *m, int ratio,
                            int combine);
+/* Host half of mx_precond_add_coarse_box (then completed by mx_precond_add_coarse_box with the
+ * same arguments). */
+int mx_precond_plan_coarse_box(mx_precond *P, const mx_matrix *A, const mx_mesh *m, int cnx,
+                               int cny, int cnz, int nq, int combine);
 /* Host copies of the coarse level, for inspection and tests: R^0 as CSR r_rowptr[n_coarse+1],
  * r_col[nnz_r] (fine edge ids), r_val[nnz_r] (real), and A^0 as a_rowptr[n_coarse+1],
  * a_col[nnz_a], a_val[2*nnz_a] (complex128).  Rows are all coarse edges: with PEC the boundary
@@ -325,6 +340,12 @@ int mx_precond_coarse_export(const mx_precond *P, int64_t *n_coarse, int64_t *nn
 int mx_coarse_operators(const mx_mesh *m, const mx_matrix *A, int ratio, int64_t *n_coarse,
                         int64_t *nnz_r, int64_t *nnz_a, int64_t *r_rowptr, int32_t *r_col,
                         double *r_val, int64_t *a_rowptr, int32_t *a_col, double *a_val);
+/* Host-only coarse operators of mx_precond_add_coarse_box (same layout and calling convention as
+ * mx_coarse_operators).  Errors: MX_EINVAL. */
+int mx_coarse_operators_box(const mx_mesh *m, const mx_matrix *A, int cnx, int cny, int cnz, int nq,
+                            int64_t *n_coarse, int64_t *nnz_r, int64_t *nnz_a, int64_t *r_rowptr,
+                            int32_t *r_col, double *r_val, int64_t *a_rowptr, int32_t *a_col,
+                            double *a_val);
 /* Factorisation tuner: sets up the preconditioner that mx_precond_setup would build from these
  * arguments once for each factorisation launch shape -- one stream, and look-ahead with 1, 2, 3
  * and 4 block columns per trailing-update pass (factor_width) -- times each factorisation, frees

@@ -3,7 +3,9 @@
 Test infrastructure only (see oracle/__init__.py).
 
 * Coarse mesh (Sec. 3.2): a box mesh of the same domain with nx/r x ny/r x nz/r cubes (one ratio
-  r for all axes), split the same way.  Every coarse tetrahedron is then a union of fine ones (the
+  r for all axes), split the same way; or any coarse box mesh (Sec. 6.1 also uses coarse meshes
+  that are not nested), with R^0 by a Gauss rule along each fine edge
+  (restriction_quadrature).  Every coarse tetrahedron is then a union of fine ones (the
   planes bounding a coarse tetrahedron, x_i/H_i = const and x_i/H_i - x_j/H_j = const at integers,
   are planes of the fine split when H_i = r h_i), so the meshes are nested as the theory
   assumes.
@@ -125,3 +127,58 @@ class TwoLevel:
         return s - self.coarse(self.A @ s) + Gv  # (I - G A) s + G v
 
     __call__ = apply
+
+
+def coarse_box_mesh(fine, cn):
+    """A coarse box mesh of the same domain with cn = (cnx, cny, cnz) cubes, nested or not."""
+    return Mesh(*(int(c) for c in cn), *fine.L)
+
+
+def restriction_quadrature(fine, coarse, bc=fem.BC_IMPEDANCE, nq=12):
+    """R^0 of eq:restriction for a coarse mesh that need not be nested (Sec. 6.1): the fine DOF
+    (line integral along fine edge j, tangent x_hi - x_lo) of coarse basis function p by the
+    nq-point Gauss-Legendre rule on the edge: (R^0)_pj = sum_q w_q w^H_p(x_q) . t, with x_q
+    located in the coarse mesh by barycentric coordinates (the first of its cube's six
+    tetrahedra holding it).  On a nested mesh the integrand is affine along each fine edge and
+    this equals restriction() up to rounding."""
+    g, _ = fem.tet_geometry(coarse)
+    H = np.array(coarse.L) / np.array(coarse.n)
+    nc = np.array(coarse.n)
+    keep = coarse_dofs(coarse, bc)
+    row_of = np.full(coarse.n_edge, -1)
+    row_of[keep] = np.arange(len(keep))
+    s, w = np.polynomial.legendre.leggauss(nq)
+    s, w = 0.5 * (s + 1.0), 0.5 * w
+    xa = fine.xyz[fine.edge_vert[:, 0]]
+    t = fine.xyz[fine.edge_vert[:, 1]] - xa
+    E = fine.n_edge
+    rows, cols, vals = [], [], []
+    for sq, wq in zip(s, w):
+        x = xa + sq * t
+        ijk = np.clip(np.floor(x / H).astype(np.int64), 0, nc - 1)
+        cube = ijk[:, 0] + nc[0] * (ijk[:, 1] + nc[1] * ijk[:, 2])
+        tet = np.full(E, -1)
+        lam = np.zeros((E, 4))
+        for q in range(6):
+            cand = 6 * cube + q
+            X0 = coarse.xyz[coarse.tet_vert[cand, 0]]
+            l = np.einsum("eai,ei->ea", g[cand], x - X0)
+            l[:, 0] += 1.0
+            take = (tet < 0) & (l.min(axis=1) >= -1e-12)
+            tet[take] = cand[take]
+            lam[take] = l[take]
+        assert np.all(tet >= 0), "quadrature point outside its coarse cube"
+        for le, (a, b) in enumerate(LOCAL_EDGES):
+            p = coarse.tet_edge[tet, le]
+            wv = lam[:, a, None] * g[tet, b] - lam[:, b, None] * g[tet, a]
+            v = wq * coarse.tet_edge_sign[tet, le] * np.einsum("ei,ei->e", wv, t)
+            ok = row_of[p] >= 0
+            rows.append(row_of[p][ok])
+            cols.append(np.nonzero(ok)[0])
+            vals.append(v[ok])
+    R = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(len(keep), E))
+    R.sum_duplicates()
+    R.eliminate_zeros()
+    R.sort_indices()
+    return R

@@ -523,14 +523,47 @@ int mx_gmres(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev, 
   });
 }
 
+// the nested coarse mesh of a common ratio (exact midpoint values of eq:restriction)
+static mx::CoarseSpec ratio_spec(const mx_mesh *m, int ratio) {
+  MX_REQUIRE(ratio >= 1 && m->m.nx % ratio == 0 && m->m.ny % ratio == 0 && m->m.nz % ratio == 0,
+             "the coarse ratio must divide the cube count of every axis");
+  mx::CoarseSpec cs;
+  cs.cn[0] = m->m.nx / ratio, cs.cn[1] = m->m.ny / ratio, cs.cn[2] = m->m.nz / ratio;
+  cs.nq = 0;
+  return cs;
+}
+
+static mx::CoarseSpec box_spec(int cnx, int cny, int cnz, int nq) {
+  MX_REQUIRE(cnx >= 1 && cny >= 1 && cnz >= 1, "coarse cube counts must be >= 1");
+  MX_REQUIRE(nq >= 1 && nq <= 64, "quadrature points per fine edge must be 1 .. 64");
+  mx::CoarseSpec cs;
+  cs.cn[0] = cnx, cs.cn[1] = cny, cs.cn[2] = cnz;
+  cs.nq = nq;
+  return cs;
+}
+
+static int add_coarse(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m,
+                      const mx::CoarseSpec &cs, int combine, void *stream) {
+  MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
+  mx::precond_refuse_failed(P);
+  bind_device(ctx->device);
+  mx::coarse_setup(ctx, P, A, m, cs, combine, (hipStream_t)stream);
+  return MX_OK;
+}
+
 int mx_precond_add_coarse(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m,
                           int ratio, int combine, void *stream) {
   MX_GUARD({
     MX_REQUIRE(ctx && P && A && m, "NULL argument");
-    MX_REQUIRE(!P->plan, "preconditioner is planned but not materialised");
-    mx::precond_refuse_failed(P);
-    bind_device(ctx->device);
-    mx::coarse_setup(ctx, P, A, m, ratio, combine, (hipStream_t)stream);
+    add_coarse(ctx, P, A, m, ratio_spec(m, ratio), combine, stream);
+  });
+}
+
+int mx_precond_add_coarse_box(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m,
+                              int cnx, int cny, int cnz, int nq, int combine, void *stream) {
+  MX_GUARD({
+    MX_REQUIRE(ctx && P && A && m, "NULL argument");
+    add_coarse(ctx, P, A, m, box_spec(cnx, cny, cnz, nq), combine, stream);
   });
 }
 
@@ -538,8 +571,42 @@ int mx_precond_plan_coarse(mx_precond *P, const mx_matrix *A, const mx_mesh *m, 
                            int combine) {
   MX_GUARD({
     MX_REQUIRE(P && A && m, "NULL argument");
-    mx::coarse_plan(P, A, m, ratio, combine);
+    mx::coarse_plan(P, A, m, ratio_spec(m, ratio), combine);
   });
+}
+
+int mx_precond_plan_coarse_box(mx_precond *P, const mx_matrix *A, const mx_mesh *m, int cnx,
+                               int cny, int cnz, int nq, int combine) {
+  MX_GUARD({
+    MX_REQUIRE(P && A && m, "NULL argument");
+    mx::coarse_plan(P, A, m, box_spec(cnx, cny, cnz, nq), combine);
+  });
+}
+
+static void coarse_operators(const mx_mesh *m, const mx_matrix *A, const mx::CoarseSpec &cs,
+                             int64_t *n_coarse, int64_t *nnz_r, int64_t *nnz_a, int64_t *r_rowptr,
+                             int32_t *r_col, double *r_val, int64_t *a_rowptr, int32_t *a_col,
+                             double *a_val) {
+  MX_REQUIRE(A->h.n == m->ndof(A->order), "matrix and mesh sizes differ");
+  mx::Mesh cm;
+  mx::HostCSR R0, R0T, A0;
+  mx::coarse_restriction(m->m, cs, A->order, A->h.n, A->bc, cm, R0, R0T);
+  mx::galerkin_coarse(A->h, R0, R0T, cm, A->bc, A0);
+  const bool sizes_only = !r_rowptr && !r_col && !r_val && !a_rowptr && !a_col && !a_val;
+  if (!sizes_only) {
+    MX_REQUIRE(*n_coarse == R0.n && *nnz_r == R0.nnz() && *nnz_a == A0.nnz(),
+               "buffer sizes differ from the coarse operators' (query them first)");
+    if (r_rowptr) std::copy(R0.rowptr.begin(), R0.rowptr.end(), r_rowptr);
+    if (r_col) std::copy(R0.col.begin(), R0.col.end(), r_col);
+    if (r_val)
+      for (int64_t q = 0; q < R0.nnz(); ++q) r_val[q] = R0.val[2 * q];
+    if (a_rowptr) std::copy(A0.rowptr.begin(), A0.rowptr.end(), a_rowptr);
+    if (a_col) std::copy(A0.col.begin(), A0.col.end(), a_col);
+    if (a_val) std::copy(A0.val.begin(), A0.val.end(), a_val);
+  }
+  *n_coarse = R0.n;
+  *nnz_r = R0.nnz();
+  *nnz_a = A0.nnz();
 }
 
 int mx_coarse_operators(const mx_mesh *m, const mx_matrix *A, int ratio, int64_t *n_coarse,
@@ -547,33 +614,19 @@ int mx_coarse_operators(const mx_mesh *m, const mx_matrix *A, int ratio, int64_t
                         double *r_val, int64_t *a_rowptr, int32_t *a_col, double *a_val) {
   MX_GUARD({
     MX_REQUIRE(m && A && n_coarse && nnz_r && nnz_a, "NULL argument");
-    MX_REQUIRE(A->h.n == m->ndof(A->order), "matrix and mesh sizes differ");
-    MX_REQUIRE(ratio >= 1 && m->m.nx % ratio == 0 && m->m.ny % ratio == 0 && m->m.nz % ratio == 0,
-               "the coarse ratio must divide the cube count of every axis");
-    mx::Mesh cm;
-    mx::build_mesh(cm, m->m.nx / ratio, m->m.ny / ratio, m->m.nz / ratio, m->m.lx, m->m.ly, m->m.lz);
-    mx::HostCSR R0, R0T, A0;
-    mx::build_restriction(m->m, cm, ratio, A->bc, R0, R0T);
-    if (A->order == 2) {  // coarse Whitney functions have Whitney coefficients only
-      R0T.rowptr.resize(A->h.n + 1, R0T.rowptr.back());
-      R0T.n = A->h.n;
-    }
-    mx::galerkin_coarse(A->h, R0, R0T, cm, A->bc, A0);
-    const bool sizes_only = !r_rowptr && !r_col && !r_val && !a_rowptr && !a_col && !a_val;
-    if (!sizes_only) {
-      MX_REQUIRE(*n_coarse == R0.n && *nnz_r == R0.nnz() && *nnz_a == A0.nnz(),
-                 "buffer sizes differ from the coarse operators' (query them first)");
-      if (r_rowptr) std::copy(R0.rowptr.begin(), R0.rowptr.end(), r_rowptr);
-      if (r_col) std::copy(R0.col.begin(), R0.col.end(), r_col);
-      if (r_val)
-        for (int64_t q = 0; q < R0.nnz(); ++q) r_val[q] = R0.val[2 * q];
-      if (a_rowptr) std::copy(A0.rowptr.begin(), A0.rowptr.end(), a_rowptr);
-      if (a_col) std::copy(A0.col.begin(), A0.col.end(), a_col);
-      if (a_val) std::copy(A0.val.begin(), A0.val.end(), a_val);
-    }
-    *n_coarse = R0.n;
-    *nnz_r = R0.nnz();
-    *nnz_a = A0.nnz();
+    coarse_operators(m, A, ratio_spec(m, ratio), n_coarse, nnz_r, nnz_a, r_rowptr, r_col, r_val,
+                     a_rowptr, a_col, a_val);
+  });
+}
+
+int mx_coarse_operators_box(const mx_mesh *m, const mx_matrix *A, int cnx, int cny, int cnz, int nq,
+                            int64_t *n_coarse, int64_t *nnz_r, int64_t *nnz_a, int64_t *r_rowptr,
+                            int32_t *r_col, double *r_val, int64_t *a_rowptr, int32_t *a_col,
+                            double *a_val) {
+  MX_GUARD({
+    MX_REQUIRE(m && A && n_coarse && nnz_r && nnz_a, "NULL argument");
+    coarse_operators(m, A, box_spec(cnx, cny, cnz, nq), n_coarse, nnz_r, nnz_a, r_rowptr, r_col,
+                     r_val, a_rowptr, a_col, a_val);
   });
 }
 

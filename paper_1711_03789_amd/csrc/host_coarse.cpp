@@ -1,6 +1,14 @@
 // Coarse space of the two-level Schwarz preconditioners (Sec. 3.2, Sec. 3.3): the restriction
-// R^0 of eq:restriction from a nested coarse box mesh, and the coarse Galerkin matrix
+// R^0 of eq:restriction from a coarse box mesh, nested or not, and the coarse Galerkin matrix
 // A^0 = R^0 A (R^0)^T (eq:minor with l = 0).
+//
+// A coarse mesh that is not nested (Sec. 6.1: the coarse tetrahedra are not unions of fine
+// ones) gives integrands that are only piecewise affine along a fine edge; there the line
+// integral is taken with an nq-point Gauss-Legendre rule along the edge, as in the paper's runs,
+// which use a fixed number of quadrature points per edge.  The coarse tetrahedron holding a
+// quadrature point is read off the Kuhn split as below; a point on a face shared by two coarse
+// tetrahedra lies there only when the whole fine edge lies in that face, and then both give the
+// same tangential values.
 //
 // The coarse mesh has the same box and split with r times fewer cubes on every axis; each coarse
 // tetrahedron is then a union of fine ones.  A fine edge therefore lies in one closed coarse
@@ -13,7 +21,7 @@
 // tetrahedra the fine edge lies in that face, and both give the same tangential values.)
 #include <cmath>
 
-#include "mx_internal.hpp"
+#include "objects.hpp"
 
 namespace mx {
 
@@ -32,6 +40,196 @@ struct REnt {
   double v;
 };
 }  // namespace
+
+// R0^T (row j = fine edge j, columns = coarse edges ascending) and R0 from the per-edge lists
+// ent[off[j] .. off[j] + cnt[j+1]).
+static void restriction_csr(int64_t E, int64_t Ec, const std::vector<int64_t> &cnt,
+                            const std::vector<int64_t> &off, const std::vector<REnt> &ent,
+                            HostCSR &R0, HostCSR &R0T) {
+  R0T.n = E;
+  R0T.rowptr.assign(E + 1, 0);
+  for (int64_t j = 0; j < E; ++j) R0T.rowptr[j + 1] = R0T.rowptr[j] + cnt[j + 1];
+  const int64_t nnz = R0T.rowptr[E];
+  R0T.col.resize(nnz);
+  R0T.val.resize(2 * nnz);
+  for (int64_t j = 0; j < E; ++j)
+    for (int64_t q = R0T.rowptr[j], i = 0; q < R0T.rowptr[j + 1]; ++q, ++i) {
+      R0T.col[q] = ent[(size_t)off[j] + i].col;
+      R0T.val[2 * q] = ent[(size_t)off[j] + i].v;
+      R0T.val[2 * q + 1] = 0.0;
+    }
+  R0.n = Ec;
+  R0.rowptr.assign(Ec + 1, 0);
+  for (int64_t q = 0; q < nnz; ++q) ++R0.rowptr[R0T.col[q] + 1];
+  for (int64_t p = 0; p < Ec; ++p) R0.rowptr[p + 1] += R0.rowptr[p];
+  R0.col.resize(nnz);
+  R0.val.resize(2 * nnz);
+  std::vector<int64_t> fill(R0.rowptr.begin(), R0.rowptr.end() - 1);
+  for (int64_t j = 0; j < E; ++j)
+    for (int64_t q = R0T.rowptr[j]; q < R0T.rowptr[j + 1]; ++q) {
+      const int64_t d = fill[R0T.col[q]]++;
+      R0.col[d] = (int32_t)j;
+      R0.val[2 * d] = R0T.val[2 * q];
+      R0.val[2 * d + 1] = 0.0;
+    }
+}
+
+// Coarse tetrahedron of the Kuhn split holding the point with coarse-cube index c and local
+// coordinates u in [0,1]^3: its vertices v and the barycentric coordinates lam and their
+// gradients (coarse spacing H).
+static void coarse_tet_at(const Mesh &coarse, const int c[3], const double u[3], const double H[3],
+                          int32_t v[4], double lam[4], double grad[4][3]) {
+  int s[3] = {0, 1, 2};  // axes by decreasing u (ties: lower axis first)
+  for (int a = 0; a < 3; ++a)
+    for (int b = a + 1; b < 3; ++b)
+      if (u[s[b]] > u[s[a]]) std::swap(s[a], s[b]);
+  if (s[0] > s[1] && u[s[0]] == u[s[1]]) std::swap(s[0], s[1]);
+  if (s[1] > s[2] && u[s[1]] == u[s[2]]) std::swap(s[1], s[2]);
+  if (s[0] > s[1] && u[s[0]] == u[s[1]]) std::swap(s[0], s[1]);
+  if (perm_rank(s) < 0) fail(MX_EINVAL, "internal: bad permutation");
+  lam[0] = 1.0 - u[s[0]], lam[1] = u[s[0]] - u[s[1]], lam[2] = u[s[1]] - u[s[2]], lam[3] = u[s[2]];
+  for (int a = 0; a < 4; ++a)
+    for (int d = 0; d < 3; ++d) grad[a][d] = 0.0;
+  grad[0][s[0]] = -1.0 / H[s[0]];
+  grad[1][s[0]] = 1.0 / H[s[0]];
+  grad[1][s[1]] = -1.0 / H[s[1]];
+  grad[2][s[1]] = 1.0 / H[s[1]];
+  grad[2][s[2]] = -1.0 / H[s[2]];
+  grad[3][s[2]] = 1.0 / H[s[2]];
+  int p[3] = {c[0], c[1], c[2]};
+  v[0] = coarse.vid(p[0], p[1], p[2]);
+  for (int k = 0; k < 3; ++k) {
+    ++p[s[k]];
+    v[k + 1] = coarse.vid(p[0], p[1], p[2]);
+  }
+}
+
+// Nodes (on [0,1]) and weights (sum 1) of the n-point Gauss-Legendre rule: Newton's method on
+// the Legendre polynomial P_n from the usual cosine first guesses, weights 2/((1-x^2) P_n'(x)^2)
+// on [-1,1].
+static void gauss_legendre01(int n, std::vector<double> &s, std::vector<double> &w) {
+  s.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;  // P_0, P_1, then the three-term recurrence up to P_n
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1, p1 = p2;
+      }
+      if (n == 1) p1 = x, p0 = 1.0;
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1, p1 = p2;
+    }
+    if (n == 1) p1 = x, p0 = 1.0;
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+    s[n - 1 - i] = 0.5 * (x + 1.0);
+    w[n - 1 - i] = 1.0 / ((1.0 - x * x) * dp * dp);  // 2/((1-x^2)P'^2) on [-1,1], halved on [0,1]
+  }
+}
+
+void build_restriction_quad(const Mesh &fine, const Mesh &coarse, int bc, int nq, HostCSR &R0,
+                            HostCSR &R0T) {
+  if (nq < 1 || nq > 64) fail(MX_EINVAL, "quadrature points per fine edge must be 1 .. 64");
+  if (fine.lx != coarse.lx || fine.ly != coarse.ly || fine.lz != coarse.lz)
+    fail(MX_EINVAL, "coarse mesh is not a mesh of the fine mesh's box");
+  const int64_t E = fine.ne, Ec = coarse.ne;
+  const int nc[3] = {coarse.nx, coarse.ny, coarse.nz};
+  const double H[3] = {coarse.lx / coarse.nx, coarse.ly / coarse.ny, coarse.lz / coarse.nz};
+  std::vector<double> gs, gw;
+  gauss_legendre01(nq, gs, gw);
+  // fine edges in chunks; each chunk packs its edges' merged (coarse edge, value) lists
+  const int64_t cs = 4096, nchunk = (E + cs - 1) / cs;
+  std::vector<std::vector<REnt>> packed(nchunk);
+  std::vector<int64_t> cnt(E + 1, 0);
+  parallel_items(nchunk, [&](auto next) {
+    std::vector<REnt> acc;
+    for (int64_t ch; (ch = next()) >= 0;) {
+      auto &out = packed[ch];
+      for (int64_t j = ch * cs; j < std::min(E, (ch + 1) * cs); ++j) {
+        const int32_t lo = fine.edge_vert[2 * j], hi = fine.edge_vert[2 * j + 1];
+        double xl[3], xh[3], t[3];
+        fine.xyz(lo, xl);
+        fine.xyz(hi, xh);
+        for (int d = 0; d < 3; ++d) t[d] = xh[d] - xl[d];
+        acc.clear();
+        for (int q = 0; q < nq; ++q) {
+          int c[3];
+          double u[3];
+          for (int d = 0; d < 3; ++d) {
+            const double y = (xl[d] + gs[q] * t[d]) / H[d];
+            c[d] = std::min(std::max((int)std::floor(y), 0), nc[d] - 1);
+            u[d] = std::min(std::max(y - c[d], 0.0), 1.0);
+          }
+          int32_t v[4];
+          double lam[4], grad[4][3];
+          coarse_tet_at(coarse, c, u, H, v, lam, grad);
+          for (int le = 0; le < 6; ++le) {
+            const int a = kLocalEdge[le][0], b = kLocalEdge[le][1];
+            const int32_t ce = coarse.edge_id(std::min(v[a], v[b]), std::max(v[a], v[b]));
+            if (ce < 0) fail(MX_EINVAL, "internal: coarse edge not found");
+            if (bc == MX_BC_PEC && coarse.edge_on_boundary[ce]) continue;  // zero tangential trace
+            double wt = 0;
+            for (int d = 0; d < 3; ++d) wt += (lam[a] * grad[b][d] - lam[b] * grad[a][d]) * t[d];
+            if (v[a] > v[b]) wt = -wt;  // global orientation lo -> hi
+            acc.push_back({ce, gw[q] * wt});
+          }
+        }
+        // merge by coarse edge, summing in quadrature-point order
+        std::stable_sort(acc.begin(), acc.end(), [](const REnt &x, const REnt &y) { return x.col < y.col; });
+        int64_t n = 0;
+        for (size_t i = 0; i < acc.size();) {
+          size_t k = i;
+          double sum = 0;
+          for (; k < acc.size() && acc[k].col == acc[i].col; ++k) sum += acc[k].v;
+          if (sum != 0.0) out.push_back({acc[i].col, sum}), ++n;
+          i = k;
+        }
+        cnt[j + 1] = n;
+      }
+    }
+  });
+  std::vector<int64_t> off(E + 1, 0);
+  for (int64_t j = 0; j < E; ++j) off[j + 1] = off[j] + cnt[j + 1];
+  std::vector<REnt> ent((size_t)off[E]);
+  for (int64_t ch = 0; ch < nchunk; ++ch)
+    std::copy(packed[ch].begin(), packed[ch].end(), ent.begin() + off[ch * cs]);
+  restriction_csr(E, Ec, cnt, off, ent, R0, R0T);
+}
+
+void coarse_restriction(const Mesh &fine, const CoarseSpec &cs, int order, int64_t ndof, int bc,
+                        Mesh &coarse, HostCSR &R0, HostCSR &R0T) {
+  const int n[3] = {fine.nx, fine.ny, fine.nz};
+  for (int d = 0; d < 3; ++d)
+    if (cs.cn[d] < 1) fail(MX_EINVAL, "coarse cube counts must be >= 1");
+  if (cs.nq == 0) {  // nested: one ratio for every axis
+    const int r = n[0] / cs.cn[0];
+    for (int d = 0; d < 3; ++d)
+      if (n[d] % cs.cn[d] || n[d] / cs.cn[d] != r)
+        fail(MX_EINVAL, "the coarse ratio must divide the cube count of every axis");
+  } else if (order != 1) {
+    fail(MX_EINVAL, "order-2 coarse levels need the nested coarse mesh of a common ratio");
+  }
+  build_mesh(coarse, cs.cn[0], cs.cn[1], cs.cn[2], fine.lx, fine.ly, fine.lz);
+  if (cs.nq == 0) build_restriction(fine, coarse, n[0] / cs.cn[0], bc, R0, R0T);
+  else build_restriction_quad(fine, coarse, bc, cs.nq, R0, R0T);
+  if (ndof > R0T.n) {
+    // order 2: the coarse Whitney functions are piecewise lowest-order fields on the fine mesh,
+    // so in the hierarchical order-2 basis they have Whitney coefficients only: R^0 keeps its
+    // columns and its transpose gains empty rows for the gradient and face functions
+    R0T.rowptr.resize(ndof + 1, R0T.rowptr.back());
+    R0T.n = ndof;
+  }
+}
 
 void build_restriction(const Mesh &fine, const Mesh &coarse, int ratio, int bc, HostCSR &R0,
                        HostCSR &R0T) {
@@ -61,29 +259,9 @@ void build_restriction(const Mesh &fine, const Mesh &coarse, int ratio, int bc, 
         c[d] = std::min(twice / (2 * ratio), nc[d] - 1);
         u[d] = (double)(twice - 2 * ratio * c[d]) / (double)(2 * ratio);
       }
-      int s[3] = {0, 1, 2};  // axes by decreasing u (ties: lower axis first)
-      for (int a = 0; a < 3; ++a)
-        for (int b = a + 1; b < 3; ++b)
-          if (u[s[b]] > u[s[a]]) std::swap(s[a], s[b]);
-      if (s[0] > s[1] && u[s[0]] == u[s[1]]) std::swap(s[0], s[1]);
-      if (s[1] > s[2] && u[s[1]] == u[s[2]]) std::swap(s[1], s[2]);
-      if (s[0] > s[1] && u[s[0]] == u[s[1]]) std::swap(s[0], s[1]);
-      if (perm_rank(s) < 0) fail(MX_EINVAL, "internal: bad permutation");
-      const double lam[4] = {1.0 - u[s[0]], u[s[0]] - u[s[1]], u[s[1]] - u[s[2]], u[s[2]]};
-      double grad[4][3] = {};
-      grad[0][s[0]] = -1.0 / H[s[0]];
-      grad[1][s[0]] = 1.0 / H[s[0]];
-      grad[1][s[1]] = -1.0 / H[s[1]];
-      grad[2][s[1]] = 1.0 / H[s[1]];
-      grad[2][s[2]] = -1.0 / H[s[2]];
-      grad[3][s[2]] = 1.0 / H[s[2]];
       int32_t v[4];
-      int p[3] = {c[0], c[1], c[2]};
-      v[0] = coarse.vid(p[0], p[1], p[2]);
-      for (int k = 0; k < 3; ++k) {
-        ++p[s[k]];
-        v[k + 1] = coarse.vid(p[0], p[1], p[2]);
-      }
+      double lam[4], grad[4][3];
+      coarse_tet_at(coarse, c, u, H, v, lam, grad);
       REnt *out = &tmp[(size_t)j * 6];
       int n = 0;
       for (int le = 0; le < 6; ++le) {
@@ -102,34 +280,9 @@ void build_restriction(const Mesh &fine, const Mesh &coarse, int ratio, int bc, 
       cnt[j + 1] = n;
     }
   });
-  // R0^T: row j = fine edge j
-  R0T.n = E;
-  R0T.rowptr.assign(E + 1, 0);
-  for (int64_t j = 0; j < E; ++j) R0T.rowptr[j + 1] = R0T.rowptr[j] + cnt[j + 1];
-  const int64_t nnz = R0T.rowptr[E];
-  R0T.col.resize(nnz);
-  R0T.val.resize(2 * nnz);
-  for (int64_t j = 0; j < E; ++j)
-    for (int64_t q = R0T.rowptr[j], i = 0; q < R0T.rowptr[j + 1]; ++q, ++i) {
-      R0T.col[q] = tmp[(size_t)j * 6 + i].col;
-      R0T.val[2 * q] = tmp[(size_t)j * 6 + i].v;
-      R0T.val[2 * q + 1] = 0.0;
-    }
-  // R0 = transpose (rows = coarse edges, columns = fine edges ascending)
-  R0.n = Ec;
-  R0.rowptr.assign(Ec + 1, 0);
-  for (int64_t q = 0; q < nnz; ++q) ++R0.rowptr[R0T.col[q] + 1];
-  for (int64_t p = 0; p < Ec; ++p) R0.rowptr[p + 1] += R0.rowptr[p];
-  R0.col.resize(nnz);
-  R0.val.resize(2 * nnz);
-  std::vector<int64_t> fill(R0.rowptr.begin(), R0.rowptr.end() - 1);
-  for (int64_t j = 0; j < E; ++j)
-    for (int64_t q = R0T.rowptr[j]; q < R0T.rowptr[j + 1]; ++q) {
-      const int64_t d = fill[R0T.col[q]]++;
-      R0.col[d] = (int32_t)j;
-      R0.val[2 * d] = R0T.val[2 * q];
-      R0.val[2 * d + 1] = 0.0;
-    }
+  std::vector<int64_t> off(E + 1);
+  for (int64_t j = 0; j <= E; ++j) off[j] = 6 * j;
+  restriction_csr(E, Ec, cnt, off, tmp, R0, R0T);
 }
 
 // Sparse product of complex CSR matrices, row-parallel: C = X Y (rows of X, columns of Y).

@@ -325,7 +325,8 @@ void matrix_upload(mx_matrix *A) {
 // the coarse mesh whose matrix is A^0 (its minor over every coarse edge is A^0 itself), so
 // G v = R^0^T (A^0)^-1 R^0 v is an SpMV, that application, and an SpMV.
 struct CoarseLevel {
-  int ratio = 0, combine = MX_COARSE_ADDITIVE;
+  CoarseSpec spec;
+  int combine = MX_COARSE_ADDITIVE;
   mx_mesh mesh;                    // coarse box mesh
   mx_partition part;               // one subdomain, no overlap
   mx_matrix R0, R0T, A0;           // restriction (coarse x fine), its transpose, coarse matrix
@@ -383,30 +384,21 @@ void precond_apply(mx_precond *P, const void *vin, void *zout, hipStream_t st) {
 }
 
 // Host half: coarse mesh, R^0, A^0 = R^0 A R^0^T, and the plan of the coarse factorisation.
-void coarse_plan(mx_precond *P, const mx_matrix *A, const mx_mesh *mh, int ratio, int combine) {
+void coarse_plan(mx_precond *P, const mx_matrix *A, const mx_mesh *mh, const CoarseSpec &cs,
+                 int combine) {
   const Mesh &m = mh->m;
   if (P->coarse) fail(MX_EINVAL, "preconditioner already has a coarse level");
   if (P->share) fail(MX_EINVAL, "a resident share cannot have a coarse level");
   if (combine < MX_COARSE_ADDITIVE || combine > MX_COARSE_DEFLATION) fail(MX_EINVAL, "unknown coarse combination");
-  if (ratio < 1 || m.nx % ratio || m.ny % ratio || m.nz % ratio)
-    fail(MX_EINVAL, "the coarse ratio must divide the cube count of every axis");
   if (A->h.n != P->E || A->order != P->order || mh->ndof(P->order) != P->E)
     fail(MX_EINVAL, "matrix, mesh and preconditioner sizes differ");
   if (A->weight || A->k != P->k || A->xi != P->xi_prec || A->bc != P->bc)
     fail(MX_EINVAL, "the matrix is not the one the preconditioner was built for (k, xi_prec, bc)");
   auto C = std::make_unique<CoarseLevel>();
-  C->ratio = ratio;
+  C->spec = cs;
   C->combine = combine;
   C->A = A;
-  build_mesh(C->mesh.m, m.nx / ratio, m.ny / ratio, m.nz / ratio, m.lx, m.ly, m.lz);
-  build_restriction(m, C->mesh.m, ratio, A->bc, C->R0.h, C->R0T.h);
-  if (A->order == 2) {
-    // the coarse Whitney functions are piecewise lowest-order fields on the fine mesh, so in the
-    // hierarchical order-2 basis they have Whitney coefficients only: R^0 keeps its columns and
-    // its transpose gains empty rows for the gradient and face functions
-    C->R0T.h.rowptr.resize(P->E + 1, C->R0T.h.rowptr.back());
-    C->R0T.h.n = P->E;
-  }
+  coarse_restriction(m, cs, A->order, P->E, A->bc, C->mesh.m, C->R0.h, C->R0T.h);
   galerkin_coarse(A->h, C->R0.h, C->R0T.h, C->mesh.m, A->bc, C->A0.h);
   for (mx_matrix *X : {&C->R0, &C->R0T, &C->A0}) X->k = A->k, X->xi = A->xi, X->bc = A->bc;
   build_partition(C->mesh.m, 1, 1, 1, nullptr, nullptr, nullptr, 0, C->part.p);
@@ -447,16 +439,16 @@ void coarse_materialize(mx_ctx *ctx, mx_precond *P, hipStream_t st) {
   C.ready = true;
 }
 
-void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *mh, int ratio,
-                  int combine, hipStream_t st) {
+void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *mh,
+                  const CoarseSpec &cs, int combine, hipStream_t st) {
   if (P->coarse) {  // planned earlier: the arguments must be the same
     const CoarseLevel &C = *P->coarse;
     if (C.ready) fail(MX_EINVAL, "preconditioner already has a coarse level");
-    if (C.A != A || C.ratio != ratio || C.combine != combine || C.mesh.m.ne == 0 ||
+    if (C.A != A || !(C.spec == cs) || C.combine != combine || C.mesh.m.ne == 0 ||
         mh->ndof(P->order) != P->E)
       fail(MX_EINVAL, "arguments differ from those the coarse level was planned with");
   } else {
-    coarse_plan(P, A, mh, ratio, combine);
+    coarse_plan(P, A, mh, cs, combine);
   }
   try {
     coarse_materialize(ctx, P, st);

@@ -287,15 +287,32 @@ void batch_apply(int njobs, const int *slots, mx_precond *const *Ps, const void 
 // coarse level (Sec. 3.2, 3.3): R^0 and A^0 = R^0 A R^0^T on the host (host_coarse.cpp)
 void build_restriction(const Mesh &fine, const Mesh &coarse, int ratio, int bc, HostCSR &R0,
                        HostCSR &R0T);
+// any coarse box mesh of the same box: each fine DOF by an nq-point Gauss rule along the edge
+void build_restriction_quad(const Mesh &fine, const Mesh &coarse, int bc, int nq, HostCSR &R0,
+                            HostCSR &R0T);
+// the coarse mesh of a coarse level: cn cubes per axis; nq = 0 for the nested mesh of a common
+// ratio (exact midpoint values), else the quadrature points per fine edge
+struct CoarseSpec {
+  int cn[3] = {0, 0, 0};
+  int nq = 0;
+  bool operator==(const CoarseSpec &o) const {
+    return cn[0] == o.cn[0] && cn[1] == o.cn[1] && cn[2] == o.cn[2] && nq == o.nq;
+  }
+};
+// validates a spec against the fine mesh (and the element order) and builds R^0 and its
+// transpose with the order's column count
+void coarse_restriction(const Mesh &fine, const CoarseSpec &cs, int order, int64_t ndof, int bc,
+                        Mesh &coarse, HostCSR &R0, HostCSR &R0T);
 void galerkin_coarse(const HostCSR &A, const HostCSR &R0, const HostCSR &R0T, const Mesh &coarse,
                      int bc, HostCSR &A0);
 // host half of a coarse level (R^0, A^0, plan of its factorisation), attached to P but not usable
 // until coarse_setup builds its device half (krylov.hip)
-void coarse_plan(mx_precond *P, const mx_matrix *A, const mx_mesh *m, int ratio, int combine);
+void coarse_plan(mx_precond *P, const mx_matrix *A, const mx_mesh *m, const CoarseSpec &cs,
+                 int combine);
 bool coarse_incomplete(const mx_precond *P);
 // attaches a coarse level to the materialised one-level P built from A, or completes a planned one
-void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m, int ratio,
-                  int combine, hipStream_t st);
+void coarse_setup(mx_ctx *ctx, mx_precond *P, const mx_matrix *A, const mx_mesh *m,
+                  const CoarseSpec &cs, int combine, hipStream_t st);
 // host copies of R^0 and A^0 (sizes when the arrays are NULL)
 void coarse_export(const mx_precond *P, int64_t *n_coarse, int64_t *nnz_r, int64_t *nnz_a,
                    int64_t *r_rowptr, int32_t *r_col, double *r_val, int64_t *a_rowptr,

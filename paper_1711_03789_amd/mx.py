@@ -36,7 +36,8 @@ SYMBOLS = [
     "mx_coarse_operators", "mx_weight_assemble", "mx_gmres_weighted", "mx_precond_plan_coarse",
     "mx_precond_tune_factor", "mx_server_batch_stats", "mx_matrix_assemble_order",
     "mx_mesh_order2_sizes", "mx_mesh_order2_export", "mx_partition_order2_export",
-    "mx_weight_assemble_order",
+    "mx_weight_assemble_order", "mx_precond_add_coarse_box", "mx_precond_plan_coarse_box",
+    "mx_coarse_operators_box",
 ]
 
 
@@ -167,6 +168,10 @@ def load(path=LIB_PATH):
                                              C.POINTER(C.c_int32), C.POINTER(C.c_double), P]),
         "mx_precond_coarse_export": (C.c_int, [P] + [C.POINTER(C.c_int64)] * 3 + [P] * 6),
         "mx_coarse_operators": (C.c_int, [P, P, C.c_int] + [C.POINTER(C.c_int64)] * 3 + [P] * 6),
+        "mx_coarse_operators_box": (C.c_int, [P, P] + [C.c_int] * 4 + [C.POINTER(C.c_int64)] * 3
+                                    + [P] * 6),
+        "mx_precond_add_coarse_box": (C.c_int, [P, P, P, P] + [C.c_int] * 5 + [P]),
+        "mx_precond_plan_coarse_box": (C.c_int, [P, P, P] + [C.c_int] * 5),
         "mx_precond_autotune": (C.c_int, [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "mx_server_create": (C.c_int, [C.c_int, C.POINTER(ServerOpts), C.POINTER(P)]),
         "mx_server_submit": (C.c_int, [P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
@@ -424,9 +429,14 @@ def _coarse_csr(fn, n_fine):
             sp.csr_matrix((av, ac, ap), shape=(n.value, n.value)))
 
 
-def coarse_operators(mesh, A, ratio):
-    """Host-only (R0, A0) of the coarse level for A on mesh (mx_coarse_operators)."""
+def coarse_operators(mesh, A, ratio=None, box=None, nq=12):
+    """Host-only (R0, A0) of the coarse level for A on mesh: the nested mesh of `ratio`
+    (mx_coarse_operators) or a coarse box mesh of box = (cnx, cny, cnz) cubes with an nq-point
+    rule per fine edge (mx_coarse_operators_box)."""
     load()
+    if box is not None:
+        return _coarse_csr(lambda *a: _lib.mx_coarse_operators_box(mesh.h, A.h, *map(int, box),
+                                                                   int(nq), *a), A.n)
     return _coarse_csr(lambda *a: _lib.mx_coarse_operators(mesh.h, A.h, int(ratio), *a), A.n)
 
 
@@ -494,16 +504,26 @@ class Precond:
     def check(self):
         _check(_lib.mx_precond_check(self.h))
 
-    def add_coarse(self, ctx, A, mesh, ratio, combine="additive", stream=None):
-        """Two-level form (mx_precond_add_coarse); A and mesh are the ones P was built from."""
-        _check(_lib.mx_precond_add_coarse(ctx.h, self.h, A.h, mesh.h, int(ratio),
-                                          COARSE.get(combine, combine), _stream(stream)))
+    def add_coarse(self, ctx, A, mesh, ratio=None, combine="additive", stream=None, box=None, nq=12):
+        """Two-level form; A and mesh are the ones P was built from.  The nested coarse mesh of
+        `ratio` (mx_precond_add_coarse) or a coarse box mesh of box = (cnx, cny, cnz) cubes with
+        an nq-point rule per fine edge (mx_precond_add_coarse_box)."""
+        if box is not None:
+            _check(_lib.mx_precond_add_coarse_box(ctx.h, self.h, A.h, mesh.h, *map(int, box), int(nq),
+                                                  COARSE.get(combine, combine), _stream(stream)))
+        else:
+            _check(_lib.mx_precond_add_coarse(ctx.h, self.h, A.h, mesh.h, int(ratio),
+                                              COARSE.get(combine, combine), _stream(stream)))
         self._coarse_A = A  # the library borrows A
 
-    def plan_coarse(self, A, mesh, ratio, combine="additive"):
-        """Host half of add_coarse (mx_precond_plan_coarse); any host thread."""
-        _check(_lib.mx_precond_plan_coarse(self.h, A.h, mesh.h, int(ratio),
-                                           COARSE.get(combine, combine)))
+    def plan_coarse(self, A, mesh, ratio=None, combine="additive", box=None, nq=12):
+        """Host half of add_coarse (mx_precond_plan_coarse[_box]); any host thread."""
+        if box is not None:
+            _check(_lib.mx_precond_plan_coarse_box(self.h, A.h, mesh.h, *map(int, box), int(nq),
+                                                   COARSE.get(combine, combine)))
+        else:
+            _check(_lib.mx_precond_plan_coarse(self.h, A.h, mesh.h, int(ratio),
+                                               COARSE.get(combine, combine)))
         self._coarse_A = A
 
     def coarse_export(self):

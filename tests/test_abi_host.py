@@ -378,3 +378,39 @@ def test_weight_matrix_matches_oracle(bc):
         O = fem.weight_matrix(om, k, bc)
         assert not np.any(val.imag)
         assert abs(L - O).max() <= 1e-14 * abs(O).max()
+
+
+@pytest.mark.parametrize("bc", [mx.MX_BC_IMPEDANCE, mx.MX_BC_PEC])
+def test_coarse_operators_non_nested_match_oracle(bc):
+    """Coarse box meshes that are not nested in the fine one: the library's R^0 (nq-point Gauss
+    rule per fine edge, closed-form point location in the Kuhn split) and A^0 equal the oracle's
+    (generic barycentric search); on a nested mesh the quadrature gives the midpoint values."""
+    from oracle import coarse
+    L = (1.0, 0.9, 1.2)
+    n, cn = (7, 5, 6), (3, 2, 4)
+    om, lm = OMesh(*n, *L), mx.Mesh(*n, *L)
+    k, xi = 4.0, 4.0
+    A = mx.Matrix(None, lm, k, xi, bc)
+    oA = fem.assemble(om, k, xi, bc)
+    oc = coarse.coarse_box_mesh(om, cn)
+    keep = coarse.coarse_dofs(oc, bc)
+    for nq in (3, 12):
+        R, A0 = mx.coarse_operators(lm, A, box=cn, nq=nq)
+        oR = coarse.restriction_quadrature(om, oc, bc, nq)
+        assert R.shape == (oc.n_edge, om.n_edge)
+        assert abs(R[keep] - oR).max() <= 1e-13 * abs(oR).max()
+        oA0 = (oR @ oA @ oR.T).tocsr()
+        assert abs(A0[keep][:, keep] - oA0).max() <= 1e-12 * abs(oA0).max()
+    # nested mesh through the quadrature entry: the exact midpoint values
+    n2 = (6, 4, 8)
+    lm2 = mx.Mesh(*n2, *L)
+    A2 = mx.Matrix(None, lm2, k, xi, bc)
+    Rn, _ = mx.coarse_operators(lm2, A2, ratio=2)
+    Rq, _ = mx.coarse_operators(lm2, A2, box=(3, 2, 4), nq=5)
+    assert abs(Rq - Rn).max() <= 1e-14 * abs(Rn).max()
+    # order 2 needs the nested mesh
+    A3 = mx.Matrix(None, lm2, k, xi, bc, order=2)
+    with pytest.raises(mx.MxError):
+        mx.coarse_operators(lm2, A3, box=(3, 2, 4), nq=5)
+    with pytest.raises(mx.MxError):
+        mx.coarse_operators(lm, A, box=(3, 2, 4), nq=0)

@@ -6,7 +6,9 @@ C ABI against the oracle (oracle/coarse.py) on the same seeded inputs:
 * single applications of every form -- AS2 (eq:defAS), RAS2 (eq:RAS2), ImpRAS2, hybrid (eq:HRAS)
   and deflated (eq:ADEF1ras) with RAS and ImpRAS -- to 1e-10 relative;
 * GMRES with the two-level forms: iterations within +-1 of the oracle's, and after exactly the
-  oracle's iteration count the solution within 1e-8 relative L2."""
+  oracle's iteration count the solution within 1e-8 relative L2;
+* the same with coarse box meshes that are not nested in the fine one (R^0 by a 12-point Gauss
+  rule along each fine edge)."""
 import sys
 
 import numpy as np
@@ -173,3 +175,54 @@ def test_two_level_planned_on_another_thread(gpu_lib, ctx):
     ref.apply(vd, z1)
     P.apply(vd, z2)
     assert np.array_equal(host(z1), host(z2))
+
+
+class BoxCase:
+    """Two-level with a coarse box mesh that is not nested in the fine one (R^0 by a 12-point
+    Gauss rule per fine edge)."""
+
+    def __init__(self, mx, ctx, n, parts, layers, k, xi, kind, cn, combine, nq=12):
+        self.om = OMesh(*n)
+        self.oA = fem.assemble(self.om, k, xi)
+        op = dd.Partition(self.om, *parts, layers)
+        oc = coarse.coarse_box_mesh(self.om, cn)
+        oR = coarse.restriction_quadrature(self.om, oc, fem.BC_IMPEDANCE, nq)
+        self.oB = coarse.TwoLevel(dd.Schwarz(op, self.oA, OKIND[kind], k, xi), self.oA, oR,
+                                  COMB[combine])
+        self.lm = mx.Mesh(*n)
+        self.lA = mx.Matrix(ctx, self.lm, k, xi)
+        self.lP = mx.Precond(ctx, self.lA, self.lm, mx.Partition(self.lm, *parts, layers), kind)
+        self.lP.add_coarse(ctx, self.lA, self.lm, combine=combine, box=cn, nq=nq)
+        self.E = self.om.n_edge
+
+
+@pytest.mark.parametrize("combine", ["additive", "hybrid", "deflation"])
+def test_two_level_non_nested_apply(gpu_lib, ctx, combine):
+    say("two-level apply, non-nested coarse mesh", combine)
+    c = BoxCase(gpu_lib, ctx, (12, 12, 12), (3, 3, 3), 2, 5.0, 5.0, "oras", (5, 5, 5), combine)
+    v = random_rhs(c.E, 13)
+    vd, zd = dev(v), dev(np.zeros(c.E))
+    c.lP.apply(vd, zd)
+    c.lP.check()
+    z = host(zd)
+    ref = c.oB(v)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say("  rel err", err)
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("kind,combine", [("oras", "hybrid"), ("ras", "deflation")])
+def test_two_level_non_nested_gmres(gpu_lib, ctx, kind, combine):
+    say("two-level GMRES, non-nested coarse mesh", kind, combine)
+    c = BoxCase(gpu_lib, ctx, (16, 16, 16), (4, 4, 4), 2, 6.0, 6.0, kind, (7, 7, 7), combine)
+    f = random_rhs(c.E, 14)
+    ores = gmres.gmres(c.oA, f, c.oB, restart=100, rtol=1e-6)
+    bd, xd = dev(f), dev(np.zeros(c.E))
+    st = gpu_lib.gmres(ctx, c.lA, c.lP, bd, xd, restart=100, rtol=1e-6)
+    say("  iterations gpu", st["iters"], "oracle", ores.iters)
+    assert st["converged"] and abs(st["iters"] - ores.iters) <= 1
+    xd2 = dev(np.zeros(c.E))
+    gpu_lib.gmres(ctx, c.lA, c.lP, bd, xd2, restart=100, fixed_iters=ores.iters)
+    err = np.linalg.norm(host(xd2) - ores.x) / np.linalg.norm(ores.x)
+    say("  rel L2 at the oracle's count", err)
+    assert err <= 1e-8

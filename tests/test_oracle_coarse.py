@@ -117,3 +117,38 @@ def test_paper_ordering_two_level_beats_one_level():
         for comb in combos:
             two = gmres.gmres(A, b, coarse.TwoLevel(B1, A, R, comb), restart=100, rtol=1e-6).iters
             assert two < one, (kind, comb, one, two)
+
+
+@pytest.mark.parametrize("bc", [fem.BC_IMPEDANCE, fem.BC_PEC])
+def test_quadrature_restriction_equals_midpoint_rule_on_nested_meshes(bc):
+    """On a nested coarse mesh the coarse Whitney functions are affine along every fine edge, so
+    the Gauss rule of restriction_quadrature gives the exact values of restriction() for any
+    number of points."""
+    fine = Mesh(6, 4, 8, 1.0, 0.8, 1.2)
+    cm = coarse.coarse_mesh(fine, 2)
+    R = coarse.restriction(fine, cm, bc)
+    for nq in (1, 3, 12):
+        Rq = coarse.restriction_quadrature(fine, cm, bc, nq)
+        assert Rq.shape == R.shape
+        assert abs(Rq - R).max() <= 1e-14 * abs(R).max()
+
+
+@pytest.mark.parametrize("fine_n,coarse_n", [((7, 5, 6), (3, 2, 4)), ((9, 9, 9), (4, 4, 4))])
+def test_quadrature_restriction_maps_coarse_to_fine_interpolants(fine_n, coarse_n):
+    """On coarse meshes that are not nested, (R^0)^T still carries the coarse interpolant of a
+    field a + b x x -- which the coarse Whitney space holds exactly -- to the fine interpolant
+    of the same field: the integrand along every fine edge is then that affine field itself."""
+    L = (1.0, 0.9, 1.1)
+    fine, cm = Mesh(*fine_n, *L), coarse.coarse_box_mesh(Mesh(*fine_n, *L), coarse_n)
+    R = coarse.restriction_quadrature(fine, cm, fem.BC_IMPEDANCE, 12)
+    rng = np.random.default_rng(sum(fine_n))
+    for _ in range(2):
+        a = rng.standard_normal(3)
+        b = rng.standard_normal(3)
+        F = lambda x, a=a, b=b: a[None, :] + np.cross(b[None, :], x)
+        vH = fem.interpolate(cm, F)
+        vh = fem.interpolate(fine, F)
+        assert np.allclose(R.T @ vH, vh, rtol=0, atol=1e-12 * np.abs(vh).max())
+    # a field that is not in the coarse space does not come back exactly (the test can fail)
+    Fq = lambda x: np.stack([x[:, 1] ** 2, 0 * x[:, 0], 0 * x[:, 0]], 1)
+    assert not np.allclose(R.T @ fem.interpolate(cm, Fq), fem.interpolate(fine, Fq), atol=1e-6)
