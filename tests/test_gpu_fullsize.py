@@ -13,7 +13,9 @@ The oracle cannot solve the whole problem in test time, so the checks are:
   the oracle's.  Bar: 1e-10 relative.  The oracle's local problems are factored in parallel on
   host worker processes;
 * a property at full size: GMRES's reported convergence holds for the oracle's matrix, i.e. the
-  true relative residual computed with the oracle's A is <= rtol."""
+  true relative residual computed with the oracle's A is <= rtol;
+* the two-level deflated form with the 16^3-cube coarse mesh: the oracle's coarse correction at
+  full size plus sampled local solves against the library's application."""
 import sys
 import time
 
@@ -152,3 +154,39 @@ def test_gmres_fullsize_true_residual(gpu_lib, big):
     say("  iterations", st["iters"], "reported", st["relres_true"], "oracle residual", rel)
     assert st["converged"] and rel <= 1e-6
     assert abs(rel - st["relres_true"]) <= 1e-9
+
+
+@pytest.mark.timeout(1200)
+def test_fullsize_two_level_deflation_sampled(gpu_lib, big):
+    """The two-level deflated form (eq:ADEF1ras) over ORAS at xi = k on the 64^3 problem, with the
+    nested coarse mesh of 16^3 cubes, as `bench.py --coarse 4 --combine deflation` runs it.  With
+    the Boolean partition of unity, B v = B1 t + G v with t = v - A G v and G v = R^0^T (A^0)^-1
+    R^0 v, so on the DOFs owned by subdomain l, (B v)_e = x_l[e] + (G v)_e with x_l the local
+    solve of t.  The oracle computes G v exactly at full size (its R^0, A^0 = R^0 A R^0^T and a
+    sparse LU of A^0) and the local solves of a corner (0) and the last subdomain (63).
+    Bar: 1e-10 relative."""
+    from oracle import coarse
+    mx, b, op, om = gpu_lib, big, big["op"], big["om"]
+    xi = K
+    v = random_rhs(b["E"], 9)
+    lA = mx.Matrix(b["ctx"], b["lm"], K, xi)
+    P = mx.Precond(b["ctx"], lA, b["lm"], b["lp"], "oras")
+    P.add_coarse(b["ctx"], lA, b["lm"], 4, "deflation")
+    z = _host_apply(P, v)
+    del P
+    t0 = time.time()
+    oA = b["oA"](xi)
+    R = coarse.restriction(om, coarse.coarse_mesh(om, 4))
+    lu0 = dd.factor_local((R @ oA @ R.T).tocsc())
+    Gv = R.T @ lu0.solve(R @ v)
+    t = v - oA @ Gv
+    say("oracle coarse correction at full size: %d coarse DOFs, %.1f s" % (R.shape[0], time.time() - t0))
+    tasks = [(dd.local_matrix(op, None, dd.ORAS, K, xi, l), t[op.oras_sets[l]]) for l in (0, 63)]
+    res = pool.solve_many(tasks)
+    for l, (x, _, _) in zip((0, 63), res):
+        idx = op.oras_sets[l]
+        own = op.pou(l, dd.ORAS) > 0
+        want = x[own] + Gv[idx[own]]
+        err = np.max(np.abs(z[idx[own]] - want)) / np.max(np.abs(want))
+        say("  ADEF1-ORAS xi %g l %d owned %d: max rel err %.2e" % (xi, l, int(own.sum()), err))
+        assert err <= 1e-10
