@@ -414,3 +414,29 @@ def test_coarse_operators_non_nested_match_oracle(bc):
         mx.coarse_operators(lm2, A3, box=(3, 2, 4), nq=5)
     with pytest.raises(mx.MxError):
         mx.coarse_operators(lm, A, box=(3, 2, 4), nq=0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_randomised_coarse_box_operators(seed):
+    """Seeded random fine and coarse boxes (coarser or finer, nested or not), quadrature orders
+    and boundary conditions: the library's R^0 and A^0 equal the oracle's."""
+    from oracle import coarse
+    rng = np.random.default_rng(200 + seed)
+    n = tuple(int(v) for v in rng.integers(2, 7, 3))
+    cn = tuple(int(v) for v in rng.integers(1, 5, 3))
+    L = tuple(float(v) for v in rng.uniform(0.5, 1.5, 3))
+    nq = int(rng.integers(1, 13))
+    bc = int(rng.integers(0, 2))
+    k, xi = float(rng.uniform(1, 6)), float(rng.uniform(0.5, 20))
+    om, lm = OMesh(*n, *L), mx.Mesh(*n, *L)
+    A = mx.Matrix(None, lm, k, xi, bc)
+    R, A0 = mx.coarse_operators(lm, A, box=cn, nq=nq)
+    oc = coarse.coarse_box_mesh(om, cn)
+    keep = coarse.coarse_dofs(oc, bc)
+    oR = coarse.restriction_quadrature(om, oc, bc, nq)
+    if oR.nnz == 0:
+        assert R[keep].count_nonzero() == 0
+        return
+    assert abs(R[keep] - oR).max() <= 1e-13 * abs(oR).max()
+    oA0 = (oR @ fem.assemble(om, k, xi, bc) @ oR.T).tocsr()
+    assert abs(A0[keep][:, keep] - oA0).max() <= 1e-12 * max(abs(oA0).max(), 1e-300)

@@ -115,3 +115,40 @@ def test_weight_matrix_order2(bc):
         O = order2.weight_matrix(S, k, bc)
         assert not np.any(L.data.imag)
         assert abs(L - O).max() <= 1e-14 * abs(O).max()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_randomised_boxes_order2(seed):
+    """Seeded random boxes (cube counts, side lengths, partitions with jittered cuts, layers,
+    boundary condition, k and xi): the order-2 numbering, owners and sets bit-exact, and the
+    matrix and one local problem of each kind equal to the oracle's to rounding."""
+    rng = np.random.default_rng(100 + seed)
+    n = tuple(int(v) for v in rng.integers(2, 6, 3))
+    L = tuple(float(v) for v in rng.uniform(0.5, 1.5, 3))
+    parts = tuple(int(min(v, c)) for v, c in zip(rng.integers(1, 3, 3), n))
+    layers = int(rng.integers(0, 3))
+    bc = int(rng.integers(0, 2))
+    k, xi = float(rng.uniform(1, 6)), float(rng.uniform(-10, 30))
+    cuts = [jittered_cuts(c, p, 0.3, seed + a) for a, (c, p) in enumerate(zip(n, parts))]
+    om, lm = OMesh(*n, *L), mx.Mesh(*n, *L)
+    S = order2.Space(om)
+    assert np.array_equal(lm.order2()["face_vert"], S.face_vert)
+    L2 = _csr(mx.Matrix(None, lm, k, xi, bc, order=2))
+    O2 = order2.assemble(S, k, xi, bc)
+    assert abs(L2 - O2).max() <= 1e-14 * abs(O2).max()
+    op = dd.Partition(om, *parts, layers, *cuts)
+    lp = mx.Partition(lm, *parts, layers, *cuts)
+    p2 = order2.Partition(S, op)
+    A = mx.Matrix(None, lm, k, xi, bc, order=2)
+    l = int(rng.integers(0, op.N))
+    for kind, okind in (("as", dd.AS), ("oras", dd.ORAS)):
+        ex = lp.export_order2(lm, kind)
+        assert np.array_equal(ex["owner"], p2.owner)
+        for q in range(op.N):
+            assert np.array_equal(ex["sets"][q], p2.local_set(okind)[q])
+        if len(p2.local_set(okind)[l]) == 0:
+            continue
+        loc = mx.local_problem(lm, A, lp, l, kind=kind, xi_prec=xi)
+        Lc = sp.csr_matrix((loc["val"], loc["col"], loc["rowptr"]), shape=(len(loc["perm"]),) * 2)
+        Oc = order2.local_matrix(p2, O2, okind, k, xi, l, bc)
+        assert abs(Lc - Oc).max() <= 1e-14 * max(abs(Oc).max(), 1.0)
