@@ -189,6 +189,57 @@ def cpu_baseline(total_iters, n_inst):
                          "/".join("%.3f" % t_sv[c] for c in classes))}
 
 
+def cpu_baseline_order2(total_iters, n_inst):
+    """The oracle (NumPy/SciPy FP64) on a bounded sample of the order-2 workload (24^3 cubes,
+    4x4x4 subdomains, 1 layer, k = 12):
+    * the order-2 space and global assembly of the whole box, one thread;
+    * the ORAS local problems of one subdomain of each class (corner, edge, face, interior),
+      assembled by the oracle, then factored (SuperLU) and solved once each on a pool of worker
+      processes.
+    Estimated seconds per solve = T_global + sum_c n_c (T_local_c + T_lu_c) / W
+    + iterations * sum_c n_c T_solve_c / W, with the class counts n_c = 8, 24, 24, 8 and the GPU
+    run's mean iteration count (the coarse level's solves, on 604 coarse DOFs, are left out)."""
+    from threadpoolctl import threadpool_limits
+
+    import numpy as np
+
+    from mx_inputs import config_order2, random_rhs
+    from oracle import dd, order2, pool
+    from oracle.mesh import Mesh as OMesh
+    w = config_order2()
+    classes = {"corner": 0, "edge": 1, "face": 5, "interior": 21}
+    counts = {"corner": 8, "edge": 24, "face": 24, "interior": 8}
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        om = OMesh(*w.n, *w.lengths)
+        S = order2.Space(om)
+        order2.assemble(S, w.k, w.xi)
+        part = dd.Partition(om, *w.parts, w.layers)
+        p2 = order2.Partition(S, part)
+        t_global = time.perf_counter() - t0
+        tasks, t_loc = [], {}
+        for name, l in classes.items():
+            t1 = time.perf_counter()
+            Al = order2.local_matrix(p2, None, dd.ORAS, w.k, w.xi, l)
+            t_loc[name] = time.perf_counter() - t1
+            tasks.append((Al, random_rhs(Al.shape[0], l)))
+    W = min(pool.default_workers(), 16)
+    t2 = time.perf_counter()
+    res = pool.solve_many(tasks, workers=W)
+    t_pool = time.perf_counter() - t2
+    t_lu = {c: r[1] for c, r in zip(classes, res)}
+    t_sv = {c: r[2] for c, r in zip(classes, res)}
+    iters = total_iters / max(n_inst, 1)
+    per_solve = (t_global + sum(counts[c] * (t_loc[c] + t_lu[c]) for c in classes) / W
+                 + iters * sum(counts[c] * t_sv[c] for c in classes) / W)
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": W, "kind": "oracle",
+            "sample": "oracle order-2 space and assembly of the whole 24^3 box (%.1f s, one thread); "
+                      "ORAS local problems of one subdomain per class (corner, edge, face, interior), "
+                      "assembled, factored (SuperLU) and solved on a pool (%.1f s wall); scaled to "
+                      "the 8/24/24/8 class counts over %d workers with the GPU run's mean of %.0f "
+                      "iterations: per-solve estimate %.1f s" % (t_global, t_pool, W, iters, per_solve)}
+
+
 def cpu_baseline_batching(w, iters, n_sample=8, seed=11):
     """The oracle (NumPy/SciPy FP64) on a bounded sample of the 96x96x192 jittered-box problem:
     * n_sample subdomains drawn at random (seeded) from the 432: each one's ORAS local problem is
@@ -810,9 +861,8 @@ def main():
         del P, A
     if order == 2:
         out["order"] = 2
-        out["cpu_baseline"] = None
-        out["cpu_baseline_note"] = ("not taken for this secondary line: the oracle's order-2 "
-                                    "local problems are timed by the parity tests only")
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_order2(sum(r["iters"] for r in recs[0][1]), len(inst))
     elif not args.no_cpu_baseline:
         if args.workload == "small":
             out["cpu_baseline"], x_or = cpu_baseline_small(w)
