@@ -15,7 +15,9 @@ The oracle cannot solve the whole problem in test time, so the checks are:
 * a property at full size: GMRES's reported convergence holds for the oracle's matrix, i.e. the
   true relative residual computed with the oracle's A is <= rtol;
 * the two-level deflated form with the 16^3-cube coarse mesh: the oracle's coarse correction at
-  full size plus sampled local solves against the library's application."""
+  full size plus sampled local solves against the library's application;
+* weighted GMRES: the reported D-norm residual equals the one recomputed with the oracle's A and
+  D_k."""
 import sys
 import time
 
@@ -190,3 +192,26 @@ def test_fullsize_two_level_deflation_sampled(gpu_lib, big):
         err = np.max(np.abs(z[idx[own]] - want)) / np.max(np.abs(want))
         say("  ADEF1-ORAS xi %g l %d owned %d: max rel err %.2e" % (xi, l, int(own.sum()), err))
         assert err <= 1e-10
+
+
+@pytest.mark.timeout(900)
+def test_weighted_gmres_fullsize_true_residual(gpu_lib, big):
+    """Weighted GMRES (Sec. 5.2, D_k = K + k^2 M) on the 64^3 ORAS problem at xi = k^2: the
+    D-norm relative residual the library reports equals the one recomputed with the oracle's A
+    and D_k, and is <= rtol (a property that holds at any size)."""
+    mx, b = gpu_lib, big
+    say("full-size weighted ORAS GMRES(100), D-norm true residual with the oracle's matrices")
+    oA = b["oA"](K * K)
+    oD = fem.weight_matrix(b["om"], K)
+    lA = mx.Matrix(b["ctx"], b["lm"], K, K * K)
+    lD = mx.Matrix.weight(b["ctx"], b["lm"], K)
+    P = mx.Precond(b["ctx"], lA, b["lm"], b["lp"], "oras")
+    f = random_rhs(b["E"], 3)
+    x = _dev(np.zeros(b["E"]))
+    st = mx.gmres(b["ctx"], lA, P, _dev(f), x, restart=100, rtol=1e-6, weight=lD)
+    r = f - oA @ _host(x)
+    dn = lambda v: np.sqrt(np.real(np.vdot(v, oD @ v)))
+    rel = dn(r) / dn(f)
+    say("  iterations", st["iters"], "reported", st["relres_true"], "oracle D-norm residual", rel)
+    assert st["converged"] and rel <= 1e-6
+    assert abs(rel - st["relres_true"]) <= 1e-9
