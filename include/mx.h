@@ -1,8 +1,9 @@
 /*
- * mx.h -- C ABI of the MI355X (gfx950) one-level Schwarz-preconditioned GMRES solver for the
- * lowest-order Nedelec discretisation of  curl curl E - (k^2 + i xi) E = F  (Bonazzoli, Dolean,
- * Graham, Spence, Tournier, "Domain decomposition preconditioning for the high-frequency
- * time-harmonic Maxwell equations with absorption", arXiv:1711.03789).
+ * mx.h -- C ABI of the MI355X (gfx950) Schwarz-preconditioned GMRES solver (one- and two-level
+ * AS, RAS and ORAS; standard or weighted GMRES) for the lowest- and second-order Nedelec
+ * discretisations of  curl curl E - (k^2 + i xi) E = F  (Bonazzoli, Dolean, Graham, Spence,
+ * Tournier, "Domain decomposition preconditioning for the high-frequency time-harmonic Maxwell
+ * equations with absorption", arXiv:1711.03789).
  *
  * Conventions for every entry point:
  *   - return value: MX_OK (0) or a negative MX_E* code; mx_last_error() gives a message for the
@@ -16,6 +17,9 @@
  *   - complex vectors are interleaved (re, im) pairs: complex128 = 2 doubles, complex64 =
  *     2 floats per entry (the C99 _Complex layout).
  *   - a context is used by one host thread at a time.
+ *   - where no "Errors:" line is given: MX_EINVAL for a NULL handle or pointer that is required,
+ *     a size or index out of range or a handle of the wrong state, MX_EDEVICE for a failing HIP
+ *     call; destroy functions return nothing.
  */
 #ifndef MX_H
 #define MX_H
@@ -258,7 +262,10 @@ int mx_precond_materialize(mx_ctx *ctx, mx_precond *P, void *stream);
 int mx_precond_stage(mx_ctx *ctx, mx_precond *P);
 /* z = sum_l R_l^T D_l (A^l)^-1 R_l v (D_l = I for AS); v_dev, z_dev complex128[E], distinct.
  * Enqueued on `stream`; device-side failures surface at the next synchronising call.
- * apply_bytes = factors read twice (forward and backward sweep) + local vectors + gathers. */
+ * apply_bytes = factors read twice (forward and backward sweep) + local vectors + gathers.
+ * With a coarse level, the two-level form (mx_precond_add_coarse).  Errors: MX_EINVAL (planned
+ * but not materialised, a planned coarse level not built), MX_EPIVOT / MX_ESTALL (a failure
+ * already reported for P), MX_EDEVICE. */
 int mx_precond_apply(mx_ctx *ctx, mx_precond *P, const void *v_dev, void *z_dev, void *stream);
 int mx_precond_get_info(const mx_precond *P, mx_precond_info *info);
 /* For subdomain l: perm[n_l] (new -> old local index, RCM) and first[n_l] (envelope start of
