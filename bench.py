@@ -586,6 +586,9 @@ def main():
                     help="two-level with a coarse box mesh of C^3 cubes, nested or not (R^0 by a "
                          "Gauss rule of --nq points per fine edge)")
     ap.add_argument("--nq", type=int, default=12, help="quadrature points per fine edge")
+    ap.add_argument("--x0", default="zero", choices=["zero", "random"],
+                    help="initial guess: zero, or a seeded random vector as in the paper's runs "
+                         "(GMRES then stops on the residual relative to b - A x0)")
     ap.add_argument("--coarse", type=int, default=0,
                     help="two-level: coarse mesh with this many times fewer cubes per axis (0: one-level)")
     ap.add_argument("--combine", default="hybrid", choices=["additive", "hybrid", "deflation"],
@@ -669,6 +672,9 @@ def main():
         m0 = mx.Mesh(*n, *w.lengths)
         rhs[0] = torch.from_numpy(m0.rhs_gaussian(w.center, w.pol, w.sigma)).cuda()
     x = torch.zeros(E, dtype=torch.complex128, device="cuda")
+    x0 = torch.from_numpy(random_rhs(E, 777)).cuda() if args.x0 == "random" else None
+    if x0 is not None:
+        cfg["workload"] += "; seeded random initial guess"
     torch.cuda.synchronize()
 
     refs = {}
@@ -743,7 +749,10 @@ def main():
                 if timed:
                     P.sweep_timing(True)
                 for q, bq in enumerate([rhs[seed]] + rhs_more[seed]):
-                    x.zero_()
+                    if x0 is None:
+                        x.zero_()
+                    else:
+                        x.copy_(x0)
                     st = mx.gmres(ctx, A, P, bq, x, restart=w.restart, rtol=w.rtol,
                                   max_iters=args.max_iters, flexible=mixed, spmv_c64=mixed, weight=D,
                                   graph=args.graph)
@@ -852,7 +861,10 @@ def main():
         A = mx.Matrix(ctx, mesh, w.k, 0.0 if zero else w.k ** e, order=order)
         A_prec = mx.Matrix(None, mesh, w.k, w.k ** e, order=order) if zero else A
         P = mx.Precond(ctx, A_prec, mesh, part, kind, xi_prec=w.k ** e, precision="c128")
-        x.zero_()
+        if x0 is None:
+            x.zero_()
+        else:
+            x.copy_(x0)
         st = mx.gmres(ctx, A, P, rhs[seed], x, restart=w.restart, rtol=w.rtol,
                       max_iters=args.max_iters)
         out["mixed_vs_c128"] = {"instance": [kind, w.k ** e], "c128_iters": st["iters"],
