@@ -484,6 +484,13 @@ int mx_server_stats(mx_server *s, uint64_t *budget, uint64_t *peak_used, int *ma
 /* Batched applications so far: launches of the batcher and the applications they carried
  * (equal when nothing was batched; both 0 without batch_applies).  Errors: MX_EINVAL. */
 int mx_server_batch_stats(mx_server *s, uint64_t *batches, uint64_t *applications);
+/* Test hook of the server's recovery path: the next n device phases fail with MX_ENOMEM right
+ * after their preconditioner has been materialised, as a late device allocation failure would.
+ * The server then releases the request's device memory, waits for another request to finish (or
+ * an idle device) and runs the device phase again from the same host plan; an injected failure
+ * is retried even when the request is alone.  For callers that test that path, not for
+ * production use.  Errors: MX_EINVAL. */
+int mx_server_inject_enomem(mx_server *s, int n);
 /* Finishes every submitted request, then stops the workers. */
 void mx_server_destroy(mx_server *s);
 

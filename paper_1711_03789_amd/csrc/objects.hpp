@@ -9,12 +9,16 @@
 
 #include "mx_internal.hpp"
 
+// A failed HIP call also leaves its error as the thread's last error; it is cleared here, so a
+// later hipGetLastError() check (after a kernel launch) does not report it a second time.
 #define MX_HIP(call)                                                                      \
   do {                                                                                    \
     hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess)                                                                 \
+    if (e_ != hipSuccess) {                                                               \
+      (void)hipGetLastError();                                                            \
       ::mx::fail(e_ == hipErrorOutOfMemory ? MX_ENOMEM : MX_EDEVICE,                      \
                  std::string(#call) + ": " + hipGetErrorString(e_));                      \
+    }                                                                                     \
   } while (0)
 
 namespace mx {

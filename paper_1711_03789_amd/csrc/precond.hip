@@ -1863,9 +1863,9 @@ void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   MX_HIP(hipStreamSynchronize(st));
   P->d_off_all.release();
   P->d_val_all.release();
-  // host staging no longer needed
-  std::vector<int64_t>().swap(plan.off);
-  std::vector<double>().swap(plan.val);
+  // The plan's host arrays stay: a caller may materialise the same plan again after releasing
+  // the device half (the server does, when a later allocation of the request fails).  Callers
+  // drop the plan when they are done with it.
   // info
   mx_precond_info &in = P->info;
   in.n_sub = N;

@@ -13,6 +13,7 @@
 // returns the same solution whether it runs alone or among others.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -34,6 +35,7 @@ struct SrvRequest {
   mx_request req;
   double t_submit = 0, t_admit = 0, t_host_done = 0, t_done = 0;
   bool done = false;
+  bool injected = false;  // the last device-phase failure was an injected one
   mx_result res{};
   std::string msg;
   std::vector<double> x;  // interleaved complex128 solution
@@ -202,6 +204,10 @@ struct Server {
   bool stop = false;
   int admitted = 0, max_admitted = 0;
   uint64_t finished = 0;  // device phases ended (successfully or not)
+  // test hook: the next `inject_enomem` device phases fail with MX_ENOMEM right after their
+  // preconditioner is materialised (the path a late allocation failure takes); such a failure
+  // is retried even when the request is alone on the device
+  std::atomic<int> inject_enomem{0};
   std::vector<std::thread> workers;
   Batcher batcher;         // used when opts.batch_applies
   std::vector<SlotHook> hooks;
@@ -282,11 +288,12 @@ void Server::run_request(int slot, mx_ctx *ctx, hipStream_t st, SrvRequest *R) {
         seen = finished;
       }
       try {
+        R->injected = false;
         device_phase(slot, ctx, st, R, A.get(), P.get(), plan, f, E);
         return;
       } catch (const Error &e) {
         release_request(ctx, st, A.get(), P.get());
-        if (e.code != MX_ENOMEM || attempt >= kMemRetries || others == 0) throw;
+        if (e.code != MX_ENOMEM || attempt >= kMemRetries || (others == 0 && !R->injected)) throw;
       } catch (...) {
         release_request(ctx, st, A.get(), P.get());
         throw;
@@ -306,6 +313,11 @@ void Server::device_phase(int slot, mx_ctx *ctx, hipStream_t st, SrvRequest *R, 
   AllocScope scope(st);
   matrix_upload(A);
   precond_materialize(P, plan, st);
+  for (int n = inject_enomem.load(); n > 0; n = inject_enomem.load())
+    if (inject_enomem.compare_exchange_weak(n, n - 1)) {
+      R->injected = true;
+      fail(MX_ENOMEM, "injected allocation failure after the preconditioner setup");
+    }
   DevBuf b, x;
   b.alloc(16 * (size_t)E);
   x.alloc(16 * (size_t)E);
@@ -385,6 +397,7 @@ void Server::worker(int slot) {
     }
     int code = MX_OK;
     std::string msg;
+    (void)hipGetLastError();  // nothing left over from an earlier request of this slot
     if (!ok) {
       code = MX_EDEVICE;
       msg = "server slot could not create its stream";
@@ -613,6 +626,17 @@ int mx_server_batch_stats(mx_server *S, uint64_t *batches, uint64_t *application
     std::lock_guard<std::mutex> lk(S->s.batcher.mu);
     if (batches) *batches = S->s.batcher.batches;
     if (applications) *applications = S->s.batcher.applications;
+    return MX_OK;
+  } catch (const Error &e) {
+    mx::set_error(e.code, e.msg);
+    return e.code;
+  }
+}
+
+int mx_server_inject_enomem(mx_server *S, int n) {
+  try {
+    if (!S || n < 0) mx::fail(MX_EINVAL, "NULL server or negative count");
+    S->s.inject_enomem.store(n);
     return MX_OK;
   } catch (const Error &e) {
     mx::set_error(e.code, e.msg);

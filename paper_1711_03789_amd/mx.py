@@ -37,7 +37,7 @@ SYMBOLS = [
     "mx_precond_tune_factor", "mx_server_batch_stats", "mx_matrix_assemble_order",
     "mx_mesh_order2_sizes", "mx_mesh_order2_export", "mx_partition_order2_export",
     "mx_weight_assemble_order", "mx_precond_add_coarse_box", "mx_precond_plan_coarse_box",
-    "mx_coarse_operators_box",
+    "mx_coarse_operators_box", "mx_server_inject_enomem",
 ]
 
 
@@ -182,6 +182,7 @@ def load(path=LIB_PATH):
                                       C.POINTER(C.c_int)]),
         "mx_server_destroy": (None, [P]),
         "mx_server_batch_stats": (C.c_int, [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+        "mx_server_inject_enomem": (C.c_int, [P, C.c_int]),
         "mx_precond_sweep_timing": (C.c_int, [P, C.c_int, C.POINTER(C.c_int64),
                                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "mx_precond_destroy": (None, [P]),
@@ -638,6 +639,10 @@ class Server:
         _check(_lib.mx_server_batch_stats(self.h, C.byref(nb), C.byref(na)))
         return {"budget": b.value, "peak_used": pk.value, "max_admitted": ma.value,
                 "batches": nb.value, "batched_applications": na.value}
+
+    def inject_enomem(self, n):
+        """Test hook: the next n device phases fail once after their setup and are retried."""
+        _check(_lib.mx_server_inject_enomem(self.h, int(n)))
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -102,3 +102,21 @@ def test_served_solution_vs_oracle(gpu_lib):
     err = np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x)
     say("  served err vs oracle", err, "iters", r["iters"], ores.iters)
     assert err <= 1e-5
+
+
+def test_retry_after_late_allocation_failure(gpu_lib):
+    """Requests whose device phase fails after their preconditioner has been set up (MX_ENOMEM,
+    injected through the server's test hook) are retried from the same host plan: every request
+    of the mix still converges, and each solution equals the one served without failures, bit
+    for bit."""
+    say("serve with injected late allocation failures")
+    srv = gpu_lib.Server(slots=3, precision="c64", restart=50)
+    r0, x0, s0 = _mix(srv)
+    srv.inject_enomem(3)
+    r1, x1, s1 = _mix(srv)
+    say("  without", r0["iters"], "with injected failures", r1["iters"], srv.stats())
+    srv.close()
+    assert r1["status"] == 0 and r1["converged"] and r1["iters"] == r0["iters"]
+    assert np.array_equal(x1, x0)
+    for u, w in zip(s0, s1):
+        assert np.array_equal(u, w)
