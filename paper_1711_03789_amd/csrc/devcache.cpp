@@ -72,6 +72,7 @@ void big_free(void *p, size_t capacity, hipStream_t st) {
     if (ev) (void)hipEventDestroy(ev);
     (void)hipDeviceSynchronize();
     (void)hipFree(p);
+    (void)hipGetLastError();  // leave no error behind for a later launch check
     return;
   }
   std::lock_guard<std::mutex> lk(g_mu);

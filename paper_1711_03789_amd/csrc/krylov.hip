@@ -697,16 +697,22 @@ void gmres_run(mx_ctx *ctx, const mx_matrix *A, mx_precond *P, const void *b_dev
             } catch (...) {
               (void)hipStreamEndCapture(st, &gr);
               if (gr) (void)hipGraphDestroy(gr);
+              (void)hipGetLastError();
               st = run_st;
               throw;
             }
             const hipError_t ec = hipStreamEndCapture(st, &gr);
             st = run_st;
-            if (ec != hipSuccess) fail(MX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+            if (ec != hipSuccess) {
+              if (gr) (void)hipGraphDestroy(gr);
+              (void)hipGetLastError();
+              fail(MX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+            }
             const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
             (void)hipGraphDestroy(gr);
             if (e != hipSuccess) {
               ex = nullptr;
+              (void)hipGetLastError();
               fail(MX_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(e));
             }
           }
