@@ -374,6 +374,7 @@ void Server::release_request(mx_ctx *ctx, hipStream_t st, mx_matrix *A, mx_preco
   A->val32.release();
   ctx->krylov.buf.release();
   (void)hipStreamSynchronize(st);
+  (void)hipGetLastError();  // the ignored errors above are not reported by a later launch check
 }
 
 void Server::worker(int slot) {
