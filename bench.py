@@ -653,8 +653,8 @@ def main():
     if order == 2 and not args.coarse:
         args.coarse, args.combine = 6, "hybrid"
     elif args.coarse:
-        if args.workload == "scale-xi0" or args.overlap_factor:
-            raise SystemExit("--coarse is not combined with scale-xi0 or --overlap-factor")
+        if args.overlap_factor:
+            raise SystemExit("--coarse is not combined with --overlap-factor")
         if order == 1:
             cfg["workload"] += ("; two-level (%s) with a nested coarse mesh of %s cubes"
                                 % (args.combine, "x".join(str(v // args.coarse) for v in w.n)))
