@@ -58,12 +58,14 @@ def instances(name):
         return [("oras", 2.0, 0)]
     if name == "order2":  # xi_prob = xi_prec = k^2, then xi_prob = 0 with xi_prec = k
         return [("oras", 2.0, 0), ("oras", 1.0, 1)]
+    if name == "scale-xi00":  # no absorption anywhere (exponent None: xi_prec = 0 too)
+        return [("oras", None, 0)]
     raise SystemExit("unknown workload " + name)
 
 
 def xi_prob_zero(name, idx):
     """Whether instance idx solves the problem without absorption (xi_prob = 0)."""
-    return name == "scale-xi0" or (name == "order2" and idx == 1)
+    return name in ("scale-xi0", "scale-xi00") or (name == "order2" and idx == 1)
 
 
 def workload_desc(name):
@@ -75,6 +77,13 @@ def workload_desc(name):
                                "ORAS two-level hybrid with the coarse mesh of 4^3 cubes: xi_prob = "
                                "xi_prec = k^2, then ImpHRAS with xi_prob = 0, xi_prec = k; "
                                "GMRES(100) rtol 1e-6, complex128, seeded random complex Gaussian J",
+                   "instances": len(instances(name))}
+    if name == "scale-xi00":
+        w = config_scale()
+        return w, {"workload": "unit cube 64^3 cubes x 6 tets (1,872,064 complex DOFs), k=16, "
+                               "no absorption anywhere (xi_prob = xi_prec = 0, as in Table "
+                               "tab:EpsPrec0), 4x4x4 subdomains, 2-layer overlap, ORAS, GMRES(100) "
+                               "rtol 1e-6, complex128, seeded random complex Gaussian J",
                    "instances": len(instances(name))}
     if name == "scale-xi0":
         w = config_scale()
@@ -683,7 +692,7 @@ def main():
         kind0, e0, _ = inst[0]
         m0 = mx.Mesh(*n, *w.lengths)
         p0 = mx.Partition(m0, *w.parts, w.layers)
-        A0 = mx.Matrix(ctx, m0, w.k, w.k ** e0, order=order)
+        A0 = mx.Matrix(ctx, m0, w.k, 0.0 if e0 is None else w.k ** e0, order=order)
         sch, wid, best, each = mx.tune_factor(ctx, A0, m0, p0, kind0, precision=args.precision)
         P0 = mx.Precond(ctx, A0, m0, p0, kind0, precision=args.precision, schedule=sch, width=wid)
         grid, ms = P0.autotune()
@@ -699,11 +708,13 @@ def main():
 
 
     def prepare(mesh, part, kind, e, idx):
-        xi = w.k ** e  # the preconditioner's absorption; also the problem's unless xi_prob = 0
+        # the preconditioner's absorption (exponent None: none); also the problem's unless
+        # xi_prob = 0
+        xi = 0.0 if e is None else w.k ** e
         zero = xi_prob_zero(args.workload, idx)
         t0 = time.perf_counter()
         A = mx.Matrix(None, mesh, w.k, 0.0 if zero else xi, order=order)
-        A_prec = mx.Matrix(None, mesh, w.k, xi, order=order) if zero else A  # host only
+        A_prec = mx.Matrix(None, mesh, w.k, xi, order=order) if zero and xi != 0 else A  # host only
         A.upload(ctx_host)  # its own stream: overlaps the device work of the current instance
         t1 = time.perf_counter()
         P = mx.Precond(ctx_host, A_prec, mesh, part, kind, xi_prec=xi, precision=args.precision,
@@ -858,16 +869,17 @@ def main():
         mesh = mx.Mesh(*n, *w.lengths)
         part = mx.Partition(mesh, *w.parts, w.layers)
         zero = xi_prob_zero(args.workload, 0)
-        A = mx.Matrix(ctx, mesh, w.k, 0.0 if zero else w.k ** e, order=order)
-        A_prec = mx.Matrix(None, mesh, w.k, w.k ** e, order=order) if zero else A
-        P = mx.Precond(ctx, A_prec, mesh, part, kind, xi_prec=w.k ** e, precision="c128")
+        xe = 0.0 if e is None else w.k ** e
+        A = mx.Matrix(ctx, mesh, w.k, 0.0 if zero else xe, order=order)
+        A_prec = mx.Matrix(None, mesh, w.k, xe, order=order) if zero and xe != 0 else A
+        P = mx.Precond(ctx, A_prec, mesh, part, kind, xi_prec=xe, precision="c128")
         if x0 is None:
             x.zero_()
         else:
             x.copy_(x0)
         st = mx.gmres(ctx, A, P, rhs[seed], x, restart=w.restart, rtol=w.rtol,
                       max_iters=args.max_iters)
-        out["mixed_vs_c128"] = {"instance": [kind, w.k ** e], "c128_iters": st["iters"],
+        out["mixed_vs_c128"] = {"instance": [kind, xe], "c128_iters": st["iters"],
                                 "rel_l2_diff": float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))}
         out["dtype"] = "complex64 factors + FP64 FGMRES"
         del P, A

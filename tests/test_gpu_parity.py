@@ -204,6 +204,45 @@ def test_gmres_absorption_only_in_preconditioner(gpu_lib, ctx, kind):
     assert st2["iters"] == ores.iters and err <= 1e-8
 
 
+@pytest.mark.parametrize("coarse_ratio", [0, 2])
+def test_gmres_without_absorption_anywhere(gpu_lib, ctx, coarse_ratio):
+    """xi_prob = xi_prec = 0, the setting of Table tab:EpsPrec0 (ImpRAS, and ImpHRAS with a
+    coarse level): no coercivity bound guarantees the pivots of the unpivoted local
+    factorisations here (a zero pivot would be reported as MX_EPIVOT), but the impedance
+    condition on the subdomain boundaries keeps the ORAS local problems nonsingular.  8^3, k = 4,
+    2x2x2 subdomains, 2 layers, Gaussian source, GMRES(50): iterations within one of the
+    oracle's, the solution at the oracle's count to 1e-8."""
+    from oracle import coarse
+    w = config_small("oras")
+    k = w.k
+    say("gmres xi_prob = xi_prec = 0, coarse ratio", coarse_ratio)
+    om = OMesh(*w.n, *w.lengths)
+    oA = fem.assemble(om, k, 0.0)
+    op = dd.Partition(om, *w.parts, w.layers)
+    oB = dd.Schwarz(op, oA, dd.ORAS, k, 0.0)
+    lm = gpu_lib.Mesh(*w.n, *w.lengths)
+    lA = gpu_lib.Matrix(ctx, lm, k, 0.0)
+    lp = gpu_lib.Partition(lm, *w.parts, w.layers)
+    lP = gpu_lib.Precond(ctx, lA, lm, lp, "oras", xi_prec=0.0)
+    if coarse_ratio:
+        oB = coarse.TwoLevel(oB, oA, coarse.restriction(om, coarse.coarse_mesh(om, coarse_ratio)),
+                             coarse.HYBRID)
+        lP.add_coarse(ctx, lA, lm, coarse_ratio, "hybrid")
+    f = fem.load_vector(om, fem.gaussian_source(w.center, w.pol, w.sigma))
+    ores = gmres.gmres(oA, f, oB, restart=w.restart, rtol=w.rtol)
+    E = om.n_edge
+    bd, xd = dev(f), dev(np.zeros(E))
+    st = gpu_lib.gmres(ctx, lA, lP, bd, xd, restart=w.restart, rtol=w.rtol)
+    say("  iters gpu", st["iters"], "oracle", ores.iters, "relres", st["relres_true"])
+    assert ores.converged and st["converged"] and st["relres_true"] <= w.rtol
+    assert abs(st["iters"] - ores.iters) <= 1
+    xd2 = dev(np.zeros(E))
+    st2 = gpu_lib.gmres(ctx, lA, lP, bd, xd2, restart=w.restart, fixed_iters=ores.iters)
+    err = np.linalg.norm(host(xd2) - ores.x) / np.linalg.norm(ores.x)
+    say("  fixed-iteration solution rel err", err)
+    assert st2["iters"] == ores.iters and err <= 1e-8
+
+
 def test_gmres_restart_and_flexible(gpu_lib, ctx):
     """Small restart length (several cycles), flexible variant, nonzero initial guess."""
     say("gmres restart")
