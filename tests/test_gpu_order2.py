@@ -224,3 +224,24 @@ def test_order2_weighted_gmres(gpu_lib, ctx, bc):
     err = np.linalg.norm(host(xd2) - ores.x) / np.linalg.norm(ores.x)
     say("  rel L2 at the oracle's count", err)
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("n,parts,layers", [((1, 1, 1), (1, 1, 1), 0), ((2, 1, 1), (2, 1, 1), 0),
+                                            ((2, 2, 1), (2, 1, 1), 1),
+                                            ((3, 2, 2), (3, 2, 1), 0)])
+def test_order2_tiny_meshes(gpu_lib, ctx, n, parts, layers):
+    """Order-2 applications on tiny meshes against the oracle: local problems of 60 to 242 DOFs,
+    below, exactly at and above one 64-row tile (one subdomain per cube, with and without
+    overlap)."""
+    say("order-2 tiny", n, parts, layers)
+    for kind in ("oras", "as"):
+        c = Case(gpu_lib, ctx, n, parts, layers, 3.0, 9.0, 9.0, kind)
+        v = random_rhs(c.N, 26)
+        vd, zd = dev(v), dev(np.zeros(c.N))
+        c.lP.apply(vd, zd)
+        c.lP.check()
+        z = host(zd)
+        ref = c.oB(v)
+        err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+        say("  ", kind, "N", c.N, "rel err", err)
+        assert err <= 1e-12
