@@ -1,7 +1,8 @@
 """GMRES without device allocation (mx_gmres_noalloc) against mx_gmres through the C ABI: two
 calls in a row on one context, the second on a smaller problem, each bitwise equal to the
 allocating entry point (same kernels, same order); the device's free memory does not shrink
-across the calls; a problem whose workspace exceeds the fixed scratch is refused."""
+across the calls; a problem whose workspace exceeds the fixed scratch is refused; and an order-2
+matrix with a two-level preconditioner."""
 import sys
 
 import numpy as np
@@ -70,3 +71,28 @@ def test_gmres_noalloc_matches_gmres(gpu_lib):
     with pytest.raises(mx.MxError) as ei:
         mx.gmres(ctx, lA, P, b, x_na, restart=400, rtol=1e-8, flexible=True, noalloc=True)
     assert ei.value.code == mx.MX_EINVAL and "fixed scratch" in str(ei.value)
+
+
+def test_gmres_noalloc_two_level_order2(gpu_lib):
+    """The no-allocation entry point with an order-2 matrix and a two-level (hybrid) preconditioner,
+    whose coarse level holds its own buffers: bitwise equal to mx_gmres, no device allocation."""
+    import torch
+    mx = gpu_lib
+    ctx = mx.Context(0)
+    lm = mx.Mesh(8, 8, 8)
+    lA = mx.Matrix(ctx, lm, 4.0, 16.0, order=2)
+    P = mx.Precond(ctx, lA, lm, mx.Partition(lm, 2, 2, 2, 1), "oras")
+    P.add_coarse(ctx, lA, lm, 2, "hybrid")
+    b = _dev(random_rhs(lA.n, 8))
+    x_ref, x_na = _dev(np.zeros(lA.n)), _dev(np.zeros(lA.n))
+    ref = mx.gmres(ctx, lA, P, b, x_ref, restart=40, rtol=1e-8, history=True)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    st = mx.gmres(ctx, lA, P, b, x_na, restart=40, rtol=1e-8, history=True, noalloc=True)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    say("order-2 two-level noalloc iterations", st["iters"], "vs", ref["iters"], "free", free0, free1)
+    assert free1 >= free0 - (1 << 20)
+    assert st["converged"] and st["iters"] == ref["iters"]
+    assert np.array_equal(st["history"], ref["history"])
+    assert np.array_equal(x_na.cpu().numpy(), x_ref.cpu().numpy())
