@@ -1,5 +1,6 @@
-"""Plain FP64 CPU oracle for the one-level AS / RAS / ORAS-preconditioned GMRES solve
-of the lowest-order Nedelec discretisation of curl curl E - (k^2 + i xi) E = F.
+"""Plain FP64 CPU oracle for the one- and two-level AS / RAS / ORAS-preconditioned (weighted)
+GMRES solve of the lowest- and second-order Nedelec discretisations of
+curl curl E - (k^2 + i xi) E = F.
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the C-ABI library and its Python
 binding) imports, links or runs anything here; only the test-suite, the smoke check and the
@@ -13,12 +14,14 @@ with absorption", Math. Comp. 2019 / arXiv:1711.03789):
 * fem.py       Whitney element matrices, Galerkin matrix A_xi and load f (Sec. 2.2,
                eq:Helmholtzvf_intro, impedance condition eq:imp)
 * order2.py    second-order Nedelec elements (first family) in a hierarchical basis: exact element
-               integrals, assembly, order-2 local DOF sets, owners and local problems
+               integrals, assembly, order-2 local DOF sets, owners and local problems, the
+               weight D_k and the coarse restriction of the order-2 space
 * dd.py        non-overlapping boxes, overlap by tetrahedron layers (Sec. 6.1), local DOF
                sets and restriction (eq:restriction1), minors (eq:minor), Boolean partition
                of unity (eq:algebPartUnity), local impedance problems (ImpRAS, Sec. 6.3),
                AS / RAS / ORAS application (eq:defAS without the coarse term, RAS_1, ImpRAS_1)
-* coarse.py    nested coarse mesh, restriction R^0 (eq:restriction), coarse Galerkin matrix and
+* coarse.py    nested or non-nested coarse mesh, restriction R^0 (eq:restriction; exact on nested
+               meshes, by a Gauss rule along each fine edge otherwise), coarse Galerkin matrix and
                the two-level AS / RAS / ImpRAS preconditioners in additive (eq:defAS,
                eq:RAS2), hybrid (eq:HRAS) and deflated (eq:ADEF1ras) form
 * rcm.py       reverse Cuthill-McKee ordering of a local matrix graph (not in the paper: the
