@@ -1752,7 +1752,7 @@ void precond_stage(mx_precond *P, PrecondPlan &plan) {
 void precond_materialize(mx_precond *P, PrecondPlan &plan, hipStream_t st) {
   const double t1 = now_s();
   const int N = P->nsub;
-  const int64_t blocks = P->blocks_total, vec = P->vec_total, tiles = P->tiles_total;
+  const int64_t vec = P->vec_total, tiles = P->tiles_total;
   AllocScope scope(st);
   // device buffers
   const size_t esz = P->prec == MX_C128 ? 16 : 8;
