@@ -254,6 +254,39 @@ def test_paper_ordering_ras_beats_as():
     assert its[dd.RAS] < its[dd.AS] and its[dd.ORAS] <= its[dd.RAS]
 
 
+def test_paper_low_absorption_and_weighting():
+    """Sec. 6.2, Tables tab:1, tab:lowAbs and tab:weighted (PEC on the global boundary, AS with
+    its PEC local problems, generous overlap).  At xi = k^2 the one-level iteration counts stay
+    flat as k grows; at xi = k (tab:lowAbs) they are larger and grow quickly with k; GMRES
+    weighted by D_k (tab:weighted) takes about as many iterations as the standard method.  The
+    paper's counts are context (other meshes and partition of unity): only these three
+    properties are checked, on one 16^3 mesh with 4x4x4 boxes and 2 layers at k = 8 and 10."""
+    with open(os.path.join(GOLDEN, "paper_one_level_counts.json")) as fh:
+        paper = json.load(fh)
+    for a in ("alpha_0.8", "alpha_0.9"):
+        flat, low, wtd = paper["tab:1"][a], paper["tab:lowAbs"][a], paper["tab:weighted"][a]
+        assert max(flat) - min(flat) <= 8 and low[0] > 2.5 * flat[0] and low[1] > 4 * flat[1]
+        assert all(abs(x - y) <= 2 for x, y in zip(wtd, flat))
+    m = Mesh(16, 16, 16)
+    f = fem.load_vector(m, fem.gaussian_source((0.5, 0.5, 0.5), (1, 0, 0), 0.1), fem.BC_PEC)
+    part = dd.Partition(m, 4, 4, 4, 2)
+    its = {}
+    for k in (8.0, 10.0):
+        for xi in (k * k, k):
+            A = fem.assemble(m, k, xi, fem.BC_PEC)
+            B = dd.Schwarz(part, A, dd.AS, k, xi, fem.BC_PEC)
+            res = gmres.gmres(A, f, B, restart=200, rtol=1e-6, max_iters=400)
+            assert res.converged and res.relres_true <= 1e-6
+            its[k, xi] = res.iters
+            if k == 8.0 and xi == k * k:
+                resw = gmres.gmres(A, f, B, restart=200, rtol=1e-6, max_iters=400,
+                                   D=fem.weight_matrix(m, k, fem.BC_PEC))
+                assert resw.converged and abs(resw.iters - res.iters) <= 3, (resw.iters, res.iters)
+    assert abs(its[10.0, 100.0] - its[8.0, 64.0]) <= 4, its
+    assert its[8.0, 8.0] >= 1.5 * its[8.0, 64.0] and its[10.0, 10.0] >= 2.5 * its[10.0, 100.0], its
+    assert its[10.0, 10.0] >= 1.4 * its[8.0, 8.0], its
+
+
 def _box_problem_on_own_mesh(m, cuts, box, k, xi, bc):
     """The local problem of box `box` of the cut planes, built independently of dd: a mesh of
     the box alone, its Galerkin matrix with the impedance term of eq:imp on its own boundary
