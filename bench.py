@@ -269,7 +269,6 @@ def cpu_baseline_batching(w, iters, n_sample=8, seed=11):
     from oracle.mesh import Mesh as OMesh
     px, py, pz = w.parts
     nsub = px * py * pz
-    h = [L / n for L, n in zip(w.lengths, w.n)]
     rng = np.random.default_rng(seed)
     sample = sorted(rng.choice(nsub, n_sample, replace=False).tolist())
     tasks, t_loc, sizes = [], [], []
@@ -280,21 +279,8 @@ def cpu_baseline_batching(w, iters, n_sample=8, seed=11):
         dd.Partition(m32, 2, 2, 2, w.layers)
         t_global = time.perf_counter() - t0
         for l in sample:
-            b = (l % px, (l // px) % py, l // (px * py))
-            lo = [w.cuts[a][b[a]] for a in range(3)]
-            hi = [w.cuts[a][b[a] + 1] for a in range(3)]
-            rlo = [max(0, lo[a] - w.layers) for a in range(3)]
-            rhi = [min(w.n[a], hi[a] + w.layers) for a in range(3)]
-            cuts, pos = [], []
-            for a in range(3):
-                c = sorted({0, lo[a] - rlo[a], hi[a] - rlo[a], rhi[a] - rlo[a]})
-                cuts.append(c)
-                pos.append(c.index(lo[a] - rlo[a]))
             t1 = time.perf_counter()
-            om = OMesh(*[rhi[a] - rlo[a] for a in range(3)], *[(rhi[a] - rlo[a]) * h[a] for a in range(3)])
-            part = dd.Partition(om, len(cuts[0]) - 1, len(cuts[1]) - 1, len(cuts[2]) - 1, w.layers,
-                                *cuts)
-            lr = pos[0] + (len(cuts[0]) - 1) * (pos[1] + (len(cuts[1]) - 1) * pos[2])
+            _, part, lr, _, _, _ = dd.sub_box(w.n, w.lengths, w.parts, w.layers, w.cuts, l)
             Al = dd.local_matrix(part, None, dd.ORAS, w.k, w.xi, lr)
             t_loc.append(time.perf_counter() - t1)
             sizes.append(Al.shape[0])

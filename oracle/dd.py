@@ -97,6 +97,35 @@ class Partition:
         return [j for j in range(self.N) if j != l and (self.tet_masks[l] & self.tet_masks[j]).any()]
 
 
+def sub_box(n, lengths, parts, layers, cuts, l):
+    """The ORAS local problem of box l of a large jittered-box partition, on a small mesh.  Its
+    overlapped subdomain reaches only `layers` cubes past the box (each sweep adds tetrahedra
+    sharing a vertex, hence at most one more cube per axis), and on its boundary the local matrix
+    has the impedance term with coefficient k whether the boundary lies on the box of the whole
+    domain (eq:imp) or inside it (ImpRAS, Sec. 6.3).  So the sub-box of cubes [rlo, rhi) (box l
+    extended by `layers` per side, clipped to the domain), cut at l's planes, holds the same
+    local problem with impedance boundary conditions (up to numbering; sub-box vertex ijk + rlo
+    is the whole mesh's).  Returns (sub-box mesh, its Partition, index of l in it, l's cube range
+    lo / hi and the sub-box origin rlo, in cubes of the whole mesh)."""
+    from .mesh import Mesh
+    px, py, _ = parts
+    b = (l % px, (l // px) % py, l // (px * py))
+    lo = [int(cuts[a][b[a]]) for a in range(3)]
+    hi = [int(cuts[a][b[a] + 1]) for a in range(3)]
+    rlo = [max(0, lo[a] - layers) for a in range(3)]
+    rhi = [min(n[a], hi[a] + layers) for a in range(3)]
+    sc, pos = [], []
+    for a in range(3):
+        c = sorted({0, lo[a] - rlo[a], hi[a] - rlo[a], rhi[a] - rlo[a]})
+        sc.append(c)
+        pos.append(c.index(lo[a] - rlo[a]))
+    ns = [rhi[a] - rlo[a] for a in range(3)]
+    m = Mesh(*ns, *[ns[a] * lengths[a] / n[a] for a in range(3)])
+    part = Partition(m, len(sc[0]) - 1, len(sc[1]) - 1, len(sc[2]) - 1, layers, *sc)
+    lr = pos[0] + (len(sc[0]) - 1) * (pos[1] + (len(sc[1]) - 1) * pos[2])
+    return m, part, lr, lo, hi, rlo
+
+
 def local_pattern(part, l, kind, bc=fem.BC_IMPEDANCE):
     """Structural pattern of A^l: local DOF pairs sharing a tetrahedron of Omega_l; with the PEC
     condition the constrained boundary edges keep only their diagonal."""

@@ -287,6 +287,37 @@ def test_paper_low_absorption_and_weighting():
     assert its[10.0, 10.0] >= 1.4 * its[8.0, 8.0], its
 
 
+def test_sub_box_local_problem_is_the_whole_problems():
+    """dd.sub_box (the oracle's stand-in for one subdomain of a problem too large to partition
+    whole): on a 24x24x48 box with jittered 3x3x6 boxes and 2 layers, for a corner, an interior
+    and the last box, the sub-box's ORAS local set maps (through integer vertex coordinates) onto
+    the whole partition's set in the same order, the whole partition's owner of every edge
+    interior to the box is that box, and the local matrices agree to rounding."""
+    n, lengths, parts, layers = (24, 24, 48), (1.0, 1.0, 2.0), (3, 3, 6), 2
+    cuts = (jittered_cuts(24, 3, 0.2, 0), jittered_cuts(24, 3, 0.2, 1), jittered_cuts(48, 6, 0.2, 2))
+    k = xi = 6.0
+    og = Mesh(*n, *lengths)
+    whole = dd.Partition(og, *parts, layers, *cuts)
+    h = np.array([L / c for L, c in zip(lengths, n)])
+    for l in (0, 1 + 3 * (1 + 3 * 3), 53):
+        m, part, lr, lo, hi, rlo = dd.sub_box(n, lengths, parts, layers, cuts, l)
+        ijk = np.rint(m.xyz / h).astype(np.int64) + np.array(rlo)
+        gv = ijk[:, 0] + (n[0] + 1) * (ijk[:, 1] + (n[1] + 1) * ijk[:, 2])
+        a, b = gv[m.edge_vert[:, 0]], gv[m.edge_vert[:, 1]]
+        assert np.all(a < b)
+        gid = og.edge_index(a, b)
+        s = part.oras_sets[lr]
+        assert np.array_equal(whole.oras_sets[l], gid[s])
+        inner = np.ones(len(s), bool)
+        for end in (0, 1):
+            c = ijk[m.edge_vert[s, end]]
+            inner &= np.all((c > np.array(lo)) & (c < np.array(hi)), axis=1)
+        assert inner.sum() > 0 and np.all(whole.owner[gid[s][inner]] == l)
+        Al = dd.local_matrix(part, None, dd.ORAS, k, xi, lr)
+        Ag = dd.local_matrix(whole, None, dd.ORAS, k, xi, l)
+        assert abs(Al - Ag).max() <= 1e-13 * abs(Ag).max()
+
+
 def _box_problem_on_own_mesh(m, cuts, box, k, xi, bc):
     """The local problem of box `box` of the cut planes, built independently of dd: a mesh of
     the box alone, its Galerkin matrix with the impedance term of eq:imp on its own boundary
