@@ -21,7 +21,8 @@ offsets).  Checked per sample:
   order and envelope starts equal the oracle's (bit-exact);
 * the application z = B v on the edges interior to the box equals the oracle's local solve there
   (Boolean partition of unity), to 1e-4 relative L2: the bar of the complex64 application tests
-  on small meshes."""
+  on small meshes.
+A property of the whole solve: the FGMRES true residual recomputed with the oracle's matrix."""
 import gc
 import sys
 import time
@@ -111,3 +112,40 @@ def test_batching_fullsize_sampled(gpu_lib):
         say("  subdomain %d: application vs oracle local solve, rel L2 %.2e (oracle LU %.1f s)"
             % (l, err, t_lu))
         assert err <= 1e-4, (l, err)
+
+
+@pytest.mark.timeout(1500)
+def test_batching_fullsize_fgmres_true_residual(gpu_lib):
+    """The whole 96x96x192 solve as the benchmark runs it (ORAS with complex64 factors,
+    FGMRES(50) with complex64 SpMV values and FP64 Krylov vectors, rtol 1e-6), on a seeded random
+    right-hand side: the library's reported convergence holds for the oracle's matrix, i.e. the
+    true relative residual recomputed with the oracle's A at full size is <= rtol and equals the
+    reported one to 1e-9."""
+    import torch
+    from oracle import fem
+    mx = gpu_lib
+    w = config_batching(0)
+    t0 = time.time()
+    ctx = mx.Context(0)
+    lm = mx.Mesh(*w.n, *w.lengths)
+    E = lm.n_edge
+    lA = mx.Matrix(ctx, lm, w.k, w.xi)
+    lp = mx.Partition(lm, *w.parts, w.layers, *w.cuts)
+    P = mx.Precond(ctx, lA, lm, lp, "oras", precision="c64")
+    f = random_rhs(E, 17)
+    fd = torch.from_numpy(f).cuda()
+    xd = torch.zeros_like(fd)
+    st = mx.gmres(ctx, lA, P, fd, xd, restart=50, rtol=1e-6, max_iters=1000, flexible=True,
+                  spmv_c64=True)
+    torch.cuda.synchronize()
+    x = xd.cpu().numpy()
+    say("library: %d iterations, reported relres %.4e, at %.1f s"
+        % (st["iters"], st["relres_true"], time.time() - t0))
+    del P, lA, fd, xd, ctx
+    gc.collect()
+    torch.cuda.empty_cache()
+    oA = fem.assemble(OMesh(*w.n, *w.lengths), w.k, w.xi)
+    rel = np.linalg.norm(f - oA @ x) / np.linalg.norm(f)
+    say("oracle residual %.4e at %.1f s" % (rel, time.time() - t0))
+    assert st["converged"] and rel <= 1e-6
+    assert abs(rel - st["relres_true"]) <= 1e-9
