@@ -112,9 +112,12 @@ __device__ __forceinline__ void tile_nt_quadrant(const cx<T> *__restrict__ A,
       for (int e = 0; e < 4; ++e) {
         cx<T> v = p[e];
         if (UNITDIAG) {
-          int k = kb + e;
-          if (k == j) v = {(T)1, (T)0};
-          else if (k > j) v = {(T)0, (T)0};
+          // v m + d with m = [k < j], d = [k == j], in arithmetic rather than a branch: a branch
+          // lets the compiler skip the load per lane and wait for every load on its own (the
+          // entries are finite: D on the diagonal, zeros above it)
+          const int k = kb + e;
+          const T m = k < j ? (T)1 : (T)0, d = k == j ? (T)1 : (T)0;
+          v = {v.re * m + d, v.im * m};
         }
         if (SCALE) v = cmul(v, s[kb + e]);
         bv[cb][e] = v;
