@@ -26,7 +26,8 @@ HBM_PEAK_GBS = 8000.0
 # command (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0: what the counters read for a 1 GiB
 # device copy), averaged over the launches; summaries in profiles/.  Valid for the sweep kernel
 # as it is now; None where not measured.
-SWEEP_TRAFFIC = {("scale", "c128"): 58.85e9, ("apply", "c128"): 65.82e9, ("order2", "c128"): 12.55e9}
+SWEEP_TRAFFIC = {("scale", "c128"): 58.85e9, ("scale", "c64"): 29.51e9, ("apply", "c128"): 65.82e9,
+                 ("order2", "c128"): 12.55e9}
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
