@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # device copy), averaged over the launches; summaries in profiles/.  Valid for the sweep kernel
 # as it is now; None where not measured.
 SWEEP_TRAFFIC = {("scale", "c128"): 58.85e9, ("scale", "c64"): 29.51e9, ("apply", "c128"): 65.82e9,
-                 ("order2", "c128"): 12.55e9}
+                 ("order2", "c128"): 12.55e9, ("batching", "c64"): 251.87e9}
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
@@ -360,7 +360,8 @@ def run_batching(args):
         "iters": st["iters"], "relres_true": st["relres_true"],
         "roofline": {"bound": "hbm", "kernel": "k_sweep<float, true> (forward block sweep)",
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                     "traffic": None, "launches": nl, "avg_launch_ms": fms / nl,
+                     "traffic": SWEEP_TRAFFIC.get(("batching", "c64")), "launches": nl,
+                     "avg_launch_ms": fms / nl,
                      "bytes_per_launch": sb,
                      "backward": {"avg_launch_ms": bms / nl, "achieved": sb / (bms / nl * 1e-3) / 1e9}},
         "factor": {"bound": "mfma", "achieved_env": inf["env_flops"] / inf["t_factor"] / 1e12,
