@@ -8,7 +8,8 @@ on the same seeded inputs:
   xi_prob = xi_prec = k^2 with minimal overlap, and ImpHRAS with xi_prob = 0, xi_prec = k (8^3
   with 2x2x2 subdomains, and 12^3 with 3x3x3, every class of box);
 * the order-2 benchmark problem (24^3) in the benchmark's launch configuration: sampled ORAS
-  local solves (corner, interior, last subdomain) against the oracle's."""
+  local solves (corner, interior, last subdomain) against the oracle's, and the two benchmark
+  solves' true residuals recomputed with the oracle's full-size matrix."""
 import sys
 
 import numpy as np
@@ -197,6 +198,35 @@ def test_order2_benchmark_size_sampled_local_solves(gpu_lib, ctx):
         say("  ORAS order 2 xi %g l %d owned %d of %d: max rel err %.2e"
             % (xi, l, int(own.sum()), len(idx), err))
         assert err <= 1e-10
+
+
+@pytest.mark.timeout(900)
+def test_order2_benchmark_size_gmres_true_residual(gpu_lib, ctx):
+    """The order-2 benchmark's two solves at full size (24^3, 542,736 DOFs, 4x4x4 subdomains, 1
+    layer, k = 12, two-level hybrid ORAS with the nested coarse mesh of 4^3 cubes, GMRES(100) to
+    rtol 1e-6) on a seeded random right-hand side: at xi_prob = xi_prec = k^2, and ImpHRAS with
+    xi_prob = 0, xi_prec = k.  The true relative residual recomputed with the oracle's order-2
+    matrix at full size is <= rtol and equals the one the library reports to 1e-9."""
+    n, k = (24, 24, 24), 12.0
+    S = order2.Space(OMesh(*n))
+    lm = gpu_lib.Mesh(*n)
+    lp = gpu_lib.Partition(lm, 4, 4, 4, 1)
+    f = random_rhs(S.n, 8)
+    for xi_prob, xi_prec in ((k * k, k * k), (0.0, k)):
+        lA = gpu_lib.Matrix(ctx, lm, k, xi_prob, order=2)
+        lAp = lA if xi_prec == xi_prob else gpu_lib.Matrix(ctx, lm, k, xi_prec, order=2)
+        P = gpu_lib.Precond(ctx, lAp, lm, lp, "oras", xi_prec=xi_prec)
+        P.add_coarse(ctx, lAp, lm, 6, "hybrid")
+        xd = dev(np.zeros(S.n))
+        st = gpu_lib.gmres(ctx, lA, P, dev(f), xd, restart=100, rtol=1e-6)
+        x = host(xd)
+        del P, lAp, lA
+        oA = order2.assemble(S, k, xi_prob)
+        rel = np.linalg.norm(f - oA @ x) / np.linalg.norm(f)
+        say("  order 2, xi_prob %g xi_prec %g: %d iterations, reported %.4e, oracle %.4e"
+            % (xi_prob, xi_prec, st["iters"], st["relres_true"], rel))
+        assert st["converged"] and rel <= 1e-6
+        assert abs(rel - st["relres_true"]) <= 1e-9
 
 
 @pytest.mark.parametrize("bc", [fem.BC_IMPEDANCE, fem.BC_PEC])
