@@ -142,12 +142,15 @@ def test_fullsize_sampled_local_solves(gpu_lib, big):
 
 
 @pytest.mark.timeout(900)
-def test_gmres_fullsize_true_residual(gpu_lib, big):
+@pytest.mark.parametrize("kind,xi", [("oras", K * K), ("as", K)])
+def test_gmres_fullsize_true_residual(gpu_lib, big, kind, xi):
+    """ORAS at xi = k^2 (13 iterations) and AS at xi = k (the batch's longest solve, over 100
+    iterations, so GMRES(100) restarts)."""
     mx, b = gpu_lib, big
-    say("full-size ORAS GMRES(100), true residual with the oracle's matrix")
-    oA = b["oA"](K * K)
-    lA = mx.Matrix(b["ctx"], b["lm"], K, K * K)
-    P = mx.Precond(b["ctx"], lA, b["lm"], b["lp"], "oras")
+    say("full-size", kind, "xi", xi, "GMRES(100), true residual with the oracle's matrix")
+    oA = b["oA"](xi)
+    lA = mx.Matrix(b["ctx"], b["lm"], K, xi)
+    P = mx.Precond(b["ctx"], lA, b["lm"], b["lp"], kind)
     f = random_rhs(b["E"], 2)
     x = _dev(np.zeros(b["E"]))
     st = mx.gmres(b["ctx"], lA, P, _dev(f), x, restart=100, rtol=1e-6)
