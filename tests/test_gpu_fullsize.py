@@ -161,6 +161,26 @@ def test_gmres_fullsize_true_residual(gpu_lib, big, kind, xi):
     assert abs(rel - st["relres_true"]) <= 1e-9
 
 
+@pytest.mark.timeout(900)
+def test_fgmres_mixed_fullsize_true_residual(gpu_lib, big):
+    """The mixed-precision path at full size (ORAS with complex64 factors and SpMV values, FP64
+    FGMRES(100), xi = k): the true residual recomputed with the oracle's FP64 matrix is <= rtol and
+    equals the reported one, so the FP64 stopping test is met for the oracle's problem."""
+    mx, b = gpu_lib, big
+    say("full-size mixed ORAS FGMRES(100), true residual with the oracle's matrix")
+    oA = b["oA"](K)
+    lA = mx.Matrix(b["ctx"], b["lm"], K, K)
+    P = mx.Precond(b["ctx"], lA, b["lm"], b["lp"], "oras", precision="c64")
+    f = random_rhs(b["E"], 3)
+    x = _dev(np.zeros(b["E"]))
+    st = mx.gmres(b["ctx"], lA, P, _dev(f), x, restart=100, rtol=1e-6, flexible=True, spmv_c64=True)
+    xs = _host(x)
+    rel = np.linalg.norm(f - oA @ xs) / np.linalg.norm(f)
+    say("  iterations", st["iters"], "reported", st["relres_true"], "oracle residual", rel)
+    assert st["converged"] and rel <= 1e-6
+    assert abs(rel - st["relres_true"]) <= 1e-9
+
+
 @pytest.mark.timeout(1200)
 def test_fullsize_two_level_deflation_sampled(gpu_lib, big):
     """The two-level deflated form (eq:ADEF1ras) over ORAS at xi = k on the 64^3 problem, with the
