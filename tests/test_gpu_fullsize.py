@@ -13,7 +13,8 @@ The oracle cannot solve the whole problem in test time, so the checks are:
   the oracle's.  Bar: 1e-10 relative.  The oracle's local problems are factored in parallel on
   host worker processes;
 * a property at full size: GMRES's reported convergence holds for the oracle's matrix, i.e. the
-  true relative residual computed with the oracle's A is <= rtol;
+  true relative residual computed with the oracle's A is <= rtol (ORAS at xi = k^2, AS at xi = k
+  through a restart, and the mixed-precision FGMRES);
 * the two-level deflated form with the 16^3-cube coarse mesh: the oracle's coarse correction at
   full size plus sampled local solves against the library's application;
 * weighted GMRES: the reported D-norm residual equals the one recomputed with the oracle's A and
