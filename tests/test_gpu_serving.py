@@ -1,7 +1,8 @@
 """Solve server (continuous batching): results are the same alone and in the mix, with the
 preconditioner applications of co-resident requests batched into shared sweep launches or each
-on its own stream; requests that can never fit the HBM budget are refused, and a served solution
-matches the FP64 oracle."""
+on its own stream; requests that can never fit the HBM budget are refused, a served solution
+matches the FP64 oracle, and the largest request of the serving configuration meets its stopping
+test for the oracle's matrix."""
 import numpy as np
 import pytest
 
@@ -102,6 +103,28 @@ def test_served_solution_vs_oracle(gpu_lib):
     err = np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x)
     say("  served err vs oracle", err, "iters", r["iters"], ores.iters)
     assert err <= 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_largest_served_request_true_residual(gpu_lib):
+    """The largest request of the serving configuration (k = 16: n = ceil(16^1.5) + 4 = 68 cubes
+    per side, 4x4x4 subdomains, about 2.3 M DOFs, xi = k, mixed precision): the true relative
+    residual recomputed with the oracle's FP64 matrix and the oracle's Gaussian load vector is
+    <= rtol and equals the one the server reports."""
+    say("largest served request vs the oracle's matrix")
+    req = dict(n=68, p=4, k=16.0, xi=16.0, center=(0.4, 0.55, 0.5), pol=(0.0, 0.6, 0.8), sigma=0.1)
+    srv = gpu_lib.Server(slots=1, precision="c64", restart=50)
+    t = srv.submit(**req)
+    r = srv.wait(t, 300.0)
+    assert r["status"] == 0 and r["converged"], r
+    x = srv.solution(t, r["n_dof"])
+    srv.close()
+    om = OMesh(req["n"], req["n"], req["n"])
+    A = fem.assemble(om, req["k"], req["xi"])
+    f = fem.load_vector(om, fem.gaussian_source(req["center"], req["pol"], req["sigma"]))
+    rel = np.linalg.norm(f - A @ x) / np.linalg.norm(f)
+    say("  n_dof", r["n_dof"], "iters", r["iters"], "reported", r["relres_true"], "oracle residual", rel)
+    assert rel <= 1e-6 and abs(rel - r["relres_true"]) <= 1e-9
 
 
 def test_retry_after_late_allocation_failure(gpu_lib):
